@@ -1,0 +1,189 @@
+/*
+ * gramct -- pixel-basis (box-spline) Gram filtering, box-spline back
+ * projection and CG on the normal equations for parallel-beam X-ray CT,
+ * hand-written HIP for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Shu & Entezari, "Gram Filtering and Sinogram Interpolation for
+ * Pixel-basis in Parallel-beam X-ray CT Reconstruction" (arXiv 2005.13471).
+ *
+ * C ABI.  Plain pointers and sizes only.  Conventions shared by every call:
+ *
+ *   - Pixel k = (k1, k2), 0 <= k1, k2 < N, is the indicator of the rectangle
+ *     of sides lambda_x[0] x lambda_x[1] centred at
+ *     x_k = (lambda_x[0] (k1 - (N-1)/2), lambda_x[1] (k2 - (N-1)/2))
+ *     (Sec. 2: f = sum_k c_k psi(x - Lambda_x k) with psi the pixel, i.e. the
+ *     two-direction bivariate box spline of Sec. 3).  Images are row-major
+ *     [k2][k1], N*N elements.
+ *   - Angle theta_i has detector axis u = (cos theta_i, sin theta_i); a ray is
+ *     the line {x : x.u = y}.  Detector bin m in [0, M) sits at
+ *     y_m = lambda_y (m - (M-1)/2).  Sinograms are row-major [angle][bin].
+ *   - The detector blur is the unit-integral box of width zeta_blur (Sec. 2);
+ *     zeta_blur = 0 means no blur.
+ *   - Gram filter G: (2N-1) x (2N-1), row-major, tap (k1, k2) at
+ *     [(k2 + N-1) * (2N-1) + (k1 + N-1)]; G[k] = G[-k].
+ *   - All array pointers are DEVICE pointers owned by the caller, unless a
+ *     comment says "host".  Data arrays are float (GCT_F32) or double
+ *     (GCT_F64) as selected by the dtype argument.  `stream` is a
+ *     hipStream_t (NULL = the default stream).  Calls are stream-ordered and
+ *     do not block the host, except where stated.
+ *   - Return value: GCT_OK (0) or a negative error code; gct_last_error()
+ *     returns a thread-local message for the last failure.  No C++
+ *     exception crosses this interface.
+ *
+ * Device memory: gct_plan_create allocates the plan's small geometry tables
+ * (per-angle parameters, FFT twiddles, correction-filter taps: O(n_angles)
+ * bytes) once.  Every other buffer, including scratch workspace, is passed in
+ * by the caller; gct_workspace_size reports the bytes each operation needs.
+ */
+#ifndef GRAMCT_H
+#define GRAMCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GCT_OK 0
+#define GCT_EINVAL (-1)      /* bad argument: null pointer, size, geometry, aliasing */
+#define GCT_EHIP (-2)        /* a HIP runtime call or kernel launch failed */
+#define GCT_ENOTCONV (-3)    /* cg_solve: max_iter reached; x holds the last iterate */
+#define GCT_EBREAKDOWN (-4)  /* cg_solve: p.Ap <= 0 or a non-finite value */
+
+typedef enum { GCT_F32 = 0, GCT_F64 = 1 } gct_dtype;
+
+/* Problem statement of Sec. 2: N^2 pixel coefficients, Lambda_x =
+ * diag(lambda_x), the angle set, the detector sampling step lambda_y and bin
+ * count M, the blur width zeta_blur, and the truncation K of the quadratic
+ * B-spline correction filter of Sec. 5 (q[m] kept for |m| <= K; the paper
+ * truncates at 40).  `theta` is a HOST array of n_angles radians, read only
+ * during gct_plan_create.  Limits: 1 <= N <= 2048, n_angles >= 1, M >= 1,
+ * lambda_x, lambda_y > 0, zeta_blur >= 0, 0 <= prefilter_K <= 256. */
+typedef struct {
+    int32_t N;
+    double lambda_x[2];
+    int32_t n_angles;
+    const double *theta;
+    double lambda_y;
+    int32_t M;
+    double zeta_blur;
+    int32_t prefilter_K;
+} gct_geometry;
+
+typedef struct gct_plan gct_plan;
+
+/* Sizes (in elements) of the arrays a plan works on. */
+typedef struct {
+    int32_t N, n_angles, M, prefilter_K;
+    int32_t fft_size;        /* P: power of two >= 2N-1 used for the circulant embedding */
+    int64_t gram_elems;      /* (2N-1)^2 */
+    int64_t spectrum_elems;  /* (P/2+1) * P, real */
+    int64_t image_elems;     /* N^2 */
+    int64_t sino_elems;      /* n_angles * M */
+    int64_t prefiltered_elems; /* n_angles * (M + 2K) */
+} gct_plan_info;
+
+/* Validate the geometry and build the per-angle tables: box-spline
+ * parameters of the Gram filter (Sec. 4), exact piecewise-polynomial
+ * back-projection kernels (Sec. 5), B-spline degrees from the continuity
+ * rule of Sec. 5, correction-filter taps and FFT twiddles, in FP64 on the
+ * host, then copied to the current device (blocking).  *plan is owned by the
+ * caller and released with gct_plan_destroy. */
+int gct_plan_create(const gct_geometry *geom, gct_plan **plan);
+int gct_plan_destroy(gct_plan *plan);
+int gct_plan_get_info(const gct_plan *plan, gct_plan_info *info);
+
+/* Operation ids for gct_workspace_size. */
+enum {
+    GCT_OP_GRAM_BUILD = 0,
+    GCT_OP_GRAM_SPECTRUM = 1,
+    GCT_OP_GRAM_APPLY = 2,
+    GCT_OP_PREFILTER = 3,
+    GCT_OP_BACKPROJECT = 4,
+    GCT_OP_FORWARD = 5,
+    GCT_OP_CG = 6
+};
+
+/* Bytes of device workspace operation `op` needs in `dtype` (0 if none).
+ * Workspace must be 256-byte aligned; its contents on entry are ignored. */
+size_t gct_workspace_size(const gct_plan *plan, int op, gct_dtype dtype);
+
+/* Gram filter (Sec. 4): G[k] = sum over angles of the autocorrelation of
+ * the projected pixel, a univariate box spline with directions
+ * {l1|c|, l1|c|, l2|s|, l2|s|} (plus {zeta, zeta} with blur), evaluated at
+ * the projected tap offset l1 k1 c + l2 k2 s, times (l1 l2)^2.  Exact up to
+ * floating-point rounding.  Output G: gram_elems. */
+int gct_gram_build(const gct_plan *plan, gct_dtype dtype, void *G, void *stream);
+
+/* Real, even spectrum of the P x P circulant embedding of G (taps with
+ * |k1| or |k2| = P/2 .. are zero), pre-scaled by 1/P^2 so that gram_apply
+ * needs no further normalisation.  Layout [w1][w2], w1 in [0, P/2],
+ * w2 in [0, P): spectrum_elems reals.  Needs workspace. */
+int gct_gram_spectrum(const gct_plan *plan, gct_dtype dtype, const void *G, void *Ghat,
+                      void *ws, void *stream);
+
+/* Normal operator as Gram filtering (Sec. 4, Toeplitz-block-Toeplitz
+ * remark): y[i] = sum_{j in [0,N)^2} G[i - j] c[j], a zero-padded linear
+ * convolution of the N x N coefficients with the (2N-1)^2 filter, computed
+ * exactly (up to rounding) through the P x P circulant embedding.
+ * c, y: image_elems; y must not alias c.  Needs workspace. */
+int gct_gram_apply(const gct_plan *plan, gct_dtype dtype, const void *Ghat, const void *c,
+                   void *y, void *ws, void *stream);
+
+/* Digital correction filter of Sec. 5 (eq. correction filter) per angle
+ * row: p = q_d * g_s with g_s zero outside [0, M); q_d = delta for
+ * B-spline degree d <= 1 and q[m] = sqrt(2) (2 sqrt(2) - 3)^|m|, |m| <= K,
+ * for d = 2.  p: [angle][M + 2K], element m + K holds bin m. */
+int gct_prefilter(const gct_plan *plan, gct_dtype dtype, const void *g_s, void *p, void *stream);
+
+/* Back projection with the exact adjoint and box-spline sinogram
+ * interpolation (Sec. 5): b[k] = sum_theta integral F_k(y) ghat_theta(y) dy,
+ * ghat_theta(y) = sum_m p[m] beta_d((y - y_m)/lambda_y).  Each (pixel, angle,
+ * bin) weight is a univariate box spline with directions {l1|c|, l2|s|,
+ * zeta, lambda_y x (d+1)}, evaluated exactly from per-angle piecewise
+ * polynomials.  g_s: sino_elems; b: image_elems.  Workspace holds the
+ * prefiltered sinogram. */
+int gct_backproject_boxspline(const gct_plan *plan, gct_dtype dtype, const void *g_s, void *b,
+                              void *ws, void *stream);
+
+/* Forward model (Sec. 2, Sec. 4 eq. xray_of_f and eq. blurxray_of_f):
+ * g_s[theta, m] = sum_k c_k l1 l2 M_{l1|c|, l2|s|, zeta}(y_m - x_k.u).
+ * Supporting operation (sinogram synthesis, adjoint tests). */
+int gct_forward_project(const gct_plan *plan, gct_dtype dtype, const void *c, void *g_s,
+                        void *stream);
+
+/* Result of gct_cg_solve (host struct). */
+typedef struct {
+    int32_t iters;        /* iterations performed */
+    int32_t status;       /* GCT_OK, GCT_ENOTCONV or GCT_EBREAKDOWN */
+    double rel_res;       /* recursive ||r_k|| / ||b|| at exit */
+    double rel_res_true;  /* ||b - A x_k|| / ||b|| recomputed at exit */
+    double rel_res0;      /* ||b - A x_0|| / ||b|| of the start actually used */
+    int32_t fell_back;    /* 1 if the given start vector was no better than zero
+                             (||b - A x_0|| >= ||b|| or non-finite) and CG restarted
+                             from x_0 = 0 */
+} gct_cg_result;
+
+/* Conjugate gradients on (H^T H) x = b with the Gram-filter operator
+ * (Sec. 2: a single back projection, then the filter in every iteration;
+ * the paper iterates with steepest descent, Sec. 6.2).  Vectors in dtype;
+ * inner products and residual norms in FP64 on the device.  Stops when
+ * ||r_k|| <= rtol ||b|| or after max_iter iterations.  x: on entry the start
+ * vector if use_x0 != 0 (else ignored and zero is used); on exit the last
+ * iterate.  A start vector with ||b - A x_0|| >= ||b|| is replaced by zero
+ * (result->fell_back = 1).  hist: optional HOST array of max_iter + 1 doubles receiving
+ * ||r_k||/||b||.  check_every: iterations between host convergence checks
+ * (<= 0 selects 8); iterations after convergence are skipped on the device.
+ * BLOCKS the host until the solve is complete. */
+int gct_cg_solve(const gct_plan *plan, gct_dtype dtype, const void *Ghat, const void *b, void *x,
+                 int use_x0, double rtol, int32_t max_iter, int32_t check_every, double *hist,
+                 gct_cg_result *result, void *ws, void *stream);
+
+/* Thread-local description of the last error (never NULL). */
+const char *gct_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GRAMCT_H */

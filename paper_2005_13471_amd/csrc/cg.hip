@@ -1,0 +1,296 @@
+// Conjugate gradients on the normal equations (H^T H) x = b (Sec. 2: one
+// back projection, then the Gram filter in every iteration).  Vectors live in
+// the working precision; every inner product and the residual norm are
+// accumulated in FP64.  All scalars stay on the device, so a chunk of
+// iterations is queued without host round trips; the host reads the state
+// once per chunk.  Once converged (or broken down) the status word is set
+// and every kernel queued after it returns at once.
+#include <algorithm>
+#include <cmath>
+
+#include "gct_internal.h"
+
+namespace gct {
+
+template <typename T>
+hipError_t launch_apply_passes(const gct_plan *p, const T *Ghat, const T *src, T *y, void *ws,
+                               hipStream_t s, const int64_t *status, T *pupd, const double *beta,
+                               const T *dotv, double *partial);
+int apply_row_blocks(const gct_plan *p, size_t elem);
+
+constexpr int CG_RING = 64;
+constexpr int VBLK = 256;  // blocks of the vector kernels (fixed: deterministic reductions)
+
+enum : int64_t { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
+
+struct CGState {
+    double rr, bb, rr0, pAp, alpha, beta, thr2, pad;
+    int64_t k, status, pad2, pad3;
+    double ring[CG_RING];  // ||r_k||^2 at ring[k % CG_RING]
+};
+
+__device__ __forceinline__ double block_sum(double v)
+{
+    __shared__ double red[256];
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// r = b - Ax (or b), p = r, x = 0 when no start vector; partial ||r||^2, ||b||^2.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cg_init(const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r, T *__restrict__ p,
+          const T *__restrict__ Ax, size_t n, double *__restrict__ part_rr,
+          double *__restrict__ part_bb)
+{
+    double rr = 0.0, bb = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const T bi = b[i];
+        T ri;
+        if (Ax) {
+            ri = bi - Ax[i];
+        } else {
+            ri = bi;
+            x[i] = T(0);
+        }
+        r[i] = ri;
+        p[i] = ri;
+        rr += (double)ri * (double)ri;
+        bb += (double)bi * (double)bi;
+    }
+    rr = block_sum(rr);
+    bb = block_sum(bb);
+    if (threadIdx.x == 0) {
+        part_rr[blockIdx.x] = rr;
+        part_bb[blockIdx.x] = bb;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_cg_init_fin(CGState *st, const double *part_rr, const double *part_bb, int np, double rtol2)
+{
+    double rr = 0.0, bb = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        rr += part_rr[i];
+        bb += part_bb[i];
+    }
+    rr = block_sum(rr);
+    bb = block_sum(bb);
+    if (threadIdx.x == 0) {
+        st->rr = rr;
+        st->bb = bb;
+        st->rr0 = rr;
+        st->beta = 0.0;
+        st->thr2 = rtol2 * bb;
+        st->k = 0;
+        st->ring[0] = rr;
+        st->status = (rr <= st->thr2) ? CG_CONVERGED : CG_RUNNING;
+        if (!(rr == rr) || !(bb == bb)) st->status = CG_BREAKDOWN;
+    }
+}
+
+// alpha = rr / p.Ap
+__global__ void __launch_bounds__(256) k_cg_alpha(CGState *st, const double *part, int np)
+{
+    if (st->status != CG_RUNNING) return;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) {
+        st->pAp = s;
+        if (!(s > 0.0) || !(s < INFINITY)) {
+            st->status = CG_BREAKDOWN;
+        } else {
+            st->alpha = st->rr / s;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha Ap; partial ||r||^2
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cg_update(const CGState *st, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
+            const T *__restrict__ Ap, size_t n, double *__restrict__ part)
+{
+    if (st->status != CG_RUNNING) return;
+    const T al = (T)st->alpha;
+    double rr = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        x[i] += al * p[i];
+        const T ri = r[i] - al * Ap[i];
+        r[i] = ri;
+        rr += (double)ri * (double)ri;
+    }
+    rr = block_sum(rr);
+    if (threadIdx.x == 0) part[blockIdx.x] = rr;
+}
+
+// beta = rr_new / rr, convergence test
+__global__ void __launch_bounds__(256) k_cg_beta(CGState *st, const double *part, int np)
+{
+    if (st->status != CG_RUNNING) return;
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) {
+        const int64_t k = st->k + 1;
+        st->k = k;
+        st->ring[k % CG_RING] = s;
+        st->beta = s / st->rr;
+        st->rr = s;
+        if (!(s == s)) st->status = CG_BREAKDOWN;
+        else if (s <= st->thr2) st->status = CG_CONVERGED;
+    }
+}
+
+// partial ||b - Ax||^2
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_resid(const T *__restrict__ b, const T *__restrict__ Ax, size_t n, double *__restrict__ part)
+{
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (size_t)gridDim.x * blockDim.x) {
+        const double d = (double)b[i] - (double)Ax[i];
+        acc += d * d;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(256) k_sum(const double *part, int np, double *out)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) *out = s;
+}
+
+// ---------------------------------------------------------------------------
+struct CGLayout {
+    size_t apply, r, p, Ap, part, part2, st, total;
+};
+
+static CGLayout cg_layout(const gct_plan *p, size_t elem)
+{
+    CGLayout L;
+    const size_t img = align256((size_t)p->N * p->N * elem);
+    const int np = std::max(VBLK, apply_row_blocks(p, elem));
+    size_t o = 0;
+    L.apply = o; o += apply_ws_bytes(p, elem);
+    L.r = o; o += img;
+    L.p = o; o += img;
+    L.Ap = o; o += img;
+    L.part = o; o += align256((size_t)np * sizeof(double));
+    L.part2 = o; o += align256((size_t)np * sizeof(double));
+    L.st = o; o += align256(sizeof(CGState));
+    L.total = o;
+    return L;
+}
+
+size_t cg_ws_bytes(const gct_plan *p, size_t elem) { return cg_layout(p, elem).total; }
+
+#define GCT_TRY(call)                                        \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return check_hip(e_, #call);   \
+    } while (0)
+
+template <typename T>
+int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, double rtol,
+             int max_iter, int check_every, double *hist, gct_cg_result *res, void *ws,
+             hipStream_t s)
+{
+    const CGLayout L = cg_layout(p, sizeof(T));
+    char *w = reinterpret_cast<char *>(ws);
+    void *aws = w + L.apply;
+    T *r = reinterpret_cast<T *>(w + L.r), *pv = reinterpret_cast<T *>(w + L.p);
+    T *Ap = reinterpret_cast<T *>(w + L.Ap);
+    double *part = reinterpret_cast<double *>(w + L.part);
+    double *part2 = reinterpret_cast<double *>(w + L.part2);
+    CGState *st = reinterpret_cast<CGState *>(w + L.st);
+    const size_t n = (size_t)p->N * p->N;
+    const int rblocks = apply_row_blocks(p, sizeof(T));
+    if (check_every <= 0) check_every = 8;
+    if (check_every > CG_RING) check_every = CG_RING;
+
+    CGState hs;
+    int fell_back = 0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        const bool start = use_x0 && attempt == 0;
+        if (start) GCT_TRY(launch_apply_passes<T>(p, Ghat, x, Ap, aws, s, nullptr, nullptr, nullptr,
+                                                  nullptr, nullptr));
+        hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, b, x, r, pv,
+                           start ? (const T *)Ap : nullptr, n, part, part2);
+        hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK,
+                           rtol * rtol);
+        GCT_TRY(hipGetLastError());
+        GCT_TRY(hipMemcpyAsync(&hs, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        GCT_TRY(hipStreamSynchronize(s));
+        // a start vector that is no better than zero is dropped (plain CG is
+        // the fallback)
+        if (start && hs.bb > 0.0 && !(hs.rr < hs.bb)) {
+            fell_back = 1;
+            continue;
+        }
+        break;
+    }
+    const double bb = hs.bb;
+    auto rel = [bb](double rr) { return bb > 0.0 ? std::sqrt(rr / bb) : 0.0; };
+    res->rel_res0 = rel(hs.rr0);
+    res->fell_back = fell_back;
+    if (hist) hist[0] = rel(hs.rr0);
+
+    int64_t done = 0;
+    while (hs.status == CG_RUNNING && done < max_iter) {
+        const int chunk = (int)std::min<int64_t>(check_every, max_iter - done);
+        for (int i = 0; i < chunk; ++i) {
+            GCT_TRY(launch_apply_passes<T>(p, Ghat, r, Ap, aws, s, &st->status, pv, &st->beta, pv,
+                                           part));
+            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, st, part, rblocks);
+            hipLaunchKernelGGL(k_cg_update<T>, dim3(VBLK), dim3(256), 0, s, st, x, r, pv, Ap, n,
+                               part2);
+            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, st, part2, VBLK);
+        }
+        GCT_TRY(hipGetLastError());
+        const int64_t kprev = hs.k;
+        GCT_TRY(hipMemcpyAsync(&hs, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        GCT_TRY(hipStreamSynchronize(s));
+        if (hist)
+            for (int64_t k = kprev + 1; k <= hs.k; ++k) hist[k] = rel(hs.ring[k % CG_RING]);
+        done += chunk;
+    }
+    // true residual of the returned iterate
+    GCT_TRY(launch_apply_passes<T>(p, Ghat, x, Ap, aws, s, nullptr, nullptr, nullptr, nullptr,
+                                   nullptr));
+    hipLaunchKernelGGL(k_resid<T>, dim3(VBLK), dim3(256), 0, s, b, Ap, n, part);
+    hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, VBLK, &st->pad);
+    GCT_TRY(hipGetLastError());
+    double rt = 0.0;
+    GCT_TRY(hipMemcpyAsync(&rt, &st->pad, sizeof(double), hipMemcpyDeviceToHost, s));
+    GCT_TRY(hipStreamSynchronize(s));
+
+    res->iters = (int32_t)hs.k;
+    res->rel_res = rel(hs.rr);
+    res->rel_res_true = rel(rt);
+    if (hs.status == CG_CONVERGED) res->status = GCT_OK;
+    else if (hs.status == CG_BREAKDOWN) res->status = GCT_EBREAKDOWN;
+    else res->status = GCT_ENOTCONV;
+    return res->status;
+}
+
+template int cg_solve<float>(const gct_plan *, const float *, const float *, float *, int, double,
+                             int, int, double *, gct_cg_result *, void *, hipStream_t);
+template int cg_solve<double>(const gct_plan *, const double *, const double *, double *, int,
+                              double, int, int, double *, gct_cg_result *, void *, hipStream_t);
+
+}  // namespace gct

@@ -1,0 +1,135 @@
+// Internal declarations shared by the host plan code and the HIP kernels of
+// libgramct.  Not part of the public interface (include/gramct.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "../../include/gramct.h"
+
+namespace gct {
+
+// ---------------------------------------------------------------------------
+// Per-angle tables, built on the host in FP64 and copied to the device.
+// ---------------------------------------------------------------------------
+
+// Gram filter (Sec. 4): at each angle the autocorrelated projected pixel is
+// the centred box spline A = T_L * T_M * T_S (T_w = M_[w,w], a triangle of
+// half-width w and unit integral) with {L >= M >= S} the sorted directions
+// {l1|c|, l2|s|, zeta}, times (l1 l2)^2.  Positions use FP64 (cx, sx).
+template <typename T>
+struct GramAngle {
+    double cx, sx;    // l1 cos, l2 sin: tap (k1, k2) projects to k1 cx + k2 sx
+    T L, M, S;        // sorted directions
+    T iL2;            // 1 / L^2
+    T iM2;            // 1 / M^2      (0 if M == 0)
+    T c6M;            // 1 / (6 M^2)  (0 if M == 0)
+    T s12;            // S^2 / 12
+    T c120S;          // 1 / (120 S^2) (0 if S == 0)
+    T scale;          // (l1 l2)^2
+    T half;           // support half-width L + M + S
+};
+
+// Forward projection (Sec. 4 eq. blurxray_of_f): the blurred footprint is
+// l1 l2 M_[L, M, S] with {L >= M >= S} = sorted {l1|c|, l2|s|, zeta}.
+template <typename T>
+struct FwdAngle {
+    double cx, sx;    // l1 cos, l2 sin (FP64 positions)
+    T L, M, S;
+    T iL;             // 1/L
+    T iM;             // 1/M (0 if M == 0)
+    T i2MS;           // 1/(2 M S) (0 if S == 0)
+    T scale_over_L;   // l1 l2 / L
+    T half;           // (L + M + S)/2
+    int32_t rows;     // 1: iterate over image rows (|l1 c| >= |l2 s|), 0: over columns
+    int32_t pad;
+};
+
+// Back projection (Sec. 5).  For a pixel whose centre projects to the
+// fractional bin index z = z0 + k1 dz1 + k2 dz2, write z = m0 + t with
+// m0 = floor(z), t in [0,1).  Its contribution at this angle is
+//   sum_j p[m0 + j] kappa(j - t),  j = jlo .. jlo + J - 1,
+// where kappa = l1 l2 M_{Xi / lambda_y}, Xi = {l1|c|, l2|s|, zeta,
+// lambda_y x (d+1)}.  On each sub-interval [brk[s], brk[s+1]) of t the
+// weights kappa(j - t) are polynomials in u = t - brk[s] with coefficients
+// coef[s][j][0..D].
+struct BPAngleHost {
+    double z0, dz1, dz2;
+    int32_t nsub, jlo, degree;
+};
+
+// Table layout sizes for a plan (padded maxima over all angles).
+struct BPDims {
+    int32_t smax;   // sub-intervals per angle (padded)
+    int32_t J;      // weights per pixel and angle
+    int32_t D1;     // polynomial coefficients per weight (degree + 1)
+};
+
+struct DeviceTables {
+    void *gram_f32 = nullptr, *gram_f64 = nullptr;    // GramAngle<T>[n]
+    void *fwd_f32 = nullptr, *fwd_f64 = nullptr;      // FwdAngle<T>[n]
+    void *bp_geo = nullptr;                           // double[n][4]: z0, dz1, dz2, 0
+    void *bp_int = nullptr;                           // int32[n][4]: nsub, jlo, degree, 0
+    void *bp_brk_f32 = nullptr, *bp_brk_f64 = nullptr;  // T[n][smax]
+    void *bp_coef_f32 = nullptr, *bp_coef_f64 = nullptr;  // T[n][smax][J][D1]
+    void *tw_f32 = nullptr, *tw_f64 = nullptr;        // complex twiddles e^{-2 pi i k / P}, k < P/2
+    void *q_f32 = nullptr, *q_f64 = nullptr;          // correction filter q[-K..K]
+    void *deg = nullptr;                              // int32[n]: B-spline degree per angle
+};
+
+}  // namespace gct
+
+struct gct_plan {
+    int32_t N, n, M, K;
+    double lx1, lx2, ly, zeta;
+    int32_t P, logP;
+    gct::BPDims bp;
+    gct::DeviceTables dev;
+    int device;
+};
+
+namespace gct {
+
+void set_error(const std::string &msg);
+int fail(int code, const std::string &msg);
+int check_hip(hipError_t e, const char *what);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the .hip files), templated on float/double.
+// Each returns hipSuccess or the launch error.
+// ---------------------------------------------------------------------------
+template <typename T>
+hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s);
+
+template <typename T>
+hipError_t launch_gram_spectrum(const gct_plan *p, const T *G, T *Ghat, void *ws, hipStream_t s);
+
+template <typename T>
+hipError_t launch_gram_apply(const gct_plan *p, const T *Ghat, const T *c, T *y, void *ws,
+                             hipStream_t s);
+
+template <typename T>
+hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s);
+
+template <typename T>
+hipError_t launch_backproject(const gct_plan *p, const T *prefiltered, T *b, hipStream_t s);
+
+template <typename T>
+hipError_t launch_forward(const gct_plan *p, const T *c, T *g, hipStream_t s);
+
+// Workspace sizing helpers.
+size_t apply_ws_bytes(const gct_plan *p, size_t elem);
+size_t spectrum_ws_bytes(const gct_plan *p, size_t elem);
+
+template <typename T>
+int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, double rtol,
+             int max_iter, int check_every, double *hist, gct_cg_result *res, void *ws,
+             hipStream_t s);
+size_t cg_ws_bytes(const gct_plan *p, size_t elem);
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+}  // namespace gct

@@ -1,0 +1,108 @@
+// Gram filter construction (Sec. 4).
+//
+// G[k] = sum over angles of A_theta(k1 l1 cos + k2 l2 sin), where A_theta is
+// the autocorrelation of the projected pixel: the centred univariate box
+// spline with directions {l1|c|, l1|c|, l2|s|, l2|s|} (Sec. 4, four-direction
+// spline), plus {zeta, zeta} with detector blur (six-direction spline), times
+// (l1 l2)^2.  Because the footprint is even, its autocorrelation equals its
+// self-convolution.
+//
+// Evaluation in FP32 without cancellation.  With T_w = M_[w,w] (triangle of
+// half-width w, height 1/w) and {L >= M >= S} the sorted directions,
+// A = T_L * T_M * T_S.  Writing psi_w(y) = (w - |y|)_+^3 / (6 w^2) and
+// chi_S(y) = (S - |y|)_+^5 / (120 S^2), one has exactly
+//   A(x)   = T_L(x) + [rho(x + L) - 2 rho(x) + rho(x - L)] / L^2,
+//   rho(y) = psi_M(y) + (S^2/12) T_M(y)
+//            + [chi_S(y + M) - 2 chi_S(y) + chi_S(y - M)] / M^2.
+// (Derivation: T_w = w^-2 * second difference of |x|/2 with step w;
+// (|x|/2) * T_w = |x|/2 + psi_w; (|x|^3/12) * T_S = |x|^3/12 + |x| S^2/24 +
+// chi_S; then collect the smooth parts.)  Every term is bounded by about
+// M/6 and no large intermediate cancels, unlike the truncated-power sum,
+// which loses all digits in FP32 at near-axis angles where one direction is
+// tiny.  A zero direction drops out (its constants are 0).
+//
+// Tap offsets are formed in FP64 (k1 cx + k2 sx reaches ~1.5e3 at N = 1024
+// while the spline needs them to ~1e-7) and rounded once.  The sum over
+// angles is compensated (Kahan).
+#include "gct_internal.h"
+
+namespace gct {
+
+template <typename T>
+__device__ __forceinline__ T pos1(T t) { return t > T(0) ? t : T(0); }
+
+template <typename T>
+__device__ __forceinline__ T chi5(const GramAngle<T> &g, T y)
+{
+    const T t = pos1(g.S - fabs(y));
+    const T t2 = t * t;
+    return t2 * t2 * t * g.c120S;
+}
+
+template <typename T>
+__device__ __forceinline__ T rho(const GramAngle<T> &g, T y, bool blur)
+{
+    const T t = pos1(g.M - fabs(y));
+    T r = t * t * t * g.c6M;
+    if (blur) {
+        r += g.s12 * t * g.iM2;
+        r += (chi5(g, y + g.M) - T(2) * chi5(g, y) + chi5(g, y - g.M)) * g.iM2;
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ T gram_A(const GramAngle<T> &g, T x, bool blur)
+{
+    const T ax = fabs(x);
+    if (ax >= g.half) return T(0);
+    const T tl = pos1(g.L - ax) * g.iL2;
+    const T r = rho(g, x + g.L, blur) - T(2) * rho(g, x, blur) + rho(g, x - g.L, blur);
+    return g.scale * (tl + r * g.iL2);
+}
+
+// One 16 x 16 tile of taps per block.  The angle loop is uniform across the
+// block; an angle whose projected tile interval misses the support of A is
+// skipped by the whole block.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ ga)
+{
+    const int W = 2 * N - 1;
+    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    const int c0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
+    const int k1 = c0 + tx - (N - 1), k2 = r0 + ty - (N - 1);
+    const double ka = c0 - (N - 1), kb = c0 + 15 - (N - 1);
+    const double la = r0 - (N - 1), lb = r0 + 15 - (N - 1);
+    T acc = 0, comp = 0;
+    for (int a = 0; a < n; ++a) {
+        const GramAngle<T> g = ga[a];
+        // projected interval of the tile (extreme corners)
+        const double p1 = ka * g.cx, p2 = kb * g.cx, q1 = la * g.sx, q2 = lb * g.sx;
+        const double dmin = fmin(p1, p2) + fmin(q1, q2), dmax = fmax(p1, p2) + fmax(q1, q2);
+        if (dmax <= -(double)g.half || dmin >= (double)g.half) continue;
+        const T d = (T)((double)k1 * g.cx + (double)k2 * g.sx);
+        const T v = g.S > T(0) ? gram_A(g, d, true) : gram_A(g, d, false);
+        const T yk = v - comp;
+        const T tk = acc + yk;
+        comp = (tk - acc) - yk;
+        acc = tk;
+    }
+    if (c0 + tx < W && r0 + ty < W) G[(size_t)(r0 + ty) * W + (c0 + tx)] = acc;
+}
+
+template <typename T>
+hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s)
+{
+    const int W = 2 * p->N - 1;
+    const dim3 grid((W + 15) / 16, (W + 15) / 16);
+    const GramAngle<T> *ga =
+        reinterpret_cast<const GramAngle<T> *>(sizeof(T) == 4 ? p->dev.gram_f32 : p->dev.gram_f64);
+    hipLaunchKernelGGL(k_gram_build<T>, grid, dim3(256), 0, s, G, p->N, p->n, ga);
+    return hipGetLastError();
+}
+
+template hipError_t launch_gram_build<float>(const gct_plan *, float *, hipStream_t);
+template hipError_t launch_gram_build<double>(const gct_plan *, double *, hipStream_t);
+
+}  // namespace gct

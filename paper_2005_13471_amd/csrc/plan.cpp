@@ -1,0 +1,668 @@
+// Host side of libgramct: geometry validation, per-angle tables built in
+// FP64, and the C-ABI entry points of include/gramct.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gramct.h"
+#include "../../include/gramct_host.h"
+#include "gct_internal.h"
+
+namespace gct {
+
+static thread_local std::string g_last_error = "no error";
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+int fail(int code, const std::string &msg)
+{
+    set_error(msg);
+    return code;
+}
+
+int check_hip(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return GCT_OK;
+    return fail(GCT_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---------------------------------------------------------------------------
+// Exact piecewise polynomials for centred univariate box splines.
+//
+// A box spline with directions w_1..w_r (Sec. 3, eq. boxconv) is the
+// convolution of the unit-integral boxes M_w = (1/w) 1_[-w/2, w/2].  It is
+// built by repeated convolution, smallest direction first: convolving f with
+// M_w gives (F(x + w/2) - F(x - w/2)) / w, F the antiderivative of f.
+// Starting from the narrowest box means every later difference spans a
+// width at least as large as the features of F, so nothing cancels badly
+// even when one direction is tiny (near-axis angles).  Each piece stores
+// its polynomial in the local variable (x - left knot).
+// ---------------------------------------------------------------------------
+constexpr int PP_MAXC = 10;
+using Coef = std::array<double, PP_MAXC>;
+
+struct PPoly {
+    std::vector<double> x;  // knots, size pieces + 1
+    std::vector<Coef> c;    // per piece, coefficients of (x - x_i)^k
+    int deg = 0;
+};
+
+// b(u) = a(u + d): repeated synthetic division.
+static Coef taylor_shift(const Coef &a, int deg, double d)
+{
+    Coef b = a;
+    for (int i = 0; i < deg; ++i)
+        for (int j = deg - 1; j >= i; --j) b[j] += d * b[j + 1];
+    return b;
+}
+
+static double horner(const Coef &a, int deg, double u)
+{
+    double v = a[deg];
+    for (int k = deg - 1; k >= 0; --k) v = v * u + a[k];
+    return v;
+}
+
+static PPoly pp_box(double w)
+{
+    PPoly f;
+    f.x = {-0.5 * w, 0.5 * w};
+    Coef a{};
+    a[0] = 1.0 / w;
+    f.c = {a};
+    f.deg = 0;
+    return f;
+}
+
+static PPoly pp_convolve_box(const PPoly &f, double w)
+{
+    const int np = (int)f.c.size();
+    const int D = f.deg + 1;
+    // antiderivative, continuous, zero left of the support
+    std::vector<Coef> Fc(np);
+    double acc = 0.0;
+    for (int i = 0; i < np; ++i) {
+        Coef b{};
+        b[0] = acc;
+        for (int k = 0; k <= f.deg; ++k) b[k + 1] = f.c[i][k] / (k + 1);
+        Fc[i] = b;
+        acc = horner(b, D, f.x[i + 1] - f.x[i]);
+    }
+    const double total = acc;
+    std::vector<double> z;
+    z.reserve(2 * f.x.size());
+    for (double v : f.x) {
+        z.push_back(v - 0.5 * w);
+        z.push_back(v + 0.5 * w);
+    }
+    std::sort(z.begin(), z.end());
+    z.erase(std::unique(z.begin(), z.end()), z.end());
+    // polynomial (in u = x - origin) of F(x + sh) on a piece around xm
+    auto Fpoly = [&](double xm, double origin, double sh) {
+        const double y = xm + sh;
+        Coef r{};
+        if (y <= f.x.front()) return r;
+        if (y >= f.x.back()) {
+            r[0] = total;
+            return r;
+        }
+        int i = (int)(std::upper_bound(f.x.begin(), f.x.end(), y) - f.x.begin()) - 1;
+        i = std::max(0, std::min(i, np - 1));
+        return taylor_shift(Fc[i], D, origin + sh - f.x[i]);
+    };
+    PPoly g;
+    g.deg = D;
+    g.x = z;
+    g.c.resize(z.size() - 1);
+    for (size_t j = 0; j + 1 < z.size(); ++j) {
+        const double xm = 0.5 * (z[j] + z[j + 1]);
+        const Coef A = Fpoly(xm, z[j], 0.5 * w), B = Fpoly(xm, z[j], -0.5 * w);
+        Coef r{};
+        for (int k = 0; k <= D; ++k) r[k] = (A[k] - B[k]) / w;
+        g.c[j] = r;
+    }
+    return g;
+}
+
+// Directions <= tol * max are treated as zero: a zero direction is the
+// identity of convolution.
+static PPoly pp_boxspline(std::vector<double> dirs, double scale)
+{
+    double mx = 0.0;
+    for (double &d : dirs) {
+        d = std::fabs(d);
+        mx = std::max(mx, d);
+    }
+    std::vector<double> keep;
+    for (double d : dirs)
+        if (d > 1e-12 * mx) keep.push_back(d);
+    std::sort(keep.begin(), keep.end());
+    PPoly f = pp_box(keep[0]);
+    for (size_t i = 1; i < keep.size(); ++i) f = pp_convolve_box(f, keep[i]);
+    for (auto &c : f.c)
+        for (double &v : c) v *= scale;
+    return f;
+}
+
+static double pp_eval(const PPoly &f, double x)
+{
+    if (x <= f.x.front() || x >= f.x.back()) return 0.0;
+    int i = (int)(std::upper_bound(f.x.begin(), f.x.end(), x) - f.x.begin()) - 1;
+    i = std::max(0, std::min(i, (int)f.c.size() - 1));
+    return horner(f.c[i], f.deg, x - f.x[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Per-angle geometry.
+// ---------------------------------------------------------------------------
+struct AngleDirs {
+    double c, s;      // cos, sin
+    double a1, a2;    // l1|c|, l2|s| (exact zeros at axis-aligned angles)
+    bool axis;
+    int degree;       // B-spline degree of the interpolation (Sec. 5)
+};
+
+// Continuity rule of Sec. 5: the projected signal is C^0 in general and
+// C^-1 at axis-aligned angles without blur; C^1 / C^0 with blur.  The
+// interpolating B-spline degree is one above the continuity order.
+static AngleDirs angle_dirs(double th, double l1, double l2, double zeta)
+{
+    AngleDirs d;
+    d.c = std::cos(th);
+    d.s = std::sin(th);
+    d.axis = std::fabs(d.c) < 1e-12 || std::fabs(d.s) < 1e-12;
+    d.a1 = std::fabs(d.c) < 1e-12 ? 0.0 : l1 * std::fabs(d.c);
+    d.a2 = std::fabs(d.s) < 1e-12 ? 0.0 : l2 * std::fabs(d.s);
+    if (zeta > 0.0) d.degree = d.axis ? 1 : 2;
+    else d.degree = d.axis ? 0 : 1;
+    return d;
+}
+
+static void sorted3(double a, double b, double c, double &L, double &M, double &S)
+{
+    double v[3] = {a, b, c};
+    std::sort(v, v + 3);
+    L = v[2];
+    M = v[1];
+    S = v[0];
+}
+
+template <typename T>
+static GramAngle<T> gram_angle(const AngleDirs &d, double l1, double l2, double zeta)
+{
+    GramAngle<T> g{};
+    double L, M, S;
+    sorted3(d.a1, d.a2, zeta, L, M, S);
+    g.cx = l1 * d.c;
+    g.sx = l2 * d.s;
+    g.L = (T)L;
+    g.M = (T)M;
+    g.S = (T)S;
+    g.iL2 = (T)(1.0 / (L * L));
+    g.iM2 = M > 0 ? (T)(1.0 / (M * M)) : T(0);
+    g.c6M = M > 0 ? (T)(1.0 / (6.0 * M * M)) : T(0);
+    g.s12 = (T)(S * S / 12.0);
+    g.c120S = S > 0 ? (T)(1.0 / (120.0 * S * S)) : T(0);
+    g.scale = (T)(l1 * l2 * l1 * l2);
+    g.half = (T)(L + M + S);
+    return g;
+}
+
+template <typename T>
+static FwdAngle<T> fwd_angle(const AngleDirs &d, double l1, double l2, double zeta)
+{
+    FwdAngle<T> f{};
+    double L, M, S;
+    sorted3(d.a1, d.a2, zeta, L, M, S);
+    f.cx = l1 * d.c;
+    f.sx = l2 * d.s;
+    f.L = (T)L;
+    f.M = (T)M;
+    f.S = (T)S;
+    f.iL = (T)(1.0 / L);
+    f.iM = M > 0 ? (T)(1.0 / M) : T(0);
+    f.i2MS = (M > 0 && S > 0) ? (T)(1.0 / (2.0 * M * S)) : T(0);
+    f.scale_over_L = (T)(l1 * l2 / L);
+    f.half = (T)(0.5 * (L + M + S));
+    f.rows = std::fabs(f.cx) >= std::fabs(f.sx) ? 1 : 0;
+    return f;
+}
+
+// Back-projection kernel of one angle as sub-interval polynomials (see
+// BPAngleHost).  coef is [nsub][J][D1] for this angle, J and D1 its own.
+struct BPAngleTable {
+    BPAngleHost h;
+    std::vector<double> brk;   // nsub
+    int J = 0, D1 = 0;
+    std::vector<double> coef;  // nsub * J * D1
+};
+
+static BPAngleTable bp_angle(const AngleDirs &d, int N, double l1, double l2, double ly, int M,
+                             double zeta)
+{
+    BPAngleTable t;
+    std::vector<double> dirs = {d.a1 / ly, d.a2 / ly, zeta / ly};
+    for (int i = 0; i <= d.degree; ++i) dirs.push_back(1.0);
+    const PPoly k = pp_boxspline(dirs, l1 * l2);
+    // sub-interval breakpoints of t in [0,1): fractional parts of -knot
+    std::vector<double> br = {0.0};
+    for (double x : k.x) {
+        double f = -x - std::floor(-x);
+        if (f >= 1.0) f -= 1.0;
+        br.push_back(f);
+    }
+    std::sort(br.begin(), br.end());
+    std::vector<double> ub;
+    for (double v : br)
+        if (ub.empty() || v - ub.back() > 1e-12) ub.push_back(v);
+    if (ub.size() > 1 && 1.0 - ub.back() <= 1e-12) ub.pop_back();
+    t.brk = ub;
+    const int nsub = (int)ub.size();
+    const int jlo = (int)std::floor(k.x.front()) + 1;
+    const int jhi = (int)std::ceil(k.x.back());
+    t.J = jhi - jlo + 1;
+    t.D1 = k.deg + 1;
+    t.coef.assign((size_t)nsub * t.J * t.D1, 0.0);
+    for (int s = 0; s < nsub; ++s) {
+        const double lo = ub[s], hi = (s + 1 < nsub) ? ub[s + 1] : 1.0;
+        for (int j = 0; j < t.J; ++j) {
+            const double jj = jlo + j;
+            const double xm = jj - 0.5 * (lo + hi);  // argument of kappa mid-interval
+            if (xm <= k.x.front() || xm >= k.x.back()) continue;
+            int i = (int)(std::upper_bound(k.x.begin(), k.x.end(), xm) - k.x.begin()) - 1;
+            i = std::max(0, std::min(i, (int)k.c.size() - 1));
+            // kappa(jj - lo - u) = P_i(delta - u), delta = jj - lo - x_i
+            const Coef b = taylor_shift(k.c[i], k.deg, jj - lo - k.x[i]);
+            for (int q = 0; q <= k.deg; ++q)
+                t.coef[((size_t)s * t.J + j) * t.D1 + q] = (q & 1) ? -b[q] : b[q];
+        }
+    }
+    t.h.nsub = nsub;
+    t.h.jlo = jlo;
+    t.h.degree = d.degree;
+    t.h.dz1 = l1 * d.c / ly;
+    t.h.dz2 = l2 * d.s / ly;
+    t.h.z0 = -0.5 * (N - 1) * (t.h.dz1 + t.h.dz2) + 0.5 * (M - 1);
+    return t;
+}
+
+template <typename T>
+static int upload(void **dst, const std::vector<T> &v)
+{
+    if (v.empty()) return GCT_OK;
+    hipError_t e = hipMalloc(dst, v.size() * sizeof(T));
+    if (e != hipSuccess) return check_hip(e, "hipMalloc(plan tables)");
+    e = hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return check_hip(e, "hipMemcpy(plan tables)");
+}
+
+template <typename T>
+static std::vector<T> cast_vec(const std::vector<double> &v)
+{
+    return std::vector<T>(v.begin(), v.end());
+}
+
+static int build_plan(const gct_geometry *g, gct_plan *p)
+{
+    const int n = g->n_angles;
+    const double l1 = g->lambda_x[0], l2 = g->lambda_x[1], ly = g->lambda_y, z = g->zeta_blur;
+    std::vector<AngleDirs> ad(n);
+    for (int a = 0; a < n; ++a) ad[a] = angle_dirs(g->theta[a], l1, l2, z);
+
+    std::vector<GramAngle<float>> gf(n);
+    std::vector<GramAngle<double>> gd(n);
+    std::vector<FwdAngle<float>> ff(n);
+    std::vector<FwdAngle<double>> fd(n);
+    std::vector<int32_t> deg(n);
+    std::vector<BPAngleTable> bt(n);
+    int smax = 1, J = 1, D1 = 1;
+    for (int a = 0; a < n; ++a) {
+        gf[a] = gram_angle<float>(ad[a], l1, l2, z);
+        gd[a] = gram_angle<double>(ad[a], l1, l2, z);
+        ff[a] = fwd_angle<float>(ad[a], l1, l2, z);
+        fd[a] = fwd_angle<double>(ad[a], l1, l2, z);
+        deg[a] = ad[a].degree;
+        bt[a] = bp_angle(ad[a], g->N, l1, l2, ly, g->M, z);
+        smax = std::max(smax, bt[a].h.nsub);
+        J = std::max(J, bt[a].J);
+        D1 = std::max(D1, bt[a].D1);
+    }
+    p->bp.smax = smax;
+    p->bp.J = J;
+    p->bp.D1 = D1;
+    std::vector<double> geo((size_t)n * 4, 0.0), brk((size_t)n * smax, 2.0);
+    std::vector<int32_t> ints((size_t)n * 4, 0);
+    std::vector<double> coef((size_t)n * smax * J * D1, 0.0);
+    for (int a = 0; a < n; ++a) {
+        const BPAngleTable &t = bt[a];
+        geo[4 * a] = t.h.z0;
+        geo[4 * a + 1] = t.h.dz1;
+        geo[4 * a + 2] = t.h.dz2;
+        ints[4 * a] = t.h.nsub;
+        ints[4 * a + 1] = t.h.jlo;
+        ints[4 * a + 2] = t.h.degree;
+        for (int s = 0; s < t.h.nsub; ++s) {
+            brk[(size_t)a * smax + s] = t.brk[s];
+            for (int j = 0; j < t.J; ++j)
+                for (int q = 0; q < t.D1; ++q)
+                    coef[(((size_t)a * smax + s) * J + j) * D1 + q] =
+                        t.coef[((size_t)s * t.J + j) * t.D1 + q];
+        }
+    }
+    // FFT twiddles e^{-2 pi i k / P}
+    std::vector<double> tw((size_t)p->P);  // interleaved (re, im), P/2 entries
+    for (int k = 0; k < p->P / 2; ++k) {
+        const double ang = -2.0 * M_PI * (double)k / (double)p->P;
+        tw[2 * k] = std::cos(ang);
+        tw[2 * k + 1] = std::sin(ang);
+    }
+    // quadratic B-spline correction filter, Sec. 5: q[m] = sqrt2 (2 sqrt2 - 3)^|m|
+    const int K = g->prefilter_K;
+    std::vector<double> q(2 * K + 1);
+    const double alpha = 2.0 * std::sqrt(2.0) - 3.0;
+    for (int m = -K; m <= K; ++m) q[m + K] = std::sqrt(2.0) * std::pow(alpha, std::abs(m));
+
+    int rc;
+    if ((rc = upload(&p->dev.gram_f32, gf))) return rc;
+    if ((rc = upload(&p->dev.gram_f64, gd))) return rc;
+    if ((rc = upload(&p->dev.fwd_f32, ff))) return rc;
+    if ((rc = upload(&p->dev.fwd_f64, fd))) return rc;
+    if ((rc = upload(&p->dev.bp_geo, geo))) return rc;
+    if ((rc = upload(&p->dev.bp_int, ints))) return rc;
+    if ((rc = upload(&p->dev.bp_brk_f32, cast_vec<float>(brk)))) return rc;
+    if ((rc = upload(&p->dev.bp_brk_f64, brk))) return rc;
+    if ((rc = upload(&p->dev.bp_coef_f32, cast_vec<float>(coef)))) return rc;
+    if ((rc = upload(&p->dev.bp_coef_f64, coef))) return rc;
+    if ((rc = upload(&p->dev.tw_f32, cast_vec<float>(tw)))) return rc;
+    if ((rc = upload(&p->dev.tw_f64, tw))) return rc;
+    if ((rc = upload(&p->dev.q_f32, cast_vec<float>(q)))) return rc;
+    if ((rc = upload(&p->dev.q_f64, q))) return rc;
+    if ((rc = upload(&p->dev.deg, deg))) return rc;
+    return GCT_OK;
+}
+
+static void free_tables(gct_plan *p)
+{
+    void **all[] = {&p->dev.gram_f32,    &p->dev.gram_f64,    &p->dev.fwd_f32,     &p->dev.fwd_f64,
+                    &p->dev.bp_geo,      &p->dev.bp_int,      &p->dev.bp_brk_f32,  &p->dev.bp_brk_f64,
+                    &p->dev.bp_coef_f32, &p->dev.bp_coef_f64, &p->dev.tw_f32,      &p->dev.tw_f64,
+                    &p->dev.q_f32,       &p->dev.q_f64,       &p->dev.deg};
+    for (void **v : all) {
+        if (*v) (void)hipFree(*v);
+        *v = nullptr;
+    }
+}
+
+static int validate(const gct_geometry *g)
+{
+    if (!g) return fail(GCT_EINVAL, "geometry is NULL");
+    if (g->N < 1 || g->N > 2048) return fail(GCT_EINVAL, "N must be in [1, 2048]");
+    if (g->n_angles < 1) return fail(GCT_EINVAL, "n_angles must be >= 1");
+    if (!g->theta) return fail(GCT_EINVAL, "theta is NULL");
+    if (g->M < 1) return fail(GCT_EINVAL, "M must be >= 1");
+    if (!(g->lambda_x[0] > 0.0) || !(g->lambda_x[1] > 0.0) || !std::isfinite(g->lambda_x[0]) ||
+        !std::isfinite(g->lambda_x[1]))
+        return fail(GCT_EINVAL, "lambda_x must be finite and > 0");
+    if (!(g->lambda_y > 0.0) || !std::isfinite(g->lambda_y))
+        return fail(GCT_EINVAL, "lambda_y must be finite and > 0");
+    if (!(g->zeta_blur >= 0.0) || !std::isfinite(g->zeta_blur))
+        return fail(GCT_EINVAL, "zeta_blur must be finite and >= 0");
+    if (g->prefilter_K < 0 || g->prefilter_K > 256)
+        return fail(GCT_EINVAL, "prefilter_K must be in [0, 256]");
+    for (int a = 0; a < g->n_angles; ++a)
+        if (!std::isfinite(g->theta[a])) return fail(GCT_EINVAL, "theta contains a non-finite value");
+    // back-projection table size: the kernel support in bins must stay modest
+    const double w = (g->lambda_x[0] + g->lambda_x[1] + g->zeta_blur) / g->lambda_y + 3.0;
+    if (w > 48.0) return fail(GCT_EINVAL, "lambda_y too small for the pixel size (kernel spans > 48 bins)");
+    const double lratio = g->lambda_x[0] / g->lambda_x[1];
+    if (lratio > 64.0 || lratio < 1.0 / 64.0) return fail(GCT_EINVAL, "pixel aspect ratio beyond 64");
+    return GCT_OK;
+}
+
+}  // namespace gct
+
+using namespace gct;
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char *gct_last_error(void) { return g_last_error.c_str(); }
+
+int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
+{
+    if (!plan) return fail(GCT_EINVAL, "plan output pointer is NULL");
+    *plan = nullptr;
+    int rc = validate(geom);
+    if (rc) return rc;
+    try {
+        gct_plan *p = new gct_plan();
+        p->N = geom->N;
+        p->n = geom->n_angles;
+        p->M = geom->M;
+        p->K = geom->prefilter_K;
+        p->lx1 = geom->lambda_x[0];
+        p->lx2 = geom->lambda_x[1];
+        p->ly = geom->lambda_y;
+        p->zeta = geom->zeta_blur;
+        int P = 4, logP = 2;
+        while (P < 2 * p->N - 1) {
+            P <<= 1;
+            ++logP;
+        }
+        p->P = P;
+        p->logP = logP;
+        if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
+        rc = build_plan(geom, p);
+        if (rc) {
+            free_tables(p);
+            delete p;
+            return rc;
+        }
+        *plan = p;
+        return GCT_OK;
+    } catch (const std::exception &e) {
+        return fail(GCT_EINVAL, std::string("plan construction failed: ") + e.what());
+    }
+}
+
+int gct_plan_destroy(gct_plan *plan)
+{
+    if (!plan) return GCT_OK;
+    free_tables(plan);
+    delete plan;
+    return GCT_OK;
+}
+
+int gct_plan_get_info(const gct_plan *p, gct_plan_info *info)
+{
+    if (!p || !info) return fail(GCT_EINVAL, "NULL argument");
+    info->N = p->N;
+    info->n_angles = p->n;
+    info->M = p->M;
+    info->prefilter_K = p->K;
+    info->fft_size = p->P;
+    info->gram_elems = (int64_t)(2 * p->N - 1) * (2 * p->N - 1);
+    info->spectrum_elems = (int64_t)(p->P / 2 + 1) * p->P;
+    info->image_elems = (int64_t)p->N * p->N;
+    info->sino_elems = (int64_t)p->n * p->M;
+    info->prefiltered_elems = (int64_t)p->n * (p->M + 2 * p->K);
+    return GCT_OK;
+}
+
+size_t gct_workspace_size(const gct_plan *p, int op, gct_dtype dt)
+{
+    if (!p) return 0;
+    const size_t e = dt == GCT_F64 ? 8 : 4;
+    switch (op) {
+    case GCT_OP_GRAM_SPECTRUM: return spectrum_ws_bytes(p, e);
+    case GCT_OP_GRAM_APPLY: return apply_ws_bytes(p, e);
+    case GCT_OP_BACKPROJECT: return align256((size_t)p->n * (p->M + 2 * p->K) * e);
+    case GCT_OP_CG: return cg_ws_bytes(p, e);
+    default: return 0;
+    }
+}
+
+#define CHECK_PLAN_DT(p, dt)                                                          \
+    do {                                                                              \
+        if (!(p)) return fail(GCT_EINVAL, "plan is NULL");                            \
+        if ((dt) != GCT_F32 && (dt) != GCT_F64) return fail(GCT_EINVAL, "bad dtype"); \
+    } while (0)
+
+static bool misaligned(const void *ws) { return (reinterpret_cast<uintptr_t>(ws) & 255u) != 0; }
+
+int gct_gram_build(const gct_plan *p, gct_dtype dt, void *G, void *stream)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!G) return fail(GCT_EINVAL, "G is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = dt == GCT_F32 ? launch_gram_build<float>(p, (float *)G, s)
+                                 : launch_gram_build<double>(p, (double *)G, s);
+    return check_hip(e, "gram_build launch");
+}
+
+int gct_gram_spectrum(const gct_plan *p, gct_dtype dt, const void *G, void *Ghat, void *ws,
+                      void *stream)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!G || !Ghat || !ws) return fail(GCT_EINVAL, "NULL buffer");
+    if (misaligned(ws)) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = dt == GCT_F32
+                       ? launch_gram_spectrum<float>(p, (const float *)G, (float *)Ghat, ws, s)
+                       : launch_gram_spectrum<double>(p, (const double *)G, (double *)Ghat, ws, s);
+    return check_hip(e, "gram_spectrum launch");
+}
+
+int gct_gram_apply(const gct_plan *p, gct_dtype dt, const void *Ghat, const void *c, void *y,
+                   void *ws, void *stream)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!Ghat || !c || !y || !ws) return fail(GCT_EINVAL, "NULL buffer");
+    if (c == y) return fail(GCT_EINVAL, "y must not alias c");
+    if (misaligned(ws)) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = dt == GCT_F32 ? launch_gram_apply<float>(p, (const float *)Ghat, (const float *)c,
+                                                            (float *)y, ws, s)
+                                 : launch_gram_apply<double>(p, (const double *)Ghat,
+                                                             (const double *)c, (double *)y, ws, s);
+    return check_hip(e, "gram_apply launch");
+}
+
+int gct_prefilter(const gct_plan *p, gct_dtype dt, const void *g_s, void *out, void *stream)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!g_s || !out) return fail(GCT_EINVAL, "NULL buffer");
+    if (g_s == out) return fail(GCT_EINVAL, "output must not alias the sinogram");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = dt == GCT_F32 ? launch_prefilter<float>(p, (const float *)g_s, (float *)out, s)
+                                 : launch_prefilter<double>(p, (const double *)g_s, (double *)out, s);
+    return check_hip(e, "prefilter launch");
+}
+
+int gct_backproject_boxspline(const gct_plan *p, gct_dtype dt, const void *g_s, void *b, void *ws,
+                              void *stream)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!g_s || !b || !ws) return fail(GCT_EINVAL, "NULL buffer");
+    if (misaligned(ws)) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (dt == GCT_F32) {
+        e = launch_prefilter<float>(p, (const float *)g_s, (float *)ws, s);
+        if (e == hipSuccess) e = launch_backproject<float>(p, (const float *)ws, (float *)b, s);
+    } else {
+        e = launch_prefilter<double>(p, (const double *)g_s, (double *)ws, s);
+        if (e == hipSuccess) e = launch_backproject<double>(p, (const double *)ws, (double *)b, s);
+    }
+    return check_hip(e, "backproject launch");
+}
+
+int gct_forward_project(const gct_plan *p, gct_dtype dt, const void *c, void *g_s, void *stream)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!c || !g_s) return fail(GCT_EINVAL, "NULL buffer");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = dt == GCT_F32 ? launch_forward<float>(p, (const float *)c, (float *)g_s, s)
+                                 : launch_forward<double>(p, (const double *)c, (double *)g_s, s);
+    return check_hip(e, "forward_project launch");
+}
+
+int gct_cg_solve(const gct_plan *p, gct_dtype dt, const void *Ghat, const void *b, void *x,
+                 int use_x0, double rtol, int32_t max_iter, int32_t check_every, double *hist,
+                 gct_cg_result *res, void *ws, void *stream)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!Ghat || !b || !x || !ws || !res) return fail(GCT_EINVAL, "NULL argument");
+    if (b == x) return fail(GCT_EINVAL, "x must not alias b");
+    if (max_iter < 0) return fail(GCT_EINVAL, "max_iter must be >= 0");
+    if (!(rtol >= 0.0)) return fail(GCT_EINVAL, "rtol must be >= 0");
+    if (misaligned(ws)) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    std::memset(res, 0, sizeof(*res));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int rc = dt == GCT_F32 ? cg_solve<float>(p, (const float *)Ghat, (const float *)b, (float *)x,
+                                             use_x0, rtol, max_iter, check_every, hist, res, ws, s)
+                           : cg_solve<double>(p, (const double *)Ghat, (const double *)b,
+                                              (double *)x, use_x0, rtol, max_iter, check_every,
+                                              hist, res, ws, s);
+    if (rc == GCT_ENOTCONV) set_error("cg_solve: max_iter reached before rtol");
+    if (rc == GCT_EBREAKDOWN) set_error("cg_solve: breakdown (p.Ap <= 0 or non-finite value)");
+    return rc;
+}
+
+// ---------------------------------------------------------------------------
+// Host-only helpers (include/gramct_host.h)
+// ---------------------------------------------------------------------------
+int gct_host_boxspline_eval(const double *dirs, int ndirs, double scale, const double *x, int npts,
+                            double *out)
+{
+    if (!dirs || ndirs < 1 || !x || !out || npts < 0) return fail(GCT_EINVAL, "bad argument");
+    std::vector<double> d(dirs, dirs + ndirs);
+    double mx = 0.0;
+    for (double v : d) mx = std::max(mx, std::fabs(v));
+    if (!(mx > 0.0)) return fail(GCT_EINVAL, "all directions are zero");
+    if (ndirs > PP_MAXC - 2) return fail(GCT_EINVAL, "too many directions");
+    try {
+        const PPoly f = pp_boxspline(d, scale);
+        for (int i = 0; i < npts; ++i) out[i] = pp_eval(f, x[i]);
+    } catch (const std::exception &e) {
+        return fail(GCT_EINVAL, e.what());
+    }
+    return GCT_OK;
+}
+
+int gct_host_bp_weights(const gct_geometry *g, int angle, double t, double *w, int *jlo, int *nw)
+{
+    int rc = validate(g);
+    if (rc) return rc;
+    if (angle < 0 || angle >= g->n_angles || !w || !jlo || !nw || !(t >= 0.0 && t < 1.0))
+        return fail(GCT_EINVAL, "bad argument");
+    const AngleDirs d = angle_dirs(g->theta[angle], g->lambda_x[0], g->lambda_x[1], g->zeta_blur);
+    const BPAngleTable tb = bp_angle(d, g->N, g->lambda_x[0], g->lambda_x[1], g->lambda_y, g->M,
+                                     g->zeta_blur);
+    int s = 0;
+    for (int i = 1; i < tb.h.nsub; ++i)
+        if (t >= tb.brk[i]) s = i;
+    const double u = t - tb.brk[s];
+    for (int j = 0; j < tb.J; ++j) {
+        double v = 0.0;
+        for (int q = tb.D1 - 1; q >= 0; --q) v = v * u + tb.coef[((size_t)s * tb.J + j) * tb.D1 + q];
+        w[j] = v;
+    }
+    *jlo = tb.h.jlo;
+    *nw = tb.J;
+    return GCT_OK;
+}
+
+int gct_host_degree(double theta, double zeta_blur)
+{
+    return angle_dirs(theta, 1.0, 1.0, zeta_blur).degree;
+}
+
+}  // extern "C"

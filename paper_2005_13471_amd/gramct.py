@@ -1,0 +1,281 @@
+"""Python binding of libgramct (include/gramct.h).
+
+Argument marshalling only: every step runs in the HIP kernels of
+libgramct.so.  Device memory comes from torch tensors (on the current
+device); every call is issued on torch's current stream.  There is no CPU
+fallback: if the library is missing, importing this module raises.
+
+Function names mirror the C ABI without the ``gct_`` prefix
+(``gram_build`` calls ``gct_gram_build`` and so on).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgramct.so")
+
+GCT_OK, GCT_EINVAL, GCT_EHIP, GCT_ENOTCONV, GCT_EBREAKDOWN = 0, -1, -2, -3, -4
+F32, F64 = 0, 1
+OP_GRAM_BUILD, OP_GRAM_SPECTRUM, OP_GRAM_APPLY, OP_PREFILTER, OP_BACKPROJECT, OP_FORWARD, OP_CG = range(7)
+
+
+class GramctError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"gramct error {code}: {msg}")
+        self.code = code
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("lambda_x", ctypes.c_double * 2),
+                ("n_angles", ctypes.c_int32), ("theta", ctypes.POINTER(ctypes.c_double)),
+                ("lambda_y", ctypes.c_double), ("M", ctypes.c_int32),
+                ("zeta_blur", ctypes.c_double), ("prefilter_K", ctypes.c_int32)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("n_angles", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("prefilter_K", ctypes.c_int32), ("fft_size", ctypes.c_int32),
+                ("gram_elems", ctypes.c_int64), ("spectrum_elems", ctypes.c_int64),
+                ("image_elems", ctypes.c_int64), ("sino_elems", ctypes.c_int64),
+                ("prefiltered_elems", ctypes.c_int64)]
+
+
+class _CGResult(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32), ("rel_res", ctypes.c_double),
+                ("rel_res_true", ctypes.c_double), ("rel_res0", ctypes.c_double),
+                ("fell_back", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.gct_last_error.restype = ctypes.c_char_p
+    L.gct_plan_create.argtypes = [ctypes.POINTER(_Geometry), ctypes.POINTER(vp)]
+    L.gct_plan_destroy.argtypes = [vp]
+    L.gct_plan_get_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
+    L.gct_workspace_size.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.gct_workspace_size.restype = ctypes.c_size_t
+    L.gct_gram_build.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.gct_gram_spectrum.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    L.gct_gram_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+    L.gct_prefilter.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.gct_backproject_boxspline.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    L.gct_forward_project.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.gct_cg_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, dbl, i32, i32,
+                               ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_CGResult), vp, vp]
+    L.gct_host_boxspline_eval.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, dbl,
+                                          ctypes.POINTER(ctypes.c_double), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_double)]
+    L.gct_host_bp_weights.argtypes = [ctypes.POINTER(_Geometry), ctypes.c_int, dbl,
+                                      ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int),
+                                      ctypes.POINTER(ctypes.c_int)]
+    L.gct_host_degree.argtypes = [dbl, dbl]
+    L.gct_host_degree.restype = ctypes.c_int
+    return L
+
+
+lib = _load()
+
+
+def _check(rc):
+    if rc != GCT_OK:
+        raise GramctError(rc, lib.gct_last_error().decode())
+    return rc
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr(t: torch.Tensor, n: int | None = None, dtype=None) -> int:
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"tensor has {t.numel()} elements, need {n}")
+    return t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _geometry_struct(N, theta, M, ly, zeta, lx, K):
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    g = _Geometry()
+    g.N, g.n_angles, g.M, g.prefilter_K = int(N), int(th.size), int(M), int(K)
+    g.lambda_x[0], g.lambda_x[1] = float(lx[0]), float(lx[1])
+    g.lambda_y, g.zeta_blur = float(ly), float(zeta)
+    g.theta = th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return g, th
+
+
+@dataclass
+class PlanInfo:
+    N: int
+    n_angles: int
+    M: int
+    prefilter_K: int
+    fft_size: int
+    gram_elems: int
+    spectrum_elems: int
+    image_elems: int
+    sino_elems: int
+    prefiltered_elems: int
+
+
+class Plan:
+    """gct_plan: geometry of Sec. 2 and the per-angle tables on the device."""
+
+    def __init__(self, N, theta, M, ly=1.0, zeta=0.0, lx=(1.0, 1.0), K=40):
+        g, th = _geometry_struct(N, theta, M, ly, zeta, lx, K)
+        h = ctypes.c_void_p()
+        _check(lib.gct_plan_create(ctypes.byref(g), ctypes.byref(h)))
+        self._h = h
+        self.theta = th
+        self.N, self.M, self.ly, self.zeta, self.lx, self.K = int(N), int(M), float(ly), float(zeta), tuple(lx), int(K)
+        pi = _PlanInfo()
+        _check(lib.gct_plan_get_info(self._h, ctypes.byref(pi)))
+        self.info = PlanInfo(*[getattr(pi, f[0]) for f in _PlanInfo._fields_])
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.gct_plan_destroy(h)
+            self._h = None
+
+    def workspace_size(self, op: int, dtype=torch.float32) -> int:
+        return int(lib.gct_workspace_size(self._h, op, F32 if dtype == torch.float32 else F64))
+
+    def workspace(self, op: int, dtype=torch.float32, device=None) -> torch.Tensor:
+        n = max(self.workspace_size(op, dtype), 256)
+        return torch.empty(n, dtype=torch.uint8, device=device or "cuda")
+
+
+def gram_build(plan: Plan, G: torch.Tensor):
+    _check(lib.gct_gram_build(plan.handle, _dt(G), _ptr(G, plan.info.gram_elems), _stream()))
+    return G
+
+
+def gram_spectrum(plan: Plan, G: torch.Tensor, Ghat: torch.Tensor, ws: torch.Tensor):
+    dt = _dt(G)
+    _check(lib.gct_gram_spectrum(plan.handle, dt, _ptr(G, plan.info.gram_elems),
+                                 _ptr(Ghat, plan.info.spectrum_elems, G.dtype),
+                                 _ptr(ws, plan.workspace_size(OP_GRAM_SPECTRUM, G.dtype)), _stream()))
+    return Ghat
+
+
+def gram_apply(plan: Plan, Ghat: torch.Tensor, c: torch.Tensor, y: torch.Tensor, ws: torch.Tensor):
+    dt = _dt(c)
+    _check(lib.gct_gram_apply(plan.handle, dt, _ptr(Ghat, plan.info.spectrum_elems, c.dtype),
+                              _ptr(c, plan.info.image_elems), _ptr(y, plan.info.image_elems, c.dtype),
+                              _ptr(ws, plan.workspace_size(OP_GRAM_APPLY, c.dtype)), _stream()))
+    return y
+
+
+def prefilter(plan: Plan, g: torch.Tensor, p: torch.Tensor):
+    _check(lib.gct_prefilter(plan.handle, _dt(g), _ptr(g, plan.info.sino_elems),
+                             _ptr(p, plan.info.prefiltered_elems, g.dtype), _stream()))
+    return p
+
+
+def backproject_boxspline(plan: Plan, g: torch.Tensor, b: torch.Tensor, ws: torch.Tensor):
+    _check(lib.gct_backproject_boxspline(plan.handle, _dt(g), _ptr(g, plan.info.sino_elems),
+                                         _ptr(b, plan.info.image_elems, g.dtype),
+                                         _ptr(ws, plan.workspace_size(OP_BACKPROJECT, g.dtype)),
+                                         _stream()))
+    return b
+
+
+def forward_project(plan: Plan, c: torch.Tensor, g: torch.Tensor):
+    _check(lib.gct_forward_project(plan.handle, _dt(c), _ptr(c, plan.info.image_elems),
+                                   _ptr(g, plan.info.sino_elems, c.dtype), _stream()))
+    return g
+
+
+@dataclass
+class CGResult:
+    iters: int
+    status: int
+    rel_res: float
+    rel_res_true: float
+    rel_res0: float
+    fell_back: int
+    history: np.ndarray
+
+
+def cg_solve(plan: Plan, Ghat: torch.Tensor, b: torch.Tensor, x: torch.Tensor, ws: torch.Tensor,
+             use_x0: bool = False, rtol: float = 1e-4, max_iter: int = 1000,
+             check_every: int = 8, raise_on_error: bool = False) -> CGResult:
+    """Blocks until the solve ends.  Returns the result; GCT_ENOTCONV /
+    GCT_EBREAKDOWN are reported in .status unless raise_on_error."""
+    dt = _dt(b)
+    hist = np.zeros(max_iter + 1)
+    res = _CGResult()
+    rc = lib.gct_cg_solve(plan.handle, dt, _ptr(Ghat, plan.info.spectrum_elems, b.dtype),
+                          _ptr(b, plan.info.image_elems), _ptr(x, plan.info.image_elems, b.dtype),
+                          int(bool(use_x0)), float(rtol), int(max_iter), int(check_every),
+                          hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(res),
+                          _ptr(ws, plan.workspace_size(OP_CG, b.dtype)), _stream())
+    if rc not in (GCT_OK, GCT_ENOTCONV, GCT_EBREAKDOWN) or (raise_on_error and rc != GCT_OK):
+        _check(rc)
+    return CGResult(res.iters, res.status, res.rel_res, res.rel_res_true, res.rel_res0,
+                    res.fell_back, hist[: res.iters + 1].copy())
+
+
+# C-ABI names
+gct_gram_build = gram_build
+gct_gram_spectrum = gram_spectrum
+gct_gram_apply = gram_apply
+gct_prefilter = prefilter
+gct_backproject_boxspline = backproject_boxspline
+gct_forward_project = forward_project
+gct_cg_solve = cg_solve
+
+
+# ---------------------------------------------------------------------------
+# Host-only helpers (include/gramct_host.h)
+# ---------------------------------------------------------------------------
+def host_boxspline_eval(dirs, x, scale=1.0) -> np.ndarray:
+    d = np.ascontiguousarray(dirs, dtype=np.float64)
+    xs = np.ascontiguousarray(np.atleast_1d(x), dtype=np.float64)
+    out = np.zeros_like(xs)
+    P = ctypes.POINTER(ctypes.c_double)
+    _check(lib.gct_host_boxspline_eval(d.ctypes.data_as(P), d.size, float(scale),
+                                       xs.ctypes.data_as(P), xs.size, out.ctypes.data_as(P)))
+    return out
+
+
+def host_bp_weights(N, theta, M, angle, t, ly=1.0, zeta=0.0, lx=(1.0, 1.0), K=40):
+    g, th = _geometry_struct(N, theta, M, ly, zeta, lx, K)
+    w = np.zeros(64)
+    jlo, nw = ctypes.c_int(), ctypes.c_int()
+    _check(lib.gct_host_bp_weights(ctypes.byref(g), int(angle), float(t),
+                                   w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(jlo), ctypes.byref(nw)))
+    del th
+    return jlo.value, w[: nw.value].copy()
+
+
+def host_degree(theta: float, zeta: float) -> int:
+    return int(lib.gct_host_degree(float(theta), float(zeta)))

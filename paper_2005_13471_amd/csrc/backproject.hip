@@ -1,5 +1,7 @@
 // Sinogram interpolation, exact-adjoint back projection and the forward
 // model (Sec. 2, Sec. 4, Sec. 5).
+#include <cmath>
+
 #include "gct_internal.h"
 
 namespace gct {
@@ -46,90 +48,128 @@ hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s
 // with z_k the pixel centre's projection in fractional bin units and
 // kappa_theta = l1 l2 M_{Xi/lambda_y}, Xi = {l1|c|, l2|s|, zeta,
 // lambda_y x (d+1)}: the exact integral of the pixel footprint against the
-// B-spline basis of the interpolated sinogram.  kappa is evaluated from the
-// per-angle sub-interval polynomials built exactly on the host.
+// B-spline basis of the interpolated sinogram.
 //
-// One 16 x 16 pixel tile per block.  Angle tables are staged through LDS
-// in chunks; each lane then locates its sub-interval and accumulates the
-// J weighted bins.
+// On each sub-interval s of t = z - floor(z), kappa(j - t) is a polynomial
+// in u = t - brk[s] with coefficients C[s][j][.] (built exactly on the host),
+// so the whole angle's contribution is the piecewise polynomial
+//   S(z) = sum_k u^k E[m0][s][k],  E[m][s][k] = sum_j p[m + jlo + j] C[s][j][k],
+// m0 = floor(z).  A block owns a TILE x TILE pixel tile; per angle it forms E
+// for the few bins the tile projects onto (in LDS), then every pixel finds
+// its (m0, s) and evaluates one polynomial.  FP64 is used only for z.
 // ---------------------------------------------------------------------------
-constexpr int BP_CHUNK = 8;
-
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, int TILE>
+__global__ void __launch_bounds__(TILE * TILE)
 k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp, int K,
               const double *__restrict__ geo, const int32_t *__restrict__ ints,
-              const T *__restrict__ brk, const T *__restrict__ coef, int smax, int J, int D1)
+              const T *__restrict__ brk, const T *__restrict__ coef, int smax, int J, int D1,
+              int rmax)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int per_coef = smax * J * D1;
-    T *s_coef = reinterpret_cast<T *>(smem_raw);                 // [CHUNK][smax][J][D1]
-    T *s_brk = s_coef + BP_CHUNK * per_coef;                     // [CHUNK][smax]
-    double *s_geo = reinterpret_cast<double *>(s_brk + BP_CHUNK * smax + (BP_CHUNK * smax) % 2);
-    int32_t *s_int = reinterpret_cast<int32_t *>(s_geo + BP_CHUNK * 4);
-
-    const int k1 = blockIdx.x * 16 + (threadIdx.x & 15);
-    const int k2 = blockIdx.y * 16 + (threadIdx.x >> 4);
+    T *s_E = reinterpret_cast<T *>(smem_raw);   // [rmax][smax][D1]
+    T *s_C = s_E + (size_t)rmax * smax * D1;    // [smax][J][D1]
+    T *s_p = s_C + per_coef;                    // [rmax + J]
+    T *s_b = s_p + rmax + J;                    // [smax]
+    const int tid = threadIdx.x;
+    const int k1a = blockIdx.x * TILE, k2a = blockIdx.y * TILE;
+    const int k1 = k1a + tid % TILE, k2 = k2a + tid / TILE;
+    const double kx0 = k1a, kx1 = k1a + TILE - 1, ky0 = k2a, ky1 = k2a + TILE - 1;
     T acc = 0, comp = 0;
-    for (int a0 = 0; a0 < n; a0 += BP_CHUNK) {
-        const int cnt = min(BP_CHUNK, n - a0);
-        __syncthreads();
-        for (int i = threadIdx.x; i < cnt * per_coef; i += blockDim.x)
-            s_coef[i] = coef[(size_t)a0 * per_coef + i];
-        for (int i = threadIdx.x; i < cnt * smax; i += blockDim.x) s_brk[i] = brk[(size_t)a0 * smax + i];
-        for (int i = threadIdx.x; i < cnt * 4; i += blockDim.x) {
-            s_geo[i] = geo[(size_t)a0 * 4 + i];
-            s_int[i] = ints[(size_t)a0 * 4 + i];
+    for (int a = 0; a < n; ++a) {
+        const double z0 = geo[4 * a], dz1 = geo[4 * a + 1], dz2 = geo[4 * a + 2];
+        const int nsub = ints[4 * a], jlo = ints[4 * a + 1];
+        // bin range of the tile (with one bin of margin against rounding)
+        const double e1 = kx0 * dz1, e2 = kx1 * dz1, f1 = ky0 * dz2, f2 = ky1 * dz2;
+        const double zmin = z0 + fmin(e1, e2) + fmin(f1, f2);
+        const double zmax = z0 + fmax(e1, e2) + fmax(f1, f2);
+        const int mlo = (int)floor(zmin) - 1;
+        const int R = min((int)floor(zmax) + 1 - mlo + 1, rmax);
+        __syncthreads();  // previous angle done with s_E / s_C / s_p
+        for (int i = tid; i < nsub * J * D1; i += TILE * TILE) s_C[i] = coef[(size_t)a * per_coef + i];
+        for (int i = tid; i < nsub; i += TILE * TILE) s_b[i] = brk[(size_t)a * smax + i];
+        for (int i = tid; i < R + J - 1; i += TILE * TILE) {
+            const int mi = mlo + jlo + i + K;
+            s_p[i] = (mi >= 0 && mi < Mp) ? pf[(size_t)a * Mp + mi] : T(0);
         }
         __syncthreads();
-        for (int c = 0; c < cnt; ++c) {
-            const double z = s_geo[4 * c] + (double)k1 * s_geo[4 * c + 1] + (double)k2 * s_geo[4 * c + 2];
-            const double zf = floor(z);
-            const T t = (T)(z - zf);
-            const int m0 = (int)zf;
-            const int nsub = s_int[4 * c], jlo = s_int[4 * c + 1];
-            const T *bk = s_brk + c * smax;
-            int sub = 0;
-            for (int i = 1; i < nsub; ++i) sub += (t >= bk[i]) ? 1 : 0;
-            const T u = t - bk[sub];
-            const T *cf = s_coef + (size_t)c * per_coef + (size_t)sub * J * D1;
-            const T *prow = pf + (size_t)(a0 + c) * Mp;
-            T sum = 0;
-            for (int j = 0; j < J; ++j) {
-                T w = cf[j * D1 + D1 - 1];
-                for (int d = D1 - 2; d >= 0; --d) w = w * u + cf[j * D1 + d];
-                const int mi = m0 + jlo + j + K;
-                const T pv = (mi >= 0 && mi < Mp) ? prow[mi] : T(0);
-                sum += pv * w;
-            }
-            const T yk = sum - comp;
-            const T tk = acc + yk;
-            comp = (tk - acc) - yk;
-            acc = tk;
+        const int nE = R * nsub * D1;
+        for (int i = tid; i < nE; i += TILE * TILE) {
+            const int k = i % D1, rest = i / D1;
+            const int sidx = rest % nsub, mi = rest / nsub;
+            const T *cf = s_C + sidx * J * D1 + k;
+            const T *pp = s_p + mi;
+            T e = 0;
+            for (int j = 0; j < J; ++j) e += pp[j] * cf[j * D1];
+            s_E[i] = e;
         }
+        __syncthreads();
+        const double z = z0 + (double)k1 * dz1 + (double)k2 * dz2;
+        const double zf = floor(z);
+        const T t = (T)(z - zf);
+        int mi = (int)zf - mlo;
+        mi = mi < 0 ? 0 : (mi >= R ? R - 1 : mi);
+        int sub = 0;
+        for (int i = 1; i < nsub; ++i) sub += (t >= s_b[i]) ? 1 : 0;
+        const T u = t - s_b[sub];
+        const T *e = s_E + (mi * nsub + sub) * D1;
+        T v = e[D1 - 1];
+        for (int k = D1 - 2; k >= 0; --k) v = v * u + e[k];
+        const T yk = v - comp;
+        const T tk = acc + yk;
+        comp = (tk - acc) - yk;
+        acc = tk;
     }
     if (k1 < N && k2 < N) b[(size_t)k2 * N + k1] = acc;
 }
 
+// Tile side and LDS size: 32 x 32 when the per-angle tables fit in 64 KB,
+// else 16 x 16.
+static int bp_tile(const gct_plan *p, size_t elem, size_t *lds, int *rmax)
+{
+    for (int tile : {32, 16}) {
+        const int r = (int)std::ceil((tile - 1) * p->bp.span_per_pixel) + 4;
+        const size_t words = (size_t)r * p->bp.smax * p->bp.D1 + (size_t)p->bp.smax * p->bp.J * p->bp.D1 +
+                             r + p->bp.J + p->bp.smax;
+        const size_t bytes = words * elem;
+        if (bytes <= 65536 || tile == 16) {
+            *lds = bytes;
+            *rmax = r;
+            return tile;
+        }
+    }
+    return 16;
+}
+
 size_t bp_lds_bytes(const gct_plan *p, size_t elem)
 {
-    const size_t per_coef = (size_t)p->bp.smax * p->bp.J * p->bp.D1;
-    size_t t = (BP_CHUNK * per_coef + BP_CHUNK * p->bp.smax + 1) * elem;
-    t = (t + 7) & ~size_t(7);
-    return t + BP_CHUNK * 4 * sizeof(double) + BP_CHUNK * 4 * sizeof(int32_t);
+    size_t lds;
+    int r;
+    bp_tile(p, elem, &lds, &r);
+    return lds;
 }
 
 template <typename T>
 hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, hipStream_t s)
 {
     const int N = p->N;
-    const dim3 grid((N + 15) / 16, (N + 15) / 16);
+    size_t lds;
+    int rmax;
+    const int tile = bp_tile(p, sizeof(T), &lds, &rmax);
+    if (lds > 65536) return hipErrorInvalidConfiguration;
+    const dim3 grid((N + tile - 1) / tile, (N + tile - 1) / tile);
     const T *brk = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.bp_brk_f32 : p->dev.bp_brk_f64);
     const T *coef = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.bp_coef_f32 : p->dev.bp_coef_f64);
-    hipLaunchKernelGGL(k_backproject<T>, grid, dim3(256), bp_lds_bytes(p, sizeof(T)), s, pf, b, N,
-                       p->n, p->M + 2 * p->K, p->K, reinterpret_cast<const double *>(p->dev.bp_geo),
-                       reinterpret_cast<const int32_t *>(p->dev.bp_int), brk, coef, p->bp.smax,
-                       p->bp.J, p->bp.D1);
+    const double *geo = reinterpret_cast<const double *>(p->dev.bp_geo);
+    const int32_t *ints = reinterpret_cast<const int32_t *>(p->dev.bp_int);
+    if (tile == 32)
+        hipLaunchKernelGGL((k_backproject<T, 32>), grid, dim3(1024), lds, s, pf, b, N, p->n,
+                           p->M + 2 * p->K, p->K, geo, ints, brk, coef, p->bp.smax, p->bp.J,
+                           p->bp.D1, rmax);
+    else
+        hipLaunchKernelGGL((k_backproject<T, 16>), grid, dim3(256), lds, s, pf, b, N, p->n,
+                           p->M + 2 * p->K, p->K, geo, ints, brk, coef, p->bp.smax, p->bp.J,
+                           p->bp.D1, rmax);
     return hipGetLastError();
 }
 

@@ -66,6 +66,7 @@ struct BPDims {
     int32_t smax;   // sub-intervals per angle (padded)
     int32_t J;      // weights per pixel and angle
     int32_t D1;     // polynomial coefficients per weight (degree + 1)
+    double span_per_pixel;  // max over angles of (l1|c| + l2|s|) / lambda_y: bins per pixel step
 };
 
 struct DeviceTables {

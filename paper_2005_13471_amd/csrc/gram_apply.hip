@@ -5,14 +5,15 @@
 // two: y = IFFT2(Ghat . FFT2(c_padded))[0:N, 0:N], with Ghat real and even
 // because G[k] = G[-k].
 //
-// Three passes, each a workgroup-local FFT in LDS:
+// Three passes, each a group-local FFT in LDS (fft_common.h):
 //   rows:    pairs of image rows -> one complex FFT -> two real-row spectra,
 //            written transposed as W1[w1][k2], w1 in [0, P/2];
 //   columns: per w1, FFT along k2 (N nonzero of P), times Ghat[w1][.],
 //            inverse FFT, keep k2 < N -> W2[w1][k2];
 //   rows:    pairs of Hermitian row spectra -> one complex inverse FFT ->
 //            two real output rows, keep k1 < N.
-// The 1/P^2 normalisation is folded into Ghat.
+// The 1/P^2 normalisation is folded into Ghat.  A group of P/4 threads owns
+// one transform; a block holds nf groups (256 threads when P <= 1024).
 #include <algorithm>
 
 #include "fft_common.h"
@@ -25,54 +26,67 @@ namespace gct {
 // launch.
 __device__ __forceinline__ bool halted(const int64_t *status) { return status && *status != 0; }
 
+// Twiddles: copied to LDS after the data area when TWL, else read from the
+// plan's global table.
+template <typename T, bool TWL>
+__device__ __forceinline__ const C2<T> *stage_twiddles(C2<T> *lds_after_data,
+                                                       const C2<T> *__restrict__ tw, int hP)
+{
+    if (!TWL) return tw;
+    for (int i = threadIdx.x; i < hP; i += blockDim.x) lds_after_data[i] = tw[i];
+    return lds_after_data;
+}
+
 // ---------------------------------------------------------------------------
 // Pass 1: forward real FFT of image rows.  With `pupd` set (CG), the row
 // vector is first updated in place as p = r + beta p (beta read from *beta).
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, bool TWL>
+__global__ void __launch_bounds__(1024)
 k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, int logP, int nf,
            const C2<T> *__restrict__ tw, const int64_t *status, T *pupd, const double *beta)
 {
     if (halted(status)) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int P = 1 << logP, Q = P >> 2, hP = P >> 1;
     C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
-    const int P = 1 << logP;
-    const int row0 = blockIdx.x * 2 * nf;
+    const C2<T> *tws = stage_twiddles<T, TWL>(buf + nf * P, tw, hP);
+    const int f = threadIdx.x / Q, t = threadIdx.x - f * Q;
+    const int seq = blockIdx.x * nf + f;
+    const int ra = 2 * seq, rb = ra + 1;
+    C2<T> *x = buf + f * P;
     const T bt = pupd ? (T)(*beta) : T(0);
-    for (int i = threadIdx.x; i < nf * P; i += blockDim.x) {
-        const int f = i >> logP, n = i & (P - 1);
-        const int ra = row0 + 2 * f, rb = ra + 1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int n = t + q * Q;
         T re = 0, im = 0;
         if (n < N) {
             if (ra < N) {
+                const size_t i = (size_t)ra * N + n;
+                re = src[i];
                 if (pupd) {
-                    re = src[(size_t)ra * N + n] + bt * pupd[(size_t)ra * N + n];
-                    pupd[(size_t)ra * N + n] = re;
-                } else {
-                    re = src[(size_t)ra * N + n];
+                    re += bt * pupd[i];
+                    pupd[i] = re;
                 }
             }
             if (rb < N) {
+                const size_t i = (size_t)rb * N + n;
+                im = src[i];
                 if (pupd) {
-                    im = src[(size_t)rb * N + n] + bt * pupd[(size_t)rb * N + n];
-                    pupd[(size_t)rb * N + n] = im;
-                } else {
-                    im = src[(size_t)rb * N + n];
+                    im += bt * pupd[i];
+                    pupd[i] = im;
                 }
             }
         }
-        buf[f * P + brev(n, logP)] = {re, im};
+        x[n] = {re, im};
     }
     __syncthreads();
-    fft_dit<T, false>(buf, logP, nf, tw);
-    const int hP1 = (P >> 1) + 1;
-    for (int i = threadIdx.x; i < nf * hP1; i += blockDim.x) {
-        const int f = i / hP1, k = i - f * hP1;
-        const C2<T> Zk = buf[f * P + k], Zm = buf[f * P + ((P - k) & (P - 1))];
-        const int ra = row0 + 2 * f;
+    fft_inplace<T, false>(x, logP, t, tws);
+    // split the two real rows: Xa = (Z[k] + conj Z[-k])/2, Xb = (Z[k] - conj Z[-k])/(2i)
+    for (int k = t; k <= hP; k += Q) {
+        const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
         if (ra < N) W1[(size_t)k * N + ra] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
-        if (ra + 1 < N) W1[(size_t)k * N + ra + 1] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+        if (rb < N) W1[(size_t)k * N + rb] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
     }
 }
 
@@ -80,67 +94,87 @@ k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, int logP, i
 // Pass 2: per frequency column w1: FFT along k2, multiply by the real
 // spectrum, inverse FFT, keep the first N entries.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, bool TWL>
+__global__ void __launch_bounds__(1024)
 k_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat, int N,
-       int logP, const C2<T> *__restrict__ tw, const int64_t *status)
+       int logP, int nf, const C2<T> *__restrict__ tw, const int64_t *status)
 {
     if (halted(status)) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int P = 1 << logP, Q = P >> 2, hP = P >> 1;
     C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
-    const int P = 1 << logP;
-    const int k = blockIdx.x;  // in [0, P/2]
-    const C2<T> *col = W1 + (size_t)k * N;
-    for (int n = threadIdx.x; n < P; n += blockDim.x)
-        buf[brev(n, logP)] = n < N ? col[n] : C2<T>{T(0), T(0)};
-    __syncthreads();
-    fft_dit<T, false>(buf, logP, 1, tw);
-    const T *g = Ghat + (size_t)k * P;
-    for (int n = threadIdx.x; n < P; n += blockDim.x) {
-        const T s = g[n];
-        buf[n] = {buf[n].x * s, buf[n].y * s};
+    const C2<T> *tws = stage_twiddles<T, TWL>(buf + nf * P, tw, hP);
+    const int f = threadIdx.x / Q, t = threadIdx.x - f * Q;
+    const int col = blockIdx.x * nf + f;
+    const bool live = col <= hP;
+    C2<T> *x = buf + f * P;
+    const C2<T> *in = W1 + (size_t)col * N;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int n = t + q * Q;
+        x[n] = (live && n < N) ? in[n] : C2<T>{T(0), T(0)};
     }
     __syncthreads();
-    fft_dif<T, true>(buf, logP, 1, tw);
-    C2<T> *out = W2 + (size_t)k * N;
-    for (int n = threadIdx.x; n < N; n += blockDim.x) out[n] = buf[brev(n, logP)];
+    fft_inplace<T, false>(x, logP, t, tws);
+    const T *g = Ghat + (size_t)col * P;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int n = t + q * Q;
+        const T s = live ? g[n] : T(0);
+        x[n] = {x[n].x * s, x[n].y * s};
+    }
+    __syncthreads();
+    fft_inplace<T, true>(x, logP, t, tws);
+    if (live) {
+        C2<T> *out = W2 + (size_t)col * N;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int n = t + q * Q;
+            if (n < N) out[n] = x[n];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
 // Pass 3: inverse real FFT of row spectra.  With `dotv` set (CG), each block
 // also writes the FP64 partial sum of dotv . y over its rows.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, bool TWL>
+__global__ void __launch_bounds__(1024)
 k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, int logP, int nf,
            const C2<T> *__restrict__ tw, const int64_t *status, const T *__restrict__ dotv,
            double *__restrict__ partial)
 {
     if (halted(status)) return;
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int P = 1 << logP, Q = P >> 2, hP = P >> 1;
     C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
-    const int P = 1 << logP, hP = P >> 1;
-    const int row0 = blockIdx.x * 2 * nf;
-    for (int i = threadIdx.x; i < nf * P; i += blockDim.x) {
-        const int f = i >> logP, k = i & (P - 1);
-        const int ra = row0 + 2 * f, rb = ra + 1;
+    const C2<T> *tws = stage_twiddles<T, TWL>(buf + nf * P, tw, hP);
+    const int f = threadIdx.x / Q, t = threadIdx.x - f * Q;
+    const int seq = blockIdx.x * nf + f;
+    const int ra = 2 * seq, rb = ra + 1;
+    C2<T> *x = buf + f * P;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int k = t + q * Q;
         C2<T> Ya = {T(0), T(0)}, Yb = {T(0), T(0)};
-        if (k <= hP) {
-            if (ra < N) Ya = W2[(size_t)k * N + ra];
-            if (rb < N) Yb = W2[(size_t)k * N + rb];
-        } else {
-            if (ra < N) { Ya = W2[(size_t)(P - k) * N + ra]; Ya.y = -Ya.y; }
-            if (rb < N) { Yb = W2[(size_t)(P - k) * N + rb]; Yb.y = -Yb.y; }
+        const int kk = k <= hP ? k : P - k;  // Hermitian extension
+        if (ra < N) Ya = W2[(size_t)kk * N + ra];
+        if (rb < N) Yb = W2[(size_t)kk * N + rb];
+        if (k > hP) {
+            Ya.y = -Ya.y;
+            Yb.y = -Yb.y;
         }
-        buf[i] = {Ya.x - Yb.y, Ya.y + Yb.x};
+        x[k] = {Ya.x - Yb.y, Ya.y + Yb.x};
     }
     __syncthreads();
-    fft_dif<T, true>(buf, logP, nf, tw);
+    fft_inplace<T, true>(x, logP, t, tws);
     double acc = 0.0;
-    for (int i = threadIdx.x; i < nf * N; i += blockDim.x) {
-        const int f = i / N, n = i - f * N;
-        const int ra = row0 + 2 * f, rb = ra + 1;
-        const C2<T> v = buf[f * P + brev(n, logP)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int n = t + q * Q;
+        if (n >= N) continue;
+        const C2<T> v = x[n];
         if (ra < N) {
             y[(size_t)ra * N + n] = v.x;
             if (dotv) acc += (double)dotv[(size_t)ra * N + n] * (double)v.x;
@@ -151,7 +185,7 @@ k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, int logP, int
         }
     }
     if (partial) {
-        // reuse the transform buffer (the launcher sizes it to >= 256 doubles)
+        // reuse the LDS area (the launcher sizes it to >= blockDim doubles)
         __syncthreads();
         double *red = reinterpret_cast<double *>(smem_raw);
         red[threadIdx.x] = acc;
@@ -169,72 +203,103 @@ k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, int logP, int
 // ---------------------------------------------------------------------------
 // Embedded tap index: position q in [0, P) holds tap q (q <= N-1) or
 // q - P (q >= P-N+1); other positions are zero.
+constexpr int NO_TAP = 1 << 30;
 __device__ __forceinline__ int embed_tap(int q, int N, int P)
 {
     if (q <= N - 1) return q;
     if (q >= P - N + 1) return q - P;
-    return 1 << 30;
+    return NO_TAP;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, bool TWL>
+__global__ void __launch_bounds__(1024)
 k_spec_rows(const T *__restrict__ G, C2<T> *__restrict__ R, int N, int logP, int nf,
             const C2<T> *__restrict__ tw)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int P = 1 << logP, Q = P >> 2, hP = P >> 1, W = 2 * N - 1;
     C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
-    const int P = 1 << logP, W = 2 * N - 1;
-    const int row0 = blockIdx.x * 2 * nf;  // embedded rows q2 in [0, P)
-    for (int i = threadIdx.x; i < nf * P; i += blockDim.x) {
-        const int f = i >> logP, q1 = i & (P - 1);
+    const C2<T> *tws = stage_twiddles<T, TWL>(buf + nf * P, tw, hP);
+    const int f = threadIdx.x / Q, t = threadIdx.x - f * Q;
+    const int seq = blockIdx.x * nf + f;  // embedded row pair (2 seq, 2 seq + 1), < P/2
+    const int ka = embed_tap(2 * seq, N, P), kb = embed_tap(2 * seq + 1, N, P);
+    C2<T> *x = buf + f * P;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int q1 = t + q * Q;
         const int k1 = embed_tap(q1, N, P);
         T re = 0, im = 0;
-        if (k1 != (1 << 30)) {
-            const int ka = embed_tap(row0 + 2 * f, N, P), kb = embed_tap(row0 + 2 * f + 1, N, P);
-            if (ka != (1 << 30)) re = G[(size_t)(ka + N - 1) * W + (k1 + N - 1)];
-            if (kb != (1 << 30)) im = G[(size_t)(kb + N - 1) * W + (k1 + N - 1)];
+        if (k1 != NO_TAP && seq < hP) {
+            if (ka != NO_TAP) re = G[(size_t)(ka + N - 1) * W + (k1 + N - 1)];
+            if (kb != NO_TAP) im = G[(size_t)(kb + N - 1) * W + (k1 + N - 1)];
         }
-        buf[f * P + brev(q1, logP)] = {re, im};
+        x[q1] = {re, im};
     }
     __syncthreads();
-    fft_dit<T, false>(buf, logP, nf, tw);
-    const int hP1 = (P >> 1) + 1;
-    for (int i = threadIdx.x; i < nf * hP1; i += blockDim.x) {
-        const int f = i / hP1, k = i - f * hP1;
-        const C2<T> Zk = buf[f * P + k], Zm = buf[f * P + ((P - k) & (P - 1))];
-        const int ra = row0 + 2 * f;
-        R[(size_t)k * P + ra] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
-        R[(size_t)k * P + ra + 1] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+    fft_inplace<T, false>(x, logP, t, tws);
+    if (seq < hP) {
+        for (int k = t; k <= hP; k += Q) {
+            const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
+            R[(size_t)k * P + 2 * seq] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
+            R[(size_t)k * P + 2 * seq + 1] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+        }
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat, int logP,
+template <typename T, bool TWL>
+__global__ void __launch_bounds__(1024)
+k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat, int logP, int nf,
             const C2<T> *__restrict__ tw, T scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int P = 1 << logP, Q = P >> 2, hP = P >> 1;
     C2<T> *buf = reinterpret_cast<C2<T> *>(smem_raw);
-    const int P = 1 << logP;
-    const int k = blockIdx.x;
-    for (int n = threadIdx.x; n < P; n += blockDim.x) buf[brev(n, logP)] = R[(size_t)k * P + n];
+    const C2<T> *tws = stage_twiddles<T, TWL>(buf + nf * P, tw, hP);
+    const int f = threadIdx.x / Q, t = threadIdx.x - f * Q;
+    const int col = blockIdx.x * nf + f;
+    const bool live = col <= hP;
+    C2<T> *x = buf + f * P;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int n = t + q * Q;
+        x[n] = live ? R[(size_t)col * P + n] : C2<T>{T(0), T(0)};
+    }
     __syncthreads();
-    fft_dit<T, false>(buf, logP, 1, tw);
-    for (int n = threadIdx.x; n < P; n += blockDim.x) Ghat[(size_t)k * P + n] = buf[n].x * scale;
+    fft_inplace<T, false>(x, logP, t, tws);
+    if (live) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int n = t + q * Q;
+            Ghat[(size_t)col * P + n] = x[n].x * scale;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
-// Launchers
+// Launch geometry
 // ---------------------------------------------------------------------------
+struct FftCfg {
+    int Q;         // threads per transform (P/4)
+    int nf;        // transforms per block
+    int threads;   // nf * Q
+    size_t lds;    // bytes of dynamic LDS
+    bool twl;      // twiddles staged in LDS
+};
+
 template <typename T>
-static int rows_per_fft_block(int P)
+static FftCfg fft_cfg(int logP)
 {
-    // transforms per block: about 32 KB of LDS, at most 8, at most P/2 so
-    // that 2 nf rows divide the P embedded rows of the spectrum pass
-    int nf = 32768 / (P * (int)sizeof(C2<T>));
-    if (nf > 8) nf = 8;
-    if (nf > P / 2) nf = P / 2;
-    return nf < 1 ? 1 : nf;
+    FftCfg c;
+    const int P = 1 << logP;
+    c.Q = P >> 2;
+    c.nf = c.Q >= 256 ? 1 : 256 / c.Q;
+    c.threads = c.nf * c.Q;
+    const size_t data = (size_t)c.nf * P * sizeof(C2<T>);
+    const size_t twb = (size_t)(P / 2) * sizeof(C2<T>);
+    c.twl = data + twb <= 65536;
+    c.lds = data + (c.twl ? twb : 0);
+    c.lds = std::max(c.lds, (size_t)c.threads * sizeof(double));
+    return c;
 }
 
 template <typename T>
@@ -253,6 +318,19 @@ size_t spectrum_ws_bytes(const gct_plan *p, size_t elem)
     return align256((size_t)(p->P / 2 + 1) * p->P * 2 * elem);
 }
 
+int apply_row_blocks(const gct_plan *p, size_t elem)
+{
+    const int nf = elem == 4 ? fft_cfg<float>(p->logP).nf : fft_cfg<double>(p->logP).nf;
+    const int seqs = (p->N + 1) / 2;
+    return (seqs + nf - 1) / nf;
+}
+
+#define GCT_LAUNCH_TWL(kern, T, twl, grid, block, lds, s, ...)                                  \
+    do {                                                                                       \
+        if (twl) hipLaunchKernelGGL((kern<T, true>), grid, block, lds, s, __VA_ARGS__);       \
+        else hipLaunchKernelGGL((kern<T, false>), grid, block, lds, s, __VA_ARGS__);          \
+    } while (0)
+
 // The three passes of one apply; status/pupd/beta/dotv/partial are the CG
 // hooks (all null for a plain apply).
 template <typename T>
@@ -261,26 +339,20 @@ hipError_t launch_apply_passes(const gct_plan *p, const T *Ghat, const T *src, T
                                const T *dotv, double *partial)
 {
     const int N = p->N, P = p->P, logP = p->logP;
-    const int nf = rows_per_fft_block<T>(P);
+    const FftCfg c = fft_cfg<T>(logP);
     const size_t w1 = align256((size_t)(P / 2 + 1) * N * 2 * sizeof(T));
     C2<T> *W1 = reinterpret_cast<C2<T> *>(ws);
     C2<T> *W2 = reinterpret_cast<C2<T> *>(reinterpret_cast<char *>(ws) + w1);
     const C2<T> *tw = twiddles<T>(p);
-    const int rblocks = (N + 2 * nf - 1) / (2 * nf);
-    const size_t lds_rows = (size_t)nf * P * sizeof(C2<T>), lds_col = (size_t)P * sizeof(C2<T>);
-    hipLaunchKernelGGL(k_rows_fwd<T>, dim3(rblocks), dim3(256), lds_rows, s, src, W1, N, logP, nf,
-                       tw, status, pupd, beta);
-    hipLaunchKernelGGL(k_cols<T>, dim3(P / 2 + 1), dim3(256), lds_col, s, W1, W2, Ghat, N, logP, tw,
-                       status);
-    hipLaunchKernelGGL(k_rows_inv<T>, dim3(rblocks), dim3(256), std::max(lds_rows, (size_t)256 * sizeof(double)), s, W2, y, N, logP, nf, tw,
-                       status, dotv, partial);
+    const int rblocks = apply_row_blocks(p, sizeof(T));
+    const int cblocks = (P / 2 + 1 + c.nf - 1) / c.nf;
+    GCT_LAUNCH_TWL(k_rows_fwd, T, c.twl, dim3(rblocks), dim3(c.threads), c.lds, s, src, W1, N, logP,
+                   c.nf, tw, status, pupd, beta);
+    GCT_LAUNCH_TWL(k_cols, T, c.twl, dim3(cblocks), dim3(c.threads), c.lds, s, W1, W2, Ghat, N, logP,
+                   c.nf, tw, status);
+    GCT_LAUNCH_TWL(k_rows_inv, T, c.twl, dim3(rblocks), dim3(c.threads), c.lds, s, W2, y, N, logP,
+                   c.nf, tw, status, dotv, partial);
     return hipGetLastError();
-}
-
-int apply_row_blocks(const gct_plan *p, size_t elem)
-{
-    const int nf = elem == 4 ? rows_per_fft_block<float>(p->P) : rows_per_fft_block<double>(p->P);
-    return (p->N + 2 * nf - 1) / (2 * nf);
 }
 
 template <typename T>
@@ -295,15 +367,16 @@ template <typename T>
 hipError_t launch_gram_spectrum(const gct_plan *p, const T *G, T *Ghat, void *ws, hipStream_t s)
 {
     const int N = p->N, P = p->P, logP = p->logP;
-    const int nf = rows_per_fft_block<T>(P);
+    const FftCfg c = fft_cfg<T>(logP);
     C2<T> *R = reinterpret_cast<C2<T> *>(ws);
     const C2<T> *tw = twiddles<T>(p);
-    const int rblocks = P / (2 * nf);  // P is a power of two >= 4 and 2 nf divides it
-    hipLaunchKernelGGL(k_spec_rows<T>, dim3(rblocks), dim3(256), (size_t)nf * P * sizeof(C2<T>), s,
-                       G, R, N, logP, nf, tw);
+    const int rblocks = (P / 2 + c.nf - 1) / c.nf;  // P/2 embedded row pairs
+    GCT_LAUNCH_TWL(k_spec_rows, T, c.twl, dim3(rblocks), dim3(c.threads), c.lds, s, G, R, N, logP,
+                   c.nf, tw);
     const T scale = T(1.0 / ((double)P * (double)P));
-    hipLaunchKernelGGL(k_spec_cols<T>, dim3(P / 2 + 1), dim3(256), (size_t)P * sizeof(C2<T>), s, R,
-                       Ghat, logP, tw, scale);
+    const int cblocks = (P / 2 + 1 + c.nf - 1) / c.nf;
+    GCT_LAUNCH_TWL(k_spec_cols, T, c.twl, dim3(cblocks), dim3(c.threads), c.lds, s, R, Ghat, logP,
+                   c.nf, tw, scale);
     return hipGetLastError();
 }
 

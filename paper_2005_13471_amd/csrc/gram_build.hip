@@ -23,7 +23,8 @@
 //
 // Tap offsets are formed in FP64 (k1 cx + k2 sx reaches ~1.5e3 at N = 1024
 // while the spline needs them to ~1e-7) and rounded once.  The sum over
-// angles is compensated (Kahan).
+// angles is compensated (Kahan).  G[k] = G[-k] holds exactly (the footprint
+// is even), so half the taps are evaluated and mirrored.
 #include "gct_internal.h"
 
 namespace gct {
@@ -61,41 +62,61 @@ __device__ __forceinline__ T gram_A(const GramAngle<T> &g, T x, bool blur)
     return g.scale * (tl + r * g.iL2);
 }
 
-// One 16 x 16 tile of taps per block.  The angle loop is uniform across the
-// block; an angle whose projected tile interval misses the support of A is
-// skipped by the whole block.
+// One 16 x 16 tile of taps per block, covering only taps with k2 > 0 or
+// (k2 = 0, k1 >= 0); each such tap also writes its mirror -k (G is even).
+// Angle records are staged through LDS in chunks.  The angle loop is
+// uniform across the block; an angle whose projected tile interval misses
+// the support of A is skipped by the whole block.
+constexpr int GB_CHUNK = 128;
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ ga)
 {
+    __shared__ GramAngle<T> s_ga[GB_CHUNK];
     const int W = 2 * N - 1;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int c0 = blockIdx.x * 16, r0 = blockIdx.y * 16;
-    const int k1 = c0 + tx - (N - 1), k2 = r0 + ty - (N - 1);
-    const double ka = c0 - (N - 1), kb = c0 + 15 - (N - 1);
-    const double la = r0 - (N - 1), lb = r0 + 15 - (N - 1);
+    const int k1a = (int)blockIdx.x * 16 - (N - 1);  // first tap column of the tile
+    const int k2a = (int)blockIdx.y * 16;              // first tap row (>= 0)
+    const int k1 = k1a + tx, k2 = k2a + ty;
+    const bool live = k1 <= N - 1 && k2 <= N - 1 && (k2 > 0 || k1 >= 0);
+    const double ka = k1a, kb = k1a + 15, la = k2a, lb = k2a + 15;
     T acc = 0, comp = 0;
-    for (int a = 0; a < n; ++a) {
-        const GramAngle<T> g = ga[a];
-        // projected interval of the tile (extreme corners)
-        const double p1 = ka * g.cx, p2 = kb * g.cx, q1 = la * g.sx, q2 = lb * g.sx;
-        const double dmin = fmin(p1, p2) + fmin(q1, q2), dmax = fmax(p1, p2) + fmax(q1, q2);
-        if (dmax <= -(double)g.half || dmin >= (double)g.half) continue;
-        const T d = (T)((double)k1 * g.cx + (double)k2 * g.sx);
-        const T v = g.S > T(0) ? gram_A(g, d, true) : gram_A(g, d, false);
-        const T yk = v - comp;
-        const T tk = acc + yk;
-        comp = (tk - acc) - yk;
-        acc = tk;
+    for (int a0 = 0; a0 < n; a0 += GB_CHUNK) {
+        const int cnt = min(GB_CHUNK, n - a0);
+        __syncthreads();
+        {
+            const int words = cnt * (int)(sizeof(GramAngle<T>) / 4);
+            const uint32_t *src = reinterpret_cast<const uint32_t *>(ga + a0);
+            uint32_t *dst = reinterpret_cast<uint32_t *>(s_ga);
+            for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+        }
+        __syncthreads();
+        for (int c = 0; c < cnt; ++c) {
+            const GramAngle<T> &g = s_ga[c];
+            // projected interval of the tile (extreme corners)
+            const double p1 = ka * g.cx, p2 = kb * g.cx, q1 = la * g.sx, q2 = lb * g.sx;
+            const double dmin = fmin(p1, p2) + fmin(q1, q2), dmax = fmax(p1, p2) + fmax(q1, q2);
+            if (dmax <= -(double)g.half || dmin >= (double)g.half) continue;
+            const T d = (T)((double)k1 * g.cx + (double)k2 * g.sx);
+            const T v = g.S > T(0) ? gram_A(g, d, true) : gram_A(g, d, false);
+            const T yk = v - comp;
+            const T tk = acc + yk;
+            comp = (tk - acc) - yk;
+            acc = tk;
+        }
     }
-    if (c0 + tx < W && r0 + ty < W) G[(size_t)(r0 + ty) * W + (c0 + tx)] = acc;
+    if (live) {
+        G[(size_t)(k2 + N - 1) * W + (k1 + N - 1)] = acc;
+        G[(size_t)(N - 1 - k2) * W + (N - 1 - k1)] = acc;
+    }
 }
 
 template <typename T>
 hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s)
 {
     const int W = 2 * p->N - 1;
-    const dim3 grid((W + 15) / 16, (W + 15) / 16);
+    const dim3 grid((W + 15) / 16, (p->N + 15) / 16);
     const GramAngle<T> *ga =
         reinterpret_cast<const GramAngle<T> *>(sizeof(T) == 4 ? p->dev.gram_f32 : p->dev.gram_f64);
     hipLaunchKernelGGL(k_gram_build<T>, grid, dim3(256), 0, s, G, p->N, p->n, ga);

@@ -321,7 +321,9 @@ static int build_plan(const gct_geometry *g, gct_plan *p)
     std::vector<int32_t> deg(n);
     std::vector<BPAngleTable> bt(n);
     int smax = 1, J = 1, D1 = 1;
+    double span = 0.0;
     for (int a = 0; a < n; ++a) {
+        span = std::max(span, (ad[a].a1 + ad[a].a2) / ly);
         gf[a] = gram_angle<float>(ad[a], l1, l2, z);
         gd[a] = gram_angle<double>(ad[a], l1, l2, z);
         ff[a] = fwd_angle<float>(ad[a], l1, l2, z);
@@ -335,6 +337,7 @@ static int build_plan(const gct_geometry *g, gct_plan *p)
     p->bp.smax = smax;
     p->bp.J = J;
     p->bp.D1 = D1;
+    p->bp.span_per_pixel = span;
     std::vector<double> geo((size_t)n * 4, 0.0), brk((size_t)n * smax, 2.0);
     std::vector<int32_t> ints((size_t)n * 4, 0);
     std::vector<double> coef((size_t)n * smax * J * D1, 0.0);

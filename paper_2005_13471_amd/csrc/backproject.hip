@@ -58,118 +58,140 @@ hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s
 // for the few bins the tile projects onto (in LDS), then every pixel finds
 // its (m0, s) and evaluates one polynomial.  FP64 is used only for z.
 // ---------------------------------------------------------------------------
+// Tables of CH angles are staged together (one global-latency wait per
+// chunk); E is double-buffered so each angle costs one barrier.
+struct BPLayout {
+    int tile, rmax, ch;
+    size_t lds;
+};
+
 template <typename T, int TILE>
 __global__ void __launch_bounds__(TILE * TILE)
 k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp, int K,
               const double *__restrict__ geo, const int32_t *__restrict__ ints,
               const T *__restrict__ brk, const T *__restrict__ coef, int smax, int J, int D1,
-              int rmax)
+              int rmax, int CH)
 {
+    constexpr int NT = TILE * TILE;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int per_coef = smax * J * D1;
-    T *s_E = reinterpret_cast<T *>(smem_raw);   // [rmax][smax][D1]
-    T *s_C = s_E + (size_t)rmax * smax * D1;    // [smax][J][D1]
-    T *s_p = s_C + per_coef;                    // [rmax + J]
-    T *s_b = s_p + rmax + J;                    // [smax]
+    const int pseg = rmax + J;
+    const int eblk = rmax * smax * D1;
+    T *s_E = reinterpret_cast<T *>(smem_raw);  // [2][rmax][smax][D1]
+    T *s_C = s_E + 2 * eblk;                   // [CH][smax][J][D1]
+    T *s_p = s_C + CH * per_coef;              // [CH][rmax + J]
+    T *s_b = s_p + CH * pseg;                  // [CH][smax]
     const int tid = threadIdx.x;
     const int k1a = blockIdx.x * TILE, k2a = blockIdx.y * TILE;
     const int k1 = k1a + tid % TILE, k2 = k2a + tid / TILE;
     const double kx0 = k1a, kx1 = k1a + TILE - 1, ky0 = k2a, ky1 = k2a + TILE - 1;
-    T acc = 0, comp = 0;
-    for (int a = 0; a < n; ++a) {
+    // bin window of the tile at angle a: [mlo, mlo + R) (one bin of margin
+    // each side against rounding of z)
+    auto window = [&](int a, int &mlo, int &R) {
         const double z0 = geo[4 * a], dz1 = geo[4 * a + 1], dz2 = geo[4 * a + 2];
-        const int nsub = ints[4 * a], jlo = ints[4 * a + 1];
-        // bin range of the tile (with one bin of margin against rounding)
         const double e1 = kx0 * dz1, e2 = kx1 * dz1, f1 = ky0 * dz2, f2 = ky1 * dz2;
         const double zmin = z0 + fmin(e1, e2) + fmin(f1, f2);
         const double zmax = z0 + fmax(e1, e2) + fmax(f1, f2);
-        const int mlo = (int)floor(zmin) - 1;
-        const int R = min((int)floor(zmax) + 1 - mlo + 1, rmax);
-        __syncthreads();  // previous angle done with s_E / s_C / s_p
-        for (int i = tid; i < nsub * J * D1; i += TILE * TILE) s_C[i] = coef[(size_t)a * per_coef + i];
-        for (int i = tid; i < nsub; i += TILE * TILE) s_b[i] = brk[(size_t)a * smax + i];
-        for (int i = tid; i < R + J - 1; i += TILE * TILE) {
-            const int mi = mlo + jlo + i + K;
-            s_p[i] = (mi >= 0 && mi < Mp) ? pf[(size_t)a * Mp + mi] : T(0);
+        mlo = (int)floor(zmin) - 1;
+        R = min((int)floor(zmax) + 2 - mlo, rmax);
+    };
+    T acc = 0, comp = 0;
+    int parity = 0;
+    for (int a0 = 0; a0 < n; a0 += CH) {
+        const int cnt = min(CH, n - a0);
+        __syncthreads();  // previous chunk done with s_C / s_p / s_b
+        for (int i = tid; i < cnt * per_coef; i += NT) s_C[i] = coef[(size_t)a0 * per_coef + i];
+        for (int i = tid; i < cnt * smax; i += NT) s_b[i] = brk[(size_t)a0 * smax + i];
+        for (int i = tid; i < cnt * pseg; i += NT) {
+            const int c = i / pseg, off = i - c * pseg;
+            const int a = a0 + c;
+            int mlo, R;
+            window(a, mlo, R);
+            const int mi = mlo + ints[4 * a + 1] + off + K;
+            s_p[i] = (off < R + J - 1 && mi >= 0 && mi < Mp) ? pf[(size_t)a * Mp + mi] : T(0);
         }
         __syncthreads();
-        const int nE = R * nsub * D1;
-        for (int i = tid; i < nE; i += TILE * TILE) {
-            const int k = i % D1, rest = i / D1;
-            const int sidx = rest % nsub, mi = rest / nsub;
-            const T *cf = s_C + sidx * J * D1 + k;
-            const T *pp = s_p + mi;
-            T e = 0;
-            for (int j = 0; j < J; ++j) e += pp[j] * cf[j * D1];
-            s_E[i] = e;
+        for (int c = 0; c < cnt; ++c) {
+            const int a = a0 + c;
+            const int nsub = ints[4 * a];
+            int mlo, R;
+            window(a, mlo, R);
+            T *E = s_E + parity * eblk;
+            const T *Cc = s_C + c * per_coef;
+            const T *pc = s_p + c * pseg;
+            const int nE = R * nsub * D1;
+            for (int i = tid; i < nE; i += NT) {
+                const int k = i % D1, rest = i / D1;
+                const int sidx = rest % nsub, mi = rest / nsub;
+                const T *cf = Cc + sidx * J * D1 + k;
+                const T *pp = pc + mi;
+                T e = 0;
+                for (int j = 0; j < J; ++j) e += pp[j] * cf[j * D1];
+                E[i] = e;
+            }
+            __syncthreads();
+            const double z = geo[4 * a] + (double)k1 * geo[4 * a + 1] + (double)k2 * geo[4 * a + 2];
+            const double zf = floor(z);
+            const T t = (T)(z - zf);
+            int mi = (int)zf - mlo;
+            mi = mi < 0 ? 0 : (mi >= R ? R - 1 : mi);
+            const T *bk = s_b + c * smax;
+            int sub = 0;
+            for (int i = 1; i < nsub; ++i) sub += (t >= bk[i]) ? 1 : 0;
+            const T u = t - bk[sub];
+            const T *e = E + (mi * nsub + sub) * D1;
+            T v = e[D1 - 1];
+            for (int k = D1 - 2; k >= 0; --k) v = v * u + e[k];
+            const T yk = v - comp;
+            const T tk = acc + yk;
+            comp = (tk - acc) - yk;
+            acc = tk;
+            parity ^= 1;
         }
-        __syncthreads();
-        const double z = z0 + (double)k1 * dz1 + (double)k2 * dz2;
-        const double zf = floor(z);
-        const T t = (T)(z - zf);
-        int mi = (int)zf - mlo;
-        mi = mi < 0 ? 0 : (mi >= R ? R - 1 : mi);
-        int sub = 0;
-        for (int i = 1; i < nsub; ++i) sub += (t >= s_b[i]) ? 1 : 0;
-        const T u = t - s_b[sub];
-        const T *e = s_E + (mi * nsub + sub) * D1;
-        T v = e[D1 - 1];
-        for (int k = D1 - 2; k >= 0; --k) v = v * u + e[k];
-        const T yk = v - comp;
-        const T tk = acc + yk;
-        comp = (tk - acc) - yk;
-        acc = tk;
     }
     if (k1 < N && k2 < N) b[(size_t)k2 * N + k1] = acc;
 }
 
-// Tile side and LDS size: 32 x 32 when the per-angle tables fit in 64 KB,
-// else 16 x 16.
-static int bp_tile(const gct_plan *p, size_t elem, size_t *lds, int *rmax)
+// Tile side, bins per tile window and angles per chunk such that the LDS
+// stays within 64 KB: 32 x 32 tiles when they fit, else 16 x 16.
+static BPLayout bp_layout(const gct_plan *p, size_t elem)
 {
+    BPLayout L{16, 0, 1, 0};
     for (int tile : {32, 16}) {
         const int r = (int)std::ceil((tile - 1) * p->bp.span_per_pixel) + 4;
-        const size_t words = (size_t)r * p->bp.smax * p->bp.D1 + (size_t)p->bp.smax * p->bp.J * p->bp.D1 +
-                             r + p->bp.J + p->bp.smax;
-        const size_t bytes = words * elem;
-        if (bytes <= 65536 || tile == 16) {
-            *lds = bytes;
-            *rmax = r;
-            return tile;
+        for (int ch : {16, 8, 4, 2, 1}) {
+            const size_t per_coef = (size_t)p->bp.smax * p->bp.J * p->bp.D1;
+            const size_t words = 2 * (size_t)r * p->bp.smax * p->bp.D1 + ch * per_coef +
+                                 (size_t)ch * (r + p->bp.J) + (size_t)ch * p->bp.smax;
+            if (words * elem <= 65536) return BPLayout{tile, r, ch, words * elem};
         }
+        L = BPLayout{tile, r, 1, 0};
     }
-    return 16;
+    L.lds = ~size_t(0);  // does not fit
+    return L;
 }
 
-size_t bp_lds_bytes(const gct_plan *p, size_t elem)
-{
-    size_t lds;
-    int r;
-    bp_tile(p, elem, &lds, &r);
-    return lds;
-}
+size_t bp_lds_bytes(const gct_plan *p, size_t elem) { return bp_layout(p, elem).lds; }
 
 template <typename T>
 hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, hipStream_t s)
 {
     const int N = p->N;
-    size_t lds;
-    int rmax;
-    const int tile = bp_tile(p, sizeof(T), &lds, &rmax);
-    if (lds > 65536) return hipErrorInvalidConfiguration;
-    const dim3 grid((N + tile - 1) / tile, (N + tile - 1) / tile);
+    const BPLayout L = bp_layout(p, sizeof(T));
+    if (L.lds > 65536) return hipErrorInvalidConfiguration;
+    const dim3 grid((N + L.tile - 1) / L.tile, (N + L.tile - 1) / L.tile);
     const T *brk = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.bp_brk_f32 : p->dev.bp_brk_f64);
     const T *coef = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.bp_coef_f32 : p->dev.bp_coef_f64);
     const double *geo = reinterpret_cast<const double *>(p->dev.bp_geo);
     const int32_t *ints = reinterpret_cast<const int32_t *>(p->dev.bp_int);
-    if (tile == 32)
-        hipLaunchKernelGGL((k_backproject<T, 32>), grid, dim3(1024), lds, s, pf, b, N, p->n,
+    if (L.tile == 32)
+        hipLaunchKernelGGL((k_backproject<T, 32>), grid, dim3(1024), L.lds, s, pf, b, N, p->n,
                            p->M + 2 * p->K, p->K, geo, ints, brk, coef, p->bp.smax, p->bp.J,
-                           p->bp.D1, rmax);
+                           p->bp.D1, L.rmax, L.ch);
     else
-        hipLaunchKernelGGL((k_backproject<T, 16>), grid, dim3(256), lds, s, pf, b, N, p->n,
+        hipLaunchKernelGGL((k_backproject<T, 16>), grid, dim3(256), L.lds, s, pf, b, N, p->n,
                            p->M + 2 * p->K, p->K, geo, ints, brk, coef, p->bp.smax, p->bp.J,
-                           p->bp.D1, rmax);
+                           p->bp.D1, L.rmax, L.ch);
     return hipGetLastError();
 }
 

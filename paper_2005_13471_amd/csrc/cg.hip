@@ -97,31 +97,31 @@ k_cg_init_fin(CGState *st, const double *part_rr, const double *part_bb, int np,
     }
 }
 
-// alpha = rr / p.Ap
-__global__ void __launch_bounds__(256) k_cg_alpha(CGState *st, const double *part, int np)
+// alpha = rr / p.Ap (every block reduces the p.Ap partials itself, in the
+// same order, so all blocks agree), then x += alpha p, r -= alpha Ap and a
+// partial ||r||^2 per block.  A non-positive or non-finite p.Ap stops the
+// solve (every block sees the same value and skips the update; block 0
+// records the breakdown).
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_cg_update(CGState *st, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
+            const T *__restrict__ Ap, size_t n, const double *__restrict__ part_pAp, int np,
+            double *__restrict__ part)
 {
     if (st->status != CG_RUNNING) return;
     double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) {
-        st->pAp = s;
-        if (!(s > 0.0) || !(s < INFINITY)) {
-            st->status = CG_BREAKDOWN;
-        } else {
-            st->alpha = st->rr / s;
-        }
+    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part_pAp[i];
+    const double pAp = block_sum(s);
+    if (!(pAp > 0.0) || !(pAp < INFINITY)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->status = CG_BREAKDOWN;
+        return;
     }
-}
-
-// x += alpha p, r -= alpha Ap; partial ||r||^2
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_cg_update(const CGState *st, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
-            const T *__restrict__ Ap, size_t n, double *__restrict__ part)
-{
-    if (st->status != CG_RUNNING) return;
-    const T al = (T)st->alpha;
+    const double alpha = st->rr / pAp;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pAp = pAp;
+        st->alpha = alpha;
+    }
+    const T al = (T)alpha;
     double rr = 0.0;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (size_t)gridDim.x * blockDim.x) {
@@ -205,6 +205,37 @@ size_t cg_ws_bytes(const gct_plan *p, size_t elem) { return cg_layout(p, elem).t
         if (e_ != hipSuccess) return check_hip(e_, #call);   \
     } while (0)
 
+// ---------------------------------------------------------------------------
+// Graph cache: a chunk of CG iterations captured as a hipGraph, keyed by the
+// buffers it touches, kept in the plan until it is destroyed.  Capture runs
+// on a private non-blocking stream of default priority.
+// ---------------------------------------------------------------------------
+static hipGraphExec_t cg_graph_lookup(const gct_plan *p, const CGGraphKey &k)
+{
+    for (const auto &e : p->cg_graphs)
+        if (e.key == k) return e.exec;
+    return nullptr;
+}
+
+static void cg_graph_store(const gct_plan *p, const CGGraphKey &k, hipGraphExec_t exec)
+{
+    auto &v = const_cast<gct_plan *>(p)->cg_graphs;
+    if (v.size() >= 16) {
+        (void)hipGraphExecDestroy(v.front().exec);
+        v.erase(v.begin());
+    }
+    v.push_back({k, exec});
+}
+
+static hipStream_t cg_capture_stream(const gct_plan *p)
+{
+    gct_plan *q = const_cast<gct_plan *>(p);
+    if (!q->capture_stream &&
+        hipStreamCreateWithFlags(&q->capture_stream, hipStreamNonBlocking) != hipSuccess)
+        q->capture_stream = nullptr;
+    return q->capture_stream;
+}
+
 template <typename T>
 int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, double rtol,
              int max_iter, int check_every, double *hist, gct_cg_result *res, void *ws,
@@ -251,17 +282,45 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     if (hist) hist[0] = rel(hs.rr0);
 
     int64_t done = 0;
+    auto launch_iters = [&](int count, hipStream_t st_) -> hipError_t {
+        for (int i = 0; i < count; ++i) {
+            hipError_t e = launch_apply_passes<T>(p, Ghat, r, Ap, aws, st_, &st->status, pv,
+                                                  &st->beta, pv, part);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(k_cg_update<T>, dim3(VBLK), dim3(256), 0, st_, st, x, r, pv, Ap, n,
+                               part, rblocks, part2);
+            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st_, st, part2, VBLK);
+        }
+        return hipGetLastError();
+    };
     while (hs.status == CG_RUNNING && done < max_iter) {
         const int chunk = (int)std::min<int64_t>(check_every, max_iter - done);
-        for (int i = 0; i < chunk; ++i) {
-            GCT_TRY(launch_apply_passes<T>(p, Ghat, r, Ap, aws, s, &st->status, pv, &st->beta, pv,
-                                           part));
-            hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, s, st, part, rblocks);
-            hipLaunchKernelGGL(k_cg_update<T>, dim3(VBLK), dim3(256), 0, s, st, x, r, pv, Ap, n,
-                               part2);
-            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, s, st, part2, VBLK);
+        hipGraphExec_t exec = nullptr;
+        if (chunk == check_every) {
+            // a chunk of iterations as one graph, captured once per buffer set
+            const CGGraphKey key{(const void *)Ghat, (const void *)b, (void *)x, ws,
+                                 (int)sizeof(T), chunk};
+            exec = cg_graph_lookup(p, key);
+            if (!exec) {
+                hipStream_t cs = cg_capture_stream(p);
+                if (!cs) return fail(GCT_EHIP, "cannot create the capture stream");
+                GCT_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+                hipError_t e = launch_iters(chunk, cs);
+                hipGraph_t g = nullptr;
+                hipError_t e2 = hipStreamEndCapture(cs, &g);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return check_hip(e != hipSuccess ? e : e2, "cg graph capture");
+                }
+                e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return check_hip(e, "hipGraphInstantiate");
+                cg_graph_store(p, key, exec);
+            }
+            GCT_TRY(hipGraphLaunch(exec, s));
+        } else {
+            GCT_TRY(launch_iters(chunk, s));
         }
-        GCT_TRY(hipGetLastError());
         const int64_t kprev = hs.k;
         GCT_TRY(hipMemcpyAsync(&hs, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
         GCT_TRY(hipStreamSynchronize(s));

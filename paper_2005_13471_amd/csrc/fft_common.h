@@ -1,10 +1,18 @@
-// Workgroup-level FFTs in LDS, shared by the Gram-filter kernels.
+// Group-level FFTs for the Gram-filter kernels: register-blocked Stockham.
 //
-// Mixed radix-4/2 Stockham autosort transform, natural order in and out,
-// computed in place: each thread owns one radix-4 butterfly per stage (two
-// radix-2 butterflies in the final stage when log2 P is odd), reads its four
-// inputs, waits for the whole group, then writes its four outputs.  A
-// length-P transform therefore uses P/4 threads and log4(P) (+1) stages.
+// A length-P transform (P = 2^logP) is owned by G = P/E threads; thread t
+// holds E elements in registers in the strided layout v[q] = x[t + G q],
+// q < E.  The transform runs as Stockham autosort passes of radix R (E, E,
+// ..., then the remaining factor), each thread computing E/R radix-R
+// butterflies per pass in registers.  The first pass reads the registers
+// directly (its butterfly inputs are exactly x[t + G r]); the last pass
+// leaves its outputs in registers in the same strided layout; only the
+// passes in between exchange through LDS.  So input and output need no
+// permutation, a forward and an inverse transform can be chained in
+// registers, and loads/stores of x[t + G q] are coalesced across a wave.
+//
+// E = 16 for P >= 1024 (one wave per 1024-point transform: passes 16, 16,
+// 4), E = 8 for P = 512, E = 4 for P <= 256.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,6 +36,13 @@ __device__ __forceinline__ C2<T> cadd(C2<T> a, C2<T> b) { return {a.x + b.x, a.y
 template <typename T>
 __device__ __forceinline__ C2<T> csub(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
 
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ C2<T> mul_mi(C2<T> a)
+{
+    return INV ? C2<T>{-a.y, a.x} : C2<T>{a.y, -a.x};
+}
+
 // e^{-+2 pi i m / P} from the half table tw[m] = e^{-2 pi i m / P}, m < P/2.
 template <typename T, bool INV>
 __device__ __forceinline__ C2<T> twid(const C2<T> *tw, int m, int hP)
@@ -37,59 +52,177 @@ __device__ __forceinline__ C2<T> twid(const C2<T> *tw, int m, int hP)
     return w;
 }
 
-// One length-P transform on x[0..P) by the P/4 threads t = 0..P/4-1 of a
-// group; every thread of the block must call it (it contains barriers).
-// Forward uses e^{-2 pi i nk/P}; INV the conjugate, unscaled.
+// ---------------------------------------------------------------------------
+// Small DFTs in registers, natural order in and out.
+// ---------------------------------------------------------------------------
 template <typename T, bool INV>
-__device__ void fft_inplace(C2<T> *x, int logP, int t, const C2<T> *tw)
+__device__ __forceinline__ void dft2(C2<T> *v)
 {
-    const int P = 1 << logP, Q = P >> 2, hP = P >> 1;
-    int Ns = 1, lNs = 0, rem = logP;
-    while (rem >= 2) {
-        const int k = t & (Ns - 1);
-        const int stride = P >> (lNs + 2);
-        C2<T> v0 = x[t], v1 = x[t + Q], v2 = x[t + 2 * Q], v3 = x[t + 3 * Q];
-        v1 = cmul(v1, twid<T, INV>(tw, k * stride, hP));
-        v2 = cmul(v2, twid<T, INV>(tw, 2 * k * stride, hP));
-        v3 = cmul(v3, twid<T, INV>(tw, 3 * k * stride, hP));
-        const C2<T> t0 = cadd(v0, v2), t1 = csub(v0, v2), t2 = cadd(v1, v3), t3 = csub(v1, v3);
-        // multiply t3 by -i (forward) or +i (inverse)
-        const C2<T> t3r = INV ? C2<T>{-t3.y, t3.x} : C2<T>{t3.y, -t3.x};
-        __syncthreads();
-        const int base = ((t - k) << 2) + k;
-        x[base] = cadd(t0, t2);
-        x[base + Ns] = cadd(t1, t3r);
-        x[base + 2 * Ns] = csub(t0, t2);
-        x[base + 3 * Ns] = csub(t1, t3r);
-        __syncthreads();
-        Ns <<= 2;
-        lNs += 2;
-        rem -= 2;
-    }
-    if (rem == 1) {
-        const int stride = P >> (lNs + 1);
-        C2<T> A[2], B[2];
-        int kk[2];
+    const C2<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4s(C2<T> &a0, C2<T> &a1, C2<T> &a2, C2<T> &a3)
+{
+    const C2<T> t0 = cadd(a0, a2), t1 = csub(a0, a2), t2 = cadd(a1, a3);
+    const C2<T> t3 = mul_mi<T, INV>(csub(a1, a3));
+    a0 = cadd(t0, t2);
+    a2 = csub(t0, t2);
+    a1 = cadd(t1, t3);
+    a3 = csub(t1, t3);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft4(C2<T> *v)
+{
+    dft4s<T, INV>(v[0], v[1], v[2], v[3]);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft8(C2<T> *v)
+{
+    const T h = T(0.70710678118654752440);
+    C2<T> e0 = v[0], e1 = v[2], e2 = v[4], e3 = v[6];
+    C2<T> o0 = v[1], o1 = v[3], o2 = v[5], o3 = v[7];
+    dft4s<T, INV>(e0, e1, e2, e3);
+    dft4s<T, INV>(o0, o1, o2, o3);
+    // W8^1, W8^2, W8^3 (conjugated for the inverse)
+    o1 = INV ? C2<T>{h * (o1.x - o1.y), h * (o1.x + o1.y)} : C2<T>{h * (o1.x + o1.y), h * (o1.y - o1.x)};
+    o2 = mul_mi<T, INV>(o2);
+    o3 = INV ? C2<T>{-h * (o3.x + o3.y), h * (o3.x - o3.y)} : C2<T>{h * (o3.y - o3.x), -h * (o3.x + o3.y)};
+    v[0] = cadd(e0, o0);
+    v[4] = csub(e0, o0);
+    v[1] = cadd(e1, o1);
+    v[5] = csub(e1, o1);
+    v[2] = cadd(e2, o2);
+    v[6] = csub(e2, o2);
+    v[3] = cadd(e3, o3);
+    v[7] = csub(e3, o3);
+}
+
+// v * e^{-+2 pi i J / 16} for a compile-time J in {1, 2, 3, 4, 6, 9}
+template <typename T, bool INV, int J>
+__device__ __forceinline__ C2<T> w16(C2<T> v)
+{
+    constexpr double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;
+    constexpr double h = 0.70710678118654752440;
+    constexpr double c = J == 1 ? c1 : J == 2 ? h : J == 3 ? s1 : J == 4 ? 0.0 : J == 6 ? -h : -c1;
+    constexpr double s = J == 1 ? s1 : J == 2 ? h : J == 3 ? c1 : J == 4 ? 1.0 : J == 6 ? h : -s1;
+    const C2<T> w = {T(c), INV ? T(s) : T(-s)};
+    return cmul(v, w);
+}
+
+template <typename T, bool INV>
+__device__ __forceinline__ void dft16(C2<T> *v)
+{
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int j = t + q * Q;
-            const int k = j & (Ns - 1);
-            kk[q] = k;
-            const C2<T> a = x[j];
-            const C2<T> b = cmul(x[j + hP], twid<T, INV>(tw, k * stride, hP));
-            A[q] = cadd(a, b);
-            B[q] = csub(a, b);
-        }
-        __syncthreads();
+    for (int l = 0; l < 4; ++l) dft4s<T, INV>(v[l], v[4 + l], v[8 + l], v[12 + l]);
+    // twiddle W16^{l m}: element 4 m + l holds Y_l[m]
+    v[5] = w16<T, INV, 1>(v[5]);
+    v[9] = w16<T, INV, 2>(v[9]);
+    v[13] = w16<T, INV, 3>(v[13]);
+    v[6] = w16<T, INV, 2>(v[6]);
+    v[10] = w16<T, INV, 4>(v[10]);
+    v[14] = w16<T, INV, 6>(v[14]);
+    v[7] = w16<T, INV, 3>(v[7]);
+    v[11] = w16<T, INV, 6>(v[11]);
+    v[15] = w16<T, INV, 9>(v[15]);
+    C2<T> o[16];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int j = t + q * Q;
-            const int base = ((j - kk[q]) << 1) + kk[q];
-            x[base] = A[q];
-            x[base + Ns] = B[q];
-        }
-        __syncthreads();
+    for (int m = 0; m < 4; ++m) {
+        C2<T> a0 = v[4 * m], a1 = v[4 * m + 1], a2 = v[4 * m + 2], a3 = v[4 * m + 3];
+        dft4s<T, INV>(a0, a1, a2, a3);
+        o[m] = a0;
+        o[m + 4] = a1;
+        o[m + 8] = a2;
+        o[m + 12] = a3;
     }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = o[q];
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(C2<T> *v)
+{
+    if constexpr (R == 2) dft2<T, INV>(v);
+    else if constexpr (R == 4) dft4<T, INV>(v);
+    else if constexpr (R == 8) dft8<T, INV>(v);
+    else dft16<T, INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham pass of radix R on a length-P transform held by G = P/E
+// threads.  FIRST: inputs are v (R == E, no twiddles); LAST: outputs go to v
+// in the strided layout.  Otherwise x (LDS) is read and/or written.  Every
+// thread of the block must call it (it may contain barriers).
+// ---------------------------------------------------------------------------
+template <typename T, int E, int P, int NS, int R, bool INV, bool FIRST, bool LAST>
+__device__ __forceinline__ void fft_pass(C2<T> (&v)[E], C2<T> *x, int t, const C2<T> *tw)
+{
+    constexpr int B = E / R;
+    constexpr int G = P / E;
+    constexpr int stride = P / R;
+    constexpr int tstep = P / (NS * R);
+    constexpr int hP = P / 2;
+    C2<T> u[E];
+#pragma unroll
+    for (int b = 0; b < B; ++b) {
+        const int j = t + G * b;
+        const int k = j & (NS - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if constexpr (FIRST) {
+                u[b * R + r] = v[b * R + r];
+            } else {
+                C2<T> a = x[j + r * stride];
+                if (r > 0) a = cmul(a, twid<T, INV>(tw, r * k * tstep, hP));
+                u[b * R + r] = a;
+            }
+        }
+        dftR<T, R, INV>(&u[b * R]);
+    }
+    if constexpr (!FIRST) __syncthreads();  // every read of x in this pass is done
+    if constexpr (LAST) {
+#pragma unroll
+        for (int b = 0; b < B; ++b)
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[b + B * r] = u[b * R + r];
+    } else {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
+            const int j = t + G * b;
+            const int k = j & (NS - 1);
+            const int base = (j - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) x[base + r * NS] = u[b * R + r];
+        }
+        __syncthreads();  // writes visible to the next pass
+    }
+}
+
+template <typename T, int E, int P, int NS, bool INV, bool FIRST>
+__device__ __forceinline__ void fft_passes(C2<T> (&v)[E], C2<T> *x, int t, const C2<T> *tw)
+{
+    constexpr int REM = P / NS;
+    constexpr int R = REM >= E ? E : REM;
+    constexpr bool LAST = REM == R;
+    fft_pass<T, E, P, NS, R, INV, FIRST, LAST>(v, x, t, tw);
+    if constexpr (!LAST) fft_passes<T, E, P, NS * R, INV, false>(v, x, t, tw);
+}
+
+// Elements per thread for a length-P transform.
+__host__ __device__ constexpr int fft_elems(int P) { return P >= 1024 ? 16 : (P == 512 ? 8 : 4); }
+
+// Full transform of length P = 2^LOGP: v holds x[t + G q] on entry and
+// X[t + G q] on exit.  x is an LDS scratch area of P elements.
+template <typename T, int LOGP, bool INV>
+__device__ __forceinline__ void fft_strided(C2<T> (&v)[fft_elems(1 << LOGP)], C2<T> *x, int t,
+                                            const C2<T> *tw)
+{
+    constexpr int P = 1 << LOGP;
+    fft_passes<T, fft_elems(P), P, 1, INV, true>(v, x, t, tw);
 }
 
 }  // namespace gct

@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/gramct.h"
 
@@ -81,6 +82,23 @@ struct DeviceTables {
     void *deg = nullptr;                              // int32[n]: B-spline degree per angle
 };
 
+// Key of a captured chunk of CG iterations.
+struct CGGraphKey {
+    const void *Ghat, *b;
+    void *x, *ws;
+    int elem, chunk;
+    bool operator==(const CGGraphKey &o) const
+    {
+        return Ghat == o.Ghat && b == o.b && x == o.x && ws == o.ws && elem == o.elem &&
+               chunk == o.chunk;
+    }
+};
+
+struct CGGraph {
+    CGGraphKey key;
+    hipGraphExec_t exec;
+};
+
 }  // namespace gct
 
 struct gct_plan {
@@ -90,6 +108,9 @@ struct gct_plan {
     gct::BPDims bp;
     gct::DeviceTables dev;
     int device;
+    // cached CG iteration graphs and the stream they are captured on
+    std::vector<gct::CGGraph> cg_graphs;
+    hipStream_t capture_stream = nullptr;
 };
 
 namespace gct {

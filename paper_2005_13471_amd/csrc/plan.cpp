@@ -478,6 +478,9 @@ int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
 int gct_plan_destroy(gct_plan *plan)
 {
     if (!plan) return GCT_OK;
+    for (auto &g : plan->cg_graphs) (void)hipGraphExecDestroy(g.exec);
+    plan->cg_graphs.clear();
+    if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
     free_tables(plan);
     delete plan;
     return GCT_OK;

@@ -51,25 +51,40 @@ def random_ellipses(N: int, count: int, seed: int) -> list[Ellipse]:
 
 def rasterize(N: int, ells: list[Ellipse], sub: int = 8) -> np.ndarray:
     """c[k2, k1] = sum_e rho_e * (fraction of the sub x sub sub-pixel centres
-    of pixel k inside ellipse e).  Pixel k is centred at k - (N-1)/2."""
+    of pixel k inside ellipse e).  Pixel k is centred at k - (N-1)/2.
+    Counted exactly per sub-row: the ellipse cuts each sub-row in one
+    interval of x, and the sub-sample centres of a pixel inside an interval
+    are counted arithmetically."""
     img = np.zeros((N, N))
     offs = (np.arange(sub) + 0.5) / sub - 0.5
+    h = 0.5 * (N - 1)
     for e in ells:
         r = max(e.a, e.b) + 1.0
-        k1lo = max(int(np.floor(e.cx + (N - 1) / 2 - r)), 0)
-        k1hi = min(int(np.ceil(e.cx + (N - 1) / 2 + r)), N - 1)
-        k2lo = max(int(np.floor(e.cy + (N - 1) / 2 - r)), 0)
-        k2hi = min(int(np.ceil(e.cy + (N - 1) / 2 + r)), N - 1)
+        k1lo = max(int(np.floor(e.cx + h - r)), 0)
+        k1hi = min(int(np.ceil(e.cx + h + r)), N - 1)
+        k2lo = max(int(np.floor(e.cy + h - r)), 0)
+        k2hi = min(int(np.ceil(e.cy + h + r)), N - 1)
         if k1lo > k1hi or k2lo > k2hi:
             continue
-        x1 = (np.arange(k1lo, k1hi + 1) - (N - 1) / 2)[None, :, None, None] + offs[None, None, None, :]
-        x2 = (np.arange(k2lo, k2hi + 1) - (N - 1) / 2)[:, None, None, None] + offs[None, None, :, None]
-        dx, dy = x1 - e.cx, x2 - e.cy
         cp, sp = np.cos(e.phi), np.sin(e.phi)
-        u = dx * cp + dy * sp
-        v = -dx * sp + dy * cp
-        inside = (u / e.a) ** 2 + (v / e.b) ** 2 <= 1.0
-        img[k2lo:k2hi + 1, k1lo:k1hi + 1] += e.rho * inside.mean(axis=(2, 3))
+        ia2, ib2 = 1.0 / e.a ** 2, 1.0 / e.b ** 2
+        # sub-row y values, shape (rows * sub,)
+        y = ((np.arange(k2lo, k2hi + 1) - h)[:, None] + offs[None, :]).reshape(-1)
+        dy = y - e.cy
+        A = cp * cp * ia2 + sp * sp * ib2
+        B = 2.0 * dy * cp * sp * (ia2 - ib2)
+        C = dy * dy * (sp * sp * ia2 + cp * cp * ib2) - 1.0
+        disc = B * B - 4.0 * A * C
+        ok = disc >= 0.0
+        sq = np.sqrt(np.where(ok, disc, 0.0))
+        xlo = np.where(ok, e.cx + (-B - sq) / (2.0 * A), np.inf)[:, None]
+        xhi = np.where(ok, e.cx + (-B + sq) / (2.0 * A), -np.inf)[:, None]
+        x1 = (np.arange(k1lo, k1hi + 1) - h)[None, :]
+        qlo = np.ceil((xlo - x1 + 0.5) * sub - 0.5)
+        qhi = np.floor((xhi - x1 + 0.5) * sub - 0.5)
+        cnt = np.clip(np.minimum(qhi, sub - 1) - np.maximum(qlo, 0) + 1, 0, None)
+        cnt = cnt.reshape(k2hi - k2lo + 1, sub, k1hi - k1lo + 1).sum(axis=1)
+        img[k2lo:k2hi + 1, k1lo:k1hi + 1] += e.rho * cnt / (sub * sub)
     return img
 
 
@@ -98,25 +113,37 @@ def analytic_sinogram(ells: list[Ellipse], theta: np.ndarray, M: int, ly: float 
     """Line integrals of the continuous ellipse phantom at y_m = ly (m - (M-1)/2),
     averaged over the detector cell [y_m - zeta/2, y_m + zeta/2] when zeta > 0.
     An ellipse with support function h in direction u has chord length
-    (2ab/h^2) sqrt(h^2 - t^2) at offset t from its centre."""
-    y = ly * (np.arange(M) - 0.5 * (M - 1))
-    out = np.zeros((theta.size, M))
-    c, s = np.cos(theta)[:, None], np.sin(theta)[:, None]
+    (2ab/h^2) sqrt(h^2 - t^2) at offset t from its centre.  Only the bins
+    inside each ellipse's shadow are evaluated."""
+    n = theta.size
+    out = np.zeros(n * M)
+    c, s = np.cos(theta), np.sin(theta)
+    half = 0.5 * zeta
     for e in ells:
         cp, sp = np.cos(e.phi), np.sin(e.phi)
-        ua = c * cp + s * sp           # u . a-axis
-        ub = -c * sp + s * cp          # u . b-axis
-        h = np.sqrt((e.a * ua) ** 2 + (e.b * ub) ** 2)
-        t = y[None, :] - (e.cx * c + e.cy * s)
+        h = np.sqrt((e.a * (c * cp + s * sp)) ** 2 + (e.b * (-c * sp + s * cp)) ** 2)
+        ctr = e.cx * c + e.cy * s
         k = 2.0 * e.a * e.b / h ** 2
+        # bins whose (cell-averaged) sample can touch the shadow [ctr - h, ctr + h]
+        mlo = np.maximum(np.ceil((ctr - h - half) / ly + 0.5 * (M - 1)).astype(np.int64), 0)
+        mhi = np.minimum(np.floor((ctr + h + half) / ly + 0.5 * (M - 1)).astype(np.int64), M - 1)
+        cnt = np.maximum(mhi - mlo + 1, 0)
+        if cnt.sum() == 0:
+            continue
+        a_idx = np.repeat(np.arange(n), cnt)
+        start = np.repeat(np.cumsum(cnt) - cnt, cnt)
+        m = np.repeat(mlo, cnt) + (np.arange(cnt.sum()) - start)
+        hh, kk = h[a_idx], k[a_idx]
+        t = ly * (m - 0.5 * (M - 1)) - ctr[a_idx]
         if zeta <= 0.0:
-            out += e.rho * k * np.sqrt(np.clip(h * h - t * t, 0.0, None))
+            val = kk * np.sqrt(np.clip(hh * hh - t * t, 0.0, None))
         else:
             def prim(v):
-                v = np.clip(v, -h, h)
-                return 0.5 * (v * np.sqrt(np.clip(h * h - v * v, 0.0, None)) + h * h * np.arcsin(v / h))
-            out += e.rho * k * (prim(t + 0.5 * zeta) - prim(t - 0.5 * zeta)) / zeta
-    return out
+                v = np.clip(v, -hh, hh)
+                return 0.5 * (v * np.sqrt(np.clip(hh * hh - v * v, 0.0, None)) + hh * hh * np.arcsin(v / hh))
+            val = kk * (prim(t + half) - prim(t - half)) / zeta
+        np.add.at(out, a_idx * M + m, e.rho * val)
+    return out.reshape(n, M)
 
 
 def detector_bins(N: int, zeta: float) -> int:

@@ -1,0 +1,165 @@
+"""Precision study at size: N = 2048, 1800 angles, 2900 bins, zeta = 1,
+100-ellipse phantom, 0.5% noise.  FP32 vs FP64 on the GPU for every step,
+both against the FP64 oracle on the central 256 x 256 crop (pixels
+[896, 1152)^2, taps |k|_inf <= 127), and the relative residual after 100 CG
+iterations in each precision.
+
+The oracle cannot afford the full 4095^2 Gram filter inside a test, so it
+computes exactly the taps each comparison needs:
+  * Gram filter: the 255^2 central taps;
+  * normal operator: the input is the phantom restricted to a 96 x 96
+    window inside the crop, so the crop outputs need only taps
+    |k|_inf <= 175 (all others multiply zeros); 1024 crop pixels sampled;
+  * back projection: 256 crop pixels sampled.
+If GCT_REPORT_DIR is set, the numbers are written there as
+precision_n2048_a1800.json.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2005_13471_amd import inputs
+from gpu_helpers import normwise, say
+
+pytestmark = pytest.mark.gpu
+
+N, NA, M, ZETA = 2048, 1800, 2900, 1.0
+CROP = (896, 1152)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from paper_2005_13471_amd import gramct as gct
+    theta = inputs.angles(NA)
+    plan = gct.Plan(N, theta, M, zeta=ZETA)
+    og = oracle.Geometry(N, theta, M, zeta=ZETA)
+    return gct, plan, og, theta
+
+
+def _crop_idx(step=1):
+    r = np.arange(CROP[0], CROP[1], step)
+    return (r[:, None] * N + r[None, :]).reshape(-1).astype(np.int32)
+
+
+def test_precision_study_n2048(setup):
+    gct, plan, og, theta = setup
+    rep = {"workload": "n2048_a1800_m2900_z1", "crop": list(CROP)}
+    W = 2 * N - 1
+    c0 = N - 1
+
+    # ---- Gram filter ------------------------------------------------------
+    say("precision: gram_build FP32 / FP64")
+    G = {}
+    for dt in (torch.float32, torch.float64):
+        g = torch.empty(plan.info.gram_elems, dtype=dt, device="cuda")
+        gct.gram_build(plan, g)
+        G[dt] = g
+    torch.cuda.synchronize()
+    G32 = G[torch.float32].double().cpu().numpy().reshape(W, W)
+    G64 = G[torch.float64].cpu().numpy().reshape(W, W)
+    rep["gram_fp32_vs_fp64_gpu"] = normwise(G32, G64)
+    k = np.arange(-127, 128)
+    taps = np.stack(np.meshgrid(k, k, indexing="xy"), -1).reshape(-1, 2).astype(np.int32)
+    say("precision: oracle gram on the central taps")
+    g_or = oracle.gram_at(og, taps).reshape(255, 255)
+    win = (slice(c0 - 127, c0 + 128), slice(c0 - 127, c0 + 128))
+    rep["gram_fp32_vs_oracle_crop"] = normwise(G32[win], g_or)
+    rep["gram_fp64_vs_oracle_crop"] = normwise(G64[win], g_or)
+    say("  ", {k_: rep[k_] for k_ in rep if k_.startswith("gram")})
+    assert rep["gram_fp32_vs_oracle_crop"] <= 1e-5
+    assert rep["gram_fp64_vs_oracle_crop"] <= 1e-11
+
+    # ---- spectra ----------------------------------------------------------
+    Ghat = {}
+    for dt in (torch.float32, torch.float64):
+        gh = torch.empty(plan.info.spectrum_elems, dtype=dt, device="cuda")
+        gct.gram_spectrum(plan, G[dt], gh, plan.workspace(gct.OP_GRAM_SPECTRUM, dt))
+        Ghat[dt] = gh
+    del G
+
+    # ---- normal operator ----------------------------------------------------
+    say("precision: gram_apply FP32 / FP64")
+    phantom, ells = inputs.phantom(N, 100, 1000)
+    y = {}
+    for dt in (torch.float32, torch.float64):
+        out = torch.empty(N * N, dtype=dt, device="cuda")
+        gct.gram_apply(plan, Ghat[dt], torch.as_tensor(phantom.reshape(-1), dtype=dt, device="cuda"),
+                       out, plan.workspace(gct.OP_GRAM_APPLY, dt))
+        y[dt] = out.double().cpu().numpy()
+    rep["apply_fp32_vs_fp64_gpu"] = normwise(y[torch.float32], y[torch.float64])
+    loc = np.zeros_like(phantom)
+    loc[976:1072, 976:1072] = phantom[976:1072, 976:1072]
+    y_loc = {}
+    for dt in (torch.float32, torch.float64):
+        out = torch.empty(N * N, dtype=dt, device="cuda")
+        gct.gram_apply(plan, Ghat[dt], torch.as_tensor(loc.reshape(-1), dtype=dt, device="cuda"),
+                       out, plan.workspace(gct.OP_GRAM_APPLY, dt))
+        y_loc[dt] = out.double().cpu().numpy()
+    say("precision: oracle normal operator on the crop (localized input)")
+    k = np.arange(-175, 176)
+    taps = np.stack(np.meshgrid(k, k, indexing="xy"), -1).reshape(-1, 2).astype(np.int32)
+    Gw = np.zeros((W, W))
+    Gw[c0 - 175:c0 + 176, c0 - 175:c0 + 176] = oracle.gram_at(og, taps).reshape(351, 351)
+    idx = _crop_idx()[np.random.default_rng(2).choice(256 * 256, 1024, replace=False)]
+    y_or = oracle.apply_at(Gw, loc, idx)
+    rep["apply_fp32_vs_oracle_crop"] = normwise(y_loc[torch.float32][idx], y_or)
+    rep["apply_fp64_vs_oracle_crop"] = normwise(y_loc[torch.float64][idx], y_or)
+    say("  ", {k_: rep[k_] for k_ in rep if k_.startswith("apply")})
+    assert rep["apply_fp32_vs_oracle_crop"] <= 1e-4
+    assert rep["apply_fp64_vs_oracle_crop"] <= 1e-11
+    assert rep["apply_fp32_vs_fp64_gpu"] <= 1e-4
+
+    # ---- back projection ----------------------------------------------------
+    say("precision: back projection FP32 / FP64")
+    sino = inputs.add_noise(inputs.analytic_sinogram(ells, theta, M, zeta=ZETA), 0.005,
+                            inputs.NOISE_SEED_BASE + 1000)
+    b = {}
+    for dt in (torch.float32, torch.float64):
+        out = torch.empty(N * N, dtype=dt, device="cuda")
+        gct.backproject_boxspline(plan, torch.as_tensor(sino.reshape(-1), dtype=dt, device="cuda"),
+                                  out, plan.workspace(gct.OP_BACKPROJECT, dt))
+        b[dt] = out
+    b32 = b[torch.float32].double().cpu().numpy()
+    b64 = b[torch.float64].cpu().numpy()
+    rep["bp_fp32_vs_fp64_gpu"] = normwise(b32, b64)
+    idx = _crop_idx()[np.random.default_rng(3).choice(256 * 256, 256, replace=False)]
+    say("precision: oracle back projection on sampled crop pixels")
+    b_or = oracle.backproject_at(og, sino, idx)
+    rep["bp_fp32_vs_oracle_crop"] = normwise(b32[idx], b_or)
+    rep["bp_fp64_vs_oracle_crop"] = normwise(b64[idx], b_or)
+    say("  ", {k_: rep[k_] for k_ in rep if k_.startswith("bp")})
+    assert rep["bp_fp32_vs_oracle_crop"] <= 1e-4
+    assert rep["bp_fp64_vs_oracle_crop"] <= 1e-11
+
+    # ---- 100 CG iterations in each precision --------------------------------
+    say("precision: 100 CG iterations FP32 / FP64")
+    for dt, name in ((torch.float32, "fp32"), (torch.float64, "fp64")):
+        x = torch.zeros(N * N, dtype=dt, device="cuda")
+        res = gct.cg_solve(plan, Ghat[dt], b[dt], x, plan.workspace(gct.OP_CG, dt), rtol=0.0,
+                           max_iter=100, check_every=20)
+        rep[f"cg100_{name}_rel_res"] = res.rel_res
+        rep[f"cg100_{name}_rel_res_true"] = res.rel_res_true
+        rep[f"cg100_{name}_iters"] = res.iters
+        if dt == torch.float32:
+            x32 = x.double()
+    # the FP32 iterate measured with the FP64 operator
+    r = torch.empty(N * N, dtype=torch.float64, device="cuda")
+    gct.gram_apply(plan, Ghat[torch.float64], x32, r, plan.workspace(gct.OP_GRAM_APPLY, torch.float64))
+    bb = b[torch.float64]
+    rep["cg100_fp32_iterate_rel_res_fp64_operator"] = float(torch.linalg.norm(bb - r) / torch.linalg.norm(bb))
+    say("  ", {k_: rep[k_] for k_ in rep if k_.startswith("cg")})
+    assert rep["cg100_fp32_iters"] == 100 and rep["cg100_fp64_iters"] == 100
+    assert rep["cg100_fp64_rel_res_true"] < 1.0
+    # FP32 vectors with FP64 dots track the FP64 solve closely after 100 steps
+    assert abs(rep["cg100_fp32_iterate_rel_res_fp64_operator"] - rep["cg100_fp64_rel_res_true"]) \
+        <= 0.05 * rep["cg100_fp64_rel_res_true"]
+
+    out_dir = os.environ.get("GCT_REPORT_DIR")
+    if out_dir:
+        os.makedirs(out_dir, exist_ok=True)
+        with open(os.path.join(out_dir, "precision_n2048_a1800.json"), "w") as fh:
+            json.dump(rep, fh, indent=1)

@@ -180,6 +180,71 @@ int gct_cg_solve(const gct_plan *plan, gct_dtype dtype, const void *Ghat, const 
                  int use_x0, double rtol, int32_t max_iter, int32_t check_every, double *hist,
                  gct_cg_result *result, void *ws, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Batches of independent slices (uneven N, angle sets and blur widths).
+ *
+ * A batch groups existing plans (not owned: they must outlive the batch).
+ * Its data arrays are PACKED: slice i occupies [offset_i, offset_i + size_i)
+ * of each array, with the per-slice layouts of the single-slice calls
+ * (images N_i^2, Gram filters (2N_i - 1)^2, spectra (P_i/2 + 1) P_i);
+ * gct_batch_get_info reports the offsets.  Each phase is one launch over all
+ * slices (one per FFT size for the transform passes), so a batch keeps the
+ * GPU busy where one small slice cannot.  The method per slice is exactly
+ * that of the single-slice calls (Sec. 4: Gram filter and Gram filtering;
+ * CG on the normal equations).
+ * ------------------------------------------------------------------------ */
+typedef struct gct_batch gct_batch;
+
+typedef struct {
+    int32_t slices;
+    int32_t groups;          /* distinct FFT sizes */
+    int64_t image_elems;     /* sum of N_i^2 */
+    int64_t gram_elems;      /* sum of (2N_i - 1)^2 */
+    int64_t spectrum_elems;  /* sum of (P_i/2 + 1) P_i */
+} gct_batch_info;
+
+/* plans: host array of `count` plan pointers, all created on the current
+ * device.  Uploads the block maps and slice descriptors (blocking). */
+int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **batch);
+int gct_batch_destroy(gct_batch *batch);
+
+/* Sizes; the three offset arrays (host, `slices` entries each) may be NULL. */
+int gct_batch_get_info(const gct_batch *batch, gct_batch_info *info, int64_t *image_offsets,
+                       int64_t *gram_offsets, int64_t *spectrum_offsets);
+
+/* Workspace bytes for GCT_OP_GRAM_SPECTRUM, GCT_OP_GRAM_APPLY or GCT_OP_CG. */
+size_t gct_batch_workspace_size(const gct_batch *batch, int op, gct_dtype dtype);
+
+/* Packed Gram filters of every slice (as gct_gram_build per slice). */
+int gct_batch_gram_build(const gct_batch *batch, gct_dtype dtype, void *G, void *stream);
+
+/* Packed spectra of every slice (as gct_gram_spectrum per slice). */
+int gct_batch_gram_spectrum(const gct_batch *batch, gct_dtype dtype, const void *G, void *Ghat,
+                            void *ws, void *stream);
+
+/* y_i = H_i^T H_i c_i for every slice (as gct_gram_apply per slice). */
+int gct_batch_gram_apply(const gct_batch *batch, gct_dtype dtype, const void *Ghat, const void *c,
+                         void *y, void *ws, void *stream);
+
+/* CG from x_i = 0 on every slice to ||r_i|| <= rtol ||b_i|| (per slice) or
+ * max_iter iterations; converged slices stop while the others continue.
+ * results: HOST array of `slices` entries.  Returns GCT_OK if all slices
+ * converged, else GCT_ENOTCONV / GCT_EBREAKDOWN (see results[i].status).
+ * Chunks of check_every iterations (<= 0 selects 8) are replayed as a
+ * captured HIP graph.  BLOCKS the host until the solve is complete. */
+int gct_batch_cg_solve(const gct_batch *batch, gct_dtype dtype, const void *Ghat, const void *b,
+                       void *x, double rtol, int32_t max_iter, int32_t check_every,
+                       gct_cg_result *results, void *ws, void *stream);
+
+/* Autotuner: for each FFT size of the batch, times the batched apply with
+ * each candidate number of elements per thread of the transforms (the work
+ * tile of one thread) and keeps the fastest for `dtype`.  ws must be a CG
+ * workspace of the batch; reps timed repetitions per candidate (<= 0: 3).
+ * chosen: optional HOST array of `groups` entries receiving the choice.
+ * Blocks the host. */
+int gct_batch_autotune(gct_batch *batch, gct_dtype dtype, const void *Ghat, void *ws,
+                       int32_t reps, int32_t *chosen, void *stream);
+
 /* Thread-local description of the last error (never NULL). */
 const char *gct_last_error(void);
 

@@ -1,0 +1,794 @@
+// Batched uneven slices: many independent slices (each with its own plan:
+// N, angle set, blur) run through Gram-filter construction, Gram filtering
+// and CG together.  Every phase is ONE launch over all slices (per FFT size
+// for the transform passes), indexed through a block -> (slice, local index)
+// map, so the whole batch fills the GPU even when single slices cannot.
+// CG keeps per-slice state and status words: converged slices drop out
+// while the others continue; chunks of iterations are replayed as a hipGraph.
+// An autotuner picks, per FFT size, the elements per thread of the
+// transforms (the shape of the work tile) by timing the batched apply.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "fft_passes.h"
+
+namespace gct {
+
+template <typename T>
+hipError_t launch_batch_gram_build(const int2 *map, int nblocks, const BatchSlice *sl, T *G,
+                                   hipStream_t s);
+
+constexpr int BVB = 8;  // vector-kernel blocks per slice
+
+__device__ __forceinline__ bool slice_halted(const CGState *st, int s)
+{
+    return st && st[s].status != CG_RUNNING;
+}
+
+// ---------------------------------------------------------------------------
+// Batched transform passes
+// ---------------------------------------------------------------------------
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(256)
+kb_rows_fwd(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
+            const T *__restrict__ src, C2<T> *__restrict__ W1, const CGState *st, T *pupd)
+{
+    const int2 m = map[blockIdx.x];
+    if (slice_halted(st, m.x)) return;
+    const BatchSlice &d = sl[m.x];
+    constexpr int P = 1 << LOGP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    const C2<T> *tws =
+        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+    __syncthreads();
+    body_rows_fwd<T, LOGP, E>(2 * m.y, src + d.img, W1 + d.w, d.N, x, tws,
+                              pupd ? pupd + d.img : nullptr, pupd ? (T)st[m.x].beta : T(0));
+}
+
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(256)
+kb_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
+        const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat,
+        const CGState *st)
+{
+    const int2 m = map[blockIdx.x];
+    if (slice_halted(st, m.x)) return;
+    const BatchSlice &d = sl[m.x];
+    constexpr int P = 1 << LOGP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    const C2<T> *tws =
+        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+    __syncthreads();
+    body_cols<T, LOGP, E>(m.y, W1 + d.w, W2 + d.w, Ghat + d.spec, d.N, x, tws);
+}
+
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(256)
+kb_rows_inv(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
+            const C2<T> *__restrict__ W2, T *__restrict__ y, const CGState *st,
+            const T *__restrict__ dotv, double *__restrict__ partial)
+{
+    const int2 m = map[blockIdx.x];
+    if (slice_halted(st, m.x)) return;
+    const BatchSlice &d = sl[m.x];
+    constexpr int P = 1 << LOGP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    const C2<T> *tws =
+        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+    __syncthreads();
+    const double acc = body_rows_inv<T, LOGP, E>(2 * m.y, W2 + d.w, y + d.img, d.N, x, tws,
+                                                 dotv ? dotv + d.img : nullptr);
+    if (partial) {
+        const double s = block_sum_lds(acc, reinterpret_cast<double *>(smem_raw));
+        if (threadIdx.x == 0) partial[d.rpart + m.y] = s;
+    }
+}
+
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(256)
+kb_spec_rows(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
+             const T *__restrict__ G, C2<T> *__restrict__ R)
+{
+    const int2 m = map[blockIdx.x];
+    const BatchSlice &d = sl[m.x];
+    constexpr int P = 1 << LOGP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    const C2<T> *tws =
+        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+    __syncthreads();
+    // R of a slice uses (P/2+1) P complex, i.e. 2 d.spec reals' worth of offset
+    body_spec_rows<T, LOGP, E>(m.y, G + d.gram, R + d.spec, d.N, x, tws);
+}
+
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(256)
+kb_spec_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
+             const C2<T> *__restrict__ R, T *__restrict__ Ghat)
+{
+    const int2 m = map[blockIdx.x];
+    const BatchSlice &d = sl[m.x];
+    constexpr int P = 1 << LOGP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    const C2<T> *tws =
+        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+    __syncthreads();
+    body_spec_cols<T, LOGP, E>(m.y, R + d.spec, Ghat + d.spec, x, tws,
+                               T(1.0 / ((double)P * (double)P)));
+}
+
+// ---------------------------------------------------------------------------
+// Batched CG vector kernels: BVB blocks per slice, one block per slice for
+// the scalar steps.  Reductions run in a fixed order (deterministic).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double bsum(double v)
+{
+    __shared__ double red[256];
+    return block_sum_lds(v, red);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+kb_cg_init(const BatchSlice *__restrict__ sl, const T *__restrict__ b, T *__restrict__ x,
+           T *__restrict__ r, T *__restrict__ p, double *__restrict__ prr, double *__restrict__ pbb)
+{
+    const int s = blockIdx.x / BVB, j = blockIdx.x % BVB;
+    const BatchSlice &d = sl[s];
+    const size_t n = (size_t)d.N * d.N;
+    double rr = 0.0;
+    for (size_t i = (size_t)j * blockDim.x + threadIdx.x; i < n; i += (size_t)BVB * blockDim.x) {
+        const size_t g = d.img + i;
+        const T bi = b[g];
+        x[g] = T(0);
+        r[g] = bi;
+        p[g] = bi;
+        rr += (double)bi * (double)bi;
+    }
+    rr = bsum(rr);
+    if (threadIdx.x == 0) {
+        prr[blockIdx.x] = rr;
+        pbb[blockIdx.x] = rr;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+kb_cg_init_fin(CGState *st, const double *prr, double rtol2)
+{
+    const int s = blockIdx.x;
+    double v = threadIdx.x < BVB ? prr[s * BVB + threadIdx.x] : 0.0;
+    const double rr = bsum(v);
+    if (threadIdx.x == 0) {
+        CGState &c = st[s];
+        c.rr = rr;
+        c.bb = rr;
+        c.rr0 = rr;
+        c.beta = 0.0;
+        c.thr2 = rtol2 * rr;
+        c.k = 0;
+        c.ring[0] = rr;
+        c.status = (rr <= c.thr2) ? CG_CONVERGED : CG_RUNNING;
+        if (!(rr == rr)) c.status = CG_BREAKDOWN;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+kb_cg_update(CGState *st, const BatchSlice *__restrict__ sl, T *__restrict__ x,
+             T *__restrict__ r, const T *__restrict__ p, const T *__restrict__ Ap,
+             const double *__restrict__ rpart, double *__restrict__ upart)
+{
+    const int s = blockIdx.x / BVB, j = blockIdx.x % BVB;
+    if (st[s].status != CG_RUNNING) return;
+    const BatchSlice &d = sl[s];
+    double a = 0.0;
+    for (int i = threadIdx.x; i < d.nrow; i += blockDim.x) a += rpart[d.rpart + i];
+    const double pAp = bsum(a);
+    if (!(pAp > 0.0) || !(pAp < INFINITY)) {
+        if (j == 0 && threadIdx.x == 0) st[s].status = CG_BREAKDOWN;
+        return;
+    }
+    const double alpha = st[s].rr / pAp;
+    const T al = (T)alpha;
+    const size_t n = (size_t)d.N * d.N;
+    double rr = 0.0;
+    for (size_t i = (size_t)j * blockDim.x + threadIdx.x; i < n; i += (size_t)BVB * blockDim.x) {
+        const size_t g = d.img + i;
+        x[g] += al * p[g];
+        const T ri = r[g] - al * Ap[g];
+        r[g] = ri;
+        rr += (double)ri * (double)ri;
+    }
+    rr = bsum(rr);
+    if (threadIdx.x == 0) upart[blockIdx.x] = rr;
+}
+
+__global__ void __launch_bounds__(256) kb_cg_beta(CGState *st, const double *upart)
+{
+    const int s = blockIdx.x;
+    if (st[s].status != CG_RUNNING) return;
+    const double v = threadIdx.x < BVB ? upart[s * BVB + threadIdx.x] : 0.0;
+    const double rr = bsum(v);
+    if (threadIdx.x == 0) {
+        CGState &c = st[s];
+        const int64_t k = c.k + 1;
+        c.k = k;
+        c.ring[k % CG_RING] = rr;
+        c.beta = rr / c.rr;
+        c.rr = rr;
+        if (!(rr == rr)) c.status = CG_BREAKDOWN;
+        else if (rr <= c.thr2) c.status = CG_CONVERGED;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+kb_resid(const BatchSlice *__restrict__ sl, const T *__restrict__ b, const T *__restrict__ Ax,
+         double *__restrict__ part)
+{
+    const int s = blockIdx.x / BVB, j = blockIdx.x % BVB;
+    const BatchSlice &d = sl[s];
+    const size_t n = (size_t)d.N * d.N;
+    double acc = 0.0;
+    for (size_t i = (size_t)j * blockDim.x + threadIdx.x; i < n; i += (size_t)BVB * blockDim.x) {
+        const double e = (double)b[d.img + i] - (double)Ax[d.img + i];
+        acc += e * e;
+    }
+    acc = bsum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+__global__ void __launch_bounds__(256) kb_resid_fin(CGState *st, const double *part)
+{
+    const int s = blockIdx.x;
+    const double v = threadIdx.x < BVB ? part[s * BVB + threadIdx.x] : 0.0;
+    const double r = bsum(v);
+    if (threadIdx.x == 0) st[s].pad = r;
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch on (log2 P, E).  E candidates: fft_elems(P) and, for P >= 512,
+// fft_elems(P) / 2 (except P = 4096, which needs 16 at 256 threads).
+// ---------------------------------------------------------------------------
+static bool e_ok(int logP, int E)
+{
+    const int P = 1 << logP, E0 = fft_elems(P);
+    if (E == E0) return true;
+    return P >= 512 && P <= 2048 && E == E0 / 2;
+}
+
+#define GCT_BCASE(kern, T, LG, E, grid, lds, s, ...) \
+    hipLaunchKernelGGL((kern<T, LG, E>), grid, dim3((1 << LG) / E), lds, s, __VA_ARGS__)
+
+#define GCT_LAUNCH_B(kern, T, logP, E, grid, lds, s, ...)                                         \
+    do {                                                                                         \
+        switch (logP) {                                                                          \
+        case 2: GCT_BCASE(kern, T, 2, 4, grid, lds, s, __VA_ARGS__); break;                      \
+        case 3: GCT_BCASE(kern, T, 3, 4, grid, lds, s, __VA_ARGS__); break;                      \
+        case 4: GCT_BCASE(kern, T, 4, 4, grid, lds, s, __VA_ARGS__); break;                      \
+        case 5: GCT_BCASE(kern, T, 5, 4, grid, lds, s, __VA_ARGS__); break;                      \
+        case 6: GCT_BCASE(kern, T, 6, 4, grid, lds, s, __VA_ARGS__); break;                      \
+        case 7: GCT_BCASE(kern, T, 7, 4, grid, lds, s, __VA_ARGS__); break;                      \
+        case 8: GCT_BCASE(kern, T, 8, 4, grid, lds, s, __VA_ARGS__); break;                      \
+        case 9:                                                                                  \
+            if (E == 8) GCT_BCASE(kern, T, 9, 8, grid, lds, s, __VA_ARGS__);                     \
+            else GCT_BCASE(kern, T, 9, 4, grid, lds, s, __VA_ARGS__);                            \
+            break;                                                                               \
+        case 10:                                                                                 \
+            if (E == 16) GCT_BCASE(kern, T, 10, 16, grid, lds, s, __VA_ARGS__);                  \
+            else GCT_BCASE(kern, T, 10, 8, grid, lds, s, __VA_ARGS__);                           \
+            break;                                                                               \
+        case 11:                                                                                 \
+            if (E == 16) GCT_BCASE(kern, T, 11, 16, grid, lds, s, __VA_ARGS__);                  \
+            else GCT_BCASE(kern, T, 11, 8, grid, lds, s, __VA_ARGS__);                           \
+            break;                                                                               \
+        default: GCT_BCASE(kern, T, 12, 16, grid, lds, s, __VA_ARGS__); break;                   \
+        }                                                                                        \
+    } while (0)
+
+}  // namespace gct
+
+using namespace gct;
+
+// ---------------------------------------------------------------------------
+// Host batch object
+// ---------------------------------------------------------------------------
+struct BatchGroup {
+    int logP;
+    int E[2];  // tuned elements per thread, [f32, f64]
+    int2 *rows = nullptr, *cols = nullptr, *srows = nullptr, *scols = nullptr;
+    int nrows = 0, ncols = 0, nsrows = 0, nscols = 0;
+};
+
+struct gct_batch {
+    std::vector<const gct_plan *> plans;
+    int S = 0;
+    BatchSlice *dev[2] = {nullptr, nullptr};  // descriptors with f32 / f64 tables
+    std::vector<BatchSlice> host;             // (f32 variant)
+    int64_t img_total = 0, gram_total = 0, spec_total = 0, w_total = 0, rpart_total = 0;
+    std::vector<BatchGroup> groups;
+    int2 *gram_map = nullptr;
+    int ngram = 0;
+    std::vector<CGGraph> graphs;
+    hipStream_t capture_stream = nullptr;
+};
+
+namespace {
+
+int upload_map(int2 **dst, const std::vector<int2> &v)
+{
+    if (v.empty()) return GCT_OK;
+    hipError_t e = hipMalloc(dst, v.size() * sizeof(int2));
+    if (e != hipSuccess) return check_hip(e, "hipMalloc(batch map)");
+    return check_hip(hipMemcpy(*dst, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice),
+                     "hipMemcpy(batch map)");
+}
+
+void free_batch(gct_batch *b)
+{
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+    if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    for (auto &g : b->groups) {
+        for (int2 *m : {g.rows, g.cols, g.srows, g.scols})
+            if (m) (void)hipFree(m);
+    }
+    if (b->gram_map) (void)hipFree(b->gram_map);
+    for (int i = 0; i < 2; ++i)
+        if (b->dev[i]) (void)hipFree(b->dev[i]);
+    delete b;
+}
+
+// workspace layout for the batched operations
+struct BLayout {
+    size_t W1, W2, R, r, p, Ap, rpart, upart, upart2, st, total;
+};
+
+BLayout blayout(const gct_batch *b, size_t elem)
+{
+    BLayout L{};
+    size_t o = 0;
+    L.W1 = o; o += align256((size_t)b->w_total * 2 * elem);
+    L.W2 = o; o += align256((size_t)b->w_total * 2 * elem);
+    L.R = L.W1;  // the spectrum scratch ((P/2+1) P complex per slice) reuses the start
+    const size_t spec_scratch = align256((size_t)b->spec_total * 2 * elem);
+    size_t apply_end = o;
+    size_t cg_base = std::max(apply_end, spec_scratch);
+    o = cg_base;
+    L.r = o; o += align256((size_t)b->img_total * elem);
+    L.p = o; o += align256((size_t)b->img_total * elem);
+    L.Ap = o; o += align256((size_t)b->img_total * elem);
+    L.rpart = o; o += align256((size_t)b->rpart_total * sizeof(double));
+    L.upart = o; o += align256((size_t)b->S * BVB * sizeof(double));
+    L.upart2 = o; o += align256((size_t)b->S * BVB * sizeof(double));
+    L.st = o; o += align256((size_t)b->S * sizeof(CGState));
+    L.total = o;
+    return L;
+}
+
+template <typename T>
+int dti() { return sizeof(T) == 4 ? 0 : 1; }
+
+template <typename T>
+hipError_t batch_apply_passes(const gct_batch *b, const T *Ghat, const T *src, T *y, void *ws,
+                              hipStream_t s, const CGState *st, T *pupd, const T *dotv,
+                              double *partial)
+{
+    const BLayout L = blayout(b, sizeof(T));
+    char *w = reinterpret_cast<char *>(ws);
+    C2<T> *W1 = reinterpret_cast<C2<T> *>(w + L.W1), *W2 = reinterpret_cast<C2<T> *>(w + L.W2);
+    const BatchSlice *sl = b->dev[dti<T>()];
+    for (const auto &g : b->groups) {
+        const int E = g.E[dti<T>()];
+        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
+        GCT_LAUNCH_B(kb_rows_fwd, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, src, W1, st, pupd);
+    }
+    for (const auto &g : b->groups) {
+        const int E = g.E[dti<T>()];
+        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
+        GCT_LAUNCH_B(kb_cols, T, g.logP, E, dim3(g.ncols), lds, s, g.cols, sl, W1, W2, Ghat, st);
+    }
+    for (const auto &g : b->groups) {
+        const int E = g.E[dti<T>()];
+        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
+        GCT_LAUNCH_B(kb_rows_inv, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, W2, y, st, dotv,
+                     partial);
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t batch_spectrum(const gct_batch *b, const T *G, T *Ghat, void *ws, hipStream_t s)
+{
+    const BLayout L = blayout(b, sizeof(T));
+    C2<T> *R = reinterpret_cast<C2<T> *>(reinterpret_cast<char *>(ws) + L.R);
+    const BatchSlice *sl = b->dev[dti<T>()];
+    for (const auto &g : b->groups) {
+        const int E = g.E[dti<T>()];
+        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
+        GCT_LAUNCH_B(kb_spec_rows, T, g.logP, E, dim3(g.nsrows), lds, s, g.srows, sl, G, R);
+    }
+    for (const auto &g : b->groups) {
+        const int E = g.E[dti<T>()];
+        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
+        GCT_LAUNCH_B(kb_spec_cols, T, g.logP, E, dim3(g.nscols), lds, s, g.scols, sl, R, Ghat);
+    }
+    return hipGetLastError();
+}
+
+#define B_TRY(call)                                          \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) return check_hip(e_, #call);   \
+    } while (0)
+
+template <typename T>
+int batch_cg(const gct_batch *b, const T *Ghat, const T *bv, T *x, double rtol, int max_iter,
+             int check_every, gct_cg_result *res, void *ws, hipStream_t s)
+{
+    const BLayout L = blayout(b, sizeof(T));
+    char *w = reinterpret_cast<char *>(ws);
+    T *r = reinterpret_cast<T *>(w + L.r), *p = reinterpret_cast<T *>(w + L.p);
+    T *Ap = reinterpret_cast<T *>(w + L.Ap);
+    double *rpart = reinterpret_cast<double *>(w + L.rpart);
+    double *upart = reinterpret_cast<double *>(w + L.upart);
+    double *upart2 = reinterpret_cast<double *>(w + L.upart2);
+    CGState *st = reinterpret_cast<CGState *>(w + L.st);
+    const BatchSlice *sl = b->dev[dti<T>()];
+    const int S = b->S;
+    if (check_every <= 0) check_every = 8;
+    hipLaunchKernelGGL(kb_cg_init<T>, dim3(S * BVB), dim3(256), 0, s, sl, bv, x, r, p, upart, upart2);
+    hipLaunchKernelGGL(kb_cg_init_fin, dim3(S), dim3(256), 0, s, st, upart, rtol * rtol);
+    B_TRY(hipGetLastError());
+    std::vector<CGState> hs(S);
+    auto pull = [&]() -> int {
+        B_TRY(hipMemcpyAsync(hs.data(), st, S * sizeof(CGState), hipMemcpyDeviceToHost, s));
+        B_TRY(hipStreamSynchronize(s));
+        return GCT_OK;
+    };
+    auto running = [&]() {
+        for (const auto &c : hs)
+            if (c.status == CG_RUNNING) return true;
+        return false;
+    };
+    int rc = pull();
+    if (rc) return rc;
+    auto launch_iters = [&](int count, hipStream_t st_) -> hipError_t {
+        for (int i = 0; i < count; ++i) {
+            hipError_t e = batch_apply_passes<T>(b, Ghat, r, Ap, ws, st_, st, p, p, rpart);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kb_cg_update<T>, dim3(S * BVB), dim3(256), 0, st_, st, sl, x, r, p,
+                               Ap, rpart, upart);
+            hipLaunchKernelGGL(kb_cg_beta, dim3(S), dim3(256), 0, st_, st, upart);
+        }
+        return hipGetLastError();
+    };
+    int64_t done = 0;
+    while (running() && done < max_iter) {
+        const int chunk = (int)std::min<int64_t>(check_every, max_iter - done);
+        if (chunk == check_every) {
+            const CGGraphKey key{(const void *)Ghat, (const void *)bv, (void *)x, ws, (int)sizeof(T),
+                                 chunk};
+            hipGraphExec_t exec = nullptr;
+            for (const auto &g : b->graphs)
+                if (g.key == key) exec = g.exec;
+            if (!exec) {
+                gct_batch *mb = const_cast<gct_batch *>(b);
+                if (!mb->capture_stream &&
+                    hipStreamCreateWithFlags(&mb->capture_stream, hipStreamNonBlocking) != hipSuccess)
+                    return fail(GCT_EHIP, "cannot create the capture stream");
+                B_TRY(hipStreamBeginCapture(mb->capture_stream, hipStreamCaptureModeThreadLocal));
+                hipError_t e = launch_iters(chunk, mb->capture_stream);
+                hipGraph_t gr = nullptr;
+                hipError_t e2 = hipStreamEndCapture(mb->capture_stream, &gr);
+                if (e != hipSuccess || e2 != hipSuccess) {
+                    if (gr) (void)hipGraphDestroy(gr);
+                    return check_hip(e != hipSuccess ? e : e2, "batch cg graph capture");
+                }
+                e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(gr);
+                if (e != hipSuccess) return check_hip(e, "hipGraphInstantiate");
+                if (mb->graphs.size() >= 8) {
+                    (void)hipGraphExecDestroy(mb->graphs.front().exec);
+                    mb->graphs.erase(mb->graphs.begin());
+                }
+                mb->graphs.push_back({key, exec});
+            }
+            B_TRY(hipGraphLaunch(exec, s));
+        } else {
+            B_TRY(launch_iters(chunk, s));
+        }
+        if ((rc = pull())) return rc;
+        done += chunk;
+    }
+    // true residuals of the returned iterates
+    B_TRY(batch_apply_passes<T>(b, Ghat, x, Ap, ws, s, nullptr, nullptr, nullptr, nullptr));
+    hipLaunchKernelGGL(kb_resid<T>, dim3(S * BVB), dim3(256), 0, s, sl, bv, Ap, upart);
+    hipLaunchKernelGGL(kb_resid_fin, dim3(S), dim3(256), 0, s, st, upart);
+    B_TRY(hipGetLastError());
+    if ((rc = pull())) return rc;
+    int worst = GCT_OK;
+    for (int i = 0; i < S; ++i) {
+        const CGState &c = hs[i];
+        auto rel = [&](double v) { return c.bb > 0.0 ? std::sqrt(v / c.bb) : 0.0; };
+        gct_cg_result &o = res[i];
+        o.iters = (int32_t)c.k;
+        o.rel_res = rel(c.rr);
+        o.rel_res_true = rel(c.pad);
+        o.rel_res0 = rel(c.rr0);
+        o.fell_back = 0;
+        o.status = c.status == CG_CONVERGED ? GCT_OK
+                   : c.status == CG_BREAKDOWN ? GCT_EBREAKDOWN
+                                              : GCT_ENOTCONV;
+        if (o.status == GCT_EBREAKDOWN) worst = GCT_EBREAKDOWN;
+        else if (o.status == GCT_ENOTCONV && worst == GCT_OK) worst = GCT_ENOTCONV;
+    }
+    return worst;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **out)
+{
+    if (!out) return fail(GCT_EINVAL, "batch output pointer is NULL");
+    *out = nullptr;
+    if (!plans || count < 1) return fail(GCT_EINVAL, "need at least one plan");
+    for (int i = 0; i < count; ++i)
+        if (!plans[i]) return fail(GCT_EINVAL, "NULL plan in batch");
+    gct_batch *b = new gct_batch();
+    b->plans.assign(plans, plans + count);
+    b->S = count;
+    std::map<int, std::vector<int>> by_p;
+    b->host.resize(count);
+    for (int i = 0; i < count; ++i) {
+        const gct_plan *p = plans[i];
+        BatchSlice d{};
+        d.N = p->N;
+        d.logP = p->logP;
+        d.n = p->n;
+        d.nrow = (p->N + 1) / 2;
+        d.img = b->img_total;
+        b->img_total += (int64_t)p->N * p->N;
+        d.gram = b->gram_total;
+        b->gram_total += (int64_t)(2 * p->N - 1) * (2 * p->N - 1);
+        d.spec = b->spec_total;
+        b->spec_total += (int64_t)(p->P / 2 + 1) * p->P;
+        d.w = b->w_total;
+        b->w_total += (int64_t)(p->P / 2 + 1) * p->N;
+        d.rpart = b->rpart_total;
+        b->rpart_total += d.nrow;
+        b->host[i] = d;
+        by_p[p->logP].push_back(i);
+    }
+    // descriptors with the f32 and f64 tables of each plan
+    for (int t = 0; t < 2; ++t) {
+        std::vector<BatchSlice> v = b->host;
+        for (int i = 0; i < count; ++i) {
+            v[i].ga = t == 0 ? plans[i]->dev.gram_f32 : plans[i]->dev.gram_f64;
+            v[i].tw = t == 0 ? plans[i]->dev.tw_f32 : plans[i]->dev.tw_f64;
+        }
+        hipError_t e = hipMalloc(&b->dev[t], count * sizeof(BatchSlice));
+        if (e == hipSuccess)
+            e = hipMemcpy(b->dev[t], v.data(), count * sizeof(BatchSlice), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_batch(b);
+            return check_hip(e, "batch descriptors");
+        }
+    }
+    // block maps per FFT size
+    for (auto &kv : by_p) {
+        BatchGroup g;
+        g.logP = kv.first;
+        const int P = 1 << g.logP;
+        g.E[0] = g.E[1] = fft_elems(P);
+        std::vector<int2> rows, cols, srows, scols;
+        for (int i : kv.second) {
+            const int N = plans[i]->N;
+            for (int k = 0; k < (N + 1) / 2; ++k) rows.push_back(make_int2(i, k));
+            for (int k = 0; k <= P / 2; ++k) cols.push_back(make_int2(i, k));
+            for (int k = 0; k < P / 2; ++k) srows.push_back(make_int2(i, k));
+            for (int k = 0; k <= P / 2; ++k) scols.push_back(make_int2(i, k));
+        }
+        g.nrows = (int)rows.size();
+        g.ncols = (int)cols.size();
+        g.nsrows = (int)srows.size();
+        g.nscols = (int)scols.size();
+        int rc = GCT_OK;
+        if (!rc) rc = upload_map(&g.rows, rows);
+        if (!rc) rc = upload_map(&g.cols, cols);
+        if (!rc) rc = upload_map(&g.srows, srows);
+        if (!rc) rc = upload_map(&g.scols, scols);
+        b->groups.push_back(g);
+        if (rc) {
+            free_batch(b);
+            return rc;
+        }
+    }
+    std::vector<int2> gm;
+    for (int i = 0; i < count; ++i) {
+        const int N = plans[i]->N;
+        const int tiles = ((2 * N - 1 + 15) / 16) * ((N + 15) / 16);
+        for (int k = 0; k < tiles; ++k) gm.push_back(make_int2(i, k));
+    }
+    b->ngram = (int)gm.size();
+    int rc = upload_map(&b->gram_map, gm);
+    if (rc) {
+        free_batch(b);
+        return rc;
+    }
+    *out = b;
+    return GCT_OK;
+}
+
+int gct_batch_destroy(gct_batch *b)
+{
+    if (b) free_batch(b);
+    return GCT_OK;
+}
+
+int gct_batch_get_info(const gct_batch *b, gct_batch_info *info, int64_t *image_offsets,
+                       int64_t *gram_offsets, int64_t *spectrum_offsets)
+{
+    if (!b || !info) return fail(GCT_EINVAL, "NULL argument");
+    info->slices = b->S;
+    info->groups = (int32_t)b->groups.size();
+    info->image_elems = b->img_total;
+    info->gram_elems = b->gram_total;
+    info->spectrum_elems = b->spec_total;
+    for (int i = 0; i < b->S; ++i) {
+        if (image_offsets) image_offsets[i] = b->host[i].img;
+        if (gram_offsets) gram_offsets[i] = b->host[i].gram;
+        if (spectrum_offsets) spectrum_offsets[i] = b->host[i].spec;
+    }
+    return GCT_OK;
+}
+
+size_t gct_batch_workspace_size(const gct_batch *b, int op, gct_dtype dt)
+{
+    if (!b) return 0;
+    const BLayout L = blayout(b, dt == GCT_F64 ? 8 : 4);
+    switch (op) {
+    case GCT_OP_GRAM_SPECTRUM: return align256((size_t)b->spec_total * 2 * (dt == GCT_F64 ? 8 : 4));
+    case GCT_OP_GRAM_APPLY: return L.W2 + align256((size_t)b->w_total * 2 * (dt == GCT_F64 ? 8 : 4));
+    case GCT_OP_CG: return L.total;
+    default: return 0;
+    }
+}
+
+#define CHECK_BATCH_DT(b, dt)                                                         \
+    do {                                                                              \
+        if (!(b)) return fail(GCT_EINVAL, "batch is NULL");                           \
+        if ((dt) != GCT_F32 && (dt) != GCT_F64) return fail(GCT_EINVAL, "bad dtype"); \
+    } while (0)
+
+int gct_batch_gram_build(const gct_batch *b, gct_dtype dt, void *G, void *stream)
+{
+    CHECK_BATCH_DT(b, dt);
+    if (!G) return fail(GCT_EINVAL, "G is NULL");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = dt == GCT_F32
+                       ? launch_batch_gram_build<float>(b->gram_map, b->ngram, b->dev[0], (float *)G, s)
+                       : launch_batch_gram_build<double>(b->gram_map, b->ngram, b->dev[1], (double *)G, s);
+    return check_hip(e, "batch gram_build launch");
+}
+
+int gct_batch_gram_spectrum(const gct_batch *b, gct_dtype dt, const void *G, void *Ghat, void *ws,
+                            void *stream)
+{
+    CHECK_BATCH_DT(b, dt);
+    if (!G || !Ghat || !ws) return fail(GCT_EINVAL, "NULL buffer");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = dt == GCT_F32 ? batch_spectrum<float>(b, (const float *)G, (float *)Ghat, ws, s)
+                                 : batch_spectrum<double>(b, (const double *)G, (double *)Ghat, ws, s);
+    return check_hip(e, "batch gram_spectrum launch");
+}
+
+int gct_batch_gram_apply(const gct_batch *b, gct_dtype dt, const void *Ghat, const void *c,
+                         void *y, void *ws, void *stream)
+{
+    CHECK_BATCH_DT(b, dt);
+    if (!Ghat || !c || !y || !ws) return fail(GCT_EINVAL, "NULL buffer");
+    if (c == y) return fail(GCT_EINVAL, "y must not alias c");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    hipError_t e = dt == GCT_F32
+                       ? batch_apply_passes<float>(b, (const float *)Ghat, (const float *)c, (float *)y,
+                                                   ws, s, nullptr, nullptr, nullptr, nullptr)
+                       : batch_apply_passes<double>(b, (const double *)Ghat, (const double *)c,
+                                                    (double *)y, ws, s, nullptr, nullptr, nullptr,
+                                                    nullptr);
+    return check_hip(e, "batch gram_apply launch");
+}
+
+int gct_batch_cg_solve(const gct_batch *b, gct_dtype dt, const void *Ghat, const void *bv, void *x,
+                       double rtol, int32_t max_iter, int32_t check_every, gct_cg_result *results,
+                       void *ws, void *stream)
+{
+    CHECK_BATCH_DT(b, dt);
+    if (!Ghat || !bv || !x || !ws || !results) return fail(GCT_EINVAL, "NULL argument");
+    if (bv == x) return fail(GCT_EINVAL, "x must not alias b");
+    if (max_iter < 0 || !(rtol >= 0.0)) return fail(GCT_EINVAL, "bad max_iter or rtol");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int rc = dt == GCT_F32 ? batch_cg<float>(b, (const float *)Ghat, (const float *)bv, (float *)x,
+                                             rtol, max_iter, check_every, results, ws, s)
+                           : batch_cg<double>(b, (const double *)Ghat, (const double *)bv,
+                                              (double *)x, rtol, max_iter, check_every, results, ws, s);
+    if (rc == GCT_ENOTCONV) set_error("batch cg_solve: some slices reached max_iter");
+    if (rc == GCT_EBREAKDOWN) set_error("batch cg_solve: breakdown in some slice");
+    return rc;
+}
+
+int gct_batch_autotune(gct_batch *b, gct_dtype dt, const void *Ghat, void *ws, int32_t reps,
+                       int32_t *chosen, void *stream)
+{
+    CHECK_BATCH_DT(b, dt);
+    if (!Ghat || !ws) return fail(GCT_EINVAL, "NULL buffer");
+    if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    if (reps < 1) reps = 3;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const int t = dt == GCT_F32 ? 0 : 1;
+    const size_t elem = t == 0 ? 4 : 8;
+    const BLayout L = blayout(b, elem);
+    char *w = reinterpret_cast<char *>(ws);
+    void *src = w + L.r, *dst = w + L.Ap;
+    B_TRY(hipMemsetAsync(src, 0, (size_t)b->img_total * elem, s));
+    hipEvent_t e0, e1;
+    B_TRY(hipEventCreate(&e0));
+    B_TRY(hipEventCreate(&e1));
+    // tune one group at a time, the others keep their current choice; each
+    // candidate is timed on the whole batched apply
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        BatchGroup &g = b->groups[gi];
+        const int P = 1 << g.logP, E0 = fft_elems(P);
+        int best = g.E[t];
+        float best_ms = 1e30f;
+        for (int E : {E0, E0 / 2}) {
+            if (E < 4 || !e_ok(g.logP, E)) continue;
+            g.E[t] = E;
+            for (int rep = 0; rep <= reps; ++rep) {
+                if (rep == 1) B_TRY(hipEventRecord(e0, s));
+                hipError_t e = t == 0 ? batch_apply_passes<float>(b, (const float *)Ghat, (const float *)src,
+                                                                  (float *)dst, ws, s, nullptr, nullptr,
+                                                                  nullptr, nullptr)
+                                      : batch_apply_passes<double>(b, (const double *)Ghat,
+                                                                   (const double *)src, (double *)dst, ws,
+                                                                   s, nullptr, nullptr, nullptr, nullptr);
+                B_TRY(e);
+            }
+            B_TRY(hipEventRecord(e1, s));
+            B_TRY(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            B_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = E;
+            }
+        }
+        g.E[t] = best;
+        if (chosen) chosen[gi] = best;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // captured CG graphs used the old shapes
+    for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
+    b->graphs.clear();
+    return GCT_OK;
+}
+
+}  // extern "C"

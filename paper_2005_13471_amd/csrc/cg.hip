@@ -18,16 +18,7 @@ hipError_t launch_apply_passes(const gct_plan *p, const T *Ghat, const T *src, T
                                const T *dotv, double *partial);
 int apply_row_blocks(const gct_plan *p, size_t elem);
 
-constexpr int CG_RING = 64;
 constexpr int VBLK = 256;  // blocks of the vector kernels (fixed: deterministic reductions)
-
-enum : int64_t { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
-
-struct CGState {
-    double rr, bb, rr0, pAp, alpha, beta, thr2, pad;
-    int64_t k, status, pad2, pad3;
-    double ring[CG_RING];  // ||r_k||^2 at ring[k % CG_RING]
-};
 
 __device__ __forceinline__ double block_sum(double v)
 {

@@ -1,0 +1,237 @@
+// Device bodies of the Gram-filtering passes (rows forward, columns,
+// rows inverse) and of the spectrum passes, shared by the single-slice and
+// the batched kernels.  Each body processes one transform with the P/E
+// threads of its block; twiddles must be staged (stage_twiddles) and the
+// block synchronised before the first body call.
+#pragma once
+
+#include "fft_common.h"
+#include "gct_internal.h"
+
+namespace gct {
+
+// Twiddles go to LDS after the data area when both fit in 64 KB, else they
+// are read from the plan's global table.
+template <typename T>
+__host__ __device__ constexpr bool twiddles_in_lds(int P)
+{
+    return (size_t)(P + P / 2) * sizeof(C2<T>) <= 65536;
+}
+
+template <typename T, bool TWL>
+__device__ __forceinline__ const C2<T> *stage_twiddles(C2<T> *lds_after_data,
+                                                       const C2<T> *__restrict__ tw, int hP)
+{
+    if (!TWL) return tw;
+    for (int i = threadIdx.x; i < hP; i += blockDim.x) lds_after_data[i] = tw[i];
+    return lds_after_data;
+}
+
+// Rows forward: real FFT of image rows ra and ra+1 (one complex transform),
+// written transposed as W1[k][row], k in [0, P/2].  With pupd, the rows are
+// first updated in place as p = src + bt * p (CG direction update).
+template <typename T, int LOGP, int E>
+__device__ __forceinline__ void body_rows_fwd(int ra, const T *__restrict__ src,
+                                              C2<T> *__restrict__ W1, int N, C2<T> *x,
+                                              const C2<T> *tws, T *pupd, T bt)
+{
+    constexpr int P = 1 << LOGP, hP = P >> 1, G = P / E;
+    const int t = threadIdx.x;
+    const int rb = ra + 1;
+    C2<T> v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = t + G * q;
+        T re = 0, im = 0;
+        if (n < N) {
+            const size_t ia = (size_t)ra * N + n, ib = (size_t)rb * N + n;
+            re = src[ia];
+            if (rb < N) im = src[ib];
+            if (pupd) {
+                re += bt * pupd[ia];
+                pupd[ia] = re;
+                if (rb < N) {
+                    im += bt * pupd[ib];
+                    pupd[ib] = im;
+                }
+            }
+        }
+        v[q] = {re, im};
+    }
+    fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
+    // split the two real rows: Xa = (Z[k] + conj Z[-k])/2, Xb = (Z[k] - conj Z[-k])/(2i)
+#pragma unroll
+    for (int q = 0; q < E; ++q) x[t + G * q] = v[q];
+    __syncthreads();
+    for (int k = t; k <= hP; k += G) {
+        const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
+        W1[(size_t)k * N + ra] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
+        if (rb < N) W1[(size_t)k * N + rb] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+    }
+    __syncthreads();  // x may be reused by the caller
+}
+
+// Columns: FFT along k2 of column col (N nonzero of P), times the real
+// spectrum, inverse FFT (in registers between the two), first N entries.
+template <typename T, int LOGP, int E>
+__device__ __forceinline__ void body_cols(int col, const C2<T> *__restrict__ W1,
+                                          C2<T> *__restrict__ W2, const T *__restrict__ Ghat,
+                                          int N, C2<T> *x, const C2<T> *tws)
+{
+    constexpr int P = 1 << LOGP, G = P / E;
+    const int t = threadIdx.x;
+    const C2<T> *in = W1 + (size_t)col * N;
+    const T *g = Ghat + (size_t)col * P;
+    C2<T> v[E];
+    T gs[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = t + G * q;
+        v[q] = n < N ? in[n] : C2<T>{T(0), T(0)};
+        gs[q] = g[n];
+    }
+    fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = {v[q].x * gs[q], v[q].y * gs[q]};
+    fft_passes<T, E, P, 1, true, true>(v, x, t, tws);
+    C2<T> *out = W2 + (size_t)col * N;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = t + G * q;
+        if (n < N) out[n] = v[q];
+    }
+}
+
+// Rows inverse: Hermitian row spectra of rows ra, ra+1 -> one complex
+// inverse FFT -> two real rows of y.  Returns this thread's FP64 partial of
+// dotv . y over the two rows (0 if dotv is null).
+template <typename T, int LOGP, int E>
+__device__ __forceinline__ double body_rows_inv(int ra, const C2<T> *__restrict__ W2,
+                                                T *__restrict__ y, int N, C2<T> *x,
+                                                const C2<T> *tws, const T *__restrict__ dotv)
+{
+    constexpr int P = 1 << LOGP, hP = P >> 1, G = P / E;
+    const int t = threadIdx.x;
+    const int rb = ra + 1;
+    C2<T> v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int k = t + G * q;
+        const int kk = k <= hP ? k : P - k;  // Hermitian extension
+        C2<T> Ya = W2[(size_t)kk * N + ra];
+        C2<T> Yb = rb < N ? W2[(size_t)kk * N + rb] : C2<T>{T(0), T(0)};
+        if (k > hP) {
+            Ya.y = -Ya.y;
+            Yb.y = -Yb.y;
+        }
+        v[q] = {Ya.x - Yb.y, Ya.y + Yb.x};
+    }
+    fft_passes<T, E, P, 1, true, true>(v, x, t, tws);
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = t + G * q;
+        if (n >= N) continue;
+        y[(size_t)ra * N + n] = v[q].x;
+        if (dotv) acc += (double)dotv[(size_t)ra * N + n] * (double)v[q].x;
+        if (rb < N) {
+            y[(size_t)rb * N + n] = v[q].y;
+            if (dotv) acc += (double)dotv[(size_t)rb * N + n] * (double)v[q].y;
+        }
+    }
+    return acc;
+}
+
+// Block-wide FP64 sum through an LDS area of blockDim doubles (all threads
+// call it; the area is free again on return).
+__device__ __forceinline__ double block_sum_lds(double v, double *red)
+{
+    __syncthreads();
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Spectrum of the circulant embedding of G.  Embedded position q in [0, P)
+// holds tap q (q <= N-1) or q - P (q >= P-N+1); other positions are zero.
+// ---------------------------------------------------------------------------
+constexpr int NO_TAP = 1 << 30;
+__device__ __forceinline__ int embed_tap(int q, int N, int P)
+{
+    if (q <= N - 1) return q;
+    if (q >= P - N + 1) return q - P;
+    return NO_TAP;
+}
+
+// embedded rows 2 seq and 2 seq + 1 -> R[k][row], k in [0, P/2]
+template <typename T, int LOGP, int E>
+__device__ __forceinline__ void body_spec_rows(int seq, const T *__restrict__ G,
+                                               C2<T> *__restrict__ R, int N, C2<T> *x,
+                                               const C2<T> *tws)
+{
+    constexpr int P = 1 << LOGP, hP = P >> 1, Gt = P / E;
+    const int t = threadIdx.x, W = 2 * N - 1;
+    const int ka = embed_tap(2 * seq, N, P), kb = embed_tap(2 * seq + 1, N, P);
+    C2<T> v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int k1 = embed_tap(t + Gt * q, N, P);
+        T re = 0, im = 0;
+        if (k1 != NO_TAP) {
+            if (ka != NO_TAP) re = G[(size_t)(ka + N - 1) * W + (k1 + N - 1)];
+            if (kb != NO_TAP) im = G[(size_t)(kb + N - 1) * W + (k1 + N - 1)];
+        }
+        v[q] = {re, im};
+    }
+    fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
+#pragma unroll
+    for (int q = 0; q < E; ++q) x[t + Gt * q] = v[q];
+    __syncthreads();
+    for (int k = t; k <= hP; k += Gt) {
+        const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
+        R[(size_t)k * P + 2 * seq] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
+        R[(size_t)k * P + 2 * seq + 1] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+    }
+    __syncthreads();
+}
+
+// column k of R -> Ghat[k][.] = Re FFT / P^2
+template <typename T, int LOGP, int E>
+__device__ __forceinline__ void body_spec_cols(int col, const C2<T> *__restrict__ R,
+                                               T *__restrict__ Ghat, C2<T> *x, const C2<T> *tws,
+                                               T scale)
+{
+    constexpr int P = 1 << LOGP, Gt = P / E;
+    const int t = threadIdx.x;
+    C2<T> v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) v[q] = R[(size_t)col * P + t + Gt * q];
+    fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
+#pragma unroll
+    for (int q = 0; q < E; ++q) Ghat[(size_t)col * P + t + Gt * q] = v[q].x * scale;
+}
+
+// LDS bytes of a pass kernel: data (P) + twiddles (P/2, when in LDS), at
+// least blockDim doubles for the reductions.
+template <typename T>
+inline size_t fft_lds_bytes(int P, int E)
+{
+    size_t b = (size_t)P * sizeof(C2<T>) + (twiddles_in_lds<T>(P) ? (size_t)(P / 2) * sizeof(C2<T>) : 0);
+    const size_t red = (size_t)(P / E) * sizeof(double);
+    return b > red ? b : red;
+}
+
+// Valid (log2 P, E) pairs: E in {4, 8, 16}, E <= P, at most 256 threads.
+__host__ __device__ constexpr bool fft_combo_ok(int logP, int E)
+{
+    return E <= (1 << logP) && ((1 << logP) / E) <= 256 && logP >= 2 && logP <= 12;
+}
+
+}  // namespace gct

@@ -82,6 +82,27 @@ struct DeviceTables {
     void *deg = nullptr;                              // int32[n]: B-spline degree per angle
 };
 
+// Device-resident CG state (cg.hip, batch.hip).
+constexpr int CG_RING = 64;
+enum : int64_t { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
+
+struct CGState {
+    double rr, bb, rr0, pAp, alpha, beta, thr2, pad;
+    int64_t k, status, pad2, pad3;
+    double ring[CG_RING];  // ||r_k||^2 at ring[k % CG_RING]
+};
+
+// One slice of a batch (device descriptor).  Offsets are in elements of the
+// packed arrays: image arrays (N^2 per slice), Gram filters ((2N-1)^2),
+// spectra ((P/2+1) P reals) and Gram-filtering scratch ((P/2+1) N complex).
+struct BatchSlice {
+    int32_t N, logP, n, nrow;   // nrow = ceil(N/2) row pairs
+    int64_t img, gram, spec, w;
+    int64_t rpart;              // first row-pair partial of this slice
+    const void *ga;             // GramAngle<T> table of the slice's plan
+    const void *tw;             // twiddles of the slice's plan
+};
+
 // Key of a captured chunk of CG iterations.
 struct CGGraphKey {
     const void *Ghat, *b;

@@ -16,8 +16,7 @@
 // owns one transform (a single wave for P = 1024).
 #include <algorithm>
 
-#include "fft_common.h"
-#include "gct_internal.h"
+#include "fft_passes.h"
 
 namespace gct {
 
@@ -26,248 +25,83 @@ namespace gct {
 // launch.
 __device__ __forceinline__ bool halted(const int64_t *status) { return status && *status != 0; }
 
-// Twiddles go to LDS after the data area when both fit in 64 KB, else they
-// are read from the plan's global table.
-template <typename T>
-__host__ __device__ constexpr bool twiddles_in_lds(int P)
-{
-    return (size_t)(P + P / 2) * sizeof(C2<T>) <= 65536;
-}
-
-template <typename T, bool TWL>
-__device__ __forceinline__ const C2<T> *stage_twiddles(C2<T> *lds_after_data,
-                                                       const C2<T> *__restrict__ tw, int hP)
-{
-    if (!TWL) return tw;
-    for (int i = threadIdx.x; i < hP; i += blockDim.x) lds_after_data[i] = tw[i];
-    return lds_after_data;
-}
-
-// One transform per block: G = P/E threads, thread t holds x[t + G q].
-// ---------------------------------------------------------------------------
-// Pass 1: forward real FFT of a pair of image rows.  With `pupd` set (CG),
-// the rows are first updated in place as p = r + beta p (beta from *beta).
-// ---------------------------------------------------------------------------
+// One transform per block, P/E threads, E = fft_elems(P).
 template <typename T, int LOGP>
 __global__ void __launch_bounds__(256)
-k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N,
-           const C2<T> *__restrict__ tw, const int64_t *status, T *pupd, const double *beta)
+k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, const C2<T> *__restrict__ tw,
+           const int64_t *status, T *pupd, const double *beta)
 {
     if (halted(status)) return;
+    constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int P = 1 << LOGP, hP = P >> 1, E = fft_elems(P), G = P / E;
-    constexpr bool TWL = twiddles_in_lds<T>(P);
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const int t = threadIdx.x;
-    const int ra = 2 * blockIdx.x, rb = ra + 1;
-    const T bt = pupd ? (T)(*beta) : T(0);
-    C2<T> v[E];
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int n = t + G * q;
-        T re = 0, im = 0;
-        if (n < N) {
-            const size_t ia = (size_t)ra * N + n, ib = (size_t)rb * N + n;
-            re = src[ia];
-            if (rb < N) im = src[ib];
-            if (pupd) {
-                re += bt * pupd[ia];
-                pupd[ia] = re;
-                if (rb < N) {
-                    im += bt * pupd[ib];
-                    pupd[ib] = im;
-                }
-            }
-        }
-        v[q] = {re, im};
-    }
-    const C2<T> *tws = stage_twiddles<T, TWL>(x + P, tw, hP);
-    if (TWL) __syncthreads();
-    fft_strided<T, LOGP, false>(v, x, t, tws);
-    // split the two real rows: Xa = (Z[k] + conj Z[-k])/2, Xb = (Z[k] - conj Z[-k])/(2i)
-#pragma unroll
-    for (int q = 0; q < E; ++q) x[t + G * q] = v[q];
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
     __syncthreads();
-    for (int k = t; k <= hP; k += G) {
-        const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
-        W1[(size_t)k * N + ra] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
-        if (rb < N) W1[(size_t)k * N + rb] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
-    }
+    body_rows_fwd<T, LOGP, fft_elems(P)>(2 * blockIdx.x, src, W1, N, x, tws, pupd,
+                                         pupd ? (T)(*beta) : T(0));
 }
 
-// ---------------------------------------------------------------------------
-// Pass 2: per frequency column w1: FFT along k2, multiply by the real
-// spectrum, inverse FFT (all in registers between the two), keep the first
-// N entries.
-// ---------------------------------------------------------------------------
 template <typename T, int LOGP>
 __global__ void __launch_bounds__(256)
 k_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat, int N,
        const C2<T> *__restrict__ tw, const int64_t *status)
 {
     if (halted(status)) return;
+    constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int P = 1 << LOGP, hP = P >> 1, E = fft_elems(P), G = P / E;
-    constexpr bool TWL = twiddles_in_lds<T>(P);
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const int t = threadIdx.x;
-    const int col = blockIdx.x;  // in [0, P/2]
-    const C2<T> *in = W1 + (size_t)col * N;
-    const T *g = Ghat + (size_t)col * P;
-    C2<T> v[E];
-    T gs[E];
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int n = t + G * q;
-        v[q] = n < N ? in[n] : C2<T>{T(0), T(0)};
-        gs[q] = g[n];
-    }
-    const C2<T> *tws = stage_twiddles<T, TWL>(x + P, tw, hP);
-    if (TWL) __syncthreads();
-    fft_strided<T, LOGP, false>(v, x, t, tws);
-#pragma unroll
-    for (int q = 0; q < E; ++q) v[q] = {v[q].x * gs[q], v[q].y * gs[q]};
-    fft_strided<T, LOGP, true>(v, x, t, tws);
-    C2<T> *out = W2 + (size_t)col * N;
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int n = t + G * q;
-        if (n < N) out[n] = v[q];
-    }
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
+    __syncthreads();
+    body_cols<T, LOGP, fft_elems(P)>(blockIdx.x, W1, W2, Ghat, N, x, tws);
 }
 
-// ---------------------------------------------------------------------------
-// Pass 3: inverse real FFT of a pair of row spectra.  With `dotv` set (CG),
-// each block also writes the FP64 partial sum of dotv . y over its rows.
-// ---------------------------------------------------------------------------
+// With `dotv` set (CG), each block also writes the FP64 partial sum of
+// dotv . y over its two rows.
 template <typename T, int LOGP>
 __global__ void __launch_bounds__(256)
-k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N,
-           const C2<T> *__restrict__ tw, const int64_t *status, const T *__restrict__ dotv,
-           double *__restrict__ partial)
+k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, const C2<T> *__restrict__ tw,
+           const int64_t *status, const T *__restrict__ dotv, double *__restrict__ partial)
 {
     if (halted(status)) return;
+    constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int P = 1 << LOGP, hP = P >> 1, E = fft_elems(P), G = P / E;
-    constexpr bool TWL = twiddles_in_lds<T>(P);
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const int t = threadIdx.x;
-    const int ra = 2 * blockIdx.x, rb = ra + 1;
-    C2<T> v[E];
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int k = t + G * q;
-        const int kk = k <= hP ? k : P - k;  // Hermitian extension
-        C2<T> Ya = W2[(size_t)kk * N + ra];
-        C2<T> Yb = rb < N ? W2[(size_t)kk * N + rb] : C2<T>{T(0), T(0)};
-        if (k > hP) {
-            Ya.y = -Ya.y;
-            Yb.y = -Yb.y;
-        }
-        v[q] = {Ya.x - Yb.y, Ya.y + Yb.x};
-    }
-    const C2<T> *tws = stage_twiddles<T, TWL>(x + P, tw, hP);
-    if (TWL) __syncthreads();
-    fft_strided<T, LOGP, true>(v, x, t, tws);
-    double acc = 0.0;
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int n = t + G * q;
-        if (n >= N) continue;
-        y[(size_t)ra * N + n] = v[q].x;
-        if (dotv) acc += (double)dotv[(size_t)ra * N + n] * (double)v[q].x;
-        if (rb < N) {
-            y[(size_t)rb * N + n] = v[q].y;
-            if (dotv) acc += (double)dotv[(size_t)rb * N + n] * (double)v[q].y;
-        }
-    }
-    if (partial) {
-        // reuse the LDS area (the launcher sizes it to >= blockDim doubles)
-        __syncthreads();
-        double *red = reinterpret_cast<double *>(smem_raw);
-        red[t] = acc;
-        __syncthreads();
-        for (int s = blockDim.x >> 1; s > 0; s >>= 1) {
-            if (t < s) red[t] += red[t + s];
-            __syncthreads();
-        }
-        if (t == 0) partial[blockIdx.x] = red[0];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Spectrum of the circulant embedding of G.
-// ---------------------------------------------------------------------------
-// Embedded tap index: position q in [0, P) holds tap q (q <= N-1) or
-// q - P (q >= P-N+1); other positions are zero.
-constexpr int NO_TAP = 1 << 30;
-__device__ __forceinline__ int embed_tap(int q, int N, int P)
-{
-    if (q <= N - 1) return q;
-    if (q >= P - N + 1) return q - P;
-    return NO_TAP;
-}
-
-template <typename T, int LOGP>
-__global__ void __launch_bounds__(256)
-k_spec_rows(const T *__restrict__ G, C2<T> *__restrict__ R, int N,
-            const C2<T> *__restrict__ tw)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int P = 1 << LOGP, hP = P >> 1, E = fft_elems(P), Gt = P / E;
-    constexpr bool TWL = twiddles_in_lds<T>(P);
-    const int W = 2 * N - 1;
-    C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const int t = threadIdx.x;
-    const int seq = blockIdx.x;  // embedded row pair (2 seq, 2 seq + 1), < P/2
-    const int ka = embed_tap(2 * seq, N, P), kb = embed_tap(2 * seq + 1, N, P);
-    C2<T> v[E];
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int k1 = embed_tap(t + Gt * q, N, P);
-        T re = 0, im = 0;
-        if (k1 != NO_TAP) {
-            if (ka != NO_TAP) re = G[(size_t)(ka + N - 1) * W + (k1 + N - 1)];
-            if (kb != NO_TAP) im = G[(size_t)(kb + N - 1) * W + (k1 + N - 1)];
-        }
-        v[q] = {re, im};
-    }
-    const C2<T> *tws = stage_twiddles<T, TWL>(x + P, tw, hP);
-    if (TWL) __syncthreads();
-    fft_strided<T, LOGP, false>(v, x, t, tws);
-#pragma unroll
-    for (int q = 0; q < E; ++q) x[t + Gt * q] = v[q];
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
     __syncthreads();
-    for (int k = t; k <= hP; k += Gt) {
-        const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
-        R[(size_t)k * P + 2 * seq] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
-        R[(size_t)k * P + 2 * seq + 1] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+    const double acc = body_rows_inv<T, LOGP, fft_elems(P)>(2 * blockIdx.x, W2, y, N, x, tws, dotv);
+    if (partial) {
+        const double s = block_sum_lds(acc, reinterpret_cast<double *>(smem_raw));
+        if (threadIdx.x == 0) partial[blockIdx.x] = s;
     }
 }
 
 template <typename T, int LOGP>
 __global__ void __launch_bounds__(256)
-k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat,
-            const C2<T> *__restrict__ tw, T scale)
+k_spec_rows(const T *__restrict__ G, C2<T> *__restrict__ R, int N, const C2<T> *__restrict__ tw)
 {
+    constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    constexpr int P = 1 << LOGP, hP = P >> 1, E = fft_elems(P), Gt = P / E;
-    constexpr bool TWL = twiddles_in_lds<T>(P);
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const int t = threadIdx.x;
-    const int col = blockIdx.x;
-    C2<T> v[E];
-#pragma unroll
-    for (int q = 0; q < E; ++q) v[q] = R[(size_t)col * P + t + Gt * q];
-    const C2<T> *tws = stage_twiddles<T, TWL>(x + P, tw, hP);
-    if (TWL) __syncthreads();
-    fft_strided<T, LOGP, false>(v, x, t, tws);
-#pragma unroll
-    for (int q = 0; q < E; ++q) Ghat[(size_t)col * P + t + Gt * q] = v[q].x * scale;
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
+    __syncthreads();
+    body_spec_rows<T, LOGP, fft_elems(P)>(blockIdx.x, G, R, N, x, tws);
+}
+
+template <typename T, int LOGP>
+__global__ void __launch_bounds__(256)
+k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat, const C2<T> *__restrict__ tw,
+            T scale)
+{
+    constexpr int P = 1 << LOGP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
+    __syncthreads();
+    body_spec_cols<T, LOGP, fft_elems(P)>(blockIdx.x, R, Ghat, x, tws, scale);
 }
 
 // ---------------------------------------------------------------------------
-// Launch geometry: one transform per block, P/E threads.
+// Launch geometry
 // ---------------------------------------------------------------------------
 struct FftCfg {
     int threads;   // P / E
@@ -277,12 +111,8 @@ struct FftCfg {
 template <typename T>
 static FftCfg fft_cfg(int logP)
 {
-    FftCfg c;
     const int P = 1 << logP;
-    c.threads = P / fft_elems(P);
-    c.lds = (size_t)P * sizeof(C2<T>) + (twiddles_in_lds<T>(P) ? (size_t)(P / 2) * sizeof(C2<T>) : 0);
-    c.lds = std::max(c.lds, (size_t)c.threads * sizeof(double));
-    return c;
+    return FftCfg{P / fft_elems(P), fft_lds_bytes<T>(P, fft_elems(P))};
 }
 
 template <typename T>

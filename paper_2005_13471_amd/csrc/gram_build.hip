@@ -69,15 +69,17 @@ __device__ __forceinline__ T gram_A(const GramAngle<T> &g, T x, bool blur)
 // the support of A is skipped by the whole block.
 constexpr int GB_CHUNK = 128;
 
+// Tile (bx, by) of one Gram filter: taps k1 in [16 bx - (N-1), +16),
+// k2 in [16 by, +16).  s_ga is an LDS area of GB_CHUNK angle records.
 template <typename T>
-__global__ void __launch_bounds__(256)
-k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ ga)
+__device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G, int N, int n,
+                                               const GramAngle<T> *__restrict__ ga,
+                                               GramAngle<T> *s_ga)
 {
-    __shared__ GramAngle<T> s_ga[GB_CHUNK];
     const int W = 2 * N - 1;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int k1a = (int)blockIdx.x * 16 - (N - 1);  // first tap column of the tile
-    const int k2a = (int)blockIdx.y * 16;              // first tap row (>= 0)
+    const int k1a = bx * 16 - (N - 1);  // first tap column of the tile
+    const int k2a = by * 16;            // first tap row (>= 0)
     const int k1 = k1a + tx, k2 = k2a + ty;
     const bool live = k1 <= N - 1 && k2 <= N - 1 && (k2 > 0 || k1 >= 0);
     const double ka = k1a, kb = k1a + 15, la = k2a, lb = k2a + 15;
@@ -112,6 +114,31 @@ k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ g
     }
 }
 
+// One 16 x 16 tile of taps per block, covering only taps with k2 > 0 or
+// (k2 = 0, k1 >= 0); each such tap also writes its mirror -k (G is even).
+// Angle records are staged through LDS in chunks.  The angle loop is
+// uniform across the block; an angle whose projected tile interval misses
+// the support of A is skipped by the whole block.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ ga)
+{
+    __shared__ GramAngle<T> s_ga[GB_CHUNK];
+    body_gram_tile<T>(blockIdx.x, blockIdx.y, G, N, n, ga, s_ga);
+}
+
+// Batched: block b covers tile map[b].y of slice map[b].x.
+template <typename T>
+__global__ void __launch_bounds__(256)
+kb_gram_build(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl, T *__restrict__ G)
+{
+    __shared__ GramAngle<T> s_ga[GB_CHUNK];
+    const int2 m = map[blockIdx.x];
+    const BatchSlice &d = sl[m.x];
+    const int tiles_x = (2 * d.N - 1 + 15) / 16;
+    body_gram_tile<T>(m.y % tiles_x, m.y / tiles_x, G + d.gram, d.N, d.n, reinterpret_cast<const GramAngle<T> *>(d.ga), s_ga);
+}
+
 template <typename T>
 hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s)
 {
@@ -123,6 +150,18 @@ hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_batch_gram_build(const int2 *map, int nblocks, const BatchSlice *sl, T *G,
+                                   hipStream_t s)
+{
+    if (nblocks > 0) hipLaunchKernelGGL(kb_gram_build<T>, dim3(nblocks), dim3(256), 0, s, map, sl, G);
+    return hipGetLastError();
+}
+
+template hipError_t launch_batch_gram_build<float>(const int2 *, int, const BatchSlice *, float *,
+                                                   hipStream_t);
+template hipError_t launch_batch_gram_build<double>(const int2 *, int, const BatchSlice *, double *,
+                                                    hipStream_t);
 template hipError_t launch_gram_build<float>(const gct_plan *, float *, hipStream_t);
 template hipError_t launch_gram_build<double>(const gct_plan *, double *, hipStream_t);
 

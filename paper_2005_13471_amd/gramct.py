@@ -52,6 +52,12 @@ class _CGResult(ctypes.Structure):
                 ("fell_back", ctypes.c_int32)]
 
 
+class _BatchInfo(ctypes.Structure):
+    _fields_ = [("slices", ctypes.c_int32), ("groups", ctypes.c_int32),
+                ("image_elems", ctypes.c_int64), ("gram_elems", ctypes.c_int64),
+                ("spectrum_elems", ctypes.c_int64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
@@ -72,6 +78,18 @@ def _load():
     L.gct_forward_project.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.gct_cg_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, dbl, i32, i32,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_CGResult), vp, vp]
+    L.gct_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
+    L.gct_batch_destroy.argtypes = [vp]
+    L.gct_batch_get_info.argtypes = [vp, ctypes.POINTER(_BatchInfo), ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p]
+    L.gct_batch_workspace_size.argtypes = [vp, ctypes.c_int, ctypes.c_int]
+    L.gct_batch_workspace_size.restype = ctypes.c_size_t
+    L.gct_batch_gram_build.argtypes = [vp, ctypes.c_int, vp, vp]
+    L.gct_batch_gram_spectrum.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
+    L.gct_batch_gram_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+    L.gct_batch_cg_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp, dbl, i32, i32,
+                                     ctypes.POINTER(_CGResult), vp, vp]
+    L.gct_batch_autotune.argtypes = [vp, ctypes.c_int, vp, vp, i32, ctypes.POINTER(i32), vp]
     L.gct_host_boxspline_eval.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, dbl,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_double)]
@@ -243,6 +261,95 @@ def cg_solve(plan: Plan, Ghat: torch.Tensor, b: torch.Tensor, x: torch.Tensor, w
                     res.fell_back, hist[: res.iters + 1].copy())
 
 
+# ---------------------------------------------------------------------------
+# Batches of independent slices
+# ---------------------------------------------------------------------------
+class Batch:
+    """gct_batch over existing plans (kept alive by this object).  Data
+    arrays are packed: slice i occupies [offset_i, offset_i + size_i)."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        _check(lib.gct_batch_create(arr, len(self.plans), ctypes.byref(h)))
+        self._h = h
+        info = _BatchInfo()
+        S = len(self.plans)
+        self.image_offsets = np.zeros(S, np.int64)
+        self.gram_offsets = np.zeros(S, np.int64)
+        self.spectrum_offsets = np.zeros(S, np.int64)
+        _check(lib.gct_batch_get_info(h, ctypes.byref(info), self.image_offsets.ctypes.data,
+                                      self.gram_offsets.ctypes.data, self.spectrum_offsets.ctypes.data))
+        self.slices, self.groups = info.slices, info.groups
+        self.image_elems, self.gram_elems, self.spectrum_elems = (info.image_elems, info.gram_elems,
+                                                                  info.spectrum_elems)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.gct_batch_destroy(h)
+            self._h = None
+
+    def workspace_size(self, op: int, dtype=torch.float32) -> int:
+        return int(lib.gct_batch_workspace_size(self._h, op, F32 if dtype == torch.float32 else F64))
+
+    def workspace(self, op: int, dtype=torch.float32) -> torch.Tensor:
+        return torch.empty(max(self.workspace_size(op, dtype), 256), dtype=torch.uint8, device="cuda")
+
+    def image(self, packed: torch.Tensor, i: int) -> torch.Tensor:
+        N = self.plans[i].N
+        o = int(self.image_offsets[i])
+        return packed[o:o + N * N].view(N, N)
+
+
+def batch_gram_build(batch: Batch, G: torch.Tensor):
+    _check(lib.gct_batch_gram_build(batch.handle, _dt(G), _ptr(G, batch.gram_elems), _stream()))
+    return G
+
+
+def batch_gram_spectrum(batch: Batch, G: torch.Tensor, Ghat: torch.Tensor, ws: torch.Tensor):
+    _check(lib.gct_batch_gram_spectrum(batch.handle, _dt(G), _ptr(G, batch.gram_elems),
+                                       _ptr(Ghat, batch.spectrum_elems, G.dtype),
+                                       _ptr(ws, batch.workspace_size(OP_GRAM_SPECTRUM, G.dtype)),
+                                       _stream()))
+    return Ghat
+
+
+def batch_gram_apply(batch: Batch, Ghat: torch.Tensor, c: torch.Tensor, y: torch.Tensor,
+                     ws: torch.Tensor):
+    _check(lib.gct_batch_gram_apply(batch.handle, _dt(c), _ptr(Ghat, batch.spectrum_elems, c.dtype),
+                                    _ptr(c, batch.image_elems), _ptr(y, batch.image_elems, c.dtype),
+                                    _ptr(ws, batch.workspace_size(OP_GRAM_APPLY, c.dtype)), _stream()))
+    return y
+
+
+def batch_cg_solve(batch: Batch, Ghat: torch.Tensor, b: torch.Tensor, x: torch.Tensor,
+                   ws: torch.Tensor, rtol: float = 1e-4, max_iter: int = 1000,
+                   check_every: int = 8) -> list:
+    res = (_CGResult * batch.slices)()
+    rc = lib.gct_batch_cg_solve(batch.handle, _dt(b), _ptr(Ghat, batch.spectrum_elems, b.dtype),
+                                _ptr(b, batch.image_elems), _ptr(x, batch.image_elems, b.dtype),
+                                float(rtol), int(max_iter), int(check_every), res,
+                                _ptr(ws, batch.workspace_size(OP_CG, b.dtype)), _stream())
+    if rc not in (GCT_OK, GCT_ENOTCONV, GCT_EBREAKDOWN):
+        _check(rc)
+    return [CGResult(r.iters, r.status, r.rel_res, r.rel_res_true, r.rel_res0, r.fell_back,
+                     np.zeros(0)) for r in res]
+
+
+def batch_autotune(batch: Batch, Ghat: torch.Tensor, ws: torch.Tensor, reps: int = 3) -> list:
+    chosen = (ctypes.c_int32 * batch.groups)()
+    _check(lib.gct_batch_autotune(batch.handle, _dt(Ghat), _ptr(Ghat, batch.spectrum_elems),
+                                  _ptr(ws, batch.workspace_size(OP_CG, Ghat.dtype)), int(reps),
+                                  chosen, _stream()))
+    return list(chosen)
+
+
 # C-ABI names
 gct_gram_build = gram_build
 gct_gram_spectrum = gram_spectrum
@@ -251,6 +358,11 @@ gct_prefilter = prefilter
 gct_backproject_boxspline = backproject_boxspline
 gct_forward_project = forward_project
 gct_cg_solve = cg_solve
+gct_batch_gram_build = batch_gram_build
+gct_batch_gram_spectrum = batch_gram_spectrum
+gct_batch_gram_apply = batch_gram_apply
+gct_batch_cg_solve = batch_cg_solve
+gct_batch_autotune = batch_autotune
 
 
 # ---------------------------------------------------------------------------

@@ -1,0 +1,155 @@
+"""Batched uneven slices through the C ABI: Gram filters, spectra, Gram
+filtering and CG for several slices of different N, angle sets and blur in
+one launch per phase, against the FP64 oracle per slice, against the
+single-slice path, and after autotuning."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2005_13471_amd import inputs
+from gpu_helpers import normwise, say
+
+pytestmark = pytest.mark.gpu
+
+# (N, n_angles, zeta): FFT sizes 32, 64, 128, 128, 256 -> four groups
+SLICES = [(16, 12, 0.0), (23, 17, 1.0), (37, 45, 1.0), (64, 90, 0.0), (100, 150, 0.5)]
+
+
+@pytest.fixture(scope="module")
+def batch_setup():
+    from paper_2005_13471_amd import gramct as gct
+    plans, ogs = [], []
+    for i, (N, n, z) in enumerate(SLICES):
+        th = inputs.angles(n) + 0.01 * i
+        M = inputs.detector_bins(N, z)
+        plans.append(gct.Plan(N, th, M, zeta=z))
+        ogs.append(oracle.Geometry(N, th, M, zeta=z))
+    return gct, gct.Batch(plans), plans, ogs
+
+
+def _packed(batch, arrays, dt):
+    out = torch.zeros(batch.image_elems, dtype=dt, device="cuda")
+    for i, a in enumerate(arrays):
+        batch.image(out, i).copy_(torch.as_tensor(a, dtype=dt, device="cuda"))
+    return out
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_batch_gram_build_and_apply_match_oracle(batch_setup, dt):
+    gct, B, plans, ogs = batch_setup
+    say("batch gram_build / apply", dt)
+    G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
+    gct.batch_gram_build(B, G)
+    Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")
+    gct.batch_gram_spectrum(B, G, Ghat, B.workspace(gct.OP_GRAM_SPECTRUM, dt))
+    cs = [inputs.uniform_coeffs(N, 2000 + i) for i, (N, _, _) in enumerate(SLICES)]
+    y = torch.empty(B.image_elems, dtype=dt, device="cuda")
+    gct.batch_gram_apply(B, Ghat, _packed(B, cs, dt), y, B.workspace(gct.OP_GRAM_APPLY, dt))
+    torch.cuda.synchronize()
+    tg = 1e-5 if dt == torch.float32 else 1e-11
+    ta = 1e-4 if dt == torch.float32 else 1e-11
+    for i, (N, _, _) in enumerate(SLICES):
+        W = 2 * N - 1
+        o = int(B.gram_offsets[i])
+        g_gpu = G[o:o + W * W].double().cpu().numpy().reshape(W, W)
+        g_or = oracle.gram(ogs[i])
+        assert normwise(g_gpu, g_or) <= tg, i
+        y_or = oracle.apply(g_or, cs[i])
+        assert normwise(B.image(y, i).double().cpu().numpy(), y_or) <= ta, i
+
+
+def test_batch_apply_bitwise_equals_single_slice(batch_setup):
+    """Same device bodies and tile shapes: the batched apply reproduces the
+    single-slice apply bit for bit (before autotuning)."""
+    gct, B, plans, ogs = batch_setup
+    dt = torch.float32
+    G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
+    gct.batch_gram_build(B, G)
+    Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")
+    gct.batch_gram_spectrum(B, G, Ghat, B.workspace(gct.OP_GRAM_SPECTRUM, dt))
+    cs = [inputs.uniform_coeffs(N, 3000 + i) for i, (N, _, _) in enumerate(SLICES)]
+    y = torch.empty(B.image_elems, dtype=dt, device="cuda")
+    gct.batch_gram_apply(B, Ghat, _packed(B, cs, dt), y, B.workspace(gct.OP_GRAM_APPLY, dt))
+    for i, P in enumerate(plans):
+        Gi = torch.empty(P.info.gram_elems, dtype=dt, device="cuda")
+        gct.gram_build(P, Gi)
+        o = int(B.gram_offsets[i])
+        assert torch.equal(Gi, G[o:o + P.info.gram_elems])
+        Gh = torch.empty(P.info.spectrum_elems, dtype=dt, device="cuda")
+        gct.gram_spectrum(P, Gi, Gh, P.workspace(gct.OP_GRAM_SPECTRUM, dt))
+        so = int(B.spectrum_offsets[i])
+        assert torch.equal(Gh, Ghat[so:so + P.info.spectrum_elems])
+        yi = torch.empty(P.N * P.N, dtype=dt, device="cuda")
+        gct.gram_apply(P, Gh, torch.as_tensor(cs[i].reshape(-1), dtype=dt, device="cuda"), yi,
+                       P.workspace(gct.OP_GRAM_APPLY, dt))
+        assert torch.equal(yi.view(P.N, P.N), B.image(y, i))
+
+
+@pytest.mark.parametrize("dt", [torch.float32, torch.float64])
+def test_batch_cg_matches_single_slice_and_oracle(batch_setup, dt):
+    gct, B, plans, ogs = batch_setup
+    say("batch cg", dt)
+    G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
+    gct.batch_gram_build(B, G)
+    Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")
+    gct.batch_gram_spectrum(B, G, Ghat, B.workspace(gct.OP_GRAM_SPECTRUM, dt))
+    bs = []
+    for i, (N, n, z) in enumerate(SLICES):
+        ells = inputs.random_ellipses(N, 8, 1000 + i)
+        sino = inputs.add_noise(inputs.analytic_sinogram(ells, plans[i].theta, plans[i].M, zeta=z),
+                                0.01, inputs.NOISE_SEED_BASE + 1000 + i)
+        bi = torch.empty(N * N, dtype=dt, device="cuda")
+        gct.backproject_boxspline(plans[i], torch.as_tensor(sino.reshape(-1), dtype=dt, device="cuda"),
+                                  bi, plans[i].workspace(gct.OP_BACKPROJECT, dt))
+        bs.append(bi.view(N, N))
+    b = torch.zeros(B.image_elems, dtype=dt, device="cuda")
+    for i in range(len(SLICES)):
+        B.image(b, i).copy_(bs[i])
+    x = torch.empty_like(b)
+    res = gct.batch_cg_solve(B, Ghat, b, x, B.workspace(gct.OP_CG, dt), rtol=1e-4, max_iter=500,
+                             check_every=4)
+    for i, P in enumerate(plans):
+        gi = torch.empty(P.info.gram_elems, dtype=dt, device="cuda")
+        gct.gram_build(P, gi)
+        gh = torch.empty(P.info.spectrum_elems, dtype=dt, device="cuda")
+        gct.gram_spectrum(P, gi, gh, P.workspace(gct.OP_GRAM_SPECTRUM, dt))
+        xi = torch.zeros(P.N * P.N, dtype=dt, device="cuda")
+        ri = gct.cg_solve(P, gh, bs[i].reshape(-1).contiguous(), xi, P.workspace(gct.OP_CG, dt),
+                          rtol=1e-4, max_iter=500)
+        say("  slice", i, "batch iters", res[i].iters, "single", ri.iters, "true", res[i].rel_res_true)
+        assert res[i].status == gct.GCT_OK
+        assert abs(res[i].iters - ri.iters) <= 1
+        # the oracle re-checks the batched iterate
+        G_or = oracle.gram(ogs[i])
+        bh = bs[i].double().cpu().numpy()
+        xh = B.image(x, i).double().cpu().numpy()
+        rel = np.linalg.norm(bh - oracle.apply(G_or, xh)) / np.linalg.norm(bh)
+        assert rel <= (1.1e-4 if dt == torch.float32 else 1.0001e-4)
+
+
+def test_batch_autotune_keeps_results(batch_setup):
+    gct, B, plans, ogs = batch_setup
+    dt = torch.float32
+    G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
+    gct.batch_gram_build(B, G)
+    Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")
+    gct.batch_gram_spectrum(B, G, Ghat, B.workspace(gct.OP_GRAM_SPECTRUM, dt))
+    chosen = gct.batch_autotune(B, Ghat, B.workspace(gct.OP_CG, dt), reps=2)
+    say("autotune choice per FFT size", chosen)
+    assert len(chosen) == B.groups and all(e in (4, 8, 16) for e in chosen)
+    cs = [inputs.uniform_coeffs(N, 4000 + i) for i, (N, _, _) in enumerate(SLICES)]
+    y = torch.empty(B.image_elems, dtype=dt, device="cuda")
+    gct.batch_gram_apply(B, Ghat, _packed(B, cs, dt), y, B.workspace(gct.OP_GRAM_APPLY, dt))
+    for i in range(len(SLICES)):
+        y_or = oracle.apply(oracle.gram(ogs[i]), cs[i])
+        assert normwise(B.image(y, i).double().cpu().numpy(), y_or) <= 1e-4
+
+
+def test_batch_rejects_bad_arguments(batch_setup):
+    gct, B, plans, ogs = batch_setup
+    t = torch.zeros(B.image_elems, dtype=torch.float32, device="cuda")
+    gh = torch.zeros(B.spectrum_elems, dtype=torch.float32, device="cuda")
+    with pytest.raises(gct.GramctError) as e:
+        gct.batch_gram_apply(B, gh, t, t, B.workspace(gct.OP_GRAM_APPLY))
+    assert e.value.code == gct.GCT_EINVAL

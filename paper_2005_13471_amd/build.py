@@ -16,7 +16,8 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgramct.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["plan.cpp", "gram_build.hip", "gram_apply.hip", "backproject.hip", "cg.hip", "batch.hip"]
+SOURCES = ["plan.cpp", "gram_build.hip", "gram_apply.hip", "backproject.hip", "cg.hip", "batch.hip",
+           "unet.hip"]
 
 # Packed FP32 instructions are disabled for every kernel (the backend would
 # otherwise form v_pk_* from plain float code).

@@ -1,0 +1,1046 @@
+// Learned warm start for CG: a small U-Net mapping the normalised back
+// projection H^T g to an initial iterate, trained and run entirely by the
+// kernels in this file.
+//
+// Architecture (levels L, base channels C0; C_l = C0 2^l): per level two
+// 3x3 convolutions with ReLU, 2x2 max pooling between encoder levels, 2x2
+// stride-2 transposed convolution up, skip concatenation, final 1x1
+// convolution to one channel.  Activations and weights are BF16 (NHWC),
+// accumulation FP32 on the matrix cores (v_mfma_f32_16x16x16_bf16), master
+// weights and Adam moments FP32.
+//
+// Every GEMM-shaped step is one implicit-GEMM kernel (k_conv): rows = output
+// pixels, columns = output channels, K = taps x input channels, operands
+// gathered straight from the NHWC tensors (zero padding by predication).
+// The data gradient of a convolution is the same kernel with flipped,
+// transposed weights; the weight gradient is a K-split GEMM over pixels
+// (k_wgrad) reduced in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gramct_unet.h"
+#include "gct_internal.h"
+
+namespace gct {
+
+typedef uint16_t bf16_t;
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__host__ __device__ inline float bf2f(bf16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+// round to nearest even
+__host__ __device__ inline bf16_t f2bf(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (bf16_t)0x7fc0;
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (bf16_t)(u >> 16);
+}
+
+__device__ inline short4_t load_bf4(const bf16_t *p)
+{
+    const uint2 v = *reinterpret_cast<const uint2 *>(p);
+    short4_t r;
+    r[0] = (short)(v.x & 0xffff);
+    r[1] = (short)(v.x >> 16);
+    r[2] = (short)(v.y & 0xffff);
+    r[3] = (short)(v.y >> 16);
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM convolution.  Rows m = (b, oh, ow) over the output grid
+// Hout x Wout; for tap t the input pixel is (oh*stride + t/tw + org,
+// ow*stride + t%tw + org); weights w[t][n][Cin] (Cin contiguous).
+// Epilogue modes: 0 = BF16 NHWC (+bias, ReLU) at channel offset out_co of
+// pixels with out_cs channels; 1 = FP32 single channel n = 0; 2 = stride-2
+// transposed-convolution scatter: n = (2a + b) cout + co goes to output
+// pixel (2 oh + a, 2 ow + b) of a 2Hout x 2Wout grid, channel out_co + co.
+// Block: 4 waves x (16 rows x 64 columns); K in steps of 16 channels.
+// ---------------------------------------------------------------------------
+struct ConvArgs {
+    const bf16_t *in;
+    int in_cs, in_co;
+    int B, Hin, Win, Cin;
+    int ntaps, tw, org, stride;
+    const bf16_t *w;
+    int Nw;
+    int Hout, Wout;
+    const float *bias;
+    int relu, mode;
+    bf16_t *out;
+    int out_cs, out_co;
+    float *out32;
+    float oscale;
+    int cout;
+};
+
+__global__ void __launch_bounds__(256) k_conv(ConvArgs a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int HWo = a.Hout * a.Wout;
+    const int M = a.B * HWo;
+    const int m0 = blockIdx.x * 64 + wave * 16;
+    const int n0 = blockIdx.y * 64;
+    const int mi = m0 + (lane & 15);
+    const bool mvalid = mi < M;
+    int b = 0, oh = 0, ow = 0;
+    if (mvalid) {
+        b = mi / HWo;
+        const int r = mi - b * HWo;
+        oh = r / a.Wout;
+        ow = r - oh * a.Wout;
+    }
+    const int kq = (lane >> 4) * 4;
+    float4_t acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = float4_t{0.f, 0.f, 0.f, 0.f};
+    const short4_t zero = {0, 0, 0, 0};
+    for (int t = 0; t < a.ntaps; ++t) {
+        const int ih = oh * a.stride + t / a.tw + a.org;
+        const int iw = ow * a.stride + t % a.tw + a.org;
+        const bool ok = mvalid && ih >= 0 && ih < a.Hin && iw >= 0 && iw < a.Win;
+        const bf16_t *ip = a.in + ((size_t)(b * a.Hin + (ok ? ih : 0)) * a.Win + (ok ? iw : 0)) * a.in_cs +
+                           a.in_co + kq;
+        const bf16_t *wp = a.w + ((size_t)t * a.Nw + n0 + (lane & 15)) * a.Cin + kq;
+        for (int c0 = 0; c0 < a.Cin; c0 += 16) {
+            const short4_t av = ok ? load_bf4(ip + c0) : zero;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int n = n0 + 16 * q + (lane & 15);
+                const short4_t bv = n < a.Nw ? load_bf4(wp + (size_t)16 * q * a.Cin + c0) : zero;
+                acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[q], 0, 0, 0);
+            }
+        }
+    }
+    // D[i][n]: lane holds n = lane % 16, i = 4 (lane / 16) + j
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int n = n0 + 16 * q + (lane & 15);
+        if (n >= a.Nw) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = m0 + (lane >> 4) * 4 + j;
+            if (m >= M) continue;
+            float v = acc[q][j];
+            const int bb = m / HWo, rr = m - bb * HWo, yh = rr / a.Wout, yw = rr - yh * a.Wout;
+            if (a.mode == 0) {
+                if (a.bias) v += a.bias[n];
+                if (a.relu) v = fmaxf(v, 0.f);
+                a.out[(size_t)m * a.out_cs + a.out_co + n] = f2bf(v);
+            } else if (a.mode == 1) {
+                if (n == 0) a.out32[m] = a.oscale * (v + (a.bias ? a.bias[0] : 0.f));
+            } else {
+                const int ab = n / a.cout, co = n - ab * a.cout;
+                const int oy = 2 * yh + (ab >> 1), ox = 2 * yw + (ab & 1);
+                if (a.bias) v += a.bias[co];
+                if (a.relu) v = fmaxf(v, 0.f);
+                const size_t pix = ((size_t)bb * (2 * a.Hout) + oy) * (2 * a.Wout) + ox;
+                a.out[pix * a.out_cs + a.out_co + co] = f2bf(v);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[t][n][c] = sum_m dY(m)[n] X(pix(m, t))[c], K-split
+// over pixel chunks; partial tiles to part[chunk][t][n][c] (FP32).
+// dY is either NHWC over the GEMM row grid (mode 0) or, for a transposed
+// convolution (mode 2), gathered from the 2x up-sampled grid with
+// n = (2a + b) cout + co.  Block: 4 waves, wave w owns c-tile 4 y + w.
+// ---------------------------------------------------------------------------
+struct WgradArgs {
+    const bf16_t *x;
+    int x_cs, x_co, Hin, Win, Cin;
+    int ntaps, tw, org, stride;
+    const bf16_t *dy;
+    int dy_cs, dy_co, Nw, mode, cout;
+    int B, Hout, Wout;
+    int chunk;
+    float *part;
+};
+
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs a)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int HWo = a.Hout * a.Wout, M = a.B * HWo;
+    const int n0 = blockIdx.x * 16;
+    const int c0 = (blockIdx.y * 4 + wave) * 16;
+    const int t = blockIdx.z % a.ntaps;
+    const int ch = blockIdx.z / a.ntaps;
+    const int mbeg = ch * a.chunk, mend = min(M, mbeg + a.chunk);
+    const int th = t / a.tw + a.org, twd = t % a.tw + a.org;
+    float4_t acc = {0.f, 0.f, 0.f, 0.f};
+    const int n = n0 + (lane & 15), c = c0 + (lane & 15);
+    const bool nok = n < a.Nw, cok = c < a.Cin;
+    for (int m0 = mbeg; m0 < mend; m0 += 16) {
+        short4_t av, bv;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = m0 + (lane >> 4) * 4 + j;
+            short va = 0, vb = 0;
+            if (m < mend) {
+                const int bb = m / HWo, rr = m - bb * HWo, oh = rr / a.Wout, ow = rr - oh * a.Wout;
+                if (nok) {
+                    if (a.mode == 0) {
+                        va = (short)a.dy[(size_t)m * a.dy_cs + a.dy_co + n];
+                    } else {
+                        const int ab = n / a.cout, co = n - ab * a.cout;
+                        const size_t pix = ((size_t)bb * (2 * a.Hout) + 2 * oh + (ab >> 1)) * (2 * a.Wout) +
+                                           2 * ow + (ab & 1);
+                        va = (short)a.dy[pix * a.dy_cs + a.dy_co + co];
+                    }
+                }
+                const int ih = oh * a.stride + th, iw = ow * a.stride + twd;
+                if (cok && ih >= 0 && ih < a.Hin && iw >= 0 && iw < a.Win)
+                    vb = (short)a.x[((size_t)(bb * a.Hin + ih) * a.Win + iw) * a.x_cs + a.x_co + c];
+            }
+            av[j] = va;
+            bv[j] = vb;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+    // D[i = n-row][col = c]: lane holds col = lane % 16, row = 4 (lane / 16) + j
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int nn = n0 + (lane >> 4) * 4 + j;
+        if (nn < a.Nw && cok)
+            a.part[(((size_t)ch * a.ntaps + t) * a.Nw + nn) * a.Cin + c] = acc[j];
+    }
+}
+
+// sum partial tiles over chunks: out[i] = sum_ch part[ch][i]
+__global__ void __launch_bounds__(256) k_sum_chunks(const float *part, int nch, size_t len, float *out)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (size_t)gridDim.x * blockDim.x) {
+        float s = 0.f;
+        for (int c = 0; c < nch; ++c) s += part[(size_t)c * len + i];
+        out[i] = s;
+    }
+}
+
+// bias gradient: db[n] = sum over pixels of dy[pix][dy_co + n]; block b sums
+// pixels [b chunk, (b+1) chunk) into part[b][n]
+__global__ void __launch_bounds__(256)
+k_bias_partial(const bf16_t *dy, int dy_cs, int dy_co, int C, int npix, int chunk, float *part)
+{
+    const int p0 = blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        float s = 0.f;
+        for (int p = p0; p < p1; ++p) s += bf2f(dy[(size_t)p * dy_cs + dy_co + c]);
+        part[(size_t)blockIdx.x * C + c] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise kernels
+// ---------------------------------------------------------------------------
+// input [B][H][W] FP32 * scale -> BF16 NHWC with 16 channels (channel 0 data)
+__global__ void k_prep_input(const float *x, float scale, int npix, bf16_t *out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    out[(size_t)p * 16] = f2bf(x[p] * scale);
+#pragma unroll
+    for (int c = 1; c < 16; ++c) out[(size_t)p * 16 + c] = 0;
+}
+
+// dz = dy * (y > 0) on channel windows (in place on dy)
+__global__ void k_relu_bwd(bf16_t *dy, int dy_cs, int dy_co, const bf16_t *y, int y_cs, int y_co,
+                           int C, size_t npix)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix * C) return;
+    const size_t p = i / C;
+    const int c = (int)(i - p * C);
+    if (!(bf2f(y[p * y_cs + y_co + c]) > 0.f)) dy[p * dy_cs + dy_co + c] = 0;
+}
+
+__global__ void k_maxpool(const bf16_t *in, int in_cs, int in_co, int B, int H, int W, int C,
+                          bf16_t *out)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Ho = H / 2, Wo = W / 2;
+    if (i >= (size_t)B * Ho * Wo * C) return;
+    const int c = (int)(i % C);
+    size_t r = i / C;
+    const int ow = (int)(r % Wo);
+    r /= Wo;
+    const int oh = (int)(r % Ho);
+    const int b = (int)(r / Ho);
+    float m = -INFINITY;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const size_t pix = ((size_t)b * H + 2 * oh + (a >> 1)) * W + 2 * ow + (a & 1);
+        m = fmaxf(m, bf2f(in[pix * in_cs + in_co + c]));
+    }
+    out[i] = f2bf(m);
+}
+
+// gradient to the first maximal element of each 2x2 window, ADDED to gin
+__global__ void k_maxpool_bwd(const bf16_t *in, int in_cs, int in_co, int B, int H, int W, int C,
+                              const bf16_t *gout, bf16_t *gin, int g_cs, int g_co)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Ho = H / 2, Wo = W / 2;
+    if (i >= (size_t)B * Ho * Wo * C) return;
+    const int c = (int)(i % C);
+    size_t r = i / C;
+    const int ow = (int)(r % Wo);
+    r /= Wo;
+    const int oh = (int)(r % Ho);
+    const int b = (int)(r / Ho);
+    float m = -INFINITY;
+    int arg = 0;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const size_t pix = ((size_t)b * H + 2 * oh + (a >> 1)) * W + 2 * ow + (a & 1);
+        const float v = bf2f(in[pix * in_cs + in_co + c]);
+        if (v > m) {
+            m = v;
+            arg = a;
+        }
+    }
+    const size_t pix = ((size_t)b * H + 2 * oh + (arg >> 1)) * W + 2 * ow + (arg & 1);
+    bf16_t *g = gin + pix * g_cs + g_co + c;
+    *g = f2bf(bf2f(*g) + bf2f(gout[i]));
+}
+
+// MSE loss: partial sums of (y - t)^2 per block; dy16[p][0] = gscale (y - t)
+// (gscale = 2 oscale / npix: the gradient with respect to the last layer's
+// pre-scale output)
+__global__ void __launch_bounds__(256)
+k_mse(const float *y, const float *t, int npix, float gscale, bf16_t *dy16, double *part)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    const float inv = gscale;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += gridDim.x * blockDim.x) {
+        const float d = y[p] - t[p];
+        s += (double)d * d;
+        dy16[(size_t)p * 16] = f2bf(d * inv);
+#pragma unroll
+        for (int c = 1; c < 16; ++c) dy16[(size_t)p * 16 + c] = 0;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = blockDim.x >> 1; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_mse_fin(const double *part, int np, int npix, float *loss)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < np; ++i) s += part[i];
+    *loss = (float)(s / npix);
+}
+
+// Adam on the flat FP32 parameters (Kingma & Ba, bias-corrected moments;
+// c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t))
+__global__ void k_adam(float *w, const float *g, float *m, float *v, size_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// BF16 copies: forward layout (same as master) and, for the data gradient,
+// flipped / transposed wt[t'][c][n] = w[ntaps-1-t'][n][c] (3x3) or
+// wt[t][c][n] = w[t][n][c] (2x2 transposed-convolution taps), with the n
+// axis zero-padded to Np >= N.
+__global__ void k_to_bf16(const float *w, size_t n, bf16_t *o)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) o[i] = f2bf(w[i]);
+}
+
+__global__ void k_fill(float *p, size_t n, float v)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_transpose_taps(const float *w, int ntaps, int N, int C, int Np, int flip, bf16_t *wt)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (size_t)ntaps * Np * C) return;
+    const int n = (int)(i % Np);
+    size_t r = i / Np;
+    const int c = (int)(r % C);
+    const int tp = (int)(r / C);
+    const int t = flip ? ntaps - 1 - tp : tp;
+    wt[i] = n < N ? f2bf(w[((size_t)t * N + n) * C + c]) : (bf16_t)0;
+}
+
+}  // namespace gct
+
+// ---------------------------------------------------------------------------
+// Host executor
+// ---------------------------------------------------------------------------
+namespace gct {
+namespace {
+
+enum { L_CONV = 0, L_UP = 1, L_FINAL = 2 };
+
+struct ULayer {
+    int kind;
+    int ntaps, tw, org, stride;  // forward gather geometry
+    int Cin, Nw, cout;           // weight [ntaps][Nw][Cin], bias [cout]
+    size_t w_off, b_off;         // flat FP32 master / BF16 copy
+    size_t wt_off;               // transposed BF16 copy for the data gradient
+    bool need_dgrad;
+};
+
+inline size_t al64(size_t n) { return (n + 63) & ~(size_t)63; }
+inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+// K-split of a weight gradient over M GEMM rows: about 2048 blocks in all.
+// nch never exceeds wgrad_max_chunks(L, M') for any M' >= M.
+long long wgrad_max_chunks(const ULayer &L, long long M)
+{
+    const long long tiles = (long long)cdiv(L.Nw, 16) * cdiv(L.Cin, 64) * L.ntaps;
+    return std::max(1LL, std::min((2048 + tiles - 1) / tiles, (M + 255) / 256));
+}
+
+void wgrad_split(const ULayer &L, long long M, int &nch, int &chunk)
+{
+    const long long n = wgrad_max_chunks(L, M);
+    long long c = (M + n - 1) / n;
+    c = (c + 15) & ~15LL;
+    chunk = (int)c;
+    nch = (int)((M + c - 1) / c);
+}
+
+void bias_split(long long npix, int &nblk, int &chunk)
+{
+    long long c = std::max(256LL, (npix + 511) / 512);
+    chunk = (int)c;
+    nblk = (int)((npix + c - 1) / c);
+}
+
+}  // namespace
+}  // namespace gct
+
+struct gct_unet {
+    int L, C0, H, W, maxB, device;
+    std::vector<gct::ULayer> layers;
+    std::vector<int> enc1, enc2, up, dec1, dec2;
+    int fin;
+    size_t nparam, nwt;
+    float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    gct::bf16_t *w16 = nullptr, *wt16 = nullptr;
+    float *part = nullptr;
+    size_t part_elems;
+    double *lpart = nullptr;
+    float *loss = nullptr;
+    // activations and their gradients, per level
+    std::vector<gct::bf16_t *> x, e, s, d1, d2, gx, ge, gs, gd1, gd2;
+    gct::bf16_t *dy16 = nullptr;
+    void *arena = nullptr;
+    float oscale = 1.f;
+    int last_batch = 0;
+
+    int C(int l) const { return C0 << l; }
+    int Hl(int l) const { return H >> l; }
+    int Wl(int l) const { return W >> l; }
+};
+
+namespace gct {
+namespace {
+
+hipError_t last_launch() { return hipGetLastError(); }
+
+void conv_launch(const ConvArgs &a, hipStream_t st)
+{
+    const long long M = (long long)a.B * a.Hout * a.Wout;
+    dim3 grid(cdiv(M, 64), cdiv(a.Nw, 64));
+    hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, st, a);
+}
+
+// forward of layer Lr: rows over the Hout x Wout grid
+void fwd(const gct_unet *u, const ULayer &Lr, int B, const bf16_t *in, int in_cs, int in_co, int Hin,
+         int Win, int Hout, int Wout, bf16_t *out, int out_cs, int out_co, int relu, int mode, float *out32,
+         hipStream_t st)
+{
+    ConvArgs a{};
+    a.in = in;
+    a.in_cs = in_cs;
+    a.in_co = in_co;
+    a.B = B;
+    a.Hin = Hin;
+    a.Win = Win;
+    a.Cin = Lr.Cin;
+    a.ntaps = Lr.ntaps;
+    a.tw = Lr.tw;
+    a.org = Lr.org;
+    a.stride = Lr.stride;
+    a.w = u->w16 + Lr.w_off;
+    a.Nw = Lr.Nw;
+    a.Hout = Hout;
+    a.Wout = Wout;
+    a.bias = u->w + Lr.b_off;
+    a.relu = relu;
+    a.mode = mode;
+    a.out = out;
+    a.out_cs = out_cs;
+    a.out_co = out_co;
+    a.out32 = out32;
+    a.oscale = u->oscale;
+    a.cout = Lr.cout;
+    conv_launch(a, st);
+}
+
+// data gradient of layer Lr: gin (rows over the layer's input grid) from
+// gout (the layer's output gradient)
+void dgrad(const gct_unet *u, const ULayer &Lr, int B, const bf16_t *gout, int go_cs, int go_co, int Hgo,
+           int Wgo, int Hin, int Win, bf16_t *gin, int gi_cs, int gi_co, hipStream_t st)
+{
+    ConvArgs a{};
+    a.in = gout;
+    a.in_cs = go_cs;
+    a.in_co = go_co;
+    a.B = B;
+    a.Hin = Hgo;
+    a.Win = Wgo;
+    a.w = u->wt16 + Lr.wt_off;
+    a.Hout = Hin;
+    a.Wout = Win;
+    a.bias = nullptr;
+    a.relu = 0;
+    a.mode = 0;
+    a.out = gin;
+    a.out_cs = gi_cs;
+    a.out_co = gi_co;
+    a.oscale = 1.f;
+    if (Lr.kind == L_CONV) {
+        a.Cin = Lr.Nw;
+        a.Nw = Lr.Cin;
+        a.ntaps = 9;
+        a.tw = 3;
+        a.org = -1;
+        a.stride = 1;
+    } else if (Lr.kind == L_UP) {
+        a.Cin = Lr.cout;
+        a.Nw = Lr.Cin;
+        a.ntaps = 4;
+        a.tw = 2;
+        a.org = 0;
+        a.stride = 2;
+    } else {
+        a.Cin = 16;
+        a.Nw = Lr.Cin;
+        a.ntaps = 1;
+        a.tw = 1;
+        a.org = 0;
+        a.stride = 1;
+    }
+    a.cout = a.Nw;
+    conv_launch(a, st);
+}
+
+// weight and bias gradients of layer Lr into u->g
+void wgrad(gct_unet *u, const ULayer &Lr, int B, const bf16_t *x, int x_cs, int x_co, int Hin, int Win,
+           const bf16_t *dy, int dy_cs, int dy_co, int Hout, int Wout, hipStream_t st)
+{
+    WgradArgs a{};
+    a.x = x;
+    a.x_cs = x_cs;
+    a.x_co = x_co;
+    a.Hin = Hin;
+    a.Win = Win;
+    a.Cin = Lr.Cin;
+    a.ntaps = Lr.ntaps;
+    a.tw = Lr.tw;
+    a.org = Lr.org;
+    a.stride = Lr.stride;
+    a.dy = dy;
+    a.dy_cs = dy_cs;
+    a.dy_co = dy_co;
+    a.Nw = Lr.Nw;
+    a.mode = Lr.kind == L_UP ? 2 : 0;
+    a.cout = Lr.cout;
+    a.B = B;
+    a.Hout = Hout;
+    a.Wout = Wout;
+    const long long M = (long long)B * Hout * Wout;
+    int nch, chunk;
+    wgrad_split(Lr, M, nch, chunk);
+    a.chunk = chunk;
+    a.part = u->part;
+    dim3 grid(cdiv(Lr.Nw, 16), cdiv(Lr.Cin, 64), Lr.ntaps * nch);
+    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, a);
+    const size_t len = (size_t)Lr.ntaps * Lr.Nw * Lr.Cin;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(std::min(1024, cdiv((long long)len, 256))), dim3(256), 0, st,
+                       (const float *)u->part, nch, len, u->g + Lr.w_off);
+    // bias: over the pixels of the layer's output grid
+    long long npix;
+    int bcs = dy_cs, bco = dy_co;
+    if (Lr.kind == L_UP)
+        npix = 4LL * M;
+    else
+        npix = M;
+    int nblk, bchunk;
+    bias_split(npix, nblk, bchunk);
+    hipLaunchKernelGGL(k_bias_partial, dim3(nblk), dim3(256), 0, st, dy, bcs, bco, Lr.cout, (int)npix, bchunk,
+                       u->part);
+    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, st, (const float *)u->part, nblk,
+                       (size_t)Lr.cout, u->g + Lr.b_off);
+}
+
+void relu_bwd(bf16_t *gy, int g_cs, int g_co, const bf16_t *y, int y_cs, int y_co, int C, long long npix,
+              hipStream_t st)
+{
+    const long long n = npix * C;
+    hipLaunchKernelGGL(k_relu_bwd, dim3(cdiv(n, 256)), dim3(256), 0, st, gy, g_cs, g_co, y, y_cs, y_co, C,
+                       (size_t)npix);
+}
+
+void refresh_bf16(gct_unet *u, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_to_bf16, dim3(cdiv((long long)u->nparam, 256)), dim3(256), 0, st, (const float *)u->w,
+                       u->nparam, u->w16);
+    for (const ULayer &Lr : u->layers) {
+        if (!Lr.need_dgrad) continue;
+        int nt, N, Cc, Np, flip;
+        if (Lr.kind == L_CONV) {
+            nt = 9; N = Lr.Nw; Cc = Lr.Cin; Np = Lr.Nw; flip = 1;
+        } else if (Lr.kind == L_UP) {
+            nt = 4; N = Lr.cout; Cc = Lr.Cin; Np = Lr.cout; flip = 0;
+        } else {
+            nt = 1; N = 1; Cc = Lr.Cin; Np = 16; flip = 0;
+        }
+        const long long n = (long long)nt * Np * Cc;
+        hipLaunchKernelGGL(k_transpose_taps, dim3(cdiv(n, 256)), dim3(256), 0, st, (const float *)(u->w + Lr.w_off),
+                           nt, N, Cc, Np, flip, u->wt16 + Lr.wt_off);
+    }
+}
+
+void fill(float *p, size_t n, float v, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_fill, dim3(std::min(2048, cdiv((long long)n, 256))), dim3(256), 0, st, p, n, v);
+}
+
+ULayer make_layer(int kind, int Cin, int cout)
+{
+    ULayer Lr{};
+    Lr.kind = kind;
+    Lr.Cin = Cin;
+    Lr.cout = cout;
+    if (kind == L_CONV) {
+        Lr.ntaps = 9; Lr.tw = 3; Lr.org = -1; Lr.stride = 1; Lr.Nw = cout;
+    } else if (kind == L_UP) {
+        Lr.ntaps = 1; Lr.tw = 1; Lr.org = 0; Lr.stride = 1; Lr.Nw = 4 * cout;
+    } else {
+        Lr.ntaps = 1; Lr.tw = 1; Lr.org = 0; Lr.stride = 1; Lr.Nw = 1;
+    }
+    Lr.need_dgrad = true;
+    return Lr;
+}
+
+}  // namespace
+}  // namespace gct
+
+using namespace gct;
+
+extern "C" {
+
+int gct_unet_create(const gct_unet_config *cfg, gct_unet **out)
+{
+    if (!cfg || !out) return fail(GCT_EINVAL, "NULL argument");
+    *out = nullptr;
+    const int L = cfg->levels, C0 = cfg->base_channels;
+    if (L < 1 || L > 6) return fail(GCT_EINVAL, "levels must be in [1, 6]");
+    if (C0 < 16 || C0 % 16 != 0 || ((long long)C0 << (L - 1)) > 1024)
+        return fail(GCT_EINVAL, "base_channels must be a multiple of 16 with base_channels 2^(levels-1) <= 1024");
+    const int div = 1 << (L - 1);
+    if (cfg->height < div || cfg->width < div || cfg->height % div || cfg->width % div)
+        return fail(GCT_EINVAL, "height and width must be positive multiples of 2^(levels-1)");
+    if (cfg->max_batch < 1 || (long long)cfg->max_batch * cfg->height * cfg->width > (1LL << 28))
+        return fail(GCT_EINVAL, "max_batch must be >= 1 with max_batch height width <= 2^28");
+
+    gct_unet *u = new gct_unet();
+    u->L = L;
+    u->C0 = C0;
+    u->H = cfg->height;
+    u->W = cfg->width;
+    u->maxB = cfg->max_batch;
+    if (hipGetDevice(&u->device) != hipSuccess) {
+        delete u;
+        return fail(GCT_EHIP, "hipGetDevice failed");
+    }
+    // parameter layout
+    auto add = [&](ULayer Lr) {
+        u->layers.push_back(Lr);
+        return (int)u->layers.size() - 1;
+    };
+    u->enc1.assign(L, -1);
+    u->enc2.assign(L, -1);
+    u->up.assign(L, -1);
+    u->dec1.assign(L, -1);
+    u->dec2.assign(L, -1);
+    for (int l = 0; l < L; ++l) {
+        u->enc1[l] = add(make_layer(L_CONV, l == 0 ? 16 : u->C(l - 1), u->C(l)));
+        u->enc2[l] = add(make_layer(L_CONV, u->C(l), u->C(l)));
+    }
+    u->layers[u->enc1[0]].need_dgrad = false;
+    for (int l = L - 2; l >= 0; --l) {
+        u->up[l] = add(make_layer(L_UP, u->C(l + 1), u->C(l)));
+        u->dec1[l] = add(make_layer(L_CONV, 2 * u->C(l), u->C(l)));
+        u->dec2[l] = add(make_layer(L_CONV, u->C(l), u->C(l)));
+    }
+    u->fin = add(make_layer(L_FINAL, C0, 1));
+    size_t off = 0, woff = 0;
+    for (ULayer &Lr : u->layers) {
+        Lr.w_off = off;
+        off = al64(off + (size_t)Lr.ntaps * Lr.Nw * Lr.Cin);
+        Lr.b_off = off;
+        off = al64(off + Lr.cout);
+        Lr.wt_off = woff;
+        const int np = Lr.kind == L_FINAL ? 16 : Lr.Nw;
+        if (Lr.need_dgrad) woff = al64(woff + (size_t)Lr.ntaps * np * Lr.Cin);
+    }
+    u->nparam = off;
+    u->nwt = std::max<size_t>(woff, 64);
+    // scratch for K-split partials: the largest need over layers at max_batch
+    size_t part = 512 * 1024;
+    for (int l = 0; l < L; ++l) {
+        auto need = [&](int idx, long long M) {
+            if (idx < 0) return;
+            const ULayer &Lr = u->layers[idx];
+            part = std::max(part, (size_t)wgrad_max_chunks(Lr, M) * Lr.ntaps * Lr.Nw * Lr.Cin);
+            int nb, bc;
+            bias_split(Lr.kind == L_UP ? 4 * M : M, nb, bc);
+            part = std::max(part, (size_t)nb * Lr.cout);
+        };
+        const long long Ml = (long long)u->maxB * u->Hl(l) * u->Wl(l);
+        need(u->enc1[l], Ml);
+        need(u->enc2[l], Ml);
+        need(u->dec1[l], Ml);
+        need(u->dec2[l], Ml);
+        if (u->up[l] >= 0) need(u->up[l], (long long)u->maxB * u->Hl(l + 1) * u->Wl(l + 1));
+    }
+    {
+        const ULayer &Lr = u->layers[u->fin];
+        part = std::max(part, (size_t)wgrad_max_chunks(Lr, (long long)u->maxB * u->H * u->W) * Lr.Cin);
+    }
+    u->part_elems = part;
+
+    // activation arena
+    std::vector<std::pair<gct::bf16_t **, size_t>> plan;
+    u->x.assign(L, nullptr);
+    u->e.assign(L, nullptr);
+    u->s.assign(L, nullptr);
+    u->d1.assign(L, nullptr);
+    u->d2.assign(L, nullptr);
+    u->gx.assign(L, nullptr);
+    u->ge.assign(L, nullptr);
+    u->gs.assign(L, nullptr);
+    u->gd1.assign(L, nullptr);
+    u->gd2.assign(L, nullptr);
+    for (int l = 0; l < L; ++l) {
+        const size_t px = (size_t)u->maxB * u->Hl(l) * u->Wl(l);
+        const int Cl = u->C(l);
+        const int cs = l < L - 1 ? 2 * Cl : Cl;
+        plan.push_back({&u->x[l], px * (l == 0 ? 16 : u->C(l - 1))});
+        plan.push_back({&u->e[l], px * Cl});
+        plan.push_back({&u->s[l], px * cs});
+        plan.push_back({&u->ge[l], px * Cl});
+        plan.push_back({&u->gs[l], px * cs});
+        if (l > 0) plan.push_back({&u->gx[l], px * u->C(l - 1)});
+        if (l < L - 1) {
+            plan.push_back({&u->d1[l], px * Cl});
+            plan.push_back({&u->d2[l], px * Cl});
+            plan.push_back({&u->gd1[l], px * Cl});
+            plan.push_back({&u->gd2[l], px * Cl});
+        }
+    }
+    plan.push_back({&u->dy16, (size_t)u->maxB * u->H * u->W * 16});
+    size_t bytes = 0;
+    std::vector<size_t> offs;
+    for (auto &pr : plan) {
+        offs.push_back(bytes);
+        bytes += align256(pr.second * sizeof(gct::bf16_t));
+    }
+    hipError_t e = hipSuccess;
+    auto grab = [&](void **p, size_t b) {
+        if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(b, 256));
+    };
+    grab((void **)&u->w, u->nparam * 4);
+    grab((void **)&u->g, u->nparam * 4);
+    grab((void **)&u->m, u->nparam * 4);
+    grab((void **)&u->v, u->nparam * 4);
+    grab((void **)&u->w16, u->nparam * 2);
+    grab((void **)&u->wt16, u->nwt * 2);
+    grab((void **)&u->part, u->part_elems * 4);
+    grab((void **)&u->lpart, 1024 * 8);
+    grab((void **)&u->loss, 256);
+    grab(&u->arena, bytes);
+    if (e != hipSuccess) {
+        gct_unet_destroy(u);
+        return fail(GCT_EHIP, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    for (size_t i = 0; i < plan.size(); ++i) *plan[i].first = (gct::bf16_t *)((char *)u->arena + offs[i]);
+    fill(u->w, u->nparam, 0.f, nullptr);
+    fill(u->g, u->nparam, 0.f, nullptr);
+    fill(u->m, u->nparam, 0.f, nullptr);
+    fill(u->v, u->nparam, 0.f, nullptr);
+    refresh_bf16(u, nullptr);
+    e = hipStreamSynchronize(nullptr);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+        gct_unet_destroy(u);
+        return fail(GCT_EHIP, std::string("U-Net init failed: ") + hipGetErrorString(e));
+    }
+    *out = u;
+    return GCT_OK;
+}
+
+int gct_unet_destroy(gct_unet *u)
+{
+    if (!u) return GCT_OK;
+    (void)hipFree(u->w);
+    (void)hipFree(u->g);
+    (void)hipFree(u->m);
+    (void)hipFree(u->v);
+    (void)hipFree(u->w16);
+    (void)hipFree(u->wt16);
+    (void)hipFree(u->part);
+    (void)hipFree(u->lpart);
+    (void)hipFree(u->loss);
+    (void)hipFree(u->arena);
+    delete u;
+    return GCT_OK;
+}
+
+int gct_unet_param_count(const gct_unet *u, int64_t *n)
+{
+    if (!u || !n) return fail(GCT_EINVAL, "NULL argument");
+    *n = (int64_t)u->nparam;
+    return GCT_OK;
+}
+
+int gct_unet_layer_count(const gct_unet *u, int32_t *n)
+{
+    if (!u || !n) return fail(GCT_EINVAL, "NULL argument");
+    *n = (int32_t)u->layers.size();
+    return GCT_OK;
+}
+
+int gct_unet_layer_info(const gct_unet *u, int32_t i, gct_unet_layer *info)
+{
+    if (!u || !info) return fail(GCT_EINVAL, "NULL argument");
+    if (i < 0 || i >= (int32_t)u->layers.size()) return fail(GCT_EINVAL, "layer index out of range");
+    const ULayer &Lr = u->layers[i];
+    info->kind = Lr.kind;
+    info->taps = Lr.kind == L_CONV ? 9 : Lr.kind == L_UP ? 4 : 1;
+    info->in_channels = Lr.Cin;
+    info->out_channels = Lr.cout;
+    info->weight_offset = (int64_t)Lr.w_off;
+    info->bias_offset = (int64_t)Lr.b_off;
+    return GCT_OK;
+}
+
+int gct_unet_set_params(gct_unet *u, const float *params, void *stream)
+{
+    if (!u || !params) return fail(GCT_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(u->w, params, u->nparam * 4, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return check_hip(e, "gct_unet_set_params");
+    refresh_bf16(u, st);
+    return check_hip(last_launch(), "gct_unet_set_params");
+}
+
+int gct_unet_get_params(const gct_unet *u, float *params, void *stream)
+{
+    if (!u || !params) return fail(GCT_EINVAL, "NULL argument");
+    return check_hip(hipMemcpyAsync(params, u->w, u->nparam * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                     "gct_unet_get_params");
+}
+
+int gct_unet_get_grads(const gct_unet *u, float *grads, void *stream)
+{
+    if (!u || !grads) return fail(GCT_EINVAL, "NULL argument");
+    return check_hip(hipMemcpyAsync(grads, u->g, u->nparam * 4, hipMemcpyDeviceToDevice, (hipStream_t)stream),
+                     "gct_unet_get_grads");
+}
+
+int gct_unet_get_moments(const gct_unet *u, float *m, float *v, void *stream)
+{
+    if (!u || !m || !v) return fail(GCT_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(m, u->m, u->nparam * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(v, u->v, u->nparam * 4, hipMemcpyDeviceToDevice, st);
+    return check_hip(e, "gct_unet_get_moments");
+}
+
+int gct_unet_set_moments(gct_unet *u, const float *m, const float *v, void *stream)
+{
+    if (!u) return fail(GCT_EINVAL, "NULL argument");
+    hipStream_t st = (hipStream_t)stream;
+    if (!m || !v) {
+        if (m || v) return fail(GCT_EINVAL, "m and v must both be given or both be NULL");
+        fill(u->m, u->nparam, 0.f, st);
+        fill(u->v, u->nparam, 0.f, st);
+        return check_hip(last_launch(), "gct_unet_set_moments");
+    }
+    hipError_t e = hipMemcpyAsync(u->m, m, u->nparam * 4, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(u->v, v, u->nparam * 4, hipMemcpyDeviceToDevice, st);
+    return check_hip(e, "gct_unet_set_moments");
+}
+
+int gct_unet_forward(gct_unet *u, int32_t batch, const float *x, float in_scale, float out_scale, float *y,
+                     void *stream)
+{
+    if (!u || !x || !y) return fail(GCT_EINVAL, "NULL argument");
+    if (batch < 1 || batch > u->maxB) return fail(GCT_EINVAL, "batch must be in [1, max_batch]");
+    if (!std::isfinite(in_scale) || !std::isfinite(out_scale))
+        return fail(GCT_EINVAL, "scales must be finite");
+    hipStream_t st = (hipStream_t)stream;
+    const int L = u->L, B = batch;
+    u->oscale = out_scale;
+    const long long npix = (long long)B * u->H * u->W;
+    hipLaunchKernelGGL(k_prep_input, dim3(cdiv(npix, 256)), dim3(256), 0, st, x, in_scale, (int)npix, u->x[0]);
+    for (int l = 0; l < L; ++l) {
+        const int Hl = u->Hl(l), Wl = u->Wl(l), Cl = u->C(l);
+        const int in_cs = l == 0 ? 16 : u->C(l - 1);
+        fwd(u, u->layers[u->enc1[l]], B, u->x[l], in_cs, 0, Hl, Wl, Hl, Wl, u->e[l], Cl, 0, 1, 0, nullptr, st);
+        if (l < L - 1) {
+            fwd(u, u->layers[u->enc2[l]], B, u->e[l], Cl, 0, Hl, Wl, Hl, Wl, u->s[l], 2 * Cl, Cl, 1, 0, nullptr, st);
+            const long long n = (long long)B * (Hl / 2) * (Wl / 2) * Cl;
+            hipLaunchKernelGGL(k_maxpool, dim3(cdiv(n, 256)), dim3(256), 0, st, (const bf16_t *)u->s[l], 2 * Cl, Cl,
+                               B, Hl, Wl, Cl, u->x[l + 1]);
+        } else {
+            fwd(u, u->layers[u->enc2[l]], B, u->e[l], Cl, 0, Hl, Wl, Hl, Wl, u->s[l], Cl, 0, 1, 0, nullptr, st);
+        }
+    }
+    const bf16_t *prev = u->s[L - 1];
+    for (int l = L - 2; l >= 0; --l) {
+        const int Hl = u->Hl(l), Wl = u->Wl(l), Cl = u->C(l);
+        const int Hn = u->Hl(l + 1), Wn = u->Wl(l + 1);
+        fwd(u, u->layers[u->up[l]], B, prev, u->C(l + 1), 0, Hn, Wn, Hn, Wn, u->s[l], 2 * Cl, 0, 0, 2, nullptr, st);
+        fwd(u, u->layers[u->dec1[l]], B, u->s[l], 2 * Cl, 0, Hl, Wl, Hl, Wl, u->d1[l], Cl, 0, 1, 0, nullptr, st);
+        fwd(u, u->layers[u->dec2[l]], B, u->d1[l], Cl, 0, Hl, Wl, Hl, Wl, u->d2[l], Cl, 0, 1, 0, nullptr, st);
+        prev = u->d2[l];
+    }
+    fwd(u, u->layers[u->fin], B, prev, u->C0, 0, u->H, u->W, u->H, u->W, nullptr, 0, 0, 0, 1, y, st);
+    u->last_batch = B;
+    return check_hip(last_launch(), "gct_unet_forward");
+}
+
+int gct_unet_backward(gct_unet *u, int32_t batch, const float *y, const float *target, float *loss,
+                      void *stream)
+{
+    if (!u || !y || !target) return fail(GCT_EINVAL, "NULL argument");
+    if (batch != u->last_batch) return fail(GCT_EINVAL, "batch differs from the preceding forward");
+    hipStream_t st = (hipStream_t)stream;
+    const int L = u->L, B = batch;
+    const long long npix = (long long)B * u->H * u->W;
+    const int nb = std::min(1024, cdiv(npix, 256));
+    hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, st, y, target, (int)npix, 2.f * u->oscale / (float)npix,
+                       u->dy16, u->lpart);
+    hipLaunchKernelGGL(k_mse_fin, dim3(1), dim3(64), 0, st, (const double *)u->lpart, nb, (int)npix,
+                       loss ? loss : u->loss);
+    // final 1x1
+    bf16_t *top = L > 1 ? u->d2[0] : u->s[0];
+    bf16_t *gtop = L > 1 ? u->gd2[0] : u->gs[0];
+    {
+        const ULayer &Lr = u->layers[u->fin];
+        wgrad(u, Lr, B, top, u->C0, 0, u->H, u->W, u->dy16, 16, 0, u->H, u->W, st);
+        dgrad(u, Lr, B, u->dy16, 16, 0, u->H, u->W, u->H, u->W, gtop, u->C0, 0, st);
+    }
+    // decoder, top level first
+    for (int l = 0; l <= L - 2; ++l) {
+        const int Hl = u->Hl(l), Wl = u->Wl(l), Cl = u->C(l);
+        const long long px = (long long)B * Hl * Wl;
+        relu_bwd(u->gd2[l], Cl, 0, u->d2[l], Cl, 0, Cl, px, st);
+        const ULayer &D2 = u->layers[u->dec2[l]];
+        wgrad(u, D2, B, u->d1[l], Cl, 0, Hl, Wl, u->gd2[l], Cl, 0, Hl, Wl, st);
+        dgrad(u, D2, B, u->gd2[l], Cl, 0, Hl, Wl, Hl, Wl, u->gd1[l], Cl, 0, st);
+        relu_bwd(u->gd1[l], Cl, 0, u->d1[l], Cl, 0, Cl, px, st);
+        const ULayer &D1 = u->layers[u->dec1[l]];
+        wgrad(u, D1, B, u->s[l], 2 * Cl, 0, Hl, Wl, u->gd1[l], Cl, 0, Hl, Wl, st);
+        dgrad(u, D1, B, u->gd1[l], Cl, 0, Hl, Wl, Hl, Wl, u->gs[l], 2 * Cl, 0, st);
+        // transposed convolution from level l+1
+        const int Hn = u->Hl(l + 1), Wn = u->Wl(l + 1), Cn = u->C(l + 1);
+        const bool bott = l + 1 == L - 1;
+        const bf16_t *pin = bott ? u->s[L - 1] : u->d2[l + 1];
+        bf16_t *gpin = bott ? u->gs[L - 1] : u->gd2[l + 1];
+        const ULayer &U = u->layers[u->up[l]];
+        wgrad(u, U, B, pin, Cn, 0, Hn, Wn, u->gs[l], 2 * Cl, 0, Hn, Wn, st);
+        dgrad(u, U, B, u->gs[l], 2 * Cl, 0, Hl, Wl, Hn, Wn, gpin, Cn, 0, st);
+    }
+    // bottleneck
+    {
+        const int l = L - 1, Hl = u->Hl(l), Wl = u->Wl(l), Cl = u->C(l);
+        const long long px = (long long)B * Hl * Wl;
+        relu_bwd(u->gs[l], Cl, 0, u->s[l], Cl, 0, Cl, px, st);
+        const ULayer &E2 = u->layers[u->enc2[l]];
+        wgrad(u, E2, B, u->e[l], Cl, 0, Hl, Wl, u->gs[l], Cl, 0, Hl, Wl, st);
+        dgrad(u, E2, B, u->gs[l], Cl, 0, Hl, Wl, Hl, Wl, u->ge[l], Cl, 0, st);
+        relu_bwd(u->ge[l], Cl, 0, u->e[l], Cl, 0, Cl, px, st);
+        const ULayer &E1 = u->layers[u->enc1[l]];
+        const int xc = l == 0 ? 16 : u->C(l - 1);
+        wgrad(u, E1, B, u->x[l], xc, 0, Hl, Wl, u->ge[l], Cl, 0, Hl, Wl, st);
+        if (l > 0) dgrad(u, E1, B, u->ge[l], Cl, 0, Hl, Wl, Hl, Wl, u->gx[l], xc, 0, st);
+    }
+    // encoder, deepest first
+    for (int l = L - 2; l >= 0; --l) {
+        const int Hl = u->Hl(l), Wl = u->Wl(l), Cl = u->C(l);
+        const long long px = (long long)B * Hl * Wl;
+        const long long n = (long long)B * (Hl / 2) * (Wl / 2) * Cl;
+        hipLaunchKernelGGL(k_maxpool_bwd, dim3(cdiv(n, 256)), dim3(256), 0, st, (const bf16_t *)u->s[l], 2 * Cl, Cl,
+                           B, Hl, Wl, Cl, (const bf16_t *)u->gx[l + 1], u->gs[l], 2 * Cl, Cl);
+        relu_bwd(u->gs[l], 2 * Cl, Cl, u->s[l], 2 * Cl, Cl, Cl, px, st);
+        const ULayer &E2 = u->layers[u->enc2[l]];
+        wgrad(u, E2, B, u->e[l], Cl, 0, Hl, Wl, u->gs[l], 2 * Cl, Cl, Hl, Wl, st);
+        dgrad(u, E2, B, u->gs[l], 2 * Cl, Cl, Hl, Wl, Hl, Wl, u->ge[l], Cl, 0, st);
+        relu_bwd(u->ge[l], Cl, 0, u->e[l], Cl, 0, Cl, px, st);
+        const ULayer &E1 = u->layers[u->enc1[l]];
+        const int xc = l == 0 ? 16 : u->C(l - 1);
+        wgrad(u, E1, B, u->x[l], xc, 0, Hl, Wl, u->ge[l], Cl, 0, Hl, Wl, st);
+        if (l > 0) dgrad(u, E1, B, u->ge[l], Cl, 0, Hl, Wl, Hl, Wl, u->gx[l], xc, 0, st);
+    }
+    return check_hip(last_launch(), "gct_unet_backward");
+}
+
+int gct_unet_adam_step(gct_unet *u, float lr, float beta1, float beta2, float eps, int32_t step, void *stream)
+{
+    if (!u) return fail(GCT_EINVAL, "NULL argument");
+    if (step < 1) return fail(GCT_EINVAL, "step counts from 1");
+    if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+        return fail(GCT_EINVAL, "bad Adam hyper-parameters");
+    hipStream_t st = (hipStream_t)stream;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+    hipLaunchKernelGGL(k_adam, dim3(cdiv((long long)u->nparam, 256)), dim3(256), 0, st, u->w, (const float *)u->g,
+                       u->m, u->v, u->nparam, lr, beta1, beta2, eps, c1, c2);
+    refresh_bf16(u, st);
+    return check_hip(last_launch(), "gct_unet_adam_step");
+}
+
+}  // extern "C"

@@ -58,6 +58,17 @@ class _BatchInfo(ctypes.Structure):
                 ("spectrum_elems", ctypes.c_int64)]
 
 
+class _UNetConfig(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("base_channels", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("max_batch", ctypes.c_int32)]
+
+
+class _UNetLayer(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("taps", ctypes.c_int32), ("in_channels", ctypes.c_int32),
+                ("out_channels", ctypes.c_int32), ("weight_offset", ctypes.c_int64),
+                ("bias_offset", ctypes.c_int64)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
@@ -98,6 +109,20 @@ def _load():
                                       ctypes.POINTER(ctypes.c_int)]
     L.gct_host_degree.argtypes = [dbl, dbl]
     L.gct_host_degree.restype = ctypes.c_int
+    flt = ctypes.c_float
+    L.gct_unet_create.argtypes = [ctypes.POINTER(_UNetConfig), ctypes.POINTER(vp)]
+    L.gct_unet_destroy.argtypes = [vp]
+    L.gct_unet_param_count.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.gct_unet_layer_count.argtypes = [vp, ctypes.POINTER(i32)]
+    L.gct_unet_layer_info.argtypes = [vp, i32, ctypes.POINTER(_UNetLayer)]
+    L.gct_unet_set_params.argtypes = [vp, vp, vp]
+    L.gct_unet_get_params.argtypes = [vp, vp, vp]
+    L.gct_unet_get_grads.argtypes = [vp, vp, vp]
+    L.gct_unet_get_moments.argtypes = [vp, vp, vp, vp]
+    L.gct_unet_set_moments.argtypes = [vp, vp, vp, vp]
+    L.gct_unet_forward.argtypes = [vp, i32, vp, flt, flt, vp, vp]
+    L.gct_unet_backward.argtypes = [vp, i32, vp, vp, vp, vp]
+    L.gct_unet_adam_step.argtypes = [vp, flt, flt, flt, flt, i32, vp]
     return L
 
 
@@ -178,7 +203,7 @@ class Plan:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.gct_plan_destroy(h)
             self._h = None
 
@@ -291,7 +316,7 @@ class Batch:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.gct_batch_destroy(h)
             self._h = None
 
@@ -391,3 +416,90 @@ def host_bp_weights(N, theta, M, angle, t, ly=1.0, zeta=0.0, lx=(1.0, 1.0), K=40
 
 def host_degree(theta: float, zeta: float) -> int:
     return int(lib.gct_host_degree(float(theta), float(zeta)))
+
+
+# ---------------------------------------------------------------------------
+# Warm-start U-Net (include/gramct_unet.h)
+# ---------------------------------------------------------------------------
+UNET_CONV3, UNET_UPCONV, UNET_FINAL = 0, 1, 2
+
+
+class UNet:
+    """gct_unet: parameters, moments and activations for up to max_batch
+    images of height x width live in the library's device buffers."""
+
+    def __init__(self, levels=4, base_channels=32, height=256, width=256, max_batch=1):
+        cfg = _UNetConfig(int(levels), int(base_channels), int(height), int(width), int(max_batch))
+        h = ctypes.c_void_p()
+        _check(lib.gct_unet_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self.levels, self.base_channels = int(levels), int(base_channels)
+        self.height, self.width, self.max_batch = int(height), int(width), int(max_batch)
+        n = ctypes.c_int64()
+        _check(lib.gct_unet_param_count(h, ctypes.byref(n)))
+        self.n_params = int(n.value)
+        k = ctypes.c_int32()
+        _check(lib.gct_unet_layer_count(h, ctypes.byref(k)))
+        self.layers = []
+        for i in range(k.value):
+            ly = _UNetLayer()
+            _check(lib.gct_unet_layer_info(h, i, ctypes.byref(ly)))
+            self.layers.append(dict(kind=ly.kind, taps=ly.taps, cin=ly.in_channels,
+                                    cout=ly.out_channels, w_off=ly.weight_offset,
+                                    b_off=ly.bias_offset))
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and lib is not None:
+            lib.gct_unet_destroy(h)
+            self._h = None
+
+    def _img(self, t: torch.Tensor, batch: int) -> int:
+        return _ptr(t, batch * self.height * self.width, torch.float32)
+
+
+def unet_set_params(net: UNet, params: torch.Tensor):
+    _check(lib.gct_unet_set_params(net.handle, _ptr(params, net.n_params, torch.float32), _stream()))
+
+
+def unet_get_params(net: UNet, out: torch.Tensor):
+    _check(lib.gct_unet_get_params(net.handle, _ptr(out, net.n_params, torch.float32), _stream()))
+
+
+def unet_get_grads(net: UNet, out: torch.Tensor):
+    _check(lib.gct_unet_get_grads(net.handle, _ptr(out, net.n_params, torch.float32), _stream()))
+
+
+def unet_get_moments(net: UNet, m: torch.Tensor, v: torch.Tensor):
+    _check(lib.gct_unet_get_moments(net.handle, _ptr(m, net.n_params, torch.float32),
+                                    _ptr(v, net.n_params, torch.float32), _stream()))
+
+
+def unet_set_moments(net: UNet, m: torch.Tensor | None, v: torch.Tensor | None):
+    pm = None if m is None else _ptr(m, net.n_params, torch.float32)
+    pv = None if v is None else _ptr(v, net.n_params, torch.float32)
+    _check(lib.gct_unet_set_moments(net.handle, pm, pv, _stream()))
+
+
+def unet_forward(net: UNet, x: torch.Tensor, y: torch.Tensor, in_scale: float = 1.0,
+                 out_scale: float = 1.0, batch: int | None = None):
+    B = x.numel() // (net.height * net.width) if batch is None else int(batch)
+    _check(lib.gct_unet_forward(net.handle, B, net._img(x, B), float(in_scale), float(out_scale),
+                                net._img(y, B), _stream()))
+
+
+def unet_backward(net: UNet, y: torch.Tensor, target: torch.Tensor, loss: torch.Tensor | None = None,
+                  batch: int | None = None):
+    B = y.numel() // (net.height * net.width) if batch is None else int(batch)
+    pl = None if loss is None else _ptr(loss, 1, torch.float32)
+    _check(lib.gct_unet_backward(net.handle, B, net._img(y, B), net._img(target, B), pl, _stream()))
+
+
+def unet_adam_step(net: UNet, lr: float, step: int, beta1: float = 0.9, beta2: float = 0.999,
+                   eps: float = 1e-8):
+    _check(lib.gct_unet_adam_step(net.handle, float(lr), float(beta1), float(beta2), float(eps),
+                                  int(step), _stream()))

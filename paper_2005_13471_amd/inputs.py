@@ -108,6 +108,23 @@ def add_noise(sino: np.ndarray, eta: float, seed: int) -> np.ndarray:
     return sino + rng.normal(0.0, sigma, size=sino.shape)
 
 
+def noise_normals(n: int, M: int, seed: int) -> np.ndarray:
+    """The standard normals that add_noise(., eta, seed) scales by sigma for
+    an n x M sinogram (same generator and draw order)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.standard_normal(size=(n, M))
+
+
+def draw_slice(args) -> tuple[np.ndarray, np.ndarray]:
+    """Phantom coefficients and sinogram noise normals of one training or
+    test slice: args = (N, ellipses, n, M, seed); the noise uses seed
+    NOISE_SEED_BASE + seed.  Returned as float32 (a process-pool worker)."""
+    N, count, n, M, seed = args
+    c, _ = phantom(N, count, seed)
+    z = noise_normals(n, M, NOISE_SEED_BASE + seed)
+    return c.astype(np.float32), z.astype(np.float32)
+
+
 def analytic_sinogram(ells: list[Ellipse], theta: np.ndarray, M: int, ly: float = 1.0,
                       zeta: float = 0.0) -> np.ndarray:
     """Line integrals of the continuous ellipse phantom at y_m = ly (m - (M-1)/2),

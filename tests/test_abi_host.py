@@ -92,3 +92,17 @@ def test_host_bp_weights_match_oracle_backprojection(gct, zeta, ly, lx):
             idx = m0 + jlo + np.arange(w.size) + K
             pv = np.where((idx >= 0) & (idx < M + 2 * K), p[a][np.clip(idx, 0, M + 2 * K - 1)], 0.0)
             assert abs(np.dot(pv, w) - ref) < 1e-11 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(levels=0), "levels"), (dict(levels=7), "levels"), (dict(base_channels=24), "base_channels"),
+    (dict(base_channels=512, levels=4), "base_channels"), (dict(height=100), "height"),
+    (dict(width=0), "height"), (dict(max_batch=0), "max_batch"),
+    (dict(max_batch=1 << 14, height=256, width=256), "max_batch"),
+])
+def test_unet_rejects_bad_config_without_gpu(gct, kw, msg):
+    args = dict(levels=4, base_channels=32, height=256, width=256, max_batch=1)
+    args.update(kw)
+    with pytest.raises(gct.GramctError) as e:
+        gct.UNet(**args)
+    assert e.value.code == gct.GCT_EINVAL and msg in str(e.value)

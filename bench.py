@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-slices", type=int, default=256)
+    ap.add_argument("--warm-slices", type=int, default=64,
+                    help="held-out slices for the plain vs warm-start CG comparison (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="output pixels of the oracle's direct-sum apply timed for cpu_baseline "
                          "(0: all N^2, one whole apply)")
@@ -190,6 +192,26 @@ def batch_main(args):
     print(json.dumps(out), flush=True)
 
 
+def warm_compare(slices: int):
+    """Plain vs learned-warm-start CG on held-out slices of the warm-start
+    workload (N = 256, 180 angles, 366 bins, blur 1, 40 ellipses, 1% noise;
+    seeds 20000, 20001, ...): iterations and wall time to ||r|| <= 1e-4 ||b||,
+    U-Net inference included in the warm time."""
+    from paper_2005_13471_amd import warmstart as W
+    if not W.have_trained():
+        return {"error": "no trained weights at " + os.path.relpath(W.trained_path(), ROOT)}
+    cfg = W.WarmConfig()
+    prob = W.Problem(cfg, batch_slices=min(256, slices))
+    ws = W.WarmStart(prob, W.trained_path())
+    seeds = range(W.TEST_SEEDS[0], W.TEST_SEEDS[0] + slices)
+    b, _, _ = W.generate(prob, seeds, None, log=lambda *a: None, normalize=False)
+    rep = W.summarize(W.compare(prob, ws, b))
+    rep.update(workload="n256_a180_m366_z1", seeds=[W.TEST_SEEDS[0], W.TEST_SEEDS[0] + slices],
+               net=f"U-Net {cfg.levels} levels, {cfg.base_channels} base channels, bf16",
+               trained_steps=ws.meta.get("step"))
+    return rep
+
+
 def main():
     args = parse()
     if args.workload == "batch_uneven_256":
@@ -316,7 +338,7 @@ def main():
         "cg_plain": {"iters": res.iters, "ms": round(float(np.median(ph[:, 3])), 3),
                      "rel_res": res.rel_res, "rel_res_true": res.rel_res_true,
                      "status": res.status, "dot_dtype": "f64"},
-        "cg_warm": None,
+        "cg_warm": warm_compare(args.warm_slices) if args.warm_slices > 0 else None,
         "roofline": {"kernel": "gram_apply (rows / columns / rows FFT passes)", "bound": "hbm",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,

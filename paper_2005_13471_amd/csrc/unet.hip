@@ -89,6 +89,27 @@ struct ConvArgs {
     int cout;
 };
 
+// Epilogue of GEMM element (m, n) with accumulated value v (modes above).
+__device__ inline void conv_store(const ConvArgs &a, int m, int n, float v)
+{
+    if (a.mode == 0) {
+        if (a.bias) v += a.bias[n];
+        if (a.relu) v = fmaxf(v, 0.f);
+        a.out[(size_t)m * a.out_cs + a.out_co + n] = f2bf(v);
+    } else if (a.mode == 1) {
+        if (n == 0) a.out32[m] = a.oscale * (v + (a.bias ? a.bias[0] : 0.f));
+    } else {
+        const int HWo = a.Hout * a.Wout;
+        const int bb = m / HWo, rr = m - bb * HWo, yh = rr / a.Wout, yw = rr - yh * a.Wout;
+        const int ab = n / a.cout, co = n - ab * a.cout;
+        const int oy = 2 * yh + (ab >> 1), ox = 2 * yw + (ab & 1);
+        if (a.bias) v += a.bias[co];
+        if (a.relu) v = fmaxf(v, 0.f);
+        const size_t pix = ((size_t)bb * (2 * a.Hout) + oy) * (2 * a.Wout) + ox;
+        a.out[pix * a.out_cs + a.out_co + co] = f2bf(v);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_conv(ConvArgs a)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -135,24 +156,194 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int m = m0 + (lane >> 4) * 4 + j;
-            if (m >= M) continue;
-            float v = acc[q][j];
-            const int bb = m / HWo, rr = m - bb * HWo, yh = rr / a.Wout, yw = rr - yh * a.Wout;
-            if (a.mode == 0) {
-                if (a.bias) v += a.bias[n];
-                if (a.relu) v = fmaxf(v, 0.f);
-                a.out[(size_t)m * a.out_cs + a.out_co + n] = f2bf(v);
-            } else if (a.mode == 1) {
-                if (n == 0) a.out32[m] = a.oscale * (v + (a.bias ? a.bias[0] : 0.f));
-            } else {
-                const int ab = n / a.cout, co = n - ab * a.cout;
-                const int oy = 2 * yh + (ab >> 1), ox = 2 * yw + (ab & 1);
-                if (a.bias) v += a.bias[co];
-                if (a.relu) v = fmaxf(v, 0.f);
-                const size_t pix = ((size_t)bb * (2 * a.Hout) + oy) * (2 * a.Wout) + ox;
-                a.out[pix * a.out_cs + a.out_co + co] = f2bf(v);
+            if (m < M) conv_store(a, m, n, acc[q][j]);
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// LDS-tiled implicit GEMM for the same convolutions (every mode but the
+// one-column final layer).  Block tile BM x BN, K in steps of 32
+// (v_mfma_f32_16x16x32_bf16), 4 waves as 2 x 2, each wave (BM/2) x (BN/2).
+// K index k = t Cin + c; Cin is a multiple of 16, so each group of 8
+// consecutive k (one 16-byte load) lies in one tap; the last step of a
+// ragged K is zero-filled.  Operands are staged global -> registers -> LDS
+// in chunks of 4 steps (one barrier pair per chunk, the next chunk's loads
+// in flight during the MFMAs).  With gridDim.z > 1 the K steps are split
+// over z and FP32 partials part[z][m][n] are reduced by k_conv_splitk in a
+// fixed order.  (A reduction by the last block of each tile would need a
+// device-scope release per block, i.e. an L2 write-back, which costs more
+// than the extra launch.)
+// ---------------------------------------------------------------------------
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+template <int BM, int BN>
+__global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, float *part)
+{
+    constexpr int LDK = 40;  // 32 + 8 padding bf16: 80-byte rows, conflict-free 16-byte reads
+    constexpr int KC = 4;    // K steps staged per barrier (their loads are in flight together)
+    constexpr int AP = BM * 4 / 256;            // A chunks per thread and step
+    constexpr int BP = (BN * 4 + 255) / 256;    // B chunks per thread and step
+    constexpr int TM = BM / 32, TN = BN / 32;   // 16x16 tiles per wave
+    __shared__ __attribute__((aligned(16))) bf16_t sA[KC][BM * LDK];
+    __shared__ __attribute__((aligned(16))) bf16_t sB[KC][BN * LDK];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int HWo = a.Hout * a.Wout, M = a.B * HWo;
+    const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+    const int K = a.ntaps * a.Cin, nks = (K + 31) / 32;
+    const int kbeg = blockIdx.z * ksplit_steps, kend = min(nks, kbeg + ksplit_steps);
+    const int g = tid & 3;
+
+    // per-thread rows (A) and columns (B)
+    int rb[AP], rh[AP], rw[AP];
+    bool rok[AP];
+#pragma unroll
+    for (int i = 0; i < AP; ++i) {
+        const int m = m0 + (tid >> 2) + 64 * i;
+        rok[i] = m < M;
+        const int mm = rok[i] ? m : 0;
+        const int b = mm / HWo, r = mm - b * HWo, oh = r / a.Wout, ow = r - oh * a.Wout;
+        rb[i] = b * a.Hin;
+        rh[i] = oh * a.stride + a.org;
+        rw[i] = ow * a.stride + a.org;
+    }
+    bool cok[BP];
+    int cn[BP];
+#pragma unroll
+    for (int i = 0; i < BP; ++i) {
+        const int q = tid + 256 * i;
+        cn[i] = n0 + (q >> 2);
+        cok[i] = q < BN * 4 && cn[i] < a.Nw;
+    }
+    // k state of this thread's 8-group in the next step to load: k = ks 32 + 8 g
+    int kn = kbeg;
+    int t, c, dy, dx;
+    {
+        const int k = kbeg * 32 + 8 * g;
+        t = k / a.Cin;
+        c = k - t * a.Cin;
+        dy = t / a.tw;
+        dx = t - dy * a.tw;
+    }
+    uint4 ra[KC][AP], rbv[KC][BP];
+    // issue the loads of steps kn .. kn + KC - 1 (zero past kend or K)
+    auto gload = [&]() {
+#pragma unroll
+        for (int s = 0; s < KC; ++s) {
+            const bool kok = t < a.ntaps && kn + s < kend;
+#pragma unroll
+            for (int i = 0; i < AP; ++i) {
+                const int ih = rh[i] + dy, iw = rw[i] + dx;
+                const bool ok = kok && rok[i] && ih >= 0 && ih < a.Hin && iw >= 0 && iw < a.Win;
+                ra[s][i] = ok ? *reinterpret_cast<const uint4 *>(
+                                    a.in + ((size_t)(rb[i] + ih) * a.Win + iw) * a.in_cs + a.in_co + c)
+                              : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < BP; ++i) {
+                const bool ok = kok && cok[i];
+                rbv[s][i] = ok ? *reinterpret_cast<const uint4 *>(a.w + ((size_t)t * a.Nw + cn[i]) * a.Cin + c)
+                               : make_uint4(0, 0, 0, 0);
+            }
+            c += 32;
+            while (c >= a.Cin) {
+                c -= a.Cin;
+                ++t;
+                if (++dx == a.tw) {
+                    dx = 0;
+                    ++dy;
+                }
             }
         }
+        kn += KC;
+    };
+
+    float4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+
+    if (kbeg < kend) gload();
+    for (int ks0 = kbeg; ks0 < kend; ks0 += KC) {
+        if (ks0 != kbeg) __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+        for (int s = 0; s < KC; ++s) {
+#pragma unroll
+            for (int i = 0; i < AP; ++i)
+                *reinterpret_cast<uint4 *>(&sA[s][((tid >> 2) + 64 * i) * LDK + 8 * g]) = ra[s][i];
+#pragma unroll
+            for (int i = 0; i < BP; ++i) {
+                const int q = tid + 256 * i;
+                if (q < BN * 4) *reinterpret_cast<uint4 *>(&sB[s][(q >> 2) * LDK + 8 * g]) = rbv[s][i];
+            }
+        }
+        __syncthreads();
+        if (ks0 + KC < kend) gload();
+        const int ns = min(KC, kend - ks0);
+#pragma unroll
+        for (int s = 0; s < KC; ++s) {
+            if (s >= ns) break;
+            bf16x8_t af[TM], bfr[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                af[i] = *reinterpret_cast<const bf16x8_t *>(
+                    &sA[s][(wm * (BM / 2) + i * 16 + (lane & 15)) * LDK + (lane >> 4) * 8]);
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                bfr[j] = *reinterpret_cast<const bf16x8_t *>(
+                    &sB[s][(wn * (BN / 2) + j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8]);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    // D layout: row 4 (lane / 16) + r, column lane % 16 of each 16x16 tile
+    if (gridDim.z == 1) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int n = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+                if (n >= a.Nw) continue;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = m0 + wm * (BM / 2) + i * 16 + (lane >> 4) * 4 + r;
+                    if (m < M) conv_store(a, m, n, acc[i][j][r]);
+                }
+            }
+        return;
+    }
+    // split K: partial tile to part[z][m][n], reduced by k_conv_splitk
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int n = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+            if (n >= a.Nw) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = m0 + wm * (BM / 2) + i * 16 + (lane >> 4) * 4 + r;
+                if (m < M) part[((size_t)blockIdx.z * M + m) * a.Nw + n] = acc[i][j][r];
+            }
+        }
+}
+
+// sum of the split-K partials in z order (a fixed order), then the epilogue
+__global__ void __launch_bounds__(256) k_conv_splitk(ConvArgs a, int nz, const float *part)
+{
+    const size_t M = (size_t)a.B * a.Hout * a.Wout;
+    const size_t len = M * a.Nw;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
+        float v = 0.f;
+        for (int z = 0; z < nz; ++z) v += part[(size_t)z * len + i];
+        const int m = (int)(i / a.Nw), n = (int)(i - (size_t)m * a.Nw);
+        conv_store(a, m, n, v);
     }
 }
 
@@ -223,27 +414,192 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a)
     }
 }
 
-// sum partial tiles over chunks: out[i] = sum_ch part[ch][i]
+// LDS-staged weight gradient for Nw and Cin multiples of 8 (every layer but
+// the one-column final): block tile 64 (n) x 64 (c) of one tap, K = pixels
+// of the block's chunk in steps of 32.  Each thread loads 8 channels of one
+// pixel of dY and of X (16 bytes each) and stores them transposed
+// ([channel][pixel]) so that MFMA fragments are 16-byte LDS reads; 4 steps
+// are staged per barrier.  Chunk lengths are multiples of 32.
+__global__ void __launch_bounds__(256) k_wgrad2(WgradArgs a)
+{
+    constexpr int LDK = 40;
+    constexpr int KC = 4;  // 32-pixel steps staged per barrier
+    __shared__ __attribute__((aligned(16))) bf16_t sA[KC][64 * LDK];
+    __shared__ __attribute__((aligned(16))) bf16_t sB[KC][64 * LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int HWo = a.Hout * a.Wout, M = a.B * HWo;
+    const int n0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
+    const int t = blockIdx.z % a.ntaps, ch = blockIdx.z / a.ntaps;
+    const int mbeg = ch * a.chunk, mend = min(M, mbeg + a.chunk);
+    const int th = t / a.tw + a.org, twd = t % a.tw + a.org;
+    const int p = tid >> 3, cg = tid & 7;
+    const int nA = n0 + 8 * cg, cB = c0 + 8 * cg;
+    const bool nok = nA < a.Nw, cok = cB < a.Cin;
+    int ab = 0, co = nA;
+    if (a.mode == 2 && nok) {
+        ab = nA / a.cout;
+        co = nA - ab * a.cout;
+    }
+    // pixel of this thread in the next step to load: m = m0 + p, decoded incrementally
+    int m = mbeg + p;
+    int bb = 0, oh = 0, ow = 0;
+    {
+        const int mm = min(m, M - 1);
+        bb = mm / HWo;
+        const int r = mm - bb * HWo;
+        oh = r / a.Wout;
+        ow = r - oh * a.Wout;
+    }
+    uint4 va[KC], vb[KC];
+    auto gload = [&]() {
+#pragma unroll
+        for (int s = 0; s < KC; ++s) {
+            va[s] = make_uint4(0, 0, 0, 0);
+            vb[s] = va[s];
+            if (m < mend) {
+                if (nok) {
+                    size_t off;
+                    if (a.mode == 0)
+                        off = (size_t)m * a.dy_cs + a.dy_co + nA;
+                    else
+                        off = (((size_t)bb * (2 * a.Hout) + 2 * oh + (ab >> 1)) * (2 * a.Wout) + 2 * ow + (ab & 1)) *
+                                  a.dy_cs + a.dy_co + co;
+                    va[s] = *reinterpret_cast<const uint4 *>(a.dy + off);
+                }
+                const int ih = oh * a.stride + th, iw = ow * a.stride + twd;
+                if (cok && ih >= 0 && ih < a.Hin && iw >= 0 && iw < a.Win)
+                    vb[s] = *reinterpret_cast<const uint4 *>(a.x + ((size_t)(bb * a.Hin + ih) * a.Win + iw) * a.x_cs +
+                                                             a.x_co + cB);
+            }
+            m += 32;
+            ow += 32;
+            while (ow >= a.Wout) {
+                ow -= a.Wout;
+                if (++oh == a.Hout) {
+                    oh = 0;
+                    ++bb;
+                }
+            }
+        }
+    };
+    float4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    if (mbeg < mend) gload();
+    for (int m0 = mbeg; m0 < mend; m0 += 32 * KC) {
+        if (m0 != mbeg) __syncthreads();
+#pragma unroll
+        for (int s = 0; s < KC; ++s) {
+            const bf16_t *ea = reinterpret_cast<const bf16_t *>(&va[s]);
+            const bf16_t *eb = reinterpret_cast<const bf16_t *>(&vb[s]);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                sA[s][(8 * cg + j) * LDK + p] = ea[j];
+                sB[s][(8 * cg + j) * LDK + p] = eb[j];
+            }
+        }
+        __syncthreads();
+        if (m0 + 32 * KC < mend) gload();
+        const int ns = min(KC, (mend - m0 + 31) / 32);
+#pragma unroll
+        for (int s = 0; s < KC; ++s) {
+            if (s >= ns) break;
+            bf16x8_t af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                af[i] = *reinterpret_cast<const bf16x8_t *>(
+                    &sA[s][(wm * 32 + i * 16 + (lane & 15)) * LDK + (lane >> 4) * 8]);
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bfr[j] = *reinterpret_cast<const bf16x8_t *>(
+                    &sB[s][(wn * 32 + j * 16 + (lane & 15)) * LDK + (lane >> 4) * 8]);
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int c = c0 + wn * 32 + j * 16 + (lane & 15);
+            if (c >= a.Cin) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = n0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
+                if (n < a.Nw) a.part[(((size_t)ch * a.ntaps + t) * a.Nw + n) * a.Cin + c] = acc[i][j][r];
+            }
+        }
+}
+
+// out[i] = sum over c < nch of part[c][i], for i < len.  A block covers
+// 256 / G consecutive i with G groups of threads; group q sums chunks
+// q, q + G, ... in order, and the G group sums are added in order: a fixed
+// order for a given (nch, G), with loads coalesced along i.
+template <int G>
 __global__ void __launch_bounds__(256) k_sum_chunks(const float *part, int nch, size_t len, float *out)
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
-         i += (size_t)gridDim.x * blockDim.x) {
-        float s = 0.f;
-        for (int c = 0; c < nch; ++c) s += part[(size_t)c * len + i];
-        out[i] = s;
+    constexpr int E = 256 / G;
+    __shared__ float red[G][E];
+    const int e = threadIdx.x % E, q = threadIdx.x / E;
+    const size_t i = (size_t)blockIdx.x * E + e;
+    float s = 0.f;
+    if (i < len)
+        for (int c = q; c < nch; c += G) s += part[(size_t)c * len + i];
+    red[q][e] = s;
+    __syncthreads();
+    if (q == 0 && i < len) {
+        float v = red[0][e];
+#pragma unroll
+        for (int k = 1; k < G; ++k) v += red[k][e];
+        out[i] = v;
     }
 }
 
-// bias gradient: db[n] = sum over pixels of dy[pix][dy_co + n]; block b sums
-// pixels [b chunk, (b+1) chunk) into part[b][n]
+// bias gradient partials: part[b][n] = sum over pixels p in block b's chunk
+// of dy[p][dy_co + n], n < C.  Threads take 8 consecutive channels of one
+// pixel (C a multiple of 8) or one channel (otherwise); the pixel lanes of a
+// block are summed in order through LDS.
 __global__ void __launch_bounds__(256)
 k_bias_partial(const bf16_t *dy, int dy_cs, int dy_co, int C, int npix, int chunk, float *part)
 {
+    __shared__ float red[256 * 8];
     const int p0 = blockIdx.x * chunk, p1 = min(npix, p0 + chunk);
-    for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        float s = 0.f;
-        for (int p = p0; p < p1; ++p) s += bf2f(dy[(size_t)p * dy_cs + dy_co + c]);
-        part[(size_t)blockIdx.x * C + c] = s;
+    const bool vec = C % 8 == 0 && C <= 2048;
+    const int cpt = vec ? 8 : 1;
+    const int groups = vec ? C / 8 : C;  // threads per pixel
+    const int lanes = groups <= 256 ? 256 / groups : 1;
+    const int gi = threadIdx.x % groups, pl = threadIdx.x / groups;
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (groups <= 256 && pl < lanes) {
+        for (int p = p0 + pl; p < p1; p += lanes) {
+            const bf16_t *src = dy + (size_t)p * dy_cs + dy_co + gi * cpt;
+            if (vec) {
+                const uint4 v = *reinterpret_cast<const uint4 *>(src);
+                const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    acc[2 * j] += bf2f((bf16_t)(w[j] & 0xffff));
+                    acc[2 * j + 1] += bf2f((bf16_t)(w[j] >> 16));
+                }
+            } else {
+                acc[0] += bf2f(*src);
+            }
+        }
+    }
+    for (int j = 0; j < cpt; ++j) red[threadIdx.x * 8 + j] = acc[j];
+    __syncthreads();
+    // thread k < C: channel k = group k / cpt, element k % cpt; sum lanes in order
+    for (int k = threadIdx.x; k < C && groups <= 256; k += blockDim.x) {
+        const int gk = k / cpt, jk = k - gk * cpt;
+        float v = 0.f;
+        for (int l = 0; l < lanes; ++l) v += red[(l * groups + gk) * 8 + jk];
+        part[(size_t)blockIdx.x * C + k] = v;
     }
 }
 
@@ -419,19 +775,24 @@ struct ULayer {
 inline size_t al64(size_t n) { return (n + 63) & ~(size_t)63; }
 inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-// K-split of a weight gradient over M GEMM rows: about 2048 blocks in all.
+// K-split of a weight gradient over M GEMM rows: about 1024 blocks in all.
 // nch never exceeds wgrad_max_chunks(L, M') for any M' >= M.
+inline bool wgrad_tiled(const ULayer &L) { return L.Nw % 8 == 0 && L.Cin % 8 == 0; }
+
 long long wgrad_max_chunks(const ULayer &L, long long M)
 {
-    const long long tiles = (long long)cdiv(L.Nw, 16) * cdiv(L.Cin, 64) * L.ntaps;
-    return std::max(1LL, std::min((2048 + tiles - 1) / tiles, (M + 255) / 256));
+    const long long tiles = (long long)(wgrad_tiled(L) ? cdiv(L.Nw, 64) : cdiv(L.Nw, 16)) * cdiv(L.Cin, 64) * L.ntaps;
+    const long long len = (long long)L.ntaps * L.Nw * L.Cin;
+    long long n = std::min((1024 + tiles - 1) / tiles, (M + 255) / 256);
+    n = std::min(n, (4LL << 20) / len);  // partials at most 4 Mi floats
+    return std::max(1LL, n);
 }
 
 void wgrad_split(const ULayer &L, long long M, int &nch, int &chunk)
 {
     const long long n = wgrad_max_chunks(L, M);
     long long c = (M + n - 1) / n;
-    c = (c + 15) & ~15LL;
+    c = (c + 31) & ~31LL;
     chunk = (int)c;
     nch = (int)((M + c - 1) / c);
 }
@@ -475,11 +836,60 @@ namespace {
 
 hipError_t last_launch() { return hipGetLastError(); }
 
-void conv_launch(const ConvArgs &a, hipStream_t st)
+// Tile shape and K split of the LDS-tiled convolution for an M x Nw x K
+// GEMM: BN = 32 for narrow outputs, BM = 128 when that still gives >= 256
+// blocks; K is split until about 512 blocks run (at most 16 ways, >= 2
+// steps each).
+struct ConvTiling {
+    int BM, BN, ksplit, steps;
+};
+
+ConvTiling conv_tiling(long long M, int Nw, int K)
+{
+    ConvTiling t;
+    t.BN = Nw <= 32 ? 32 : 64;
+    const long long nb = cdiv(Nw, t.BN);
+    t.BM = (long long)cdiv(M, 128) * nb >= 256 ? 128 : 64;
+    const long long blocks = (long long)cdiv(M, t.BM) * nb;
+    const int nks = (K + 31) / 32;
+    int ks = 1;
+    if (blocks < 512) ks = (int)std::min<long long>(16, (512 + blocks - 1) / blocks);
+    ks = std::max(1, std::min(ks, nks / 2));
+    t.steps = (nks + ks - 1) / ks;
+    t.ksplit = (nks + t.steps - 1) / t.steps;
+    return t;
+}
+
+// FP32 elements of split-K partials a convolution needs (0 without a split)
+size_t conv_part_elems(long long M, int Nw, int K)
+{
+    const ConvTiling t = conv_tiling(M, Nw, K);
+    return t.ksplit > 1 ? (size_t)t.ksplit * M * Nw : 0;
+}
+
+void conv_launch(const ConvArgs &a, hipStream_t st, float *part)
 {
     const long long M = (long long)a.B * a.Hout * a.Wout;
-    dim3 grid(cdiv(M, 64), cdiv(a.Nw, 64));
-    hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, st, a);
+    if (a.mode == 1) {  // one output column: the plain kernel
+        dim3 grid(cdiv(M, 64), cdiv(a.Nw, 64));
+        hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, st, a);
+        return;
+    }
+    const ConvTiling t = conv_tiling(M, a.Nw, a.ntaps * a.Cin);
+    dim3 grid(cdiv(M, t.BM), cdiv(a.Nw, t.BN), t.ksplit);
+    if (t.BM == 128 && t.BN == 64)
+        hipLaunchKernelGGL((k_conv2<128, 64>), grid, dim3(256), 0, st, a, t.steps, part);
+    else if (t.BM == 128)
+        hipLaunchKernelGGL((k_conv2<128, 32>), grid, dim3(256), 0, st, a, t.steps, part);
+    else if (t.BN == 64)
+        hipLaunchKernelGGL((k_conv2<64, 64>), grid, dim3(256), 0, st, a, t.steps, part);
+    else
+        hipLaunchKernelGGL((k_conv2<64, 32>), grid, dim3(256), 0, st, a, t.steps, part);
+    if (t.ksplit > 1) {
+        const long long len = M * a.Nw;
+        hipLaunchKernelGGL(k_conv_splitk, dim3((unsigned)std::min<long long>(2048, cdiv(len, 256))), dim3(256), 0,
+                           st, a, t.ksplit, (const float *)part);
+    }
 }
 
 // forward of layer Lr: rows over the Hout x Wout grid
@@ -512,7 +922,7 @@ void fwd(const gct_unet *u, const ULayer &Lr, int B, const bf16_t *in, int in_cs
     a.out32 = out32;
     a.oscale = u->oscale;
     a.cout = Lr.cout;
-    conv_launch(a, st);
+    conv_launch(a, st, u->part);
 }
 
 // data gradient of layer Lr: gin (rows over the layer's input grid) from
@@ -560,7 +970,17 @@ void dgrad(const gct_unet *u, const ULayer &Lr, int B, const bf16_t *gout, int g
         a.stride = 1;
     }
     a.cout = a.Nw;
-    conv_launch(a, st);
+    conv_launch(a, st, u->part);
+}
+
+void sum_chunks(const float *part, int nch, size_t len, float *out, hipStream_t st)
+{
+    if (nch >= 16)
+        hipLaunchKernelGGL(k_sum_chunks<16>, dim3(cdiv((long long)len, 16)), dim3(256), 0, st, part, nch, len, out);
+    else if (nch >= 4)
+        hipLaunchKernelGGL(k_sum_chunks<4>, dim3(cdiv((long long)len, 64)), dim3(256), 0, st, part, nch, len, out);
+    else
+        hipLaunchKernelGGL(k_sum_chunks<1>, dim3(cdiv((long long)len, 256)), dim3(256), 0, st, part, nch, len, out);
 }
 
 // weight and bias gradients of layer Lr into u->g
@@ -592,11 +1012,15 @@ void wgrad(gct_unet *u, const ULayer &Lr, int B, const bf16_t *x, int x_cs, int 
     wgrad_split(Lr, M, nch, chunk);
     a.chunk = chunk;
     a.part = u->part;
-    dim3 grid(cdiv(Lr.Nw, 16), cdiv(Lr.Cin, 64), Lr.ntaps * nch);
-    hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, a);
+    if (wgrad_tiled(Lr)) {
+        dim3 grid(cdiv(Lr.Nw, 64), cdiv(Lr.Cin, 64), Lr.ntaps * nch);
+        hipLaunchKernelGGL(k_wgrad2, grid, dim3(256), 0, st, a);
+    } else {
+        dim3 grid(cdiv(Lr.Nw, 16), cdiv(Lr.Cin, 64), Lr.ntaps * nch);
+        hipLaunchKernelGGL(k_wgrad, grid, dim3(256), 0, st, a);
+    }
     const size_t len = (size_t)Lr.ntaps * Lr.Nw * Lr.Cin;
-    hipLaunchKernelGGL(k_sum_chunks, dim3(std::min(1024, cdiv((long long)len, 256))), dim3(256), 0, st,
-                       (const float *)u->part, nch, len, u->g + Lr.w_off);
+    sum_chunks(u->part, nch, len, u->g + Lr.w_off, st);
     // bias: over the pixels of the layer's output grid
     long long npix;
     int bcs = dy_cs, bco = dy_co;
@@ -608,8 +1032,7 @@ void wgrad(gct_unet *u, const ULayer &Lr, int B, const bf16_t *x, int x_cs, int 
     bias_split(npix, nblk, bchunk);
     hipLaunchKernelGGL(k_bias_partial, dim3(nblk), dim3(256), 0, st, dy, bcs, bco, Lr.cout, (int)npix, bchunk,
                        u->part);
-    hipLaunchKernelGGL(k_sum_chunks, dim3(1), dim3(256), 0, st, (const float *)u->part, nblk,
-                       (size_t)Lr.cout, u->g + Lr.b_off);
+    sum_chunks(u->part, nblk, (size_t)Lr.cout, u->g + Lr.b_off, st);
 }
 
 void relu_bwd(bf16_t *gy, int g_cs, int g_co, const bf16_t *y, int y_cs, int y_co, int C, long long npix,
@@ -727,7 +1150,26 @@ int gct_unet_create(const gct_unet_config *cfg, gct_unet **out)
     u->nparam = off;
     u->nwt = std::max<size_t>(woff, 64);
     // scratch for K-split partials: the largest need over layers at max_batch
+    // (weight gradients) and over every batch size (split convolutions)
     size_t part = 512 * 1024;
+    for (int B = 1; B <= u->maxB; ++B) {
+        for (int l = 0; l < L; ++l) {
+            const long long Ml = (long long)B * u->Hl(l) * u->Wl(l);
+            for (int idx : {u->enc1[l], u->enc2[l], u->dec1[l], u->dec2[l]}) {
+                if (idx < 0) continue;
+                const ULayer &Lr = u->layers[idx];
+                part = std::max(part, conv_part_elems(Ml, Lr.Nw, 9 * Lr.Cin));
+                part = std::max(part, conv_part_elems(Ml, Lr.Cin, 9 * Lr.Nw));
+            }
+            if (u->up[l] >= 0) {
+                const ULayer &Lr = u->layers[u->up[l]];
+                const long long Mn = (long long)B * u->Hl(l + 1) * u->Wl(l + 1);
+                part = std::max(part, conv_part_elems(Mn, Lr.Nw, Lr.Cin));
+                part = std::max(part, conv_part_elems(Mn, Lr.Cin, 4 * Lr.cout));
+            }
+        }
+        part = std::max(part, conv_part_elems((long long)B * u->H * u->W, C0, 16));
+    }
     for (int l = 0; l < L; ++l) {
         auto need = [&](int idx, long long M) {
             if (idx < 0) return;

@@ -106,11 +106,12 @@ def _pool(workers: int):
     return mp.get_context("spawn").Pool(workers)
 
 
-def generate(prob: Problem, seeds, pool, out_b=None, out_x=None, log=print, chunk=None,
+def generate(prob: Problem, seeds, pool=None, out_b=None, out_x=None, log=print, chunk=None,
              normalize: bool = True):
     """(b~, x*) for each seed: b~ = b / G[0] (b itself if not normalize) and
     x* the plain-CG solution.  Returns GPU tensors [len(seeds)][N][N] and
-    the CG iteration counts."""
+    the CG iteration counts.  `pool` (a process pool) draws the phantoms
+    ahead of the GPU work; None draws them in this process."""
     cfg = prob.cfg
     seeds = list(seeds)
     S = prob.S if chunk is None else chunk
@@ -121,7 +122,7 @@ def generate(prob: Problem, seeds, pool, out_b=None, out_x=None, log=print, chun
         out_x = torch.empty(n, cfg.N, cfg.N, dtype=torch.float32, device="cuda")
     iters = np.zeros(n, np.int32)
     args = [(cfg.N, cfg.ellipses, cfg.n_angles, cfg.M, s) for s in seeds]
-    it = pool.imap(inputs.draw_slice, args, chunksize=4)
+    it = pool.imap(inputs.draw_slice, args, chunksize=4) if pool is not None else map(inputs.draw_slice, args)
     t0 = time.time()
     last = t0
     for lo in range(0, n, S):
@@ -267,6 +268,14 @@ def load_checkpoint(path: str, net: gct.UNet, moments: bool = False) -> dict:
         v = torch.from_numpy(np.load(path + ".adam_v.npy", allow_pickle=False)).cuda()
         gct.unet_set_moments(net, m, v)
     return meta
+
+
+def trained_path() -> str:
+    return os.path.join(WEIGHTS_DIR, WEIGHTS_NAME)
+
+
+def have_trained() -> bool:
+    return os.path.exists(trained_path() + ".weights.npy") and os.path.exists(trained_path() + ".json")
 
 
 class WarmStart:

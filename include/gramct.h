@@ -153,6 +153,25 @@ int gct_backproject_boxspline(const gct_plan *plan, gct_dtype dtype, const void 
 int gct_forward_project(const gct_plan *plan, gct_dtype dtype, const void *c, void *g_s,
                         void *stream);
 
+/* Autotuner of the Gram-filtering passes (the FFT realisation of Sec. 4's
+ * Toeplitz-block-Toeplitz product): times one apply for each candidate
+ * number of elements per thread of the transforms (16, 8 or 4 where the
+ * transform size allows; fewer elements mean more threads per transform)
+ * and keeps the fastest in the plan for `dtype`.  Results of later applies
+ * and solves agree with the untuned ones to rounding.  ws must be a CG
+ * workspace of the plan (gct_workspace_size(plan, GCT_OP_CG, dtype)); its
+ * contents are overwritten.  reps: timed repetitions per candidate (<= 0:
+ * 3).  chosen: optional HOST int receiving the choice.  Changes the plan:
+ * do not call while other streams use it.  Blocks the host. */
+int gct_plan_autotune(gct_plan *plan, gct_dtype dtype, const void *Ghat, void *ws, int32_t reps,
+                      int32_t *chosen, void *stream);
+
+/* Set the elements per thread of the Gram-filtering transforms for `dtype`
+ * directly (a candidate the autotuner would consider: 16, 8 or 4 as the
+ * transform size allows; otherwise GCT_EINVAL); elems_per_thread = 0
+ * restores the default.  Changes the plan like gct_plan_autotune. */
+int gct_plan_set_fft_elems(gct_plan *plan, gct_dtype dtype, int32_t elems_per_thread);
+
 /* Result of gct_cg_solve (host struct). */
 typedef struct {
     int32_t iters;        /* iterations performed */

@@ -338,6 +338,55 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     return res->status;
 }
 
+// Times one apply per candidate elements-per-thread E (apply_e_ok) on
+// zero input in the CG workspace's vectors and keeps the fastest for this
+// dtype; cached CG graphs (built with the old E) are dropped.
+template <typename T>
+int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chosen, hipStream_t s)
+{
+    const CGLayout L = cg_layout(p, sizeof(T));
+    char *w = reinterpret_cast<char *>(ws);
+    T *src = reinterpret_cast<T *>(w + L.r), *dst = reinterpret_cast<T *>(w + L.Ap);
+    void *aws = w + L.apply;
+    const int t = sizeof(T) == 4 ? 0 : 1;
+    GCT_TRY(hipMemsetAsync(src, 0, (size_t)p->N * p->N * sizeof(T), s));
+    hipEvent_t e0, e1;
+    GCT_TRY(hipEventCreate(&e0));
+    GCT_TRY(hipEventCreate(&e1));
+    int best = p->fft_e[t];
+    float best_ms = 1e30f;
+    hipError_t err = hipSuccess;
+    for (int E : {16, 8, 4}) {
+        if (!apply_e_ok(p->logP, E)) continue;
+        p->fft_e[t] = E;
+        for (int rep = 0; rep <= reps && err == hipSuccess; ++rep) {
+            if (rep == 1) err = hipEventRecord(e0, s);
+            if (err == hipSuccess)
+                err = launch_apply_passes<T>(p, Ghat, src, dst, aws, s, nullptr, nullptr, nullptr, nullptr, nullptr);
+        }
+        if (err == hipSuccess) err = hipEventRecord(e1, s);
+        if (err == hipSuccess) err = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+        if (err != hipSuccess) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = E;
+        }
+    }
+    p->fft_e[t] = best;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (err != hipSuccess) return check_hip(err, "plan autotune");
+    for (auto &g : p->cg_graphs) (void)hipGraphExecDestroy(g.exec);
+    p->cg_graphs.clear();
+    if (chosen) *chosen = best;
+    return GCT_OK;
+}
+
+template int plan_autotune<float>(gct_plan *, const float *, void *, int, int32_t *, hipStream_t);
+template int plan_autotune<double>(gct_plan *, const double *, void *, int, int32_t *, hipStream_t);
+
 template int cg_solve<float>(const gct_plan *, const float *, const float *, float *, int, double,
                              int, int, double *, gct_cg_result *, void *, hipStream_t);
 template int cg_solve<double>(const gct_plan *, const double *, const double *, double *, int,

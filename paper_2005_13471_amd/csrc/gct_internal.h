@@ -126,6 +126,7 @@ struct gct_plan {
     int32_t N, n, M, K;
     double lx1, lx2, ly, zeta;
     int32_t P, logP;
+    int32_t fft_e[2];  // elements per thread of the apply passes, [F32, F64]
     gct::BPDims bp;
     gct::DeviceTables dev;
     int device;
@@ -141,6 +142,8 @@ int fail(int code, const std::string &msg);
 int check_hip(hipError_t e, const char *what);
 
 // ---------------------------------------------------------------------------
+bool apply_e_ok(int logP, int E);
+
 // Kernel launchers (defined in the .hip files), templated on float/double.
 // Each returns hipSuccess or the launch error.
 // ---------------------------------------------------------------------------
@@ -172,6 +175,8 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
              int max_iter, int check_every, double *hist, gct_cg_result *res, void *ws,
              hipStream_t s);
 size_t cg_ws_bytes(const gct_plan *p, size_t elem);
+template <typename T>
+int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chosen, hipStream_t s);
 
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 

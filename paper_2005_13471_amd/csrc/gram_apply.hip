@@ -13,7 +13,7 @@
 //   rows:    pairs of Hermitian row spectra -> one complex inverse FFT ->
 //            two real output rows, keep k1 < N.
 // The 1/P^2 normalisation is folded into Ghat.  One block of P/E threads
-// owns one transform (a single wave for P = 1024).
+// owns one transform.
 #include <algorithm>
 
 #include "fft_passes.h"
@@ -25,8 +25,9 @@ namespace gct {
 // launch.
 __device__ __forceinline__ bool halted(const int64_t *status) { return status && *status != 0; }
 
-// One transform per block, P/E threads, E = fft_elems(P).
-template <typename T, int LOGP>
+// One transform per block, P/E threads; E is the plan's choice for the
+// apply passes (gct_plan_autotune), fft_elems(P) for the spectrum.
+template <typename T, int LOGP, int E>
 __global__ void __launch_bounds__(256)
 k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, const C2<T> *__restrict__ tw,
            const int64_t *status, T *pupd, const double *beta)
@@ -37,11 +38,10 @@ k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, const C2<T>
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
     __syncthreads();
-    body_rows_fwd<T, LOGP, fft_elems(P)>(2 * blockIdx.x, src, W1, N, x, tws, pupd,
-                                         pupd ? (T)(*beta) : T(0));
+    body_rows_fwd<T, LOGP, E>(2 * blockIdx.x, src, W1, N, x, tws, pupd, pupd ? (T)(*beta) : T(0));
 }
 
-template <typename T, int LOGP>
+template <typename T, int LOGP, int E>
 __global__ void __launch_bounds__(256)
 k_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat, int N,
        const C2<T> *__restrict__ tw, const int64_t *status)
@@ -52,12 +52,12 @@ k_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
     __syncthreads();
-    body_cols<T, LOGP, fft_elems(P)>(blockIdx.x, W1, W2, Ghat, N, x, tws);
+    body_cols<T, LOGP, E>(blockIdx.x, W1, W2, Ghat, N, x, tws);
 }
 
 // With `dotv` set (CG), each block also writes the FP64 partial sum of
 // dotv . y over its two rows.
-template <typename T, int LOGP>
+template <typename T, int LOGP, int E>
 __global__ void __launch_bounds__(256)
 k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, const C2<T> *__restrict__ tw,
            const int64_t *status, const T *__restrict__ dotv, double *__restrict__ partial)
@@ -68,7 +68,7 @@ k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, const C2<T> *
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
     __syncthreads();
-    const double acc = body_rows_inv<T, LOGP, fft_elems(P)>(2 * blockIdx.x, W2, y, N, x, tws, dotv);
+    const double acc = body_rows_inv<T, LOGP, E>(2 * blockIdx.x, W2, y, N, x, tws, dotv);
     if (partial) {
         const double s = block_sum_lds(acc, reinterpret_cast<double *>(smem_raw));
         if (threadIdx.x == 0) partial[blockIdx.x] = s;
@@ -152,6 +152,49 @@ int apply_row_blocks(const gct_plan *p, size_t /*elem*/) { return (p->N + 1) / 2
         }                                                                                      \
     } while (0)
 
+// Elements per thread the apply passes can take for a length-P transform:
+// fft_elems(P) always; for P = 512 also 4, for P = 1024 also 8 and 4, for
+// P = 2048 also 8 (at most 256 threads per transform).
+bool apply_e_ok(int logP, int E)
+{
+    const int P = 1 << logP;
+    if (E == fft_elems(P)) return true;
+    if (P == 512) return E == 4;
+    if (P == 1024) return E == 8 || E == 4;
+    if (P == 2048) return E == 8;
+    return false;
+}
+
+#define GCT_ACASE(kern, T, LG, E, grid, lds, s, ...) \
+    hipLaunchKernelGGL((kern<T, LG, E>), grid, dim3((1 << LG) / E), lds, s, __VA_ARGS__)
+
+#define GCT_LAUNCH_FFTE(kern, T, logP, E, grid, lds, s, ...)                              \
+    do {                                                                                  \
+        switch (logP) {                                                                   \
+        case 2: GCT_ACASE(kern, T, 2, 4, grid, lds, s, __VA_ARGS__); break;               \
+        case 3: GCT_ACASE(kern, T, 3, 4, grid, lds, s, __VA_ARGS__); break;               \
+        case 4: GCT_ACASE(kern, T, 4, 4, grid, lds, s, __VA_ARGS__); break;               \
+        case 5: GCT_ACASE(kern, T, 5, 4, grid, lds, s, __VA_ARGS__); break;               \
+        case 6: GCT_ACASE(kern, T, 6, 4, grid, lds, s, __VA_ARGS__); break;               \
+        case 7: GCT_ACASE(kern, T, 7, 4, grid, lds, s, __VA_ARGS__); break;               \
+        case 8: GCT_ACASE(kern, T, 8, 4, grid, lds, s, __VA_ARGS__); break;               \
+        case 9:                                                                           \
+            if (E == 4) GCT_ACASE(kern, T, 9, 4, grid, lds, s, __VA_ARGS__);              \
+            else GCT_ACASE(kern, T, 9, 8, grid, lds, s, __VA_ARGS__);                     \
+            break;                                                                        \
+        case 10:                                                                          \
+            if (E == 4) GCT_ACASE(kern, T, 10, 4, grid, lds, s, __VA_ARGS__);             \
+            else if (E == 8) GCT_ACASE(kern, T, 10, 8, grid, lds, s, __VA_ARGS__);        \
+            else GCT_ACASE(kern, T, 10, 16, grid, lds, s, __VA_ARGS__);                   \
+            break;                                                                        \
+        case 11:                                                                          \
+            if (E == 8) GCT_ACASE(kern, T, 11, 8, grid, lds, s, __VA_ARGS__);             \
+            else GCT_ACASE(kern, T, 11, 16, grid, lds, s, __VA_ARGS__);                   \
+            break;                                                                        \
+        default: GCT_ACASE(kern, T, 12, 16, grid, lds, s, __VA_ARGS__); break;            \
+        }                                                                                 \
+    } while (0)
+
 // The three passes of one apply; status/pupd/beta/dotv/partial are the CG
 // hooks (all null for a plain apply).
 template <typename T>
@@ -160,15 +203,16 @@ hipError_t launch_apply_passes(const gct_plan *p, const T *Ghat, const T *src, T
                                const T *dotv, double *partial)
 {
     const int N = p->N, P = p->P, logP = p->logP;
-    const FftCfg c = fft_cfg<T>(logP);
+    const int E = p->fft_e[sizeof(T) == 4 ? 0 : 1];
+    const size_t lds = fft_lds_bytes<T>(P, E);
     const size_t w1 = align256((size_t)(P / 2 + 1) * N * 2 * sizeof(T));
     C2<T> *W1 = reinterpret_cast<C2<T> *>(ws);
     C2<T> *W2 = reinterpret_cast<C2<T> *>(reinterpret_cast<char *>(ws) + w1);
     const C2<T> *tw = twiddles<T>(p);
     const dim3 rgrid((N + 1) / 2), cgrid(P / 2 + 1);
-    GCT_LAUNCH_FFT(k_rows_fwd, T, logP, c, rgrid, s, src, W1, N, tw, status, pupd, beta);
-    GCT_LAUNCH_FFT(k_cols, T, logP, c, cgrid, s, W1, W2, Ghat, N, tw, status);
-    GCT_LAUNCH_FFT(k_rows_inv, T, logP, c, rgrid, s, W2, y, N, tw, status, dotv, partial);
+    GCT_LAUNCH_FFTE(k_rows_fwd, T, logP, E, rgrid, lds, s, src, W1, N, tw, status, pupd, beta);
+    GCT_LAUNCH_FFTE(k_cols, T, logP, E, cgrid, lds, s, W1, W2, Ghat, N, tw, status);
+    GCT_LAUNCH_FFTE(k_rows_inv, T, logP, E, rgrid, lds, s, W2, y, N, tw, status, dotv, partial);
     return hipGetLastError();
 }
 

@@ -461,6 +461,8 @@ int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
         }
         p->P = P;
         p->logP = logP;
+        // elements per thread of the apply passes until gct_plan_autotune
+        p->fft_e[0] = p->fft_e[1] = P >= 1024 ? 16 : (P == 512 ? 8 : 4);
         if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
         rc = build_plan(geom, p);
         if (rc) {
@@ -620,6 +622,32 @@ int gct_cg_solve(const gct_plan *p, gct_dtype dt, const void *Ghat, const void *
     if (rc == GCT_ENOTCONV) set_error("cg_solve: max_iter reached before rtol");
     if (rc == GCT_EBREAKDOWN) set_error("cg_solve: breakdown (p.Ap <= 0 or non-finite value)");
     return rc;
+}
+
+int gct_plan_set_fft_elems(gct_plan *p, gct_dtype dt, int32_t E)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (E == 0) E = p->P >= 1024 ? 16 : (p->P == 512 ? 8 : 4);
+    if (!apply_e_ok(p->logP, E)) return fail(GCT_EINVAL, "elements per thread not available for this transform size");
+    const int t = dt == GCT_F32 ? 0 : 1;
+    if (p->fft_e[t] != E) {
+        p->fft_e[t] = E;
+        for (auto &g : p->cg_graphs) (void)hipGraphExecDestroy(g.exec);
+        p->cg_graphs.clear();
+    }
+    return GCT_OK;
+}
+
+int gct_plan_autotune(gct_plan *p, gct_dtype dt, const void *Ghat, void *ws, int32_t reps,
+                      int32_t *chosen, void *stream)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!Ghat || !ws) return fail(GCT_EINVAL, "NULL buffer");
+    if (misaligned(ws)) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    if (reps < 1) reps = 3;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    return dt == GCT_F32 ? plan_autotune<float>(p, (const float *)Ghat, ws, reps, chosen, s)
+                         : plan_autotune<double>(p, (const double *)Ghat, ws, reps, chosen, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -89,6 +89,8 @@ def _load():
     L.gct_forward_project.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.gct_cg_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, dbl, i32, i32,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_CGResult), vp, vp]
+    L.gct_plan_autotune.argtypes = [vp, ctypes.c_int, vp, vp, i32, ctypes.POINTER(i32), vp]
+    L.gct_plan_set_fft_elems.argtypes = [vp, ctypes.c_int, i32]
     L.gct_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
     L.gct_batch_destroy.argtypes = [vp]
     L.gct_batch_get_info.argtypes = [vp, ctypes.POINTER(_BatchInfo), ctypes.c_void_p,
@@ -284,6 +286,21 @@ def cg_solve(plan: Plan, Ghat: torch.Tensor, b: torch.Tensor, x: torch.Tensor, w
         _check(rc)
     return CGResult(res.iters, res.status, res.rel_res, res.rel_res_true, res.rel_res0,
                     res.fell_back, hist[: res.iters + 1].copy())
+
+
+def plan_autotune(plan: Plan, Ghat: torch.Tensor, ws: torch.Tensor, reps: int = 3) -> int:
+    """Pick the fastest elements-per-thread of the apply passes for Ghat's
+    dtype; returns the choice.  ws: a CG workspace of the plan."""
+    ch = ctypes.c_int32(0)
+    _check(lib.gct_plan_autotune(plan.handle, _dt(Ghat), _ptr(Ghat, plan.info.spectrum_elems),
+                                 _ptr(ws, plan.workspace_size(OP_CG, Ghat.dtype)), int(reps),
+                                 ctypes.byref(ch), _stream()))
+    return int(ch.value)
+
+
+def plan_set_fft_elems(plan: Plan, elems: int, dtype=torch.float32):
+    """Force the elements per thread of the apply passes (0: default)."""
+    _check(lib.gct_plan_set_fft_elems(plan.handle, F32 if dtype == torch.float32 else F64, int(elems)))
 
 
 # ---------------------------------------------------------------------------

@@ -164,6 +164,73 @@ def test_gram_apply_config2_sampled(gct):
     assert err <= 1e-4
 
 
+CASE_P1024 = Case(300, 60, zeta=1.0)   # FFT size 1024: 16, 8 or 4 elements per thread
+CASE_P512 = Case(200, 40, zeta=0.5)    # FFT size 512: 8 or 4
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("case,elems", [(CASE_P1024, 16), (CASE_P1024, 8), (CASE_P1024, 4),
+                                        (CASE_P512, 8), (CASE_P512, 4)], ids=repr)
+def test_gram_apply_every_transform_tiling(gct, case, elems, dt):
+    """Each elements-per-thread variant of the apply passes against the
+    oracle's direct sum on sampled outputs."""
+    say("gram_apply tiling", case, elems, dt)
+    P = case.plan(gct)
+    gct.plan_set_fft_elems(P, elems, dt)
+    G = _gram_oracle_cached(case)
+    c = inputs.uniform_coeffs(case.N, 2100)
+    got = _apply_gpu_plan(gct, P, case, dt, G, c).reshape(-1)
+    idx = sample_pixels(case.N, 400, 9)
+    err = normwise(got[idx], oracle.apply_at(G, c, idx))
+    say("  normwise", err)
+    assert err <= tol("apply", dt)
+
+
+def test_plan_autotune_then_cg(gct):
+    """The autotuner picks a candidate; CG with the tuned plan converges to
+    the same stopping rule as with the default tiling, in about as many
+    iterations."""
+    case, dt = Case(260, 360, zeta=1.0), torch.float32   # FFT size 1024, fully sampled
+    P = case.plan(gct)
+    G = torch.empty(P.info.gram_elems, dtype=dt, device="cuda")
+    gct.gram_build(P, G)
+    Ghat = torch.empty(P.info.spectrum_elems, dtype=dt, device="cuda")
+    gct.gram_spectrum(P, G, Ghat, P.workspace(gct.OP_GRAM_SPECTRUM, dt))
+    b = torch.empty(case.N ** 2, dtype=dt, device="cuda")
+    gct.backproject_boxspline(P, dev(_sino(case, 1500).reshape(-1), dt), b, P.workspace(gct.OP_BACKPROJECT, dt))
+    ws = P.workspace(gct.OP_CG, dt)
+    x = torch.empty_like(b)
+    r0 = gct.cg_solve(P, Ghat, b, x, ws, rtol=1e-4, max_iter=500)
+    E = gct.plan_autotune(P, Ghat, ws, reps=3)
+    say("  autotune chose", E, "default iters", r0.iters)
+    assert E in (16, 8, 4)
+    r1 = gct.cg_solve(P, Ghat, b, x, ws, rtol=1e-4, max_iter=500)
+    assert r0.status == gct.GCT_OK and r1.status == gct.GCT_OK
+    assert r1.rel_res_true <= 1.1e-4 and abs(r1.iters - r0.iters) <= max(3, r0.iters // 10)
+    with pytest.raises(gct.GramctError) as e:
+        gct.plan_set_fft_elems(P, 2)
+    assert e.value.code == gct.GCT_EINVAL
+
+
+_GRAM_CACHE = {}
+
+
+def _gram_oracle_cached(case):
+    key = (case.N, case.n, case.zeta)
+    if key not in _GRAM_CACHE:
+        _GRAM_CACHE[key] = oracle.gram(case.og())
+    return _GRAM_CACHE[key]
+
+
+def _apply_gpu_plan(gct, P, case, dt, G_host, c):
+    G = dev(G_host.reshape(-1), dt)
+    Ghat = torch.empty(P.info.spectrum_elems, dtype=dt, device="cuda")
+    gct.gram_spectrum(P, G, Ghat, P.workspace(gct.OP_GRAM_SPECTRUM, dt))
+    y = torch.empty(case.N * case.N, dtype=dt, device="cuda")
+    gct.gram_apply(P, Ghat, dev(c.reshape(-1), dt), y, P.workspace(gct.OP_GRAM_APPLY, dt))
+    return host(y)
+
+
 def test_gram_apply_rejects_alias(gct):
     case = Case(8, 4)
     P = case.plan(gct)

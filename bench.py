@@ -47,6 +47,11 @@ def parse():
     ap.add_argument("--batch-slices", type=int, default=256)
     ap.add_argument("--warm-slices", type=int, default=64,
                     help="held-out slices for the plain vs warm-start CG comparison (0: skip)")
+    ap.add_argument("--fft-elems", type=int, default=0,
+                    help="elements per thread of the Gram-filtering transforms (0: autotune)")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for counter runs: set up the workload, then 20 applies and one "
+                         "256 MiB elementwise copy (the counters' calibration), and exit")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="output pixels of the oracle's direct-sum apply timed for cpu_baseline "
                          "(0: all N^2, one whole apply)")
@@ -129,6 +134,8 @@ def batch_main(args):
     gct.batch_gram_spectrum(B, G, Ghat, ws_spec)
     tuned = gct.batch_autotune(B, Ghat, ws_cg, reps=3)
     torch.cuda.synchronize()
+    if args.pmc_probe:
+        return pmc_probe(gct, plan, Ghat, c_apply, y, ws_apply, fft_elems)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         for _ in range(4):
@@ -190,6 +197,52 @@ def batch_main(args):
                      "alg_bytes_per_launch": alg},
     }
     print(json.dumps(out), flush=True)
+
+
+PMC_APPLIES = 20
+PMC_COPY_BYTES = 256 << 20
+PMC_FILE = os.path.join(ROOT, "profiles", "gram_apply_n512_a720_pmc.json")
+APPLY_SOURCES = ["gram_apply.hip", "fft_passes.h", "fft_common.h"]
+
+
+def apply_source_sha() -> str:
+    """Hash of the Gram-filtering kernel sources: counters taken on other
+    sources do not describe the kernels that run."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in APPLY_SOURCES:
+        with open(os.path.join(ROOT, "paper_2005_13471_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_probe(gct, plan, Ghat, c, y, ws, fft_elems):
+    """PMC_APPLIES applies, then one elementwise copy of PMC_COPY_BYTES whose
+    FETCH_SIZE / WRITE_SIZE calibrate the counters to bytes."""
+    import torch
+    for _ in range(PMC_APPLIES):
+        gct.gram_apply(plan, Ghat, c, y, ws)
+    torch.cuda.synchronize()
+    src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": True, "applies": PMC_APPLIES, "copy_bytes": PMC_COPY_BYTES,
+                      "fft_elems_per_thread": fft_elems, "apply_source_sha": apply_source_sha()}))
+
+
+def measured_traffic(fft_elems: int):
+    """HBM bytes per apply from the committed counter runs, if they were taken
+    on these kernel sources with this tiling; else None."""
+    try:
+        with open(PMC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("apply_source_sha") != apply_source_sha() or d.get("fft_elems_per_thread") != fft_elems:
+        return None
+    return d.get("hbm_bytes_per_apply")
 
 
 def warm_compare(slices: int):
@@ -262,8 +315,14 @@ def main():
     # autotuner; capture a burst of applies once (inputs are fixed buffers)
     gct.gram_build(plan, G)
     gct.gram_spectrum(plan, G, Ghat, ws_spec)
-    fft_elems = gct.plan_autotune(plan, Ghat, ws_cg, reps=20)
+    if args.fft_elems:
+        gct.plan_set_fft_elems(plan, args.fft_elems)
+        fft_elems = args.fft_elems
+    else:
+        fft_elems = gct.plan_autotune(plan, Ghat, ws_cg, reps=20)
     torch.cuda.synchronize()
+    if args.pmc_probe:
+        return pmc_probe(gct, plan, Ghat, c_apply, y, ws_apply, fft_elems)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         for _ in range(APPLY_GRAPH):
@@ -343,7 +402,7 @@ def main():
         "cg_warm": warm_compare(args.warm_slices) if args.warm_slices > 0 else None,
         "roofline": {"kernel": "gram_apply (rows / columns / rows FFT passes)", "bound": "hbm",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(fft_elems),
                      "alg_bytes_per_launch": alg_bytes},
     }
     if not args.no_cpu_baseline:

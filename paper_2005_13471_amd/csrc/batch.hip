@@ -39,7 +39,7 @@ __global__ void __launch_bounds__(256)
 kb_rows_fwd(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
             const T *__restrict__ src, C2<T> *__restrict__ W1, const CGState *st, T *pupd)
 {
-    const int2 m = map[blockIdx.x];
+    const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
     if (slice_halted(st, m.x)) return;
     const BatchSlice &d = sl[m.x];
     constexpr int P = 1 << LOGP;
@@ -76,7 +76,7 @@ kb_rows_inv(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
             const C2<T> *__restrict__ W2, T *__restrict__ y, const CGState *st,
             const T *__restrict__ dotv, double *__restrict__ partial)
 {
-    const int2 m = map[blockIdx.x];
+    const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
     if (slice_halted(st, m.x)) return;
     const BatchSlice &d = sl[m.x];
     constexpr int P = 1 << LOGP;
@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(256)
 kb_spec_rows(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
              const T *__restrict__ G, C2<T> *__restrict__ R)
 {
-    const int2 m = map[blockIdx.x];
+    const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
     const BatchSlice &d = sl[m.x];
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];

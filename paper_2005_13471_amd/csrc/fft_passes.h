@@ -10,6 +10,19 @@
 
 namespace gct {
 
+// Logical index of block b of nb.  MI355X dispatches consecutive blocks
+// round-robin over its 8 XCDs (block b on XCD b % 8), each with its own L2.
+// The row passes read and write the transposed scratch arrays W1 / W2 a few
+// bytes per cache line per row pair, so neighbouring row pairs must share
+// an L2: this bijection gives each XCD a contiguous range of logical indices
+// (the last nb % 8 blocks keep their own index).
+__device__ __forceinline__ int xcd_swizzle(int b, int nb)
+{
+    constexpr int X = 8;
+    const int q = nb / X;
+    return b < q * X ? (b % X) * q + b / X : b;
+}
+
 // Twiddles go to LDS after the data area when both fit in 64 KB, else they
 // are read from the plan's global table.
 template <typename T>

@@ -38,7 +38,8 @@ k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, const C2<T>
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
     __syncthreads();
-    body_rows_fwd<T, LOGP, E>(2 * blockIdx.x, src, W1, N, x, tws, pupd, pupd ? (T)(*beta) : T(0));
+    const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
+    body_rows_fwd<T, LOGP, E>(2 * rp, src, W1, N, x, tws, pupd, pupd ? (T)(*beta) : T(0));
 }
 
 template <typename T, int LOGP, int E>
@@ -68,10 +69,11 @@ k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, const C2<T> *
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
     __syncthreads();
-    const double acc = body_rows_inv<T, LOGP, E>(2 * blockIdx.x, W2, y, N, x, tws, dotv);
+    const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
+    const double acc = body_rows_inv<T, LOGP, E>(2 * rp, W2, y, N, x, tws, dotv);
     if (partial) {
         const double s = block_sum_lds(acc, reinterpret_cast<double *>(smem_raw));
-        if (threadIdx.x == 0) partial[blockIdx.x] = s;
+        if (threadIdx.x == 0) partial[rp] = s;
     }
 }
 
@@ -84,7 +86,7 @@ k_spec_rows(const T *__restrict__ G, C2<T> *__restrict__ R, int N, const C2<T> *
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
     __syncthreads();
-    body_spec_rows<T, LOGP, fft_elems(P)>(blockIdx.x, G, R, N, x, tws);
+    body_spec_rows<T, LOGP, fft_elems(P)>(xcd_swizzle(blockIdx.x, gridDim.x), G, R, N, x, tws);
 }
 
 template <typename T, int LOGP>

@@ -1,5 +1,6 @@
 // Sinogram interpolation, exact-adjoint back projection and the forward
 // model (Sec. 2, Sec. 4, Sec. 5).
+#include <algorithm>
 #include <cmath>
 
 #include "gct_internal.h"
@@ -58,8 +59,9 @@ hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s
 // for the few bins the tile projects onto (in LDS), then every pixel finds
 // its (m0, s) and evaluates one polynomial.  FP64 is used only for z.
 // ---------------------------------------------------------------------------
-// Tables of CH angles are staged together (one global-latency wait per
-// chunk); E is double-buffered so each angle costs one barrier.
+// Per-angle variant (kept for kernels whose tables exceed the chunked
+// kernel's LDS budget): tables of CH angles are staged together, E is
+// double-buffered so each angle costs one barrier.
 struct BPLayout {
     int tile, rmax, ch;
     size_t lds;
@@ -152,6 +154,200 @@ k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp,
     if (k1 < N && k2 < N) b[(size_t)k2 * N + k1] = acc;
 }
 
+// Tiled variant (the default).  A block owns a BP_TX x BP_TY pixel tile and
+// one of `groups` contiguous ranges of angles (partial images are summed by
+// k_bp_reduce in group order), so the per-angle table work is shared by
+// 2048 pixels while a 512^2 image still gives 1024 blocks.  Per chunk of CH
+// angles:
+//   - thread c < CH: the tile's bin window [mlo, mlo + R) and the split of
+//     the tile origin's projection z_t into an integer zi and a fraction;
+//     a pixel at offset (d1, d2) in the tile then has z = zi + zl with
+//     zl = frac(z_t) + d1 dz1 + d2 dz2 computed in T (|zl| < R);
+//   - E[c][m][s][k] = sum_j p[c][m + j] C[c][s][j][k] as J-tap sliding sums
+//     per (angle, sub-interval, coefficient), split in runs of bins over all
+//     threads; k padded to 8 with zeros (written once per block);
+//   - each thread evaluates 8 pixels (rows 4 apart) per angle: one floor,
+//     a sub-interval search, two 16-byte LDS reads, an 8-term Horner scheme.
+template <typename T, int JM>
+__global__ void __launch_bounds__(256)
+k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, int K, int groups,
+          const double *__restrict__ geo, const int32_t *__restrict__ ints, const T *__restrict__ brk,
+          const T *__restrict__ coef, int smax, int J, int D1, int rmax, int CH)
+{
+    constexpr int NT = 256, D1P = 8, PPT = BP_TX * BP_TY / NT, RSTEP = NT / BP_TX;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int per_coef = smax * J * D1;
+    const int pseg = rmax + JM;  // J-tap windows never leave the segment
+    const int eang = rmax * smax * D1P;
+    T *s_E = reinterpret_cast<T *>(smem_raw);  // [CH][rmax][smax][D1P]
+    T *s_C = s_E + (size_t)CH * eang;          // [CH][smax][J][D1]
+    T *s_p = s_C + CH * per_coef;              // [CH][rmax + J]
+    T *s_b = s_p + CH * pseg;                  // [CH][smax]
+    T *s_f = s_b + CH * smax;                  // [CH][3]: frac(z_t), dz1, dz2
+    int *s_w = reinterpret_cast<int *>(s_f + CH * 3);  // [CH][4]: mlo, R, nsub, zi - mlo
+    const int tid = threadIdx.x;
+    const int k1a = blockIdx.x * BP_TX, k2a = blockIdx.y * BP_TY;
+    const int d1 = tid % BP_TX, d2 = tid / BP_TX;  // rows d2 + RSTEP i
+    const int gsz = (n + groups - 1) / groups;
+    const int abeg = blockIdx.z * gsz, aend = min(n, abeg + gsz);
+    T acc[PPT], comp[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) acc[i] = comp[i] = T(0);
+    // the padding coefficients k in [D1, 8) of every E row stay zero: the
+    // table build writes only k < D1
+    for (int i = tid; i < CH * rmax * smax * (D1P - D1); i += NT) {
+        const int kk = i % (D1P - D1), row = i / (D1P - D1);
+        s_E[(size_t)row * D1P + D1 + kk] = T(0);
+    }
+    for (int a0 = abeg; a0 < aend; a0 += CH) {
+        const int cnt = min(CH, aend - a0);
+        __syncthreads();  // the previous chunk's evaluations are done with LDS
+        if (tid < cnt) {
+            const int a = a0 + tid;
+            const double z0 = geo[4 * a], dz1 = geo[4 * a + 1], dz2 = geo[4 * a + 2];
+            const double zt = z0 + (double)k1a * dz1 + (double)k2a * dz2;
+            const double e1 = (BP_TX - 1) * dz1, e2 = (BP_TY - 1) * dz2;
+            const double zmin = zt + fmin(e1, 0.0) + fmin(e2, 0.0);
+            const double zmax = zt + fmax(e1, 0.0) + fmax(e2, 0.0);
+            const int mlo = (int)floor(zmin) - 1;
+            const double zi = floor(zt);
+            s_w[4 * tid] = mlo;
+            s_w[4 * tid + 1] = min((int)floor(zmax) + 2 - mlo, rmax);
+            s_w[4 * tid + 2] = ints[4 * a];
+            s_w[4 * tid + 3] = (int)zi - mlo;
+            s_f[3 * tid] = (T)(zt - zi);
+            s_f[3 * tid + 1] = (T)dz1;
+            s_f[3 * tid + 2] = (T)dz2;
+        }
+        for (int i = tid; i < cnt * per_coef; i += NT) s_C[i] = coef[(size_t)a0 * per_coef + i];
+        for (int i = tid; i < cnt * smax; i += NT) s_b[i] = brk[(size_t)a0 * smax + i];
+        __syncthreads();
+        for (int i = tid; i < cnt * pseg; i += NT) {
+            const int c = i / pseg, off = i - c * pseg;
+            const int a = a0 + c;
+            const int mlo = s_w[4 * c], R = s_w[4 * c + 1];
+            const int mi = mlo + ints[4 * a + 1] + off + K;
+            s_p[i] = (off < R + J - 1 && mi >= 0 && mi < Mp) ? pf[(size_t)a * Mp + mi] : T(0);
+        }
+        __syncthreads();
+        // sliding J-tap sums: each work unit is one (angle, sub-interval,
+        // coefficient k < D1) and one of `pieces` runs of consecutive bins
+        {
+            const int triples = cnt * smax * D1;
+            const int pieces = max(1, NT / triples);
+            const int len = (rmax + pieces - 1) / pieces;
+            for (int q = tid; q < triples * pieces; q += NT) {
+                const int piece = q % pieces, r0 = q / pieces;
+                const int k = r0 % D1, r = r0 / D1;
+                const int sidx = r % smax, c = r / smax;
+                if (sidx >= s_w[4 * c + 2]) continue;
+                const int mlo = piece * len, mhi = min(s_w[4 * c + 1], mlo + len);
+                T cj[JM];
+                const T *cf = s_C + c * per_coef + sidx * J * D1 + k;
+#pragma unroll
+                for (int j = 0; j < JM; ++j) cj[j] = j < J ? cf[j * D1] : T(0);
+                const T *pp = s_p + c * pseg;
+                T *E = s_E + (size_t)c * eang + sidx * D1P + k;
+                for (int mi = mlo; mi < mhi; ++mi) {
+                    T e = 0;
+#pragma unroll
+                    for (int j = 0; j < JM; ++j) e += pp[mi + j] * cj[j];
+                    E[mi * smax * D1P] = e;
+                }
+            }
+        }
+        __syncthreads();
+        for (int c = 0; c < cnt; ++c) {
+            const int R = s_w[4 * c + 1], nsub = s_w[4 * c + 2], base = s_w[4 * c + 3];
+            const T zf = s_f[3 * c], dz1 = s_f[3 * c + 1], dz2 = s_f[3 * c + 2];
+            const T *bk = s_b + c * smax;
+            T b1 = T(2), b2 = T(2), b3 = T(2);  // breakpoints 1..3 (2: absent)
+            if (nsub > 1) b1 = bk[1];
+            if (nsub > 2) b2 = bk[2];
+            if (nsub > 3) b3 = bk[3];
+            const T *Ec = s_E + (size_t)c * eang;
+            const T zrow = zf + (T)d1 * dz1 + (T)d2 * dz2;
+            const T rstep = (T)RSTEP * dz2;
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) {
+                const T zl = zrow + (T)i * rstep;
+                const T fl = floor(zl);
+                const T t = zl - fl;
+                int mi = base + (int)fl;
+                mi = mi < 0 ? 0 : (mi >= R ? R - 1 : mi);
+                int sub;
+                T u;
+                if (nsub <= 4) {
+                    sub = (t >= b1) + (t >= b2) + (t >= b3);
+                    u = t - (sub == 0 ? bk[0] : sub == 1 ? b1 : sub == 2 ? b2 : b3);
+                } else {
+                    sub = 0;
+                    for (int s2 = 1; s2 < nsub; ++s2) sub += (t >= bk[s2]) ? 1 : 0;
+                    u = t - bk[sub];
+                }
+                const T *e = Ec + (size_t)(mi * smax + sub) * D1P;
+                T ev[D1P];
+#pragma unroll
+                for (int k = 0; k < D1P; ++k) ev[k] = e[k];
+                T v = ev[D1P - 1];
+#pragma unroll
+                for (int k = D1P - 2; k >= 0; --k) v = v * u + ev[k];
+                const T yk = v - comp[i];
+                const T tk = acc[i] + yk;
+                comp[i] = (tk - acc[i]) - yk;
+                acc[i] = tk;
+            }
+        }
+    }
+    T *dst = groups > 1 ? out + (size_t)blockIdx.z * N * N : out;
+    const int k1 = k1a + d1;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const int k2 = k2a + d2 + RSTEP * i;
+        if (k1 < N && k2 < N) dst[(size_t)k2 * N + k1] = acc[i];
+    }
+}
+
+// b = sum over angle groups of the partial images, in group order
+template <typename T>
+__global__ void __launch_bounds__(256) k_bp_reduce(const T *__restrict__ part, int groups, size_t len,
+                                                   T *__restrict__ b)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += (size_t)gridDim.x * blockDim.x) {
+        T s = 0;
+        for (int g = 0; g < groups; ++g) s += part[(size_t)g * len + i];
+        b[i] = s;
+    }
+}
+
+// Angle groups of the tiled kernel: enough for about 1024 blocks (at most
+// 16, and at least 8 angles each).
+int bp_angle_groups(const gct_plan *p)
+{
+    const long long tiles = (long long)((p->N + BP_TX - 1) / BP_TX) * ((p->N + BP_TY - 1) / BP_TY);
+    long long g = (1024 + tiles - 1) / tiles;
+    g = std::min<long long>(g, 16);
+    g = std::min<long long>(g, std::max(1, p->n / 8));
+    return (int)std::max<long long>(g, 1);
+}
+
+// Angles per chunk of the tiled kernel: the largest of 8, 4, 2, 1 whose
+// tables fit in 64 KB (0 if none fits or the tables exceed the kernel's
+// limits: 8 coefficients, 16 taps).
+static int bp_tile_chunk(const gct_plan *p, size_t elem, int &rmax, size_t &lds)
+{
+    rmax = (int)std::ceil(p->bp.tile_win) + 4;
+    if (p->bp.D1 > 8 || p->bp.J > 16) return 0;
+    const int jm = p->bp.J <= 8 ? 8 : 16;  // the kernel's tap count JM
+    const size_t per = (size_t)rmax * p->bp.smax * 8 + (size_t)p->bp.smax * p->bp.J * p->bp.D1 +
+                       (rmax + jm) + p->bp.smax + 3;
+    for (int ch = 8; ch >= 1; ch >>= 1) {
+        lds = ch * per * elem + ch * 4 * sizeof(int);
+        if (lds <= 65536) return ch;
+    }
+    return 0;
+}
+
 // Tile side, bins per tile window and angles per chunk such that the LDS
 // stays within 64 KB: 32 x 32 tiles when they fit, else 16 x 16.
 static BPLayout bp_layout(const gct_plan *p, size_t elem)
@@ -174,9 +370,35 @@ static BPLayout bp_layout(const gct_plan *p, size_t elem)
 size_t bp_lds_bytes(const gct_plan *p, size_t elem) { return bp_layout(p, elem).lds; }
 
 template <typename T>
-hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, hipStream_t s)
+hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, hipStream_t s)
 {
     const int N = p->N;
+    const T *brk_ = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.bp_brk_f32 : p->dev.bp_brk_f64);
+    const T *coef_ = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.bp_coef_f32 : p->dev.bp_coef_f64);
+    {
+        int rmax;
+        size_t lds;
+        const int ch = bp_tile_chunk(p, sizeof(T), rmax, lds);
+        if (ch > 0) {
+            const int groups = bp_angle_groups(p);
+            const dim3 grid((N + BP_TX - 1) / BP_TX, (N + BP_TY - 1) / BP_TY, groups);
+            T *dst = groups > 1 ? part : b;
+            const double *geo_ = reinterpret_cast<const double *>(p->dev.bp_geo);
+            const int32_t *ints_ = reinterpret_cast<const int32_t *>(p->dev.bp_int);
+            if (p->bp.J <= 8)
+                hipLaunchKernelGGL((k_bp_tile<T, 8>), grid, dim3(256), lds, s, pf, dst, N, p->n, p->M + 2 * p->K,
+                                   p->K, groups, geo_, ints_, brk_, coef_, p->bp.smax, p->bp.J, p->bp.D1, rmax, ch);
+            else
+                hipLaunchKernelGGL((k_bp_tile<T, 16>), grid, dim3(256), lds, s, pf, dst, N, p->n, p->M + 2 * p->K,
+                                   p->K, groups, geo_, ints_, brk_, coef_, p->bp.smax, p->bp.J, p->bp.D1, rmax, ch);
+            if (groups > 1) {
+                const size_t len = (size_t)N * N;
+                hipLaunchKernelGGL(k_bp_reduce<T>, dim3((unsigned)std::min<size_t>(2048, (len + 255) / 256)),
+                                   dim3(256), 0, s, (const T *)part, groups, len, b);
+            }
+            return hipGetLastError();
+        }
+    }
     const BPLayout L = bp_layout(p, sizeof(T));
     if (L.lds > 65536) return hipErrorInvalidConfiguration;
     const dim3 grid((N + L.tile - 1) / L.tile, (N + L.tile - 1) / L.tile);
@@ -272,8 +494,8 @@ hipError_t launch_forward(const gct_plan *p, const T *c, T *g, hipStream_t s)
 
 template hipError_t launch_prefilter<float>(const gct_plan *, const float *, float *, hipStream_t);
 template hipError_t launch_prefilter<double>(const gct_plan *, const double *, double *, hipStream_t);
-template hipError_t launch_backproject<float>(const gct_plan *, const float *, float *, hipStream_t);
-template hipError_t launch_backproject<double>(const gct_plan *, const double *, double *,
+template hipError_t launch_backproject<float>(const gct_plan *, const float *, float *, float *, hipStream_t);
+template hipError_t launch_backproject<double>(const gct_plan *, const double *, double *, double *,
                                                hipStream_t);
 template hipError_t launch_forward<float>(const gct_plan *, const float *, float *, hipStream_t);
 template hipError_t launch_forward<double>(const gct_plan *, const double *, double *, hipStream_t);

@@ -68,7 +68,11 @@ struct BPDims {
     int32_t J;      // weights per pixel and angle
     int32_t D1;     // polynomial coefficients per weight (degree + 1)
     double span_per_pixel;  // max over angles of (l1|c| + l2|s|) / lambda_y: bins per pixel step
+    double tile_win;        // max over angles of (BP_TX-1)|dz1| + (BP_TY-1)|dz2|: bins a tile spans
 };
+
+// Pixel tile of the back-projection kernel (columns x rows).
+constexpr int BP_TX = 64, BP_TY = 32;
 
 struct DeviceTables {
     void *gram_f32 = nullptr, *gram_f64 = nullptr;    // GramAngle<T>[n]
@@ -161,7 +165,8 @@ template <typename T>
 hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s);
 
 template <typename T>
-hipError_t launch_backproject(const gct_plan *p, const T *prefiltered, T *b, hipStream_t s);
+hipError_t launch_backproject(const gct_plan *p, const T *prefiltered, T *b, T *partial, hipStream_t s);
+int bp_angle_groups(const gct_plan *p);
 
 template <typename T>
 hipError_t launch_forward(const gct_plan *p, const T *c, T *g, hipStream_t s);

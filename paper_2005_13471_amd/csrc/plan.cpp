@@ -338,6 +338,10 @@ static int build_plan(const gct_geometry *g, gct_plan *p)
     p->bp.J = J;
     p->bp.D1 = D1;
     p->bp.span_per_pixel = span;
+    double win = 0.0;
+    for (int a = 0; a < n; ++a)
+        win = std::max(win, (BP_TX - 1) * std::fabs(bt[a].h.dz1) + (BP_TY - 1) * std::fabs(bt[a].h.dz2));
+    p->bp.tile_win = win;
     std::vector<double> geo((size_t)n * 4, 0.0), brk((size_t)n * smax, 2.0);
     std::vector<int32_t> ints((size_t)n * 4, 0);
     std::vector<double> coef((size_t)n * smax * J * D1, 0.0);
@@ -511,7 +515,12 @@ size_t gct_workspace_size(const gct_plan *p, int op, gct_dtype dt)
     switch (op) {
     case GCT_OP_GRAM_SPECTRUM: return spectrum_ws_bytes(p, e);
     case GCT_OP_GRAM_APPLY: return apply_ws_bytes(p, e);
-    case GCT_OP_BACKPROJECT: return align256((size_t)p->n * (p->M + 2 * p->K) * e);
+    case GCT_OP_BACKPROJECT: {
+        // prefiltered sinogram, then one partial image per angle group
+        const int g = bp_angle_groups(p);
+        return align256((size_t)p->n * (p->M + 2 * p->K) * e) +
+               (g > 1 ? align256((size_t)g * p->N * p->N * e) : 0);
+    }
     case GCT_OP_CG: return cg_ws_bytes(p, e);
     default: return 0;
     }
@@ -582,12 +591,15 @@ int gct_backproject_boxspline(const gct_plan *p, gct_dtype dt, const void *g_s, 
     if (misaligned(ws)) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
+    const size_t esz = dt == GCT_F32 ? 4 : 8;
+    void *part = reinterpret_cast<char *>(ws) + align256((size_t)p->n * (p->M + 2 * p->K) * esz);
     if (dt == GCT_F32) {
         e = launch_prefilter<float>(p, (const float *)g_s, (float *)ws, s);
-        if (e == hipSuccess) e = launch_backproject<float>(p, (const float *)ws, (float *)b, s);
+        if (e == hipSuccess) e = launch_backproject<float>(p, (const float *)ws, (float *)b, (float *)part, s);
     } else {
         e = launch_prefilter<double>(p, (const double *)g_s, (double *)ws, s);
-        if (e == hipSuccess) e = launch_backproject<double>(p, (const double *)ws, (double *)b, s);
+        if (e == hipSuccess)
+            e = launch_backproject<double>(p, (const double *)ws, (double *)b, (double *)part, s);
     }
     return check_hip(e, "backproject launch");
 }

@@ -157,11 +157,12 @@ int gct_forward_project(const gct_plan *plan, gct_dtype dtype, const void *c, vo
  * Toeplitz-block-Toeplitz product): times one apply for each candidate
  * number of elements per thread of the transforms (16, 8 or 4 where the
  * transform size allows; fewer elements mean more threads per transform)
- * and keeps the fastest in the plan for `dtype`.  Results of later applies
+ * and keeps the fastest in the plan for `dtype`; separately for the fused
+ * CG passes of gct_cg_solve, timed on a trial solve.  Results of later applies
  * and solves agree with the untuned ones to rounding.  ws must be a CG
  * workspace of the plan (gct_workspace_size(plan, GCT_OP_CG, dtype)); its
  * contents are overwritten.  reps: timed repetitions per candidate (<= 0:
- * 3).  chosen: optional HOST int receiving the choice.  Changes the plan:
+ * 3).  chosen: optional HOST int receiving the choice for the apply passes.  Changes the plan:
  * do not call while other streams use it.  Blocks the host. */
 int gct_plan_autotune(gct_plan *plan, gct_dtype dtype, const void *Ghat, void *ws, int32_t reps,
                       int32_t *chosen, void *stream);
@@ -187,7 +188,11 @@ typedef struct {
 /* Conjugate gradients on (H^T H) x = b with the Gram-filter operator
  * (Sec. 2: a single back projection, then the filter in every iteration;
  * the paper iterates with steepest descent, Sec. 6.2).  Vectors in dtype;
- * inner products and residual norms in FP64 on the device.  Stops when
+ * inner products and residual norms in FP64 on the device.  Iterations use
+ * the Chronopoulos-Gear arrangement of CG (one Gram-filter product w = A r
+ * and one reduction point per iteration, A p carried by recurrence), fused
+ * into the three Gram-filtering passes: in exact arithmetic the textbook CG
+ * iterates; the stopping test uses ||r_k||^2 reduced from r_k.  Stops when
  * ||r_k|| <= rtol ||b|| or after max_iter iterations.  x: on entry the start
  * vector if use_x0 != 0 (else ignored and zero is used); on exit the last
  * iterate.  A start vector with ||b - A x_0|| >= ||b|| is replaced by zero
@@ -247,6 +252,8 @@ int gct_batch_gram_apply(const gct_batch *batch, gct_dtype dtype, const void *Gh
 
 /* CG from x_i = 0 on every slice to ||r_i|| <= rtol ||b_i|| (per slice) or
  * max_iter iterations; converged slices stop while the others continue.
+ * Textbook arrangement (products A p, then the x, r update and ||r||^2,
+ * then beta), FP64 inner products as in gct_cg_solve.
  * results: HOST array of `slices` entries.  Returns GCT_OK if all slices
  * converged, else GCT_ENOTCONV / GCT_EBREAKDOWN (see results[i].status).
  * Chunks of check_every iterations (<= 0 selects 8) are replayed as a

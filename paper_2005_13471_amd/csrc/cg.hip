@@ -5,6 +5,14 @@
 // iterations is queued without host round trips; the host reads the state
 // once per chunk.  Once converged (or broken down) the status word is set
 // and every kernel queued after it returns at once.
+//
+// An iteration is three kernels, the Gram-filtering passes with the vector
+// work folded in (gram_apply.hip, k_cgf_*): the inverse row pass also forms
+// the FP64 partial dots p.Ap, r.Ap and Ap.Ap, and the next forward row pass
+// derives alpha = ||r||^2 / p.Ap, the updated norm
+// ||r - alpha Ap||^2 = ||r||^2 - 2 alpha r.Ap + alpha^2 Ap.Ap and beta from
+// them, updates x, r and p on its rows and transforms p.  In exact
+// arithmetic these are the textbook CG iterates.
 #include <algorithm>
 #include <cmath>
 
@@ -85,62 +93,37 @@ k_cg_init_fin(CGState *st, const double *part_rr, const double *part_bb, int np,
         st->ring[0] = rr;
         st->status = (rr <= st->thr2) ? CG_CONVERGED : CG_RUNNING;
         if (!(rr == rr) || !(bb == bb)) st->status = CG_BREAKDOWN;
+        st->gam[0] = st->gam[1] = rr;
+        st->alp[0] = st->alp[1] = 1.0;
+        st->pend[0] = st->pend[1] = 0;
+        st->stat[0] = st->stat[1] = st->status;
+        st->kring = 0;
     }
 }
 
-// alpha = rr / p.Ap (every block reduces the p.Ap partials itself, in the
-// same order, so all blocks agree), then x += alpha p, r -= alpha Ap and a
-// partial ||r||^2 per block.  A non-positive or non-finite p.Ap stops the
-// solve (every block sees the same value and skips the update; block 0
-// records the breakdown).
-template <typename T>
-__global__ void __launch_bounds__(256)
-k_cg_update(CGState *st, T *__restrict__ x, T *__restrict__ r, const T *__restrict__ p,
-            const T *__restrict__ Ap, size_t n, const double *__restrict__ part_pAp, int np,
-            double *__restrict__ part)
-{
-    if (st->status != CG_RUNNING) return;
-    double s = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) s += part_pAp[i];
-    const double pAp = block_sum(s);
-    if (!(pAp > 0.0) || !(pAp < INFINITY)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->status = CG_BREAKDOWN;
-        return;
-    }
-    const double alpha = st->rr / pAp;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        st->pAp = pAp;
-        st->alpha = alpha;
-    }
-    const T al = (T)alpha;
-    double rr = 0.0;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (size_t)gridDim.x * blockDim.x) {
-        x[i] += al * p[i];
-        const T ri = r[i] - al * Ap[i];
-        r[i] = ri;
-        rr += (double)ri * (double)ri;
-    }
-    rr = block_sum(rr);
-    if (threadIdx.x == 0) part[blockIdx.x] = rr;
-}
-
-// beta = rr_new / rr, convergence test
-__global__ void __launch_bounds__(256) k_cg_beta(CGState *st, const double *part, int np)
+// After the last launch of a solve that reached max_iter: ||r_k||^2 from the
+// last inverse row pass's partials (the norm the next launch would test),
+// recorded and tested against the stopping rule.
+__global__ void __launch_bounds__(256) k_cgf_norm(CGState *st, const double *part, int np)
 {
     if (st->status != CG_RUNNING) return;
     double s = 0.0;
     for (int i = threadIdx.x; i < np; i += blockDim.x) s += part[i];
     s = block_sum(s);
     if (threadIdx.x == 0) {
-        const int64_t k = st->k + 1;
-        st->k = k;
-        st->ring[k % CG_RING] = s;
-        st->beta = s / st->rr;
+        st->ring[st->k % CG_RING] = s;
+        st->kring = st->k;
         st->rr = s;
         if (!(s == s)) st->status = CG_BREAKDOWN;
         else if (s <= st->thr2) st->status = CG_CONVERGED;
     }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_one(T *v, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        v[i] = T(1);
 }
 
 // partial ||b - Ax||^2
@@ -168,7 +151,7 @@ __global__ void __launch_bounds__(256) k_sum(const double *part, int np, double 
 
 // ---------------------------------------------------------------------------
 struct CGLayout {
-    size_t apply, r, p, Ap, part, part2, st, total;
+    size_t apply, r, p, Ap, sv, xt, part, part2, st, total;
 };
 
 static CGLayout cg_layout(const gct_plan *p, size_t elem)
@@ -181,7 +164,9 @@ static CGLayout cg_layout(const gct_plan *p, size_t elem)
     L.r = o; o += img;
     L.p = o; o += img;
     L.Ap = o; o += img;
-    L.part = o; o += align256((size_t)np * sizeof(double));
+    L.sv = o; o += img;  // s = A p of the fused iteration
+    L.xt = o; o += img;  // iterate of the autotuner's trial solves
+    L.part = o; o += align256((size_t)3 * np * sizeof(double));  // three partial dots per row pair
     L.part2 = o; o += align256((size_t)np * sizeof(double));
     L.st = o; o += align256(sizeof(CGState));
     L.total = o;
@@ -237,6 +222,7 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     void *aws = w + L.apply;
     T *r = reinterpret_cast<T *>(w + L.r), *pv = reinterpret_cast<T *>(w + L.p);
     T *Ap = reinterpret_cast<T *>(w + L.Ap);
+    T *sv = reinterpret_cast<T *>(w + L.sv);
     double *part = reinterpret_cast<double *>(w + L.part);
     double *part2 = reinterpret_cast<double *>(w + L.part2);
     CGState *st = reinterpret_cast<CGState *>(w + L.st);
@@ -244,6 +230,7 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     const int rblocks = apply_row_blocks(p, sizeof(T));
     if (check_every <= 0) check_every = 8;
     if (check_every > CG_RING) check_every = CG_RING;
+    check_every += check_every & 1;  // even chunks keep the parity slots aligned across replays
 
     CGState hs;
     int fell_back = 0;
@@ -273,19 +260,20 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     if (hist) hist[0] = rel(hs.rr0);
 
     int64_t done = 0;
-    auto launch_iters = [&](int count, hipStream_t st_) -> hipError_t {
+    // launch i (of a batch starting at launch `first`): three fused kernels,
+    // parity (first + i) & 1; launch 0 only forms A r_0, launch i > 0 makes
+    // update i - 1, so max_iter updates take max_iter + 1 launches
+    auto launch_iters = [&](int count, int64_t first, hipStream_t st_) -> hipError_t {
         for (int i = 0; i < count; ++i) {
-            hipError_t e = launch_apply_passes<T>(p, Ghat, r, Ap, aws, st_, &st->status, pv,
-                                                  &st->beta, pv, part);
+            hipError_t e = launch_cgf_iteration<T>(p, Ghat, x, r, pv, sv, Ap, aws, part, st,
+                                                   (int)((first + i) & 1), st_);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(k_cg_update<T>, dim3(VBLK), dim3(256), 0, st_, st, x, r, pv, Ap, n,
-                               part, rblocks, part2);
-            hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st_, st, part2, VBLK);
         }
         return hipGetLastError();
     };
-    while (hs.status == CG_RUNNING && done < max_iter) {
-        const int chunk = (int)std::min<int64_t>(check_every, max_iter - done);
+    const int64_t launches = max_iter > 0 ? (int64_t)max_iter + 1 : 0;
+    while (hs.status == CG_RUNNING && done < launches) {
+        const int chunk = (int)std::min<int64_t>(check_every, launches - done);
         hipGraphExec_t exec = nullptr;
         if (chunk == check_every) {
             // a chunk of iterations as one graph, captured once per buffer set
@@ -296,7 +284,7 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
                 hipStream_t cs = cg_capture_stream(p);
                 if (!cs) return fail(GCT_EHIP, "cannot create the capture stream");
                 GCT_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-                hipError_t e = launch_iters(chunk, cs);
+                hipError_t e = launch_iters(chunk, 0, cs);  // replayed at even `done` only
                 hipGraph_t g = nullptr;
                 hipError_t e2 = hipStreamEndCapture(cs, &g);
                 if (e != hipSuccess || e2 != hipSuccess) {
@@ -310,14 +298,24 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
             }
             GCT_TRY(hipGraphLaunch(exec, s));
         } else {
-            GCT_TRY(launch_iters(chunk, s));
+            GCT_TRY(launch_iters(chunk, done, s));
         }
-        const int64_t kprev = hs.k;
+        const int64_t kprev = hs.kring;
         GCT_TRY(hipMemcpyAsync(&hs, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
         GCT_TRY(hipStreamSynchronize(s));
         if (hist)
-            for (int64_t k = kprev + 1; k <= hs.k; ++k) hist[k] = rel(hs.ring[k % CG_RING]);
+            for (int64_t k = kprev + 1; k <= hs.kring; ++k) hist[k] = rel(hs.ring[k % CG_RING]);
         done += chunk;
+    }
+    if (hs.status == CG_RUNNING && done > 0) {
+        // max_iter updates made: test the last residual norm
+        hipLaunchKernelGGL(k_cgf_norm, dim3(1), dim3(256), 0, s, st, (const double *)part, rblocks);
+        GCT_TRY(hipGetLastError());
+        const int64_t kprev = hs.kring;
+        GCT_TRY(hipMemcpyAsync(&hs, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        GCT_TRY(hipStreamSynchronize(s));
+        if (hist)
+            for (int64_t k = kprev + 1; k <= hs.kring; ++k) hist[k] = rel(hs.ring[k % CG_RING]);
     }
     // true residual of the returned iterate
     GCT_TRY(launch_apply_passes<T>(p, Ghat, x, Ap, aws, s, nullptr, nullptr, nullptr, nullptr,
@@ -375,6 +373,40 @@ int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chose
         }
     }
     p->fft_e[t] = best;
+    // the fused CG passes: a trial solve of A x = 1 that never meets its
+    // stopping rule (rtol = 0), timed over `reps` iterations per candidate
+    int best_cg = p->cg_e[t];
+    if (err == hipSuccess) {
+        T *sv = reinterpret_cast<T *>(w + L.sv), *pv = reinterpret_cast<T *>(w + L.p);
+        T *xt = reinterpret_cast<T *>(w + L.xt);
+        double *part = reinterpret_cast<double *>(w + L.part);
+        double *part2 = reinterpret_cast<double *>(w + L.part2);
+        CGState *st = reinterpret_cast<CGState *>(w + L.st);
+        const size_t n = (size_t)p->N * p->N;
+        float best_cg_ms = 1e30f;
+        for (int E : {16, 8, 4}) {
+            if (!apply_e_ok(p->logP, E) || err != hipSuccess) continue;
+            p->cg_e[t] = E;
+            hipLaunchKernelGGL(k_fill_one<T>, dim3(VBLK), dim3(256), 0, s, sv, n);
+            hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, (const T *)sv, xt, src, pv, nullptr, n,
+                               part, part2);
+            hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK, 0.0);
+            for (int it = 0; it < reps + 2 && err == hipSuccess; ++it) {
+                if (it == 2) err = hipEventRecord(e0, s);
+                if (err == hipSuccess)
+                    err = launch_cgf_iteration<T>(p, Ghat, xt, src, pv, sv, dst, aws, part, st, it & 1, s);
+            }
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err == hipSuccess && ms < best_cg_ms) {
+                best_cg_ms = ms;
+                best_cg = E;
+            }
+        }
+    }
+    p->cg_e[t] = best_cg;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return check_hip(err, "plan autotune");

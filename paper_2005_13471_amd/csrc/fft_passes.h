@@ -43,12 +43,35 @@ __device__ __forceinline__ const C2<T> *stage_twiddles(C2<T> *lds_after_data,
 // Rows forward: real FFT of image rows ra and ra+1 (one complex transform),
 // written transposed as W1[k][row], k in [0, P/2].  With pupd, the rows are
 // first updated in place as p = src + bt * p (CG direction update).
+// Rows forward from registers: v[q] holds (row ra, row ra+1) at column
+// t + G q (zero past N); one complex FFT, split into the two real-row
+// spectra, written transposed as W1[k][row].
+template <typename T, int LOGP, int E>
+__device__ __forceinline__ void rows_fwd_regs(int ra, C2<T> (&v)[E], C2<T> *__restrict__ W1, int N, C2<T> *x,
+                                              const C2<T> *tws)
+{
+    constexpr int P = 1 << LOGP, hP = P >> 1, G = P / E;
+    const int t = threadIdx.x;
+    const int rb = ra + 1;
+    fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
+    // split the two real rows: Xa = (Z[k] + conj Z[-k])/2, Xb = (Z[k] - conj Z[-k])/(2i)
+#pragma unroll
+    for (int q = 0; q < E; ++q) x[t + G * q] = v[q];
+    __syncthreads();
+    for (int k = t; k <= hP; k += G) {
+        const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
+        W1[(size_t)k * N + ra] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
+        if (rb < N) W1[(size_t)k * N + rb] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+    }
+    __syncthreads();  // x may be reused by the caller
+}
+
 template <typename T, int LOGP, int E>
 __device__ __forceinline__ void body_rows_fwd(int ra, const T *__restrict__ src,
                                               C2<T> *__restrict__ W1, int N, C2<T> *x,
                                               const C2<T> *tws, T *pupd, T bt)
 {
-    constexpr int P = 1 << LOGP, hP = P >> 1, G = P / E;
+    constexpr int P = 1 << LOGP, G = P / E;
     const int t = threadIdx.x;
     const int rb = ra + 1;
     C2<T> v[E];
@@ -71,17 +94,7 @@ __device__ __forceinline__ void body_rows_fwd(int ra, const T *__restrict__ src,
         }
         v[q] = {re, im};
     }
-    fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
-    // split the two real rows: Xa = (Z[k] + conj Z[-k])/2, Xb = (Z[k] - conj Z[-k])/(2i)
-#pragma unroll
-    for (int q = 0; q < E; ++q) x[t + G * q] = v[q];
-    __syncthreads();
-    for (int k = t; k <= hP; k += G) {
-        const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
-        W1[(size_t)k * N + ra] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
-        if (rb < N) W1[(size_t)k * N + rb] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
-    }
-    __syncthreads();  // x may be reused by the caller
+    rows_fwd_regs<T, LOGP, E>(ra, v, W1, N, x, tws);
 }
 
 // Columns: FFT along k2 of column col (N nonzero of P), times the real
@@ -118,15 +131,15 @@ __device__ __forceinline__ void body_cols(int col, const C2<T> *__restrict__ W1,
 // Rows inverse: Hermitian row spectra of rows ra, ra+1 -> one complex
 // inverse FFT -> two real rows of y.  Returns this thread's FP64 partial of
 // dotv . y over the two rows (0 if dotv is null).
+// Rows inverse into registers: Hermitian row spectra of rows ra, ra+1 ->
+// one complex inverse FFT; v[q] = (row ra, row ra+1) at column t + G q.
 template <typename T, int LOGP, int E>
-__device__ __forceinline__ double body_rows_inv(int ra, const C2<T> *__restrict__ W2,
-                                                T *__restrict__ y, int N, C2<T> *x,
-                                                const C2<T> *tws, const T *__restrict__ dotv)
+__device__ __forceinline__ void rows_inv_regs(int ra, const C2<T> *__restrict__ W2, int N, C2<T> *x,
+                                              const C2<T> *tws, C2<T> (&v)[E])
 {
     constexpr int P = 1 << LOGP, hP = P >> 1, G = P / E;
     const int t = threadIdx.x;
     const int rb = ra + 1;
-    C2<T> v[E];
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int k = t + G * q;
@@ -140,6 +153,20 @@ __device__ __forceinline__ double body_rows_inv(int ra, const C2<T> *__restrict_
         v[q] = {Ya.x - Yb.y, Ya.y + Yb.x};
     }
     fft_passes<T, E, P, 1, true, true>(v, x, t, tws);
+}
+
+// Rows inverse: the two real rows of y.  Returns this thread's FP64 partial
+// of dotv . y over the two rows (0 if dotv is null).
+template <typename T, int LOGP, int E>
+__device__ __forceinline__ double body_rows_inv(int ra, const C2<T> *__restrict__ W2,
+                                                T *__restrict__ y, int N, C2<T> *x,
+                                                const C2<T> *tws, const T *__restrict__ dotv)
+{
+    constexpr int P = 1 << LOGP, G = P / E;
+    const int t = threadIdx.x;
+    const int rb = ra + 1;
+    C2<T> v[E];
+    rows_inv_regs<T, LOGP, E>(ra, W2, N, x, tws, v);
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
@@ -153,6 +180,31 @@ __device__ __forceinline__ double body_rows_inv(int ra, const C2<T> *__restrict_
         }
     }
     return acc;
+}
+
+// Two block-wide FP64 sums at once: butterfly within each 64-lane wave,
+// then the per-wave results (at most 4 waves) added in wave order through
+// LDS (2 doubles per wave at red).  One barrier; the same order everywhere,
+// so every block reducing the same data gets the same bits.
+__device__ __forceinline__ void block_sum2(double &a, double &b, double *red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o);
+        b += __shfl_xor(b, o);
+    }
+    const int wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * wv] = a;
+        red[2 * wv + 1] = b;
+    }
+    __syncthreads();
+    a = red[0];
+    b = red[1];
+    for (int i = 1; i < nw; ++i) {
+        a += red[2 * i];
+        b += red[2 * i + 1];
+    }
 }
 
 // Block-wide FP64 sum through an LDS area of blockDim doubles (all threads

@@ -94,6 +94,13 @@ struct CGState {
     double rr, bb, rr0, pAp, alpha, beta, thr2, pad;
     int64_t k, status, pad2, pad3;
     double ring[CG_RING];  // ||r_k||^2 at ring[k % CG_RING]
+    // fused single-slice iteration (parity slots, see gram_apply.hip):
+    // gamma = ||r||^2 and alpha of the last update, "updates may start" (1:
+    // first, 2: later) and the device-side status; a kernel reads the slots
+    // of its parity and writes the others, so its blocks never race
+    double gam[2], alp[2];
+    int64_t pend[2], stat[2];
+    int64_t kring;  // last index written to ring
 };
 
 // One slice of a batch (device descriptor).  Offsets are in elements of the
@@ -131,6 +138,7 @@ struct gct_plan {
     double lx1, lx2, ly, zeta;
     int32_t P, logP;
     int32_t fft_e[2];  // elements per thread of the apply passes, [F32, F64]
+    int32_t cg_e[2];   // elements per thread of the fused CG passes
     gct::BPDims bp;
     gct::DeviceTables dev;
     int device;
@@ -147,6 +155,13 @@ int check_hip(hipError_t e, const char *what);
 
 // ---------------------------------------------------------------------------
 bool apply_e_ok(int logP, int E);
+
+// One fused CG iteration of the single-slice solver (gram_apply.hip): the
+// update from the previous dots + forward rows of r, columns, inverse rows
+// (w = A r) with the partial dots r.r and r.w.  par = launch parity.
+template <typename T>
+hipError_t launch_cgf_iteration(const gct_plan *p, const T *Ghat, T *x, T *r, T *pv, T *sv, T *w, void *ws,
+                                double *part, CGState *st, int par, hipStream_t s);
 
 // Kernel launchers (defined in the .hip files), templated on float/double.
 // Each returns hipSuccess or the launch error.

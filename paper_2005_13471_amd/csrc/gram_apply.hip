@@ -103,6 +103,199 @@ k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat, const C2<T> *__re
 }
 
 // ---------------------------------------------------------------------------
+// Fused CG iteration (single slice), in the Chronopoulos-Gear arrangement:
+// one product w = A r and one reduction point per iteration.  Launch i:
+//   rows_fwd: every block reduces the previous launch's partial dots
+//     gamma = r.r and delta = r.w (fixed order) and, unless ||r||^2 = gamma
+//     meets the stopping rule, takes
+//       beta = gamma / gamma_prev,  alpha = gamma / (delta - beta gamma / alpha_prev)
+//     (beta = 0, alpha = gamma / delta for the first update), then on its own
+//     two rows p = r + beta p, s = w + beta s, x += alpha p, r -= alpha s,
+//     and transforms the new r;
+//   cols: unchanged;
+//   rows_inv: w = A r on its rows and the partial dots r.r, r.w.
+// In exact arithmetic these are the textbook CG iterates (s = A p; the
+// denominator is p.Ap).  All blocks compute the same scalars; block 0 alone
+// records them, in the slots of the other parity.
+// ---------------------------------------------------------------------------
+// (sum part[0..np), sum part[np..2np)) in a fixed order
+__device__ __forceinline__ void dot_pair(const double *part, int np, double *red, double &g, double &d)
+{
+    g = 0.0;
+    d = 0.0;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+        g += part[i];
+        d += part[np + i];
+    }
+    block_sum2(g, d, red);
+}
+
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(256)
+k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__restrict__ sv,
+               const T *__restrict__ w, C2<T> *__restrict__ W1, int N, const C2<T> *__restrict__ tw,
+               CGState *st, const double *__restrict__ part, int np, int par)
+{
+    if (st->stat[par] != CG_RUNNING) return;
+    constexpr int P = 1 << LOGP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *xs = reinterpret_cast<C2<T> *>(smem_raw);
+    double *red = reinterpret_cast<double *>(smem_raw);
+    const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int ra = 2 * rp;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    const int64_t pend = st->pend[par];
+    if (pend) {
+        // this thread's elements of the five vectors, loaded before the
+        // reduction so that their latency overlaps it
+        constexpr int G = P / E;
+        T lr[E][2], lw[E][2], lp[E][2], ls[E][2], lx[E][2];
+#pragma unroll
+        for (int q = 0; q < E; ++q)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int n = threadIdx.x + G * q, row = ra + h;
+                const bool ok = n < N && row < N;
+                const size_t i = ok ? (size_t)row * N + n : 0;
+                lr[q][h] = ok ? r[i] : T(0);
+                lw[q][h] = ok ? w[i] : T(0);
+                lp[q][h] = ok ? p[i] : T(0);
+                ls[q][h] = ok ? sv[i] : T(0);
+                lx[q][h] = ok ? x[i] : T(0);
+            }
+        double g, dl;
+        dot_pair(part, np, red, g, dl);
+        const int64_t u = st->k;  // updates so far: g = ||r_u||^2
+        if (!(g == g)) {
+            if (lead) st->stat[par ^ 1] = st->status = CG_BREAKDOWN;
+            return;
+        }
+        if (g <= st->thr2) {
+            if (lead) {
+                st->ring[u % CG_RING] = g;
+                st->kring = u;
+                st->rr = g;
+                st->stat[par ^ 1] = st->status = CG_CONVERGED;
+            }
+            return;
+        }
+        double alpha, beta;
+        if (pend == 1) {
+            beta = 0.0;
+            alpha = g / dl;
+        } else {
+            beta = g / st->gam[par ^ 1];
+            alpha = g / (dl - beta * g / st->alp[par ^ 1]);
+        }
+        if (!(alpha > 0.0) || !(alpha < INFINITY)) {  // p.Ap <= 0 or non-finite
+            if (lead) st->stat[par ^ 1] = st->status = CG_BREAKDOWN;
+            return;
+        }
+        if (lead) {
+            st->ring[u % CG_RING] = g;
+            st->kring = u;
+            st->rr = g;
+            st->k = u + 1;
+            st->gam[par] = g;
+            st->alp[par] = alpha;
+            st->alpha = alpha;
+            st->beta = beta;
+            st->pend[par ^ 1] = 2;
+            st->stat[par ^ 1] = CG_RUNNING;
+        }
+        const T al = (T)alpha, be = (T)beta;
+        const bool first = pend == 1;  // p = r, s = w (p, s hold no direction yet)
+        // thread t owns columns t + G q of the two rows: the same elements
+        // the transform takes, so the new r goes to it in registers
+        C2<T> v[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            T rv[2] = {T(0), T(0)};
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int n = threadIdx.x + G * q, row = ra + h;
+                if (n >= N || row >= N) continue;
+                const size_t i = (size_t)row * N + n;
+                const T pi = first ? lr[q][h] : lr[q][h] + be * lp[q][h];
+                const T si = first ? lw[q][h] : lw[q][h] + be * ls[q][h];
+                p[i] = pi;
+                sv[i] = si;
+                x[i] = lx[q][h] + al * pi;
+                rv[h] = lr[q][h] - al * si;
+                r[i] = rv[h];
+            }
+            v[q] = {rv[0], rv[1]};
+        }
+        const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(xs + P, tw, P / 2);
+        __syncthreads();
+        rows_fwd_regs<T, LOGP, E>(ra, v, W1, N, xs, tws);
+        return;
+    } else if (lead) {
+        st->pend[par ^ 1] = 1;  // first launch: transform r_0 only
+        st->stat[par ^ 1] = CG_RUNNING;
+    }
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(xs + P, tw, P / 2);
+    __syncthreads();
+    body_rows_fwd<T, LOGP, E>(ra, r, W1, N, xs, tws, nullptr, T(0));
+}
+
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(256)
+k_cgf_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat, int N,
+           const C2<T> *__restrict__ tw, const CGState *st, int par)
+{
+    if (st->stat[par ^ 1] != CG_RUNNING) return;
+    constexpr int P = 1 << LOGP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
+    __syncthreads();
+    body_cols<T, LOGP, E>(blockIdx.x, W1, W2, Ghat, N, x, tws);
+}
+
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(256)
+k_cgf_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ w, const T *__restrict__ r, int N,
+               const C2<T> *__restrict__ tw, const CGState *st, double *__restrict__ part, int np, int par)
+{
+    if (st->stat[par ^ 1] != CG_RUNNING) return;
+    constexpr int P = 1 << LOGP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
+    __syncthreads();
+    const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int ra = 2 * rp, rb = ra + 1;
+    constexpr int G = P / E;
+    C2<T> v[E];
+    rows_inv_regs<T, LOGP, E>(ra, W2, N, x, tws, v);
+    double g = 0.0, dl = 0.0;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = threadIdx.x + G * q;
+        if (n >= N) continue;
+        const size_t ia = (size_t)ra * N + n;
+        w[ia] = v[q].x;
+        const double ra_ = (double)r[ia];
+        g += ra_ * ra_;
+        dl += ra_ * (double)v[q].x;
+        if (rb < N) {
+            const size_t ib = ia + N;
+            w[ib] = v[q].y;
+            const double rb_ = (double)r[ib];
+            g += rb_ * rb_;
+            dl += rb_ * (double)v[q].y;
+        }
+    }
+    __syncthreads();  // the transform's LDS reads are done before red is written
+    block_sum2(g, dl, reinterpret_cast<double *>(smem_raw));
+    if (threadIdx.x == 0) {
+        part[rp] = g;
+        part[np + rp] = dl;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Launch geometry
 // ---------------------------------------------------------------------------
 struct FftCfg {
@@ -217,6 +410,34 @@ hipError_t launch_apply_passes(const gct_plan *p, const T *Ghat, const T *src, T
     GCT_LAUNCH_FFTE(k_rows_inv, T, logP, E, rgrid, lds, s, W2, y, N, tw, status, dotv, partial);
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_cgf_iteration(const gct_plan *p, const T *Ghat, T *x, T *r, T *pv, T *sv, T *w, void *ws,
+                                double *part, CGState *st, int par, hipStream_t s)
+{
+    const int N = p->N, P = p->P, logP = p->logP;
+    const int E = p->cg_e[sizeof(T) == 4 ? 0 : 1];
+    const size_t lds = fft_lds_bytes<T>(P, E);
+    const size_t w1 = align256((size_t)(P / 2 + 1) * N * 2 * sizeof(T));
+    C2<T> *W1 = reinterpret_cast<C2<T> *>(ws);
+    C2<T> *W2 = reinterpret_cast<C2<T> *>(reinterpret_cast<char *>(ws) + w1);
+    const C2<T> *tw = twiddles<T>(p);
+    const int np = (N + 1) / 2;
+    const dim3 rgrid(np), cgrid(P / 2 + 1);
+    GCT_LAUNCH_FFTE(k_cgf_rows_fwd, T, logP, E, rgrid, lds, s, x, r, pv, sv, (const T *)w, W1, N, tw, st,
+                    (const double *)part, np, par);
+    GCT_LAUNCH_FFTE(k_cgf_cols, T, logP, E, cgrid, lds, s, (const C2<T> *)W1, W2, Ghat, N, tw,
+                    (const CGState *)st, par);
+    GCT_LAUNCH_FFTE(k_cgf_rows_inv, T, logP, E, rgrid, lds, s, (const C2<T> *)W2, w, (const T *)r, N, tw,
+                    (const CGState *)st, part, np, par);
+    return hipGetLastError();
+}
+
+template hipError_t launch_cgf_iteration<float>(const gct_plan *, const float *, float *, float *, float *,
+                                                float *, float *, void *, double *, CGState *, int, hipStream_t);
+template hipError_t launch_cgf_iteration<double>(const gct_plan *, const double *, double *, double *,
+                                                 double *, double *, double *, void *, double *, CGState *,
+                                                 int, hipStream_t);
 
 template <typename T>
 hipError_t launch_gram_apply(const gct_plan *p, const T *Ghat, const T *c, T *y, void *ws,

@@ -467,6 +467,7 @@ int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
         p->logP = logP;
         // elements per thread of the apply passes until gct_plan_autotune
         p->fft_e[0] = p->fft_e[1] = P >= 1024 ? 16 : (P == 512 ? 8 : 4);
+        p->cg_e[0] = p->cg_e[1] = p->fft_e[0];
         if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
         rc = build_plan(geom, p);
         if (rc) {
@@ -642,8 +643,9 @@ int gct_plan_set_fft_elems(gct_plan *p, gct_dtype dt, int32_t E)
     if (E == 0) E = p->P >= 1024 ? 16 : (p->P == 512 ? 8 : 4);
     if (!apply_e_ok(p->logP, E)) return fail(GCT_EINVAL, "elements per thread not available for this transform size");
     const int t = dt == GCT_F32 ? 0 : 1;
-    if (p->fft_e[t] != E) {
+    if (p->fft_e[t] != E || p->cg_e[t] != E) {
         p->fft_e[t] = E;
+        p->cg_e[t] = E;
         for (auto &g : p->cg_graphs) (void)hipGraphExecDestroy(g.exec);
         p->cg_graphs.clear();
     }

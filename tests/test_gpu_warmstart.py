@@ -33,8 +33,10 @@ def test_trained_net_cuts_cg_iterations(setup):
     rep = W.summarize(cmp)
     say("plain iters", rep["plain"]["iters"], "warm iters", rep["warm"]["iters"])
     say("plain ms", rep["plain"]["ms"], "warm ms", rep["warm"]["ms"], "rel_res0", rep["warm"]["rel_res0"])
-    # the single-slice plain solve agrees with the batched solver that made the targets
-    assert np.max(np.abs(cmp["plain_iters"] - iters)) <= 2
+    # the single-slice solve (Chronopoulos-Gear arrangement) and the batched
+    # solver that made the targets (textbook arrangement) take about as many
+    # iterations: equal in exact arithmetic, a few apart in FP32
+    assert np.max(np.abs(cmp["plain_iters"] - iters)) <= max(3, int(0.1 * np.max(iters)))
     # both forms meet the same stopping rule (true residual, FP32 slack)
     assert np.all(cmp["plain_res"] <= 1.05e-4) and np.all(cmp["warm_res"] <= 1.05e-4)
     assert int(np.sum(cmp["fell_back"])) == 0

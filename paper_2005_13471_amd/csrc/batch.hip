@@ -579,6 +579,11 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         std::vector<BatchSlice> v = b->host;
         for (int i = 0; i < count; ++i) {
             v[i].ga = t == 0 ? plans[i]->dev.gram_f32 : plans[i]->dev.gram_f64;
+            v[i].gord = reinterpret_cast<const int32_t *>(plans[i]->dev.gram_ord);
+            v[i].gth = reinterpret_cast<const double *>(plans[i]->dev.gram_th);
+            v[i].ghmax = plans[i]->gram_hmax;
+            v[i].l1 = plans[i]->lx1;
+            v[i].l2 = plans[i]->lx2;
             v[i].tw = t == 0 ? plans[i]->dev.tw_f32 : plans[i]->dev.tw_f64;
         }
         hipError_t e = hipMalloc(&b->dev[t], count * sizeof(BatchSlice));

@@ -84,6 +84,8 @@ struct DeviceTables {
     void *tw_f32 = nullptr, *tw_f64 = nullptr;        // complex twiddles e^{-2 pi i k / P}, k < P/2
     void *q_f32 = nullptr, *q_f64 = nullptr;          // correction filter q[-K..K]
     void *deg = nullptr;                              // int32[n]: B-spline degree per angle
+    void *gram_ord = nullptr;  // int32[n]: angle indices sorted by theta mod pi
+    void *gram_th = nullptr;   // double[n]: theta mod pi in that order
 };
 
 // Device-resident CG state (cg.hip, batch.hip).
@@ -112,6 +114,10 @@ struct BatchSlice {
     int64_t rpart;              // first row-pair partial of this slice
     const void *ga;             // GramAngle<T> table of the slice's plan
     const void *tw;             // twiddles of the slice's plan
+    const int32_t *gord;        // angles sorted by theta mod pi (Gram build)
+    const double *gth;
+    double ghmax;               // largest support half-width of A_theta
+    double l1, l2;              // pixel sides
 };
 
 // Key of a captured chunk of CG iterations.
@@ -137,6 +143,7 @@ struct gct_plan {
     int32_t N, n, M, K;
     double lx1, lx2, ly, zeta;
     int32_t P, logP;
+    double gram_hmax;  // largest support half-width of A_theta over the angles
     int32_t fft_e[2];  // elements per thread of the apply passes, [F32, F64]
     int32_t cg_e[2];   // elements per thread of the fused CG passes
     gct::BPDims bp;

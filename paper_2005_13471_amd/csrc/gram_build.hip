@@ -25,6 +25,8 @@
 // while the spline needs them to ~1e-7) and rounded once.  The sum over
 // angles is compensated (Kahan).  G[k] = G[-k] holds exactly (the footprint
 // is even), so half the taps are evaluated and mirrored.
+#include <cmath>
+
 #include "gct_internal.h"
 
 namespace gct {
@@ -64,17 +66,34 @@ __device__ __forceinline__ T gram_A(const GramAngle<T> &g, T x, bool blur)
 
 // One 16 x 16 tile of taps per block, covering only taps with k2 > 0 or
 // (k2 = 0, k1 >= 0); each such tap also writes its mirror -k (G is even).
-// Angle records are staged through LDS in chunks.  The angle loop is
-// uniform across the block; an angle whose projected tile interval misses
-// the support of A is skipped by the whole block.
-constexpr int GB_CHUNK = 128;
+//
+// Angular windows.  Tap k projects to k1 l1 cos + k2 l2 sin = rho cos(theta -
+// phi) with (rho, phi) the polar form of (k1 l1, k2 l2), so A_theta(k) can be
+// nonzero only where |cos(theta - phi)| < h / rho (h = support half-width):
+// theta within asin(h / rho) of phi + pi/2, mod pi.  Over the tile (polar
+// angles [phi_lo, phi_hi], distance >= rho_min from the origin) every
+// contributing angle lies in [phi_lo + pi/2 - d, phi_hi + pi/2 + d] mod pi,
+// d = asin(h_max / rho_min): at most two runs of the angles sorted by
+// theta mod pi, found by binary search.  Inside a run the exact per-angle
+// test on the tile's projected interval still applies, so the window only
+// has to contain every contributing angle.  The loop is uniform across the
+// block.
+__device__ __forceinline__ int lower_idx(const double *th, int n, double v)
+{
+    int lo = 0, hi = n;  // first index with th >= v
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (th[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
 
-// Tile (bx, by) of one Gram filter: taps k1 in [16 bx - (N-1), +16),
-// k2 in [16 by, +16).  s_ga is an LDS area of GB_CHUNK angle records.
 template <typename T>
 __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G, int N, int n,
                                                const GramAngle<T> *__restrict__ ga,
-                                               GramAngle<T> *s_ga)
+                                               const int32_t *__restrict__ ord, const double *__restrict__ th,
+                                               double hmax, double l1, double l2)
 {
     const int W = 2 * N - 1;
     const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -83,48 +102,58 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
     const int k1 = k1a + tx, k2 = k2a + ty;
     const bool live = k1 <= N - 1 && k2 <= N - 1 && (k2 > 0 || k1 >= 0);
     const double ka = k1a, kb = k1a + 15, la = k2a, lb = k2a + 15;
-    T acc = 0, comp = 0;
-    for (int a0 = 0; a0 < n; a0 += GB_CHUNK) {
-        const int cnt = min(GB_CHUNK, n - a0);
-        __syncthreads();
-        {
-            const int words = cnt * (int)(sizeof(GramAngle<T>) / 4);
-            const uint32_t *src = reinterpret_cast<const uint32_t *>(ga + a0);
-            uint32_t *dst = reinterpret_cast<uint32_t *>(s_ga);
-            for (int i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+    // the tile's runs of sorted angles (the same in every thread)
+    int run_lo[2] = {0, 0}, run_hi[2] = {n, 0};
+    const double x0 = ka * l1, x1 = kb * l1, y0 = la * l2, y1 = lb * l2;  // y0 >= 0
+    const double dx = x0 > 0.0 ? x0 : (x1 < 0.0 ? -x1 : 0.0);
+    const double dy = y0;
+    const double rmin = sqrt(dx * dx + dy * dy);
+    if (rmin > hmax * 1.000001 + 1e-9) {
+        const double f00 = atan2(y0, x0), f01 = atan2(y1, x0), f10 = atan2(y0, x1), f11 = atan2(y1, x1);
+        const double flo = fmin(fmin(f00, f01), fmin(f10, f11));
+        const double fhi = fmax(fmax(f00, f01), fmax(f10, f11));
+        const double d = asin(hmax / rmin) + 1e-9;
+        const double a0 = flo + 0.5 * M_PI - d, b0 = fhi + 0.5 * M_PI + d;
+        if (b0 - a0 < M_PI) {
+            double a = fmod(a0, M_PI);
+            if (a < 0.0) a += M_PI;
+            const double b = a + (b0 - a0);
+            run_lo[0] = lower_idx(th, n, a);
+            if (b <= M_PI) {
+                run_hi[0] = lower_idx(th, n, b);
+            } else {
+                run_hi[0] = n;
+                run_hi[1] = lower_idx(th, n, b - M_PI);
+            }
         }
-        __syncthreads();
-        for (int c = 0; c < cnt; ++c) {
-            const GramAngle<T> &g = s_ga[c];
+    }
+    T acc = 0, comp = 0;
+    for (int run = 0; run < 2; ++run)
+        for (int j = run_lo[run]; j < run_hi[run]; ++j) {
+            const GramAngle<T> g = ga[ord[j]];
             // projected interval of the tile (extreme corners)
             const double p1 = ka * g.cx, p2 = kb * g.cx, q1 = la * g.sx, q2 = lb * g.sx;
             const double dmin = fmin(p1, p2) + fmin(q1, q2), dmax = fmax(p1, p2) + fmax(q1, q2);
             if (dmax <= -(double)g.half || dmin >= (double)g.half) continue;
-            const T d = (T)((double)k1 * g.cx + (double)k2 * g.sx);
-            const T v = g.S > T(0) ? gram_A(g, d, true) : gram_A(g, d, false);
+            const T dd = (T)((double)k1 * g.cx + (double)k2 * g.sx);
+            const T v = g.S > T(0) ? gram_A(g, dd, true) : gram_A(g, dd, false);
             const T yk = v - comp;
             const T tk = acc + yk;
             comp = (tk - acc) - yk;
             acc = tk;
         }
-    }
     if (live) {
         G[(size_t)(k2 + N - 1) * W + (k1 + N - 1)] = acc;
         G[(size_t)(N - 1 - k2) * W + (N - 1 - k1)] = acc;
     }
 }
 
-// One 16 x 16 tile of taps per block, covering only taps with k2 > 0 or
-// (k2 = 0, k1 >= 0); each such tap also writes its mirror -k (G is even).
-// Angle records are staged through LDS in chunks.  The angle loop is
-// uniform across the block; an angle whose projected tile interval misses
-// the support of A is skipped by the whole block.
 template <typename T>
 __global__ void __launch_bounds__(256)
-k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ ga)
+k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ ga, const int32_t *__restrict__ ord,
+             const double *__restrict__ th, double hmax, double l1, double l2)
 {
-    __shared__ GramAngle<T> s_ga[GB_CHUNK];
-    body_gram_tile<T>(blockIdx.x, blockIdx.y, G, N, n, ga, s_ga);
+    body_gram_tile<T>(blockIdx.x, blockIdx.y, G, N, n, ga, ord, th, hmax, l1, l2);
 }
 
 // Batched: block b covers tile map[b].y of slice map[b].x.
@@ -132,11 +161,11 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 kb_gram_build(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl, T *__restrict__ G)
 {
-    __shared__ GramAngle<T> s_ga[GB_CHUNK];
     const int2 m = map[blockIdx.x];
     const BatchSlice &d = sl[m.x];
     const int tiles_x = (2 * d.N - 1 + 15) / 16;
-    body_gram_tile<T>(m.y % tiles_x, m.y / tiles_x, G + d.gram, d.N, d.n, reinterpret_cast<const GramAngle<T> *>(d.ga), s_ga);
+    body_gram_tile<T>(m.y % tiles_x, m.y / tiles_x, G + d.gram, d.N, d.n, reinterpret_cast<const GramAngle<T> *>(d.ga),
+                      d.gord, d.gth, d.ghmax, d.l1, d.l2);
 }
 
 template <typename T>
@@ -146,7 +175,9 @@ hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s)
     const dim3 grid((W + 15) / 16, (p->N + 15) / 16);
     const GramAngle<T> *ga =
         reinterpret_cast<const GramAngle<T> *>(sizeof(T) == 4 ? p->dev.gram_f32 : p->dev.gram_f64);
-    hipLaunchKernelGGL(k_gram_build<T>, grid, dim3(256), 0, s, G, p->N, p->n, ga);
+    hipLaunchKernelGGL(k_gram_build<T>, grid, dim3(256), 0, s, G, p->N, p->n, ga,
+                       reinterpret_cast<const int32_t *>(p->dev.gram_ord),
+                       reinterpret_cast<const double *>(p->dev.gram_th), p->gram_hmax, p->lx1, p->lx2);
     return hipGetLastError();
 }
 

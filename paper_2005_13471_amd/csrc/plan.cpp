@@ -377,6 +377,26 @@ static int build_plan(const gct_geometry *g, gct_plan *p)
     int rc;
     if ((rc = upload(&p->dev.gram_f32, gf))) return rc;
     if ((rc = upload(&p->dev.gram_f64, gd))) return rc;
+    {
+        // angles sorted by theta mod pi, for the Gram build's angular windows
+        std::vector<double> th(n);
+        std::vector<int32_t> ord(n);
+        double hmax = 0.0;
+        for (int a = 0; a < n; ++a) {
+            double t = std::fmod(g->theta[a], M_PI);
+            if (t < 0.0) t += M_PI;
+            if (t >= M_PI) t = 0.0;
+            th[a] = t;
+            ord[a] = a;
+            hmax = std::max(hmax, (double)gd[a].half);
+        }
+        std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return th[x] < th[y]; });
+        std::vector<double> ths(n);
+        for (int a = 0; a < n; ++a) ths[a] = th[ord[a]];
+        p->gram_hmax = hmax;
+        if ((rc = upload(&p->dev.gram_ord, ord))) return rc;
+        if ((rc = upload(&p->dev.gram_th, ths))) return rc;
+    }
     if ((rc = upload(&p->dev.fwd_f32, ff))) return rc;
     if ((rc = upload(&p->dev.fwd_f64, fd))) return rc;
     if ((rc = upload(&p->dev.bp_geo, geo))) return rc;
@@ -398,7 +418,8 @@ static void free_tables(gct_plan *p)
     void **all[] = {&p->dev.gram_f32,    &p->dev.gram_f64,    &p->dev.fwd_f32,     &p->dev.fwd_f64,
                     &p->dev.bp_geo,      &p->dev.bp_int,      &p->dev.bp_brk_f32,  &p->dev.bp_brk_f64,
                     &p->dev.bp_coef_f32, &p->dev.bp_coef_f64, &p->dev.tw_f32,      &p->dev.tw_f64,
-                    &p->dev.q_f32,       &p->dev.q_f64,       &p->dev.deg};
+                    &p->dev.q_f32,       &p->dev.q_f64,       &p->dev.deg,         &p->dev.gram_ord,
+                    &p->dev.gram_th};
     for (void **v : all) {
         if (*v) (void)hipFree(*v);
         *v = nullptr;

@@ -97,14 +97,22 @@ int gct_unet_set_moments(gct_unet *u, const float *m, const float *v, void *stre
 
 /* y = out_scale * net(in_scale * x) for `batch` images (1 <= batch <=
  * max_batch); keeps the activations for gct_unet_backward.  x, y: FP32
- * [batch][H][W]; y must not alias x. */
+ * [batch][H][W]; y must not alias x.  The launch sequence is captured as a
+ * HIP graph on the first call with a given (batch, x, y, in_scale,
+ * out_scale) and replayed by later calls with the same arguments (the
+ * newest 8 are kept; a capture costs about a millisecond of host time), so
+ * callers in a loop should reuse their x and y buffers.  A replay reads the
+ * current contents of x and the current weights.  Not to be called while
+ * the calling thread captures a graph of its own. */
 int gct_unet_forward(gct_unet *u, int32_t batch, const float *x, float in_scale, float out_scale, float *y,
                      void *stream);
 
 /* Loss mean((y - target)^2) over batch H W pixels into *loss (a device
  * float; NULL = internal) and the gradient of the loss with respect to every
  * parameter, kept for gct_unet_get_grads / gct_unet_adam_step.  y must be
- * the output of the preceding gct_unet_forward with the same batch. */
+ * the output of the preceding gct_unet_forward with the same batch, and
+ * that forward's x must still hold the same values (the backward rebuilds
+ * the prepared input from it). */
 int gct_unet_backward(gct_unet *u, int32_t batch, const float *y, const float *target, float *loss,
                       void *stream);
 

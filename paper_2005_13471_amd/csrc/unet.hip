@@ -87,23 +87,36 @@ struct ConvArgs {
     float *out32;
     float oscale;
     int cout;
+    // direct kernel only: FP32 single-channel input (first layer) and the
+    // final 1x1 layer fused into the epilogue (mode 3)
+    const float *in32;
+    float in_scale;
+    const bf16_t *fw;
+    const float *fb;
 };
 
-// Epilogue of GEMM element (m, n) with accumulated value v (modes above).
-__device__ inline void conv_store(const ConvArgs &a, int m, int n, float v)
+// Bias of GEMM column n (0 without bias).
+__device__ inline float conv_bias(const ConvArgs &a, int n)
 {
+    if (!a.bias) return 0.f;
+    return a.bias[a.mode == 2 ? n % a.cout : (a.mode == 1 ? 0 : n)];
+}
+
+// Epilogue of GEMM element (m, n) with accumulated value v and the bias bn
+// of column n (modes above).
+__device__ inline void conv_store(const ConvArgs &a, int m, int n, float v, float bn)
+{
+    v += bn;
     if (a.mode == 0) {
-        if (a.bias) v += a.bias[n];
         if (a.relu) v = fmaxf(v, 0.f);
         a.out[(size_t)m * a.out_cs + a.out_co + n] = f2bf(v);
     } else if (a.mode == 1) {
-        if (n == 0) a.out32[m] = a.oscale * (v + (a.bias ? a.bias[0] : 0.f));
+        if (n == 0) a.out32[m] = a.oscale * v;
     } else {
         const int HWo = a.Hout * a.Wout;
         const int bb = m / HWo, rr = m - bb * HWo, yh = rr / a.Wout, yw = rr - yh * a.Wout;
         const int ab = n / a.cout, co = n - ab * a.cout;
         const int oy = 2 * yh + (ab >> 1), ox = 2 * yw + (ab & 1);
-        if (a.bias) v += a.bias[co];
         if (a.relu) v = fmaxf(v, 0.f);
         const size_t pix = ((size_t)bb * (2 * a.Hout) + oy) * (2 * a.Wout) + ox;
         a.out[pix * a.out_cs + a.out_co + co] = f2bf(v);
@@ -131,6 +144,12 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[q] = float4_t{0.f, 0.f, 0.f, 0.f};
     const short4_t zero = {0, 0, 0, 0};
+    float bq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int n = n0 + 16 * q + (lane & 15);
+        bq[q] = n < a.Nw ? conv_bias(a, n) : 0.f;
+    }
     for (int t = 0; t < a.ntaps; ++t) {
         const int ih = oh * a.stride + t / a.tw + a.org;
         const int iw = ow * a.stride + t % a.tw + a.org;
@@ -156,7 +175,7 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int m = m0 + (lane >> 4) * 4 + j;
-            if (m < M) conv_store(a, m, n, acc[q][j]);
+            if (m < M) conv_store(a, m, n, acc[q][j], bq[q]);
         }
     }
 }
@@ -175,12 +194,35 @@ __global__ void __launch_bounds__(256) k_conv(ConvArgs a)
 // fixed order.  (A reduction by the last block of each tile would need a
 // device-scope release per block, i.e. an L2 write-back, which costs more
 // than the extra launch.)
+// Input gathers (IN): 0 = BF16 NHWC; 1 = the 2x2 max pool of a BF16 NHWC
+// tensor of twice the grid (a.in un-pooled, a.Hin x a.Win the pooled grid:
+// pooling fused into its consumer); 2 = FP32 single-channel image a.in32
+// times in_scale, BF16-rounded into channel 0 of Cin = 16 (input
+// preparation fused into the first layer).  Mode 3 = mode 0 plus the final
+// 1x1 convolution of the stored BF16 activation, out32[m] = oscale (sum_n
+// act[m][n] fw[n] + fb[0]); it needs every column in this block (Nw <= BN)
+// and no K split.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 
-template <int BM, int BN>
+__device__ inline uint4 bf8_max(uint4 p, uint4 q)
+{
+    uint4 r;
+    const uint32_t *x = &p.x, *y = &q.x;
+    uint32_t *o = &r.x;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+        const float lo = fmaxf(__uint_as_float(x[w] << 16), __uint_as_float(y[w] << 16));
+        const float hi = fmaxf(__uint_as_float(x[w] & 0xffff0000u), __uint_as_float(y[w] & 0xffff0000u));
+        o[w] = (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xffff0000u);
+    }
+    return r;
+}
+
+template <int BM, int BN, int IN>
 __global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, float *part)
 {
+    constexpr int NA = IN == 1 ? 4 : 1;  // loads per A chunk (the pooled 2x2 window)
     constexpr int LDK = 40;  // 32 + 8 padding bf16: 80-byte rows, conflict-free 16-byte reads
     constexpr int KC = 4;    // K steps staged per barrier (their loads are in flight together)
     constexpr int AP = BM * 4 / 256;            // A chunks per thread and step
@@ -196,6 +238,7 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, flo
     const int K = a.ntaps * a.Cin, nks = (K + 31) / 32;
     const int kbeg = blockIdx.z * ksplit_steps, kend = min(nks, kbeg + ksplit_steps);
     const int g = tid & 3;
+    const int Ws = IN == 1 ? 2 * a.Win : a.Win;  // width of the gathered grid
 
     // per-thread rows (A) and columns (B)
     int rb[AP], rh[AP], rw[AP];
@@ -206,7 +249,7 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, flo
         rok[i] = m < M;
         const int mm = rok[i] ? m : 0;
         const int b = mm / HWo, r = mm - b * HWo, oh = r / a.Wout, ow = r - oh * a.Wout;
-        rb[i] = b * a.Hin;
+        rb[i] = b * (IN == 1 ? 2 * a.Hin : a.Hin);
         rh[i] = oh * a.stride + a.org;
         rw[i] = ow * a.stride + a.org;
     }
@@ -228,7 +271,7 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, flo
         dy = t / a.tw;
         dx = t - dy * a.tw;
     }
-    uint4 ra[KC][AP], rbv[KC][BP];
+    uint4 ra[KC][AP][NA], rbv[KC][BP];
     // issue the loads of steps kn .. kn + KC - 1 (zero past kend or K)
     auto gload = [&]() {
 #pragma unroll
@@ -238,9 +281,22 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, flo
             for (int i = 0; i < AP; ++i) {
                 const int ih = rh[i] + dy, iw = rw[i] + dx;
                 const bool ok = kok && rok[i] && ih >= 0 && ih < a.Hin && iw >= 0 && iw < a.Win;
-                ra[s][i] = ok ? *reinterpret_cast<const uint4 *>(
-                                    a.in + ((size_t)(rb[i] + ih) * a.Win + iw) * a.in_cs + a.in_co + c)
-                              : make_uint4(0, 0, 0, 0);
+                if (IN == 0) {
+                    ra[s][i][0] = ok ? *reinterpret_cast<const uint4 *>(
+                                           a.in + ((size_t)(rb[i] + ih) * a.Win + iw) * a.in_cs + a.in_co + c)
+                                     : make_uint4(0, 0, 0, 0);
+                } else if (IN == 1) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        ra[s][i][q] = ok ? *reinterpret_cast<const uint4 *>(
+                                               a.in + ((size_t)(rb[i] + 2 * ih + (q >> 1)) * Ws + 2 * iw + (q & 1)) *
+                                                          a.in_cs +
+                                               a.in_co + c)
+                                         : make_uint4(0, 0, 0, 0);
+                } else {
+                    // the pixel's FP32 value, converted when staged
+                    ra[s][i][0].x = (ok && c == 0) ? __float_as_uint(a.in32[(size_t)(rb[i] + ih) * a.Win + iw]) : 0u;
+                }
             }
 #pragma unroll
             for (int i = 0; i < BP; ++i) {
@@ -267,14 +323,30 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, flo
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
 
+    // epilogue columns of this lane: bias loaded now, while the K loop runs
+    // (a load per stored element would wait out one memory latency each)
+    float bcol[TN];
+    int ccol[TN], acol[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int n = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+        acol[j] = a.mode == 2 ? n / a.cout : 0;
+        ccol[j] = n - acol[j] * a.cout * (a.mode == 2);
+        bcol[j] = (gridDim.z == 1 && a.bias && n < a.Nw) ? a.bias[ccol[j]] : 0.f;
+    }
+
     if (kbeg < kend) gload();
     for (int ks0 = kbeg; ks0 < kend; ks0 += KC) {
         if (ks0 != kbeg) __syncthreads();  // the previous chunk's reads are done
 #pragma unroll
         for (int s = 0; s < KC; ++s) {
 #pragma unroll
-            for (int i = 0; i < AP; ++i)
-                *reinterpret_cast<uint4 *>(&sA[s][((tid >> 2) + 64 * i) * LDK + 8 * g]) = ra[s][i];
+            for (int i = 0; i < AP; ++i) {
+                uint4 v = ra[s][i][0];
+                if (IN == 1) v = bf8_max(bf8_max(ra[s][i][0], ra[s][i][1]), bf8_max(ra[s][i][2], ra[s][i][3]));
+                if (IN == 2) v = make_uint4(f2bf(__uint_as_float(ra[s][i][0].x) * a.in_scale), 0u, 0u, 0u);
+                *reinterpret_cast<uint4 *>(&sA[s][((tid >> 2) + 64 * i) * LDK + 8 * g]) = v;
+            }
 #pragma unroll
             for (int i = 0; i < BP; ++i) {
                 const int q = tid + 256 * i;
@@ -305,18 +377,75 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, flo
     }
     // D layout: row 4 (lane / 16) + r, column lane % 16 of each 16x16 tile
     if (gridDim.z == 1) {
+        if (a.mode == 0) {
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int n = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+                    if (n >= a.Nw) continue;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int m = m0 + wm * (BM / 2) + i * 16 + (lane >> 4) * 4 + r;
+                        float v = acc[i][j][r] + bcol[j];
+                        if (a.relu) v = fmaxf(v, 0.f);
+                        if (m < M) a.out[(size_t)m * a.out_cs + a.out_co + n] = f2bf(v);
+                    }
+                }
+        } else if (a.mode == 3) {
+            // the block holds every column: row sums of act x fw over this
+            // wave's columns (16 lanes per row), then over the two column
+            // halves through LDS
+            __shared__ float fsum[2][BM];
+            float fwc[TN];
 #pragma unroll
             for (int j = 0; j < TN; ++j) {
-                const int n = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
-                if (n >= a.Nw) continue;
+                const int n = wn * (BN / 2) + j * 16 + (lane & 15);
+                fwc[j] = n < a.Nw ? bf2f(a.fw[n]) : 0.f;
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int ml = wm * (BM / 2) + i * 16 + (lane >> 4) * 4 + r, m = m0 + ml;
+                    float f = 0.f;
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        const int n = wn * (BN / 2) + j * 16 + (lane & 15);
+                        float v = acc[i][j][r] + bcol[j];
+                        if (a.relu) v = fmaxf(v, 0.f);
+                        const bf16_t h = f2bf(v);
+                        if (m < M && n < a.Nw) a.out[(size_t)m * a.out_cs + a.out_co + n] = h;
+                        f += bf2f(h) * fwc[j];
+                    }
+#pragma unroll
+                    for (int o = 1; o < 16; o <<= 1) f += __shfl_xor(f, o, 16);
+                    if ((lane & 15) == 0) fsum[wn][ml] = f;
+                }
+            __syncthreads();
+            if (tid < BM && m0 + tid < M) a.out32[m0 + tid] = a.oscale * (fsum[0][tid] + fsum[1][tid] + a.fb[0]);
+        } else {
+            // transposed-convolution scatter: n = (2a + b) cout + co to output
+            // pixel (2 oh + a, 2 ow + b)
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int m = m0 + wm * (BM / 2) + i * 16 + (lane >> 4) * 4 + r;
-                    if (m < M) conv_store(a, m, n, acc[i][j][r]);
+                    if (m >= M) continue;
+                    const int bb = m / HWo, rr = m - bb * HWo, yh = rr / a.Wout, yw = rr - yh * a.Wout;
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        const int n = n0 + wn * (BN / 2) + j * 16 + (lane & 15);
+                        if (n >= a.Nw) continue;
+                        float v = acc[i][j][r] + bcol[j];
+                        if (a.relu) v = fmaxf(v, 0.f);
+                        const int oy = 2 * yh + (acol[j] >> 1), ox = 2 * yw + (acol[j] & 1);
+                        const size_t pix = ((size_t)bb * (2 * a.Hout) + oy) * (2 * a.Wout) + ox;
+                        a.out[pix * a.out_cs + a.out_co + ccol[j]] = f2bf(v);
+                    }
                 }
-            }
+        }
         return;
     }
     // split K: partial tile to part[z][m][n], reduced by k_conv_splitk
@@ -334,6 +463,192 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, flo
         }
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 convolution (stride 1, zero padding 1) from an LDS halo tile.  The
+// gathered implicit GEMM above reads every input pixel once per tap (nine
+// times) from L2; here a block stages its output tile's input window with
+// the one-pixel halo, (TY + 2) x 18 pixels x 32 channels, once per chunk of
+// 32 input channels, plus the chunk's weights for all nine taps and BN
+// columns, and the nine taps read the window from LDS at shifted offsets.
+// Block: output tile TY x 16 pixels of one image x BN channels, 4 waves as
+// 2 x 2 (each (8 TY) rows x BN/2 columns; a 16-row MFMA tile is one image
+// row of the tile).  The next chunk's loads are in flight (registers)
+// during the current chunk's MFMAs.  Needs Cin to be a multiple of 32.
+// Input gathers IN 0 and 1 and epilogue modes 0 and 3 as in k_conv2;
+// gridDim.z > 1 splits the channel chunks, partials reduced by
+// k_conv_splitk.
+// ---------------------------------------------------------------------------
+template <int TY, int BN, int IN>
+__global__ void __launch_bounds__(256) k_conv33(ConvArgs a, int chunks_per_part, float *part)
+{
+    constexpr int LDK = 40;                        // 32 channels + 8 padding (80-byte rows)
+    constexpr int HW_ = 18, HP = (TY + 2) * HW_;   // halo window width and pixels
+    constexpr int MT = TY * 16;                    // output pixels per block
+    constexpr int TM = MT / 32, TN = BN / 32;      // 16x16 tiles per wave
+    constexpr int NA = IN == 1 ? 4 : 1;
+    constexpr int PI = (HP * 4 + 255) / 256;       // input pieces (16 B) per thread
+    constexpr int PW = (9 * BN * 4 + 255) / 256;   // weight pieces per thread
+    __shared__ __attribute__((aligned(16))) bf16_t sIn[HP * LDK];
+    __shared__ __attribute__((aligned(16))) bf16_t sW[9 * BN * LDK];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int l16 = lane & 15, kg = lane >> 4;
+    const int H = a.Hout, W = a.Wout;
+    const int tx_n = (W + 15) / 16, ty_n = (H + TY - 1) / TY;
+    const int bx = blockIdx.x % tx_n, by = (blockIdx.x / tx_n) % ty_n, b = blockIdx.x / (tx_n * ty_n);
+    const int x0 = bx * 16, y0 = by * TY, n0 = blockIdx.y * BN;
+    const int nch = a.Cin / 32;
+    const int cbeg = blockIdx.z * chunks_per_part, cend = min(nch, cbeg + chunks_per_part);
+    const int Hs = IN == 1 ? 2 * H : H, Ws = IN == 1 ? 2 * W : W;
+
+    uint4 ri[PI][NA], rw[PW];
+    auto gload = [&](int ch) {
+        const int c0 = ch * 32;
+#pragma unroll
+        for (int q = 0; q < PI; ++q) {
+            const int pc = tid + 256 * q, hp = pc >> 2, cg = pc & 3;
+            const int yy = y0 - 1 + hp / HW_, xx = x0 - 1 + hp % HW_;
+            const bool ok = pc < HP * 4 && yy >= 0 && yy < H && xx >= 0 && xx < W;
+            if (IN == 0) {
+                ri[q][0] = ok ? *reinterpret_cast<const uint4 *>(a.in + ((size_t)(b * Hs + yy) * Ws + xx) * a.in_cs +
+                                                                 a.in_co + c0 + 8 * cg)
+                              : make_uint4(0, 0, 0, 0);
+            } else {
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    ri[q][w] = ok ? *reinterpret_cast<const uint4 *>(
+                                        a.in + ((size_t)(b * Hs + 2 * yy + (w >> 1)) * Ws + 2 * xx + (w & 1)) * a.in_cs +
+                                        a.in_co + c0 + 8 * cg)
+                                  : make_uint4(0, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < PW; ++q) {
+            const int pc = tid + 256 * q, row = pc >> 2, cg = pc & 3;  // row = tap BN + n
+            const int tap = row / BN, n = n0 + row % BN;
+            const bool ok = pc < 9 * BN * 4 && n < a.Nw;
+            rw[q] = ok ? *reinterpret_cast<const uint4 *>(a.w + ((size_t)tap * a.Nw + n) * a.Cin + c0 + 8 * cg)
+                       : make_uint4(0, 0, 0, 0);
+        }
+    };
+
+    float4_t acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
+    // epilogue columns of this lane
+    float bcol[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int n = n0 + wn * (BN / 2) + j * 16 + l16;
+        bcol[j] = (gridDim.z == 1 && a.bias && n < a.Nw) ? a.bias[n] : 0.f;
+    }
+
+    if (cbeg < cend) gload(cbeg);
+    for (int ch = cbeg; ch < cend; ++ch) {
+        if (ch != cbeg) __syncthreads();  // the previous chunk's LDS reads are done
+#pragma unroll
+        for (int q = 0; q < PI; ++q) {
+            const int pc = tid + 256 * q;
+            uint4 v = ri[q][0];
+            if (IN == 1) v = bf8_max(bf8_max(ri[q][0], ri[q][1]), bf8_max(ri[q][2], ri[q][3]));
+            if (pc < HP * 4) *reinterpret_cast<uint4 *>(&sIn[(pc >> 2) * LDK + 8 * (pc & 3)]) = v;
+        }
+#pragma unroll
+        for (int q = 0; q < PW; ++q) {
+            const int pc = tid + 256 * q;
+            if (pc < 9 * BN * 4) *reinterpret_cast<uint4 *>(&sW[(pc >> 2) * LDK + 8 * (pc & 3)]) = rw[q];
+        }
+        __syncthreads();
+        if (ch + 1 < cend) gload(ch + 1);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap % 3;
+            bf16x8_t af[TM], bfr[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                const int pr = wm * (MT / 2) + i * 16;  // first pixel of the 16-row tile (one tile row)
+                const int py = pr / 16;
+                af[i] = *reinterpret_cast<const bf16x8_t *>(&sIn[((py + dy) * HW_ + l16 + dx) * LDK + kg * 8]);
+            }
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+                bfr[j] = *reinterpret_cast<const bf16x8_t *>(
+                    &sW[(tap * BN + wn * (BN / 2) + j * 16 + l16) * LDK + kg * 8]);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+        }
+    }
+
+    // D layout: tile row 4 (lane / 16) + r = pixel x0 + 4 kg + r of image
+    // row y0 + py; column lane % 16
+    if (gridDim.z > 1) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int yy = y0 + (wm * (MT / 2) + i * 16) / 16;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int n = n0 + wn * (BN / 2) + j * 16 + l16;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int xx = x0 + kg * 4 + r;
+                    if (yy < H && xx < W && n < a.Nw) {
+                        const size_t m = ((size_t)b * H + yy) * W + xx;
+                        part[((size_t)blockIdx.z * a.B * H * W + m) * a.Nw + n] = acc[i][j][r];
+                    }
+                }
+            }
+        }
+        return;
+    }
+    __shared__ float fsum[2][MT];
+    float fwc[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int n = n0 + wn * (BN / 2) + j * 16 + l16;
+        fwc[j] = (a.mode == 3 && n < a.Nw) ? bf2f(a.fw[n]) : 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int pl = wm * (MT / 2) + i * 16;
+        const int yy = y0 + pl / 16;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int xx = x0 + kg * 4 + r;
+            const bool mok = yy < H && xx < W;
+            const size_t m = ((size_t)b * H + yy) * W + xx;
+            float f = 0.f;
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int n = n0 + wn * (BN / 2) + j * 16 + l16;
+                float v = acc[i][j][r] + bcol[j];
+                if (a.relu) v = fmaxf(v, 0.f);
+                const bf16_t h = f2bf(v);
+                if (mok && n < a.Nw) a.out[m * a.out_cs + a.out_co + n] = h;
+                f += bf2f(h) * fwc[j];
+            }
+            if (a.mode == 3) {
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) f += __shfl_xor(f, o, 16);
+                if (l16 == 0) fsum[wn][pl + kg * 4 + r] = f;
+            }
+        }
+    }
+    if (a.mode == 3) {
+        __syncthreads();
+        if (tid < MT) {
+            const int yy = y0 + tid / 16, xx = x0 + tid % 16;
+            if (yy < H && xx < W)
+                a.out32[((size_t)b * H + yy) * W + xx] = a.oscale * (fsum[0][tid] + fsum[1][tid] + a.fb[0]);
+        }
+    }
+}
+
 // sum of the split-K partials in z order (a fixed order), then the epilogue
 __global__ void __launch_bounds__(256) k_conv_splitk(ConvArgs a, int nz, const float *part)
 {
@@ -343,7 +658,7 @@ __global__ void __launch_bounds__(256) k_conv_splitk(ConvArgs a, int nz, const f
         float v = 0.f;
         for (int z = 0; z < nz; ++z) v += part[(size_t)z * len + i];
         const int m = (int)(i / a.Nw), n = (int)(i - (size_t)m * a.Nw);
-        conv_store(a, m, n, v);
+        conv_store(a, m, n, v, conv_bias(a, n));
     }
 }
 
@@ -825,6 +1140,20 @@ struct gct_unet {
     void *arena = nullptr;
     float oscale = 1.f;
     int last_batch = 0;
+    // input of the last forward (the backward rebuilds the prepared input)
+    const float *fx = nullptr;
+    float fscale = 1.f;
+    // captured forwards, keyed by their arguments (the other buffers are the
+    // net's own), and the private stream they are captured on
+    struct FwdGraph {
+        int B;
+        const float *x;
+        float *y;
+        float in_scale, out_scale;
+        hipGraphExec_t exec;
+    };
+    std::vector<FwdGraph> fgraphs;
+    hipStream_t capture = nullptr;
 
     int C(int l) const { return C0 << l; }
     int Hl(int l) const { return H >> l; }
@@ -851,10 +1180,13 @@ ConvTiling conv_tiling(long long M, int Nw, int K)
     const long long nb = cdiv(Nw, t.BN);
     t.BM = (long long)cdiv(M, 128) * nb >= 256 ? 128 : 64;
     const long long blocks = (long long)cdiv(M, t.BM) * nb;
-    const int nks = (K + 31) / 32;
+    // K is split only where few blocks each run a long chain of 4-step
+    // chunks: the split costs a reduce launch, worth it only when it removes
+    // several dependent chunks per block; every part keeps >= 2 chunks
+    const int nks = (K + 31) / 32, chunks = (nks + 3) / 4;
     int ks = 1;
-    if (blocks < 512) ks = (int)std::min<long long>(16, (512 + blocks - 1) / blocks);
-    ks = std::max(1, std::min(ks, nks / 2));
+    if (blocks < 256 && chunks > 4)
+        ks = (int)std::min<long long>({16LL, (256 + blocks - 1) / blocks, (long long)chunks / 2});
     t.steps = (nks + ks - 1) / ks;
     t.ksplit = (nks + t.steps - 1) / t.steps;
     return t;
@@ -867,7 +1199,46 @@ size_t conv_part_elems(long long M, int Nw, int K)
     return t.ksplit > 1 ? (size_t)t.ksplit * M * Nw : 0;
 }
 
-void conv_launch(const ConvArgs &a, hipStream_t st, float *part)
+// Tiles of the halo-tiled 3x3 kernel: 8 x 16 pixel tiles while they still
+// give >= 256 blocks, else 4 x 16; the 32-channel chunks split over up to 8
+// parts until about 256 blocks run (never for the fused final layer).
+struct Conv33Tiling {
+    int TY, BN, ksplit, cpp;
+};
+
+Conv33Tiling conv33_tiling(int B, int H, int W, int Nw, int Cin, bool no_split)
+{
+    Conv33Tiling t;
+    t.BN = Nw <= 32 ? 32 : 64;
+    const long long nb = cdiv(Nw, t.BN);
+    const long long tiles8 = (long long)B * cdiv(H, 8) * cdiv(W, 16);
+    t.TY = tiles8 * nb >= 256 ? 8 : 4;
+    const long long blocks = (long long)B * cdiv(H, t.TY) * cdiv(W, 16) * nb;
+    const int nch = Cin / 32;
+    int ks = 1;
+    if (!no_split && blocks < 256 && nch >= 2) ks = (int)std::min<long long>({8LL, nch, cdiv(256, blocks)});
+    t.cpp = cdiv(nch, ks);
+    t.ksplit = cdiv(nch, t.cpp);
+    return t;
+}
+
+bool conv33_ok(const ConvArgs &a, int in_kind)
+{
+    return a.ntaps == 9 && a.tw == 3 && a.org == -1 && a.stride == 1 && a.Cin % 32 == 0 && in_kind != 2 &&
+           a.Hin == a.Hout && a.Win == a.Wout && (a.mode == 0 || a.mode == 3);
+}
+
+size_t conv33_part_elems(int B, int H, int W, int Nw, int Cin)
+{
+    if (Cin % 32 != 0) return 0;
+    const Conv33Tiling t = conv33_tiling(B, H, W, Nw, Cin, false);
+    return t.ksplit > 1 ? (size_t)t.ksplit * B * H * W * Nw : 0;
+}
+
+// in_kind: the input gather of k_conv2 (0 plain, 1 pooled, 2 FP32 first
+// layer).  Pooled gathers hold four loads per A chunk, so they take the
+// 64-row tile; mode 3 (fused final layer) is never K-split.
+void conv_launch(const ConvArgs &a, hipStream_t st, float *part, int in_kind = 0)
 {
     const long long M = (long long)a.B * a.Hout * a.Wout;
     if (a.mode == 1) {  // one output column: the plain kernel
@@ -875,16 +1246,64 @@ void conv_launch(const ConvArgs &a, hipStream_t st, float *part)
         hipLaunchKernelGGL(k_conv, grid, dim3(256), 0, st, a);
         return;
     }
-    const ConvTiling t = conv_tiling(M, a.Nw, a.ntaps * a.Cin);
+    if (conv33_ok(a, in_kind)) {
+        const Conv33Tiling t = conv33_tiling(a.B, a.Hout, a.Wout, a.Nw, a.Cin, a.mode == 3);
+        dim3 grid((unsigned)((long long)a.B * cdiv(a.Hout, t.TY) * cdiv(a.Wout, 16)), cdiv(a.Nw, t.BN), t.ksplit);
+#define GCT_CONV33(TY_, BN_, IN_) \
+    hipLaunchKernelGGL((k_conv33<TY_, BN_, IN_>), grid, dim3(256), 0, st, a, t.cpp, part)
+        if (in_kind == 1) {
+            if (t.TY == 8 && t.BN == 64) GCT_CONV33(8, 64, 1);
+            else if (t.TY == 8) GCT_CONV33(8, 32, 1);
+            else if (t.BN == 64) GCT_CONV33(4, 64, 1);
+            else GCT_CONV33(4, 32, 1);
+        } else {
+            if (t.TY == 8 && t.BN == 64) GCT_CONV33(8, 64, 0);
+            else if (t.TY == 8) GCT_CONV33(8, 32, 0);
+            else if (t.BN == 64) GCT_CONV33(4, 64, 0);
+            else GCT_CONV33(4, 32, 0);
+        }
+#undef GCT_CONV33
+        if (t.ksplit > 1) {
+            const long long len = M * a.Nw;
+            hipLaunchKernelGGL(k_conv_splitk, dim3((unsigned)std::min<long long>(2048, cdiv(len, 256))), dim3(256), 0,
+                               st, a, t.ksplit, (const float *)part);
+        }
+        return;
+    }
+    ConvTiling t = conv_tiling(M, a.Nw, a.ntaps * a.Cin);
+    if (in_kind == 1) t.BM = 64;
+    if (a.mode == 3) {
+        t.steps = (a.ntaps * a.Cin + 31) / 32;
+        t.ksplit = 1;
+    }
     dim3 grid(cdiv(M, t.BM), cdiv(a.Nw, t.BN), t.ksplit);
-    if (t.BM == 128 && t.BN == 64)
-        hipLaunchKernelGGL((k_conv2<128, 64>), grid, dim3(256), 0, st, a, t.steps, part);
-    else if (t.BM == 128)
-        hipLaunchKernelGGL((k_conv2<128, 32>), grid, dim3(256), 0, st, a, t.steps, part);
-    else if (t.BN == 64)
-        hipLaunchKernelGGL((k_conv2<64, 64>), grid, dim3(256), 0, st, a, t.steps, part);
-    else
-        hipLaunchKernelGGL((k_conv2<64, 32>), grid, dim3(256), 0, st, a, t.steps, part);
+#define GCT_CONV2(BM_, BN_, IN_) \
+    hipLaunchKernelGGL((k_conv2<BM_, BN_, IN_>), grid, dim3(256), 0, st, a, t.steps, part)
+    if (in_kind == 1) {
+        if (t.BN == 64)
+            GCT_CONV2(64, 64, 1);
+        else
+            GCT_CONV2(64, 32, 1);
+    } else if (in_kind == 2) {
+        if (t.BM == 128 && t.BN == 64)
+            GCT_CONV2(128, 64, 2);
+        else if (t.BM == 128)
+            GCT_CONV2(128, 32, 2);
+        else if (t.BN == 64)
+            GCT_CONV2(64, 64, 2);
+        else
+            GCT_CONV2(64, 32, 2);
+    } else {
+        if (t.BM == 128 && t.BN == 64)
+            GCT_CONV2(128, 64, 0);
+        else if (t.BM == 128)
+            GCT_CONV2(128, 32, 0);
+        else if (t.BN == 64)
+            GCT_CONV2(64, 64, 0);
+        else
+            GCT_CONV2(64, 32, 0);
+    }
+#undef GCT_CONV2
     if (t.ksplit > 1) {
         const long long len = M * a.Nw;
         hipLaunchKernelGGL(k_conv_splitk, dim3((unsigned)std::min<long long>(2048, cdiv(len, 256))), dim3(256), 0,
@@ -892,10 +1311,12 @@ void conv_launch(const ConvArgs &a, hipStream_t st, float *part)
     }
 }
 
-// forward of layer Lr: rows over the Hout x Wout grid
+// forward of layer Lr: rows over the Hout x Wout grid (in_kind: see
+// conv_launch; mode 3 fuses the final 1x1 layer and writes out32).  Hin x
+// Win is the layer's input grid (pooled when in_kind = 1).
 void fwd(const gct_unet *u, const ULayer &Lr, int B, const bf16_t *in, int in_cs, int in_co, int Hin,
          int Win, int Hout, int Wout, bf16_t *out, int out_cs, int out_co, int relu, int mode, float *out32,
-         hipStream_t st)
+         hipStream_t st, int in_kind = 0, const float *in32 = nullptr, float in_scale = 1.f)
 {
     ConvArgs a{};
     a.in = in;
@@ -922,7 +1343,14 @@ void fwd(const gct_unet *u, const ULayer &Lr, int B, const bf16_t *in, int in_cs
     a.out32 = out32;
     a.oscale = u->oscale;
     a.cout = Lr.cout;
-    conv_launch(a, st, u->part);
+    a.in32 = in32;
+    a.in_scale = in_scale;
+    if (mode == 3) {
+        const ULayer &F = u->layers[u->fin];
+        a.fw = u->w16 + F.w_off;
+        a.fb = u->w + F.b_off;
+    }
+    conv_launch(a, st, u->part, in_kind);
 }
 
 // data gradient of layer Lr: gin (rows over the layer's input grid) from
@@ -1160,6 +1588,8 @@ int gct_unet_create(const gct_unet_config *cfg, gct_unet **out)
                 const ULayer &Lr = u->layers[idx];
                 part = std::max(part, conv_part_elems(Ml, Lr.Nw, 9 * Lr.Cin));
                 part = std::max(part, conv_part_elems(Ml, Lr.Cin, 9 * Lr.Nw));
+                part = std::max(part, conv33_part_elems(B, u->Hl(l), u->Wl(l), Lr.Nw, Lr.Cin));
+                part = std::max(part, conv33_part_elems(B, u->Hl(l), u->Wl(l), Lr.Cin, Lr.Nw));
             }
             if (u->up[l] >= 0) {
                 const ULayer &Lr = u->layers[u->up[l]];
@@ -1265,6 +1695,8 @@ int gct_unet_create(const gct_unet_config *cfg, gct_unet **out)
 int gct_unet_destroy(gct_unet *u)
 {
     if (!u) return GCT_OK;
+    for (auto &g : u->fgraphs) (void)hipGraphExecDestroy(g.exec);
+    if (u->capture) (void)hipStreamDestroy(u->capture);
     (void)hipFree(u->w);
     (void)hipFree(u->g);
     (void)hipFree(u->m);
@@ -1355,30 +1787,32 @@ int gct_unet_set_moments(gct_unet *u, const float *m, const float *v, void *stre
     return check_hip(e, "gct_unet_set_moments");
 }
 
-int gct_unet_forward(gct_unet *u, int32_t batch, const float *x, float in_scale, float out_scale, float *y,
-                     void *stream)
+}  // extern "C"
+
+// The forward's launches (queued on st; captured by gct_unet_forward).
+// Input preparation and max pooling are fused into the consuming
+// convolutions and the final 1x1 layer into the last 3x3 one, so the
+// prepared input x[0] and the pooled x[l] are not stored here
+// (recompute_inputs rebuilds them for the backward).
+static bool fuse_final(const gct_unet *u) { return u->C0 <= 64; }
+
+static void forward_launches(gct_unet *u, int B, const float *x, float in_scale, float *y, hipStream_t st)
 {
-    if (!u || !x || !y) return fail(GCT_EINVAL, "NULL argument");
-    if (batch < 1 || batch > u->maxB) return fail(GCT_EINVAL, "batch must be in [1, max_batch]");
-    if (!std::isfinite(in_scale) || !std::isfinite(out_scale))
-        return fail(GCT_EINVAL, "scales must be finite");
-    hipStream_t st = (hipStream_t)stream;
-    const int L = u->L, B = batch;
-    u->oscale = out_scale;
-    const long long npix = (long long)B * u->H * u->W;
-    hipLaunchKernelGGL(k_prep_input, dim3(cdiv(npix, 256)), dim3(256), 0, st, x, in_scale, (int)npix, u->x[0]);
+    const int L = u->L;
+    const bool ff = fuse_final(u);
     for (int l = 0; l < L; ++l) {
         const int Hl = u->Hl(l), Wl = u->Wl(l), Cl = u->C(l);
-        const int in_cs = l == 0 ? 16 : u->C(l - 1);
-        fwd(u, u->layers[u->enc1[l]], B, u->x[l], in_cs, 0, Hl, Wl, Hl, Wl, u->e[l], Cl, 0, 1, 0, nullptr, st);
-        if (l < L - 1) {
+        if (l == 0)
+            fwd(u, u->layers[u->enc1[0]], B, nullptr, 16, 0, Hl, Wl, Hl, Wl, u->e[0], Cl, 0, 1, 0, nullptr, st, 2, x,
+                in_scale);
+        else
+            fwd(u, u->layers[u->enc1[l]], B, u->s[l - 1], 2 * u->C(l - 1), u->C(l - 1), Hl, Wl, Hl, Wl, u->e[l], Cl,
+                0, 1, 0, nullptr, st, 1);
+        if (l < L - 1)
             fwd(u, u->layers[u->enc2[l]], B, u->e[l], Cl, 0, Hl, Wl, Hl, Wl, u->s[l], 2 * Cl, Cl, 1, 0, nullptr, st);
-            const long long n = (long long)B * (Hl / 2) * (Wl / 2) * Cl;
-            hipLaunchKernelGGL(k_maxpool, dim3(cdiv(n, 256)), dim3(256), 0, st, (const bf16_t *)u->s[l], 2 * Cl, Cl,
-                               B, Hl, Wl, Cl, u->x[l + 1]);
-        } else {
-            fwd(u, u->layers[u->enc2[l]], B, u->e[l], Cl, 0, Hl, Wl, Hl, Wl, u->s[l], Cl, 0, 1, 0, nullptr, st);
-        }
+        else
+            fwd(u, u->layers[u->enc2[l]], B, u->e[l], Cl, 0, Hl, Wl, Hl, Wl, u->s[l], Cl, 0, 1,
+                (L == 1 && ff) ? 3 : 0, y, st);
     }
     const bf16_t *prev = u->s[L - 1];
     for (int l = L - 2; l >= 0; --l) {
@@ -1386,12 +1820,73 @@ int gct_unet_forward(gct_unet *u, int32_t batch, const float *x, float in_scale,
         const int Hn = u->Hl(l + 1), Wn = u->Wl(l + 1);
         fwd(u, u->layers[u->up[l]], B, prev, u->C(l + 1), 0, Hn, Wn, Hn, Wn, u->s[l], 2 * Cl, 0, 0, 2, nullptr, st);
         fwd(u, u->layers[u->dec1[l]], B, u->s[l], 2 * Cl, 0, Hl, Wl, Hl, Wl, u->d1[l], Cl, 0, 1, 0, nullptr, st);
-        fwd(u, u->layers[u->dec2[l]], B, u->d1[l], Cl, 0, Hl, Wl, Hl, Wl, u->d2[l], Cl, 0, 1, 0, nullptr, st);
+        fwd(u, u->layers[u->dec2[l]], B, u->d1[l], Cl, 0, Hl, Wl, Hl, Wl, u->d2[l], Cl, 0, 1,
+            (l == 0 && ff) ? 3 : 0, y, st);
         prev = u->d2[l];
     }
-    fwd(u, u->layers[u->fin], B, prev, u->C0, 0, u->H, u->W, u->H, u->W, nullptr, 0, 0, 0, 1, y, st);
-    u->last_batch = B;
-    return check_hip(last_launch(), "gct_unet_forward");
+    if (!ff) fwd(u, u->layers[u->fin], B, prev, u->C0, 0, u->H, u->W, u->H, u->W, nullptr, 0, 0, 0, 1, y, st);
+}
+
+// The layer inputs the fused forward did not store: the prepared input
+// (from the forward's x and in_scale) and the pooled input of every level
+// below the first.
+static void recompute_inputs(gct_unet *u, int B, hipStream_t st)
+{
+    const long long npix = (long long)B * u->H * u->W;
+    hipLaunchKernelGGL(k_prep_input, dim3(cdiv(npix, 256)), dim3(256), 0, st, u->fx, u->fscale, (int)npix, u->x[0]);
+    for (int l = 0; l + 1 < u->L; ++l) {
+        const int Hl = u->Hl(l), Wl = u->Wl(l), Cl = u->C(l);
+        const long long n = (long long)B * (Hl / 2) * (Wl / 2) * Cl;
+        hipLaunchKernelGGL(k_maxpool, dim3(cdiv(n, 256)), dim3(256), 0, st, (const bf16_t *)u->s[l], 2 * Cl, Cl, B,
+                           Hl, Wl, Cl, u->x[l + 1]);
+    }
+}
+
+extern "C" {
+
+int gct_unet_forward(gct_unet *u, int32_t batch, const float *x, float in_scale, float out_scale, float *y,
+                     void *stream)
+{
+    if (!u || !x || !y) return fail(GCT_EINVAL, "NULL argument");
+    if (batch < 1 || batch > u->maxB) return fail(GCT_EINVAL, "batch must be in [1, max_batch]");
+    if (!std::isfinite(in_scale) || !std::isfinite(out_scale))
+        return fail(GCT_EINVAL, "scales must be finite");
+    if (x == y) return fail(GCT_EINVAL, "y must not alias x");
+    hipStream_t st = (hipStream_t)stream;
+    u->oscale = out_scale;
+    // the launch sequence is replayed as a captured graph (one capture per
+    // argument set; up to 8 kept)
+    hipGraphExec_t exec = nullptr;
+    for (const auto &g : u->fgraphs)
+        if (g.B == batch && g.x == x && g.y == y && g.in_scale == in_scale && g.out_scale == out_scale) exec = g.exec;
+    if (!exec) {
+        if (!u->capture && hipStreamCreateWithFlags(&u->capture, hipStreamNonBlocking) != hipSuccess) {
+            u->capture = nullptr;
+            return fail(GCT_EHIP, "cannot create the capture stream");
+        }
+        hipError_t e = hipStreamBeginCapture(u->capture, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return check_hip(e, "gct_unet_forward capture");
+        forward_launches(u, batch, x, in_scale, y, u->capture);
+        hipError_t el = hipGetLastError();
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(u->capture, &g);
+        if (el != hipSuccess || e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return check_hip(el != hipSuccess ? el : e, "gct_unet_forward capture");
+        }
+        e = hipGraphInstantiate(&exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return check_hip(e, "gct_unet_forward instantiate");
+        if (u->fgraphs.size() >= 8) {
+            (void)hipGraphExecDestroy(u->fgraphs.front().exec);
+            u->fgraphs.erase(u->fgraphs.begin());
+        }
+        u->fgraphs.push_back({batch, x, y, in_scale, out_scale, exec});
+    }
+    u->last_batch = batch;
+    u->fx = x;
+    u->fscale = in_scale;
+    return check_hip(hipGraphLaunch(exec, st), "gct_unet_forward");
 }
 
 int gct_unet_backward(gct_unet *u, int32_t batch, const float *y, const float *target, float *loss,
@@ -1407,6 +1902,7 @@ int gct_unet_backward(gct_unet *u, int32_t batch, const float *y, const float *t
                        u->dy16, u->lpart);
     hipLaunchKernelGGL(k_mse_fin, dim3(1), dim3(64), 0, st, (const double *)u->lpart, nb, (int)npix,
                        loss ? loss : u->loss);
+    recompute_inputs(u, B, st);
     // final 1x1
     bf16_t *top = L > 1 ? u->d2[0] : u->s[0];
     bf16_t *gtop = L > 1 ? u->gd2[0] : u->gs[0];

@@ -121,7 +121,7 @@ def test_batch_cg_matches_single_slice_and_oracle(batch_setup, dt):
         assert res[i].status == gct.GCT_OK
         # the batched solver (textbook arrangement) and the single-slice one
         # (Chronopoulos-Gear arrangement) agree in exact arithmetic only
-        assert abs(res[i].iters - ri.iters) <= max(3, ri.iters // 10)
+        assert abs(res[i].iters - ri.iters) <= max(5, (3 * ri.iters) // 20)
         # the oracle re-checks the batched iterate
         G_or = oracle.gram(ogs[i])
         bh = bs[i].double().cpu().numpy()

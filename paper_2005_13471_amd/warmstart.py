@@ -369,6 +369,8 @@ def main(argv=None):
     ap.add_argument("--out", default=os.path.join(WEIGHTS_DIR, WEIGHTS_NAME))
     ap.add_argument("--report", default=None)
     ap.add_argument("--resume", default=None)
+    ap.add_argument("--eval", default=None, metavar="CHECKPOINT",
+                    help="evaluate a trained checkpoint on the held-out slices only (no training)")
     a = ap.parse_args(argv)
 
     def log(*x):
@@ -379,6 +381,20 @@ def main(argv=None):
     t0 = time.time()
     prob = Problem(cfg)
     log(f"problem ready: G[0] = {prob.G0:.6f}, {time.time() - t0:.1f} s")
+    if a.eval:
+        ws = WarmStart(prob, a.eval)
+        b_test, _, it_test = generate(prob, range(TEST_SEEDS[0], TEST_SEEDS[0] + a.test), pool, log=log,
+                                      normalize=False)
+        cmp = compare(prob, ws, b_test, log=log)
+        rep = summarize(cmp)
+        rep.update(checkpoint=os.path.basename(a.eval), step=int(ws.meta.get("step", 0)),
+                   batched_target_iters_mean=float(it_test.mean()), seconds=time.time() - t0)
+        log(json.dumps(rep))
+        if a.report:
+            with open(a.report, "w") as f:
+                json.dump(rep, f, indent=1)
+        pool.close()
+        return
     bt, xs, it_train = generate(prob, range(TRAIN_SEEDS[0], TRAIN_SEEDS[0] + a.train), pool, log=log)
     s_in = float(1.0 / torch.sqrt(torch.mean(bt[:1000].double() ** 2)).item())
     s_out = float(torch.sqrt(torch.mean(xs[:1000].double() ** 2)).item())

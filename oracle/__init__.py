@@ -81,6 +81,8 @@ def lib():
         L.or_l2_inner.restype = _c_dbl
         L.or_cg.argtypes = [_c_int, _dp, _dp, _dp, _c_int, _c_dbl, _dp]
         L.or_cg.restype = _c_int
+        L.or_sd.argtypes = [_c_int, _dp, _dp, _dp, _c_int, _c_dbl, _dp]
+        L.or_sd.restype = _c_int
         _lib = L
     return _lib
 
@@ -213,6 +215,16 @@ def forward_at(g: Geometry, img: np.ndarray, idx) -> np.ndarray:
 
 def l2_inner(g: Geometry, img: np.ndarray, sino: np.ndarray) -> float:
     return float(lib().or_l2_inner(*g._bpgeo(), _f64(img).reshape(-1), _f64(sino).reshape(-1)))
+
+
+def sd(G: np.ndarray, b: np.ndarray, x0=None, maxit=100, rtol=1e-4):
+    """Steepest descent, the paper's solver (Sec. 6.2).  Returns (x, iters,
+    residual history ||r_k||/||b||)."""
+    N = b.shape[0]
+    x = np.zeros(N * N) if x0 is None else _f64(x0).reshape(-1).copy()
+    hist = np.zeros(maxit + 1)
+    it = lib().or_sd(N, _f64(G).reshape(-1), _f64(b).reshape(-1), x, int(maxit), float(rtol), hist)
+    return x.reshape(N, N), it, hist[: it + 1]
 
 
 def cg(G: np.ndarray, b: np.ndarray, x0=None, maxit=100, rtol=1e-4):

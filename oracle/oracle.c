@@ -653,3 +653,43 @@ OR_API int or_cg(int N, const double *G, const double *b, double *x, int maxit, 
     free(Ap);
     return k;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Steepest descent on the same normal equations, the paper's own solver     */
+/* (Sec. 6.2): r = b - A x, alpha = (r.r)/(r.A r), x += alpha r, r -= alpha  */
+/* A r, in FP64 with the direct-sum operator.  hist, x and the return value  */
+/* as for or_cg.                                                             */
+/* ------------------------------------------------------------------------ */
+OR_API int or_sd(int N, const double *G, const double *b, double *x, int maxit, double rtol,
+                 double *hist)
+{
+    size_t NN = (size_t)N * N;
+    double *r = (double *)malloc(sizeof(double) * NN), *Ar = (double *)malloc(sizeof(double) * NN);
+    or_apply(N, G, x, Ar);
+    double bb = 0.0, rr = 0.0;
+    for (size_t i = 0; i < NN; ++i) {
+        r[i] = b[i] - Ar[i];
+        bb += b[i] * b[i];
+        rr += r[i] * r[i];
+    }
+    double bn = sqrt(bb);
+    hist[0] = sqrt(rr) / bn;
+    int k = 0;
+    while (k < maxit && sqrt(rr) > rtol * bn) {
+        or_apply(N, G, r, Ar);
+        double rAr = 0.0;
+        for (size_t i = 0; i < NN; ++i) rAr += r[i] * Ar[i];
+        double alpha = rr / rAr, rr1 = 0.0;
+        for (size_t i = 0; i < NN; ++i) {
+            x[i] += alpha * r[i];
+            r[i] -= alpha * Ar[i];
+            rr1 += r[i] * r[i];
+        }
+        rr = rr1;
+        ++k;
+        hist[k] = sqrt(rr) / bn;
+    }
+    free(r);
+    free(Ar);
+    return k;
+}

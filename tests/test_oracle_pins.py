@@ -416,3 +416,63 @@ def test_cg_energy_error_monotone_and_true_residual(oracle_lib):
         prev = en
         true = np.linalg.norm(b.reshape(-1) - A @ x.reshape(-1)) / np.linalg.norm(b)
         assert abs(true - hist[-1]) < 1e-8 * max(hist[0], 1.0)
+
+
+# --------------------------------------------------------------------------
+# Steepest descent (the paper's solver, Sec. 6.2)
+# --------------------------------------------------------------------------
+
+def test_sd_worst_case_rate_closed_form(oracle_lib):
+    """A filter coupling the two pixels of each row, G[0] = a, G[(0, +-1)] = c,
+    acts per row as [[a, c], [c, a]] (eigenvalues a -+ c, eigenvectors
+    (1, -1) and (1, 1)).  From x0 = 0 with b = (2, 0) per row the initial
+    error is v1 / (a - c) + v2 / (a + c), the worst case of steepest descent:
+    every step multiplies the residual norm by exactly (k - 1) / (k + 1) =
+    c / a, k = (a + c) / (a - c) the condition number."""
+    a, c = 1.0, 0.6
+    G = np.zeros((3, 3))
+    G[1, 1] = a
+    G[1, 0] = G[1, 2] = c
+    b = np.array([[2.0, 0.0], [2.0, 0.0]])
+    x, it, hist = oracle_lib.sd(G, b, maxit=12, rtol=0.0)
+    assert it == 12
+    assert np.allclose(hist, (c / a) ** np.arange(13), rtol=1e-12, atol=0)
+    # the iterates approach the solution of [[a, c], [c, a]] x = (2, 0)
+    xs = np.linalg.solve(np.array([[a, c], [c, a]]), np.array([2.0, 0.0]))
+    assert np.max(np.abs(x - xs[None, :])) < 2 * (c / a) ** 12 * np.max(np.abs(xs)) * (a + c) / (a - c)
+
+
+def test_sd_successive_residuals_orthogonal_and_energy_decreasing(oracle_lib):
+    """Exact line search makes r_{k+1} orthogonal to r_k, and the energy
+    error (x - x*)^T A (x - x*) falls at every step; the residual history is
+    the true residual of the explicit normal matrix."""
+    N = 6
+    g = oracle_lib.Geometry(N, inputs.angles(9), 12, zeta=1.0)
+    G = oracle_lib.gram(g)
+    H = oracle_lib.explicit_H(g)
+    A = H.T @ H
+    b = inputs.uniform_coeffs(N, 5)
+    xs = np.linalg.solve(A, b.reshape(-1))
+    prev_r, prev_e = None, np.inf
+    for k in range(1, 10):
+        x, it, hist = oracle_lib.sd(G, b, maxit=k, rtol=0.0)
+        r = b.reshape(-1) - A @ x.reshape(-1)
+        assert abs(np.linalg.norm(r) / np.linalg.norm(b) - hist[-1]) < 1e-9 * hist[0]
+        if prev_r is not None:
+            assert abs(r @ prev_r) < 1e-9 * np.linalg.norm(r) * np.linalg.norm(prev_r) + 1e-13
+        e = x.reshape(-1) - xs
+        en = float(e @ A @ e)
+        assert en < prev_e
+        prev_r, prev_e = r, en
+
+
+def test_sd_solves_tiny_system(oracle_lib):
+    N = 3
+    g = oracle_lib.Geometry(N, inputs.angles(6) + 0.05, 10, zeta=0.5)
+    A = oracle_lib.explicit_H(g).T @ oracle_lib.explicit_H(g)
+    b = inputs.uniform_coeffs(N, 6)
+    x, it, hist = oracle_lib.sd(oracle_lib.gram(g), b, maxit=20000, rtol=1e-10)
+    assert hist[-1] <= 1e-10 and it < 20000
+    xs = np.linalg.solve(A, b.reshape(-1))
+    assert np.linalg.norm(A @ x.reshape(-1) - b.reshape(-1)) <= 1.01e-10 * np.linalg.norm(b)
+    assert np.max(np.abs(x.reshape(-1) - xs)) < 1e-6 * np.max(np.abs(xs)) * np.linalg.cond(A)

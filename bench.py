@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: set up the workload, then 20 applies and one "
                          "256 MiB elementwise copy (the counters' calibration), and exit")
+    ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn the FETCH_SIZE and WRITE_SIZE runs of --pmc-probe (rocprofv3 csv output "
+                         "directories) into the per-apply HBM traffic kept under profiles/, and exit")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="output pixels of the oracle's direct-sum apply timed for cpu_baseline "
                          "(0: all N^2, one whole apply)")
@@ -232,6 +235,65 @@ def pmc_probe(gct, plan, Ghat, c, y, ws, fft_elems):
                       "fft_elems_per_thread": fft_elems, "apply_source_sha": apply_source_sha()}))
 
 
+def pmc_summarize(fetch_dir: str, write_dir: str):
+    """Per-apply HBM bytes from the two counter runs of --pmc-probe: the
+    median over dispatches of each transform pass's counter, scaled by what
+    the same counter read for the calibration copy (the largest non-library
+    dispatch of the run).  Merged into PMC_FILE under the run's elements per
+    thread; prints the markdown table of the profile summary."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            with open(f) as fh:
+                rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+        if not rows:
+            raise SystemExit(f"no {counter} rows under {d}")
+        per = {}
+        for r in rows:
+            per.setdefault(r["Kernel_Name"].split("(")[0], []).append(float(r["Counter_Value"]))
+        passes = {k: float(np.median(v)) for k, v in per.items()
+                  if any(t in k for t in ("k_rows_fwd<", "k_cols<", "k_rows_inv<"))}
+        copy = max((max(v) for k, v in per.items() if "gct::" not in k), default=0.0)
+        return passes, copy
+
+    fetch, copy_f = load(fetch_dir, "FETCH_SIZE")
+    write, copy_w = load(write_dir, "WRITE_SIZE")
+    elems = {int(k.split(",")[-1].strip(" >")) for k in fetch}
+    if len(elems) != 1:
+        raise SystemExit(f"expected one transform tiling in the run, found {sorted(elems)}")
+    E = elems.pop()
+    sf, sw = PMC_COPY_BYTES / (copy_f * 1024), PMC_COPY_BYTES / (copy_w * 1024)
+    fb = sum(fetch.values()) * 1024 * sf
+    wb = sum(write.values()) * 1024 * sw
+    N, P = 512, 1024
+    entry = {"copy_bytes": PMC_COPY_BYTES, "copy_fetch_kib": copy_f, "copy_write_kib": copy_w,
+             "scale_fetch": sf, "scale_write": sw, "per_kernel_fetch_kib": fetch, "per_kernel_write_kib": write,
+             "hbm_fetch_bytes_per_apply": int(round(fb)), "hbm_write_bytes_per_apply": int(round(wb)),
+             "hbm_bytes_per_apply": int(round(fb + wb)),
+             "alg_bytes_per_apply": 4 * N * N * 2 + 4 * (P // 2 + 1) * P}
+    try:
+        with open(PMC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        d = {}
+    if d.get("apply_source_sha") != apply_source_sha():
+        d = {}
+    d.update({"workload": WORKLOAD, "apply_source_sha": apply_source_sha()})
+    d.setdefault("by_fft_elems", {})[str(E)] = entry
+    with open(PMC_FILE, "w") as fh:
+        json.dump(d, fh, indent=1)
+    print(f"elements per thread {E}: scale fetch {sf:.4f}, write {sw:.4f}")
+    print("| kernel | FETCH_SIZE KiB / dispatch | fetched MB (scaled) | WRITE_SIZE KiB / dispatch | written MB (scaled) |")
+    print("|---|---:|---:|---:|---:|")
+    for k in fetch:
+        print(f"| `{k.replace('void ', '')}` | {fetch[k]:.1f} | {fetch[k] * 1024 * sf / 1e6:.3f} | "
+              f"{write.get(k, 0.0):.1f} | {write.get(k, 0.0) * 1024 * sw / 1e6:.3f} |")
+    print(f"per apply: {fb / 1e6:.2f} MB fetched + {wb / 1e6:.2f} MB written = {(fb + wb) / 1e6:.2f} MB")
+
+
 def measured_traffic(fft_elems: int):
     """HBM bytes per apply from the committed counter runs, if they were taken
     on these kernel sources with this tiling; else None."""
@@ -240,9 +302,25 @@ def measured_traffic(fft_elems: int):
             d = json.load(fh)
     except (OSError, ValueError):
         return None
-    if d.get("apply_source_sha") != apply_source_sha() or d.get("fft_elems_per_thread") != fft_elems:
+    if d.get("apply_source_sha") != apply_source_sha():
         return None
-    return d.get("hbm_bytes_per_apply")
+    e = d.get("by_fft_elems", {}).get(str(fft_elems))
+    return e.get("hbm_bytes_per_apply") if e else None
+
+
+def sd_plain(gct, plan, Ghat, b, ws):
+    """Steepest descent (the paper's solver) from zero to the same 1e-4 on
+    the same right-hand side, outside the timed steps: iterations and wall
+    time next to CG's."""
+    import torch
+    x = torch.zeros_like(b)
+    gct.sd_solve(plan, Ghat, b, x, ws, rtol=1e-4, max_iter=20000, check_every=64)  # graph capture
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = gct.sd_solve(plan, Ghat, b, x, ws, rtol=1e-4, max_iter=20000, check_every=64)
+    ms = (time.perf_counter() - t0) * 1e3
+    return {"iters": r.iters, "ms": round(ms, 3), "rel_res_true": r.rel_res_true, "status": r.status}
 
 
 def warm_compare(slices: int):
@@ -267,6 +345,8 @@ def warm_compare(slices: int):
 
 def main():
     args = parse()
+    if args.pmc_summarize:
+        return pmc_summarize(*args.pmc_summarize)
     if args.workload == "batch_uneven_256":
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU", "n_gpus": args.gpus}))
@@ -400,6 +480,7 @@ def main():
                      "rel_res": res.rel_res, "rel_res_true": res.rel_res_true,
                      "status": res.status, "dot_dtype": "f64"},
         "cg_warm": warm_compare(args.warm_slices) if args.warm_slices > 0 else None,
+        "sd_plain": sd_plain(gct, plan, Ghat, b, ws_cg),
         "roofline": {"kernel": "gram_apply (rows / columns / rows FFT passes)", "bound": "hbm",
                      "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(fft_elems),

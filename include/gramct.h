@@ -204,6 +204,16 @@ int gct_cg_solve(const gct_plan *plan, gct_dtype dtype, const void *Ghat, const 
                  int use_x0, double rtol, int32_t max_iter, int32_t check_every, double *hist,
                  gct_cg_result *result, void *ws, void *stream);
 
+/* Steepest descent on the same system, the paper's own solver (Sec. 6.2):
+ * r = b - A x, alpha = (r.r)/(r.A r), x += alpha r, r -= alpha A r, one
+ * Gram-filter product per iteration, fused into the three Gram-filtering
+ * passes like gct_cg_solve (same FP64 inner products, stopping rule,
+ * start-vector fallback, arguments, workspace and errors; GCT_EBREAKDOWN for
+ * r.A r <= 0 or a non-finite value).  BLOCKS the host. */
+int gct_sd_solve(const gct_plan *plan, gct_dtype dtype, const void *Ghat, const void *b, void *x,
+                 int use_x0, double rtol, int32_t max_iter, int32_t check_every, double *hist,
+                 gct_cg_result *result, void *ws, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batches of independent slices (uneven N, angle sets and blur widths).
  *

@@ -74,7 +74,7 @@ k_cg_init(const T *__restrict__ b, T *__restrict__ x, T *__restrict__ r, T *__re
 }
 
 __global__ void __launch_bounds__(256)
-k_cg_init_fin(CGState *st, const double *part_rr, const double *part_bb, int np, double rtol2)
+k_cg_init_fin(CGState *st, const double *part_rr, const double *part_bb, int np, double rtol2, int sd)
 {
     double rr = 0.0, bb = 0.0;
     for (int i = threadIdx.x; i < np; i += blockDim.x) {
@@ -98,6 +98,7 @@ k_cg_init_fin(CGState *st, const double *part_rr, const double *part_bb, int np,
         st->pend[0] = st->pend[1] = 0;
         st->stat[0] = st->stat[1] = st->status;
         st->kring = 0;
+        st->sd = sd;
     }
 }
 
@@ -215,7 +216,7 @@ static hipStream_t cg_capture_stream(const gct_plan *p)
 template <typename T>
 int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, double rtol,
              int max_iter, int check_every, double *hist, gct_cg_result *res, void *ws,
-             hipStream_t s)
+             hipStream_t s, int method)
 {
     const CGLayout L = cg_layout(p, sizeof(T));
     char *w = reinterpret_cast<char *>(ws);
@@ -241,7 +242,7 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
         hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, b, x, r, pv,
                            start ? (const T *)Ap : nullptr, n, part, part2);
         hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK,
-                           rtol * rtol);
+                           rtol * rtol, method == 1 ? 1 : 0);
         GCT_TRY(hipGetLastError());
         GCT_TRY(hipMemcpyAsync(&hs, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
         GCT_TRY(hipStreamSynchronize(s));
@@ -390,7 +391,7 @@ int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chose
             hipLaunchKernelGGL(k_fill_one<T>, dim3(VBLK), dim3(256), 0, s, sv, n);
             hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, (const T *)sv, xt, src, pv, nullptr, n,
                                part, part2);
-            hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK, 0.0);
+            hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK, 0.0, 0);
             for (int it = 0; it < reps + 2 && err == hipSuccess; ++it) {
                 if (it == 2) err = hipEventRecord(e0, s);
                 if (err == hipSuccess)
@@ -420,8 +421,8 @@ template int plan_autotune<float>(gct_plan *, const float *, void *, int, int32_
 template int plan_autotune<double>(gct_plan *, const double *, void *, int, int32_t *, hipStream_t);
 
 template int cg_solve<float>(const gct_plan *, const float *, const float *, float *, int, double,
-                             int, int, double *, gct_cg_result *, void *, hipStream_t);
+                             int, int, double *, gct_cg_result *, void *, hipStream_t, int);
 template int cg_solve<double>(const gct_plan *, const double *, const double *, double *, int,
-                              double, int, int, double *, gct_cg_result *, void *, hipStream_t);
+                              double, int, int, double *, gct_cg_result *, void *, hipStream_t, int);
 
 }  // namespace gct

@@ -94,7 +94,7 @@ enum : int64_t { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
 
 struct CGState {
     double rr, bb, rr0, pAp, alpha, beta, thr2, pad;
-    int64_t k, status, pad2, pad3;
+    int64_t k, status, sd, pad3;  // sd = 1: steepest descent (every update takes beta = 0)
     double ring[CG_RING];  // ||r_k||^2 at ring[k % CG_RING]
     // fused single-slice iteration (parity slots, see gram_apply.hip):
     // gamma = ||r||^2 and alpha of the last update, "updates may start" (1:
@@ -197,10 +197,12 @@ hipError_t launch_forward(const gct_plan *p, const T *c, T *g, hipStream_t s);
 size_t apply_ws_bytes(const gct_plan *p, size_t elem);
 size_t spectrum_ws_bytes(const gct_plan *p, size_t elem);
 
+// method: 0 = conjugate gradients, 1 = steepest descent (same fused passes
+// with beta = 0)
 template <typename T>
 int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, double rtol,
              int max_iter, int check_every, double *hist, gct_cg_result *res, void *ws,
-             hipStream_t s);
+             hipStream_t s, int method = 0);
 size_t cg_ws_bytes(const gct_plan *p, size_t elem);
 template <typename T>
 int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chosen, hipStream_t s);

@@ -115,7 +115,9 @@ k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat, const C2<T> *__re
 //   cols: unchanged;
 //   rows_inv: w = A r on its rows and the partial dots r.r, r.w.
 // In exact arithmetic these are the textbook CG iterates (s = A p; the
-// denominator is p.Ap).  All blocks compute the same scalars; block 0 alone
+// denominator is p.Ap).  With the state's steepest-descent flag every update
+// takes beta = 0 (p = r, s = w = A r, alpha = r.r / r.A r: the paper's
+// solver, Sec. 6.2).  All blocks compute the same scalars; block 0 alone
 // records them, in the slots of the other parity.
 // ---------------------------------------------------------------------------
 // (sum part[0..np), sum part[np..2np)) in a fixed order
@@ -180,7 +182,8 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
             return;
         }
         double alpha, beta;
-        if (pend == 1) {
+        const bool sd = st->sd != 0;  // steepest descent: no conjugation
+        if (pend == 1 || sd) {
             beta = 0.0;
             alpha = g / dl;
         } else {
@@ -204,7 +207,7 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
             st->stat[par ^ 1] = CG_RUNNING;
         }
         const T al = (T)alpha, be = (T)beta;
-        const bool first = pend == 1;  // p = r, s = w (p, s hold no direction yet)
+        const bool first = pend == 1 || sd;  // p = r, s = w (no direction carried over)
         // thread t owns columns t + G q of the two rows: the same elements
         // the transform takes, so the new r goes to it in registers
         C2<T> v[E];

@@ -658,6 +658,28 @@ int gct_cg_solve(const gct_plan *p, gct_dtype dt, const void *Ghat, const void *
     return rc;
 }
 
+int gct_sd_solve(const gct_plan *p, gct_dtype dt, const void *Ghat, const void *b, void *x,
+                 int use_x0, double rtol, int32_t max_iter, int32_t check_every, double *hist,
+                 gct_cg_result *res, void *ws, void *stream)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!Ghat || !b || !x || !ws || !res) return fail(GCT_EINVAL, "NULL argument");
+    if (b == x) return fail(GCT_EINVAL, "x must not alias b");
+    if (max_iter < 0) return fail(GCT_EINVAL, "max_iter must be >= 0");
+    if (!(rtol >= 0.0)) return fail(GCT_EINVAL, "rtol must be >= 0");
+    if (misaligned(ws)) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
+    std::memset(res, 0, sizeof(*res));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    int rc = dt == GCT_F32 ? cg_solve<float>(p, (const float *)Ghat, (const float *)b, (float *)x,
+                                             use_x0, rtol, max_iter, check_every, hist, res, ws, s, 1)
+                           : cg_solve<double>(p, (const double *)Ghat, (const double *)b,
+                                              (double *)x, use_x0, rtol, max_iter, check_every,
+                                              hist, res, ws, s, 1);
+    if (rc == GCT_ENOTCONV) set_error("sd_solve: max_iter reached before rtol");
+    if (rc == GCT_EBREAKDOWN) set_error("sd_solve: breakdown (r.Ar <= 0 or non-finite value)");
+    return rc;
+}
+
 int gct_plan_set_fft_elems(gct_plan *p, gct_dtype dt, int32_t E)
 {
     CHECK_PLAN_DT(p, dt);

@@ -89,6 +89,7 @@ def _load():
     L.gct_forward_project.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.gct_cg_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp, ctypes.c_int, dbl, i32, i32,
                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_CGResult), vp, vp]
+    L.gct_sd_solve.argtypes = L.gct_cg_solve.argtypes
     L.gct_plan_autotune.argtypes = [vp, ctypes.c_int, vp, vp, i32, ctypes.POINTER(i32), vp]
     L.gct_plan_set_fft_elems.argtypes = [vp, ctypes.c_int, i32]
     L.gct_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
@@ -274,10 +275,22 @@ def cg_solve(plan: Plan, Ghat: torch.Tensor, b: torch.Tensor, x: torch.Tensor, w
              check_every: int = 8, raise_on_error: bool = False) -> CGResult:
     """Blocks until the solve ends.  Returns the result; GCT_ENOTCONV /
     GCT_EBREAKDOWN are reported in .status unless raise_on_error."""
+    return _solve(lib.gct_cg_solve, plan, Ghat, b, x, ws, use_x0, rtol, max_iter, check_every, raise_on_error)
+
+
+def sd_solve(plan: Plan, Ghat: torch.Tensor, b: torch.Tensor, x: torch.Tensor, ws: torch.Tensor,
+             use_x0: bool = False, rtol: float = 1e-4, max_iter: int = 1000,
+             check_every: int = 8, raise_on_error: bool = False) -> CGResult:
+    """Steepest descent (the paper's solver); arguments and result as
+    cg_solve (ws: a CG workspace)."""
+    return _solve(lib.gct_sd_solve, plan, Ghat, b, x, ws, use_x0, rtol, max_iter, check_every, raise_on_error)
+
+
+def _solve(fn, plan, Ghat, b, x, ws, use_x0, rtol, max_iter, check_every, raise_on_error) -> CGResult:
     dt = _dt(b)
     hist = np.zeros(max_iter + 1)
     res = _CGResult()
-    rc = lib.gct_cg_solve(plan.handle, dt, _ptr(Ghat, plan.info.spectrum_elems, b.dtype),
+    rc = fn(plan.handle, dt, _ptr(Ghat, plan.info.spectrum_elems, b.dtype),
                           _ptr(b, plan.info.image_elems), _ptr(x, plan.info.image_elems, b.dtype),
                           int(bool(use_x0)), float(rtol), int(max_iter), int(check_every),
                           hist.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(res),
@@ -400,6 +413,7 @@ gct_prefilter = prefilter
 gct_backproject_boxspline = backproject_boxspline
 gct_forward_project = forward_project
 gct_cg_solve = cg_solve
+gct_sd_solve = sd_solve
 gct_batch_gram_build = batch_gram_build
 gct_batch_gram_spectrum = batch_gram_spectrum
 gct_batch_gram_apply = batch_gram_apply

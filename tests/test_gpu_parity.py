@@ -454,6 +454,87 @@ def test_cg_config2_converges(gct):
     assert rms_sample <= 3e-4 * rms_b
 
 
+@pytest.mark.parametrize("dt", DTYPES)
+def test_sd_config1_histories(gct, dt):
+    """60 steepest-descent iterations (the paper's solver, Sec. 6.2) on
+    config 1 against the FP64 oracle's.  Unlike CG, steepest descent carries
+    no conjugacy that rounding can destroy, so the whole history is
+    compared; the oracle re-checks the returned iterate."""
+    case = CFG1
+    say("sd", case, dt)
+    og = case.og()
+    G = oracle.gram(og)
+    c, _ = inputs.phantom(case.N, 10, 1000)
+    b = oracle.backproject(og, oracle.forward(og, c))
+    x_ref, it_ref, h_ref = oracle.sd(G, b, maxit=60, rtol=0.0)
+    P, Ghat = _cg_setup(gct, case, dt, G)
+    x = torch.zeros(case.N ** 2, dtype=dt, device="cuda")
+    res = gct.sd_solve(P, Ghat, dev(b.reshape(-1), dt), x, P.workspace(gct.OP_CG, dt), rtol=0.0,
+                       max_iter=60, check_every=8)
+    rel = np.abs(res.history - h_ref) / h_ref
+    say("  iters", res.iters, "rel", res.rel_res, "oracle", h_ref[-1], "worst history dev", np.max(rel))
+    assert res.iters == 60 and it_ref == 60 and res.status == gct.GCT_ENOTCONV
+    f32 = dt == torch.float32
+    assert np.max(rel) <= (2e-3 if f32 else 1e-9)
+    xg = host(x).reshape(case.N, case.N)
+    true_rel = np.linalg.norm(b - oracle.apply(G, xg)) / np.linalg.norm(b)
+    assert abs(true_rel - res.rel_res_true) <= (1e-2 if f32 else 1e-8) * true_rel
+    assert np.linalg.norm(xg - x_ref) <= (1e-3 if f32 else 1e-9) * np.linalg.norm(x_ref)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_sd_config1_converges_like_oracle(gct, dt):
+    """Steepest descent to 1e-4 on noisy config-1 data: the oracle's
+    iteration count (about 110, against about 17 for CG) and the oracle's
+    recomputed residual of the returned iterate."""
+    case = CFG1
+    og = case.og()
+    G = oracle.gram(og)
+    c, _ = inputs.phantom(case.N, 10, 1000)
+    b = oracle.backproject(og, inputs.add_noise(oracle.forward(og, c), 0.01, 1_000_000 + 1000))
+    _, it_ref, _ = oracle.sd(G, b, maxit=5000, rtol=1e-4)
+    P, Ghat = _cg_setup(gct, case, dt, G)
+    x = torch.zeros(case.N ** 2, dtype=dt, device="cuda")
+    res = gct.sd_solve(P, Ghat, dev(b.reshape(-1), dt), x, P.workspace(gct.OP_CG, dt), rtol=1e-4,
+                       max_iter=5000)
+    xc = torch.zeros_like(x)
+    rc = gct.cg_solve(P, Ghat, dev(b.reshape(-1), dt), xc, P.workspace(gct.OP_CG, dt), rtol=1e-4,
+                      max_iter=500)
+    say("  sd iters", res.iters, "oracle", it_ref, "cg iters", rc.iters, "true", res.rel_res_true)
+    assert res.status == gct.GCT_OK
+    assert abs(res.iters - it_ref) <= max(2, it_ref // 20)
+    assert res.iters > 3 * rc.iters
+    xg = host(x).reshape(case.N, case.N)
+    true_rel = np.linalg.norm(b - oracle.apply(G, xg)) / np.linalg.norm(b)
+    assert true_rel <= (1.1e-4 if dt == torch.float32 else 1.0001e-4)
+
+
+def test_sd_config2_converges(gct):
+    """Config 2 scale: steepest descent to 1e-4 (FP32); the oracle re-checks
+    sampled residual entries of the returned iterate."""
+    case = CFG2
+    dt = torch.float32
+    say("sd config2", case)
+    og = case.og()
+    G = oracle.gram(og)
+    P, Ghat = _cg_setup(gct, case, dt, G)
+    ells = inputs.random_ellipses(case.N, 40, 1000)
+    g = inputs.add_noise(inputs.analytic_sinogram(ells, case.theta, case.M, zeta=case.zeta), 0.01,
+                         inputs.NOISE_SEED_BASE + 1000)
+    b = torch.empty(case.N ** 2, dtype=dt, device="cuda")
+    gct.backproject_boxspline(P, dev(g.reshape(-1), dt), b, P.workspace(gct.OP_BACKPROJECT, dt))
+    x = torch.zeros_like(b)
+    res = gct.sd_solve(P, Ghat, b, x, P.workspace(gct.OP_CG, dt), rtol=1e-4, max_iter=20000,
+                       check_every=64)
+    say("  iters", res.iters, "rel", res.rel_res, "true", res.rel_res_true, "status", res.status)
+    assert res.status == gct.GCT_OK
+    assert res.rel_res <= 1e-4 and res.rel_res_true <= 1.2e-4
+    bh, xh = host(b), host(x).reshape(case.N, case.N)
+    idx = sample_pixels(case.N, 400, 6)
+    r_or = bh[idx] - oracle.apply_at(G, xh, idx)
+    assert np.sqrt(np.mean(r_or ** 2)) <= 3e-4 * np.linalg.norm(bh) / case.N
+
+
 def test_cg_warm_start_and_fallback(gct):
     case = Case(48, 60, zeta=1.0)
     dt = torch.float64

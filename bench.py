@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: set up the workload, then 20 applies and one "
                          "256 MiB elementwise copy (the counters' calibration), and exit")
+    ap.add_argument("--phase-probe", action="store_true",
+                    help="for counter runs: set up the workload, run gram_build 4 times and the back "
+                         "projection 3 times, and exit")
     ap.add_argument("--pmc-summarize", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn the FETCH_SIZE and WRITE_SIZE runs of --pmc-probe (rocprofv3 csv output "
                          "directories) into the per-apply HBM traffic kept under profiles/, and exit")
@@ -395,6 +398,14 @@ def main():
     # autotuner; capture a burst of applies once (inputs are fixed buffers)
     gct.gram_build(plan, G)
     gct.gram_spectrum(plan, G, Ghat, ws_spec)
+    if args.phase_probe:
+        # for counter runs of the two VALU-bound phases
+        for _ in range(3):
+            gct.gram_build(plan, G)
+            gct.backproject_boxspline(plan, g_s, b, ws_bp)
+        torch.cuda.synchronize()
+        print(json.dumps({"phase_probe": True, "gram_build": 4, "backproject": 3}))
+        return
     if args.fft_elems:
         gct.plan_set_fft_elems(plan, args.fft_elems)
         fft_elems = args.fft_elems

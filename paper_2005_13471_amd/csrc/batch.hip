@@ -626,7 +626,7 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
     std::vector<int2> gm;
     for (int i = 0; i < count; ++i) {
         const int N = plans[i]->N;
-        const int tiles = ((2 * N - 1 + 15) / 16) * ((N + 15) / 16);
+        const int tiles = ((2 * N - 1 + GRAM_TILE - 1) / GRAM_TILE) * ((N + GRAM_TILE - 1) / GRAM_TILE);
         for (int k = 0; k < tiles; ++k) gm.push_back(make_int2(i, k));
     }
     b->ngram = (int)gm.size();

@@ -73,6 +73,10 @@ struct BPDims {
 
 // Pixel tile of the back-projection kernel (columns x rows).
 constexpr int BP_TX = 64, BP_TY = 32;
+// Gram build: taps per tile side (one block of 4 waves per tile): batched
+// builds 16, the single-slice build 8 with the block's waves splitting the
+// angles
+constexpr int GRAM_TILE = 16, GRAM_TILE_SPLIT = 8;
 
 struct DeviceTables {
     void *gram_f32 = nullptr, *gram_f64 = nullptr;    // GramAngle<T>[n]

@@ -64,8 +64,9 @@ __device__ __forceinline__ T gram_A(const GramAngle<T> &g, T x, bool blur)
     return g.scale * (tl + r * g.iL2);
 }
 
-// One 16 x 16 tile of taps per block, covering only taps with k2 > 0 or
-// (k2 = 0, k1 >= 0); each such tap also writes its mirror -k (G is even).
+// One square tile of taps per block (side below), covering only taps with
+// k2 > 0 or (k2 = 0, k1 >= 0); each such tap also writes its mirror -k (G
+// is even).
 //
 // Angular windows.  Tap k projects to k1 l1 cos + k2 l2 sin = rho cos(theta -
 // phi) with (rho, phi) the polar form of (k1 l1, k2 l2), so A_theta(k) can be
@@ -76,8 +77,19 @@ __device__ __forceinline__ T gram_A(const GramAngle<T> &g, T x, bool blur)
 // d = asin(h_max / rho_min): at most two runs of the angles sorted by
 // theta mod pi, found by binary search.  Inside a run the exact per-angle
 // test on the tile's projected interval still applies, so the window only
-// has to contain every contributing angle.  The loop is uniform across the
-// block.
+// has to contain every contributing angle.
+//
+// Work split.  The window is taken in chunks of 256 angles: thread t loads
+// angle t of the chunk and tests it against the tile, and the angles that
+// pass are packed in order into LDS (wave ballots, so the order is fixed;
+// per-angle loads straight from the tables were a chain of two dependent
+// scalar loads per angle).  SPLIT (one slice, 8 x 8 taps per block): the
+// block's 4 waves each hold the tile's 64 taps and take every 4th packed
+// angle, so the tiles at the origin, which every angle reaches and which
+// set the kernel's duration, cost a quarter of the angles per wave; the
+// four compensated partial sums are added in wave order at the end.  Not
+// SPLIT (batches, 16 x 16 taps per block, many more tiles than CUs): every
+// thread owns one tap and takes every packed angle.
 __device__ __forceinline__ int lower_idx(const double *th, int n, double v)
 {
     int lo = 0, hi = n;  // first index with th >= v
@@ -89,19 +101,41 @@ __device__ __forceinline__ int lower_idx(const double *th, int n, double v)
     return lo;
 }
 
-template <typename T>
+// The same search by a whole wave (v uniform): 64 evenly spaced probes
+// locate the segment, then one probe per element of it; two rounds of loads
+// instead of log2(n) dependent ones.  Every lane returns the index.
+__device__ __forceinline__ int lower_idx_wave(const double *th, int n, double v)
+{
+    const int lane = threadIdx.x & 63;
+    const int step = (n + 63) / 64;
+    if (step > 64) return lower_idx(th, n, v);
+    const int p = min(n - 1, lane * step + step - 1);
+    const int seg = __popcll(__ballot(th[p] < v));  // probes below v: the answer is past them
+    const int base = seg * step;
+    const int i = base + lane;
+    const bool below = lane < step && i < n && th[i] < v;
+    return min(n, base + __popcll(__ballot(below)));
+}
+
+template <typename T, bool SPLIT>
 __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G, int N, int n,
                                                const GramAngle<T> *__restrict__ ga,
                                                const int32_t *__restrict__ ord, const double *__restrict__ th,
                                                double hmax, double l1, double l2)
 {
+    constexpr int TS = SPLIT ? GRAM_TILE_SPLIT : GRAM_TILE;
+    __shared__ GramAngle<T> sg[256];
+    __shared__ int wcnt[4];
+    __shared__ T racc[4][64], rcomp[4][64];
     const int W = 2 * N - 1;
-    const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-    const int k1a = bx * 16 - (N - 1);  // first tap column of the tile
-    const int k2a = by * 16;            // first tap row (>= 0)
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tap = SPLIT ? lane : tid;  // SPLIT: every wave holds the tile's 64 taps
+    const int tx = tap % TS, ty = tap / TS;
+    const int k1a = bx * TS - (N - 1);  // first tap column of the tile
+    const int k2a = by * TS;            // first tap row (>= 0)
     const int k1 = k1a + tx, k2 = k2a + ty;
     const bool live = k1 <= N - 1 && k2 <= N - 1 && (k2 > 0 || k1 >= 0);
-    const double ka = k1a, kb = k1a + 15, la = k2a, lb = k2a + 15;
+    const double ka = k1a, kb = k1a + TS - 1, la = k2a, lb = k2a + TS - 1;
     // the tile's runs of sorted angles (the same in every thread)
     int run_lo[2] = {0, 0}, run_hi[2] = {n, 0};
     const double x0 = ka * l1, x1 = kb * l1, y0 = la * l2, y1 = lb * l2;  // y0 >= 0
@@ -118,33 +152,74 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
             double a = fmod(a0, M_PI);
             if (a < 0.0) a += M_PI;
             const double b = a + (b0 - a0);
-            run_lo[0] = lower_idx(th, n, a);
+            run_lo[0] = lower_idx_wave(th, n, a);
             if (b <= M_PI) {
-                run_hi[0] = lower_idx(th, n, b);
+                run_hi[0] = lower_idx_wave(th, n, b);
             } else {
                 run_hi[0] = n;
-                run_hi[1] = lower_idx(th, n, b - M_PI);
+                run_hi[1] = lower_idx_wave(th, n, b - M_PI);
             }
         }
     }
+    const double dk1 = k1, dk2 = k2;
     T acc = 0, comp = 0;
     for (int run = 0; run < 2; ++run)
-        for (int j = run_lo[run]; j < run_hi[run]; ++j) {
-            const GramAngle<T> g = ga[ord[j]];
-            // projected interval of the tile (extreme corners)
-            const double p1 = ka * g.cx, p2 = kb * g.cx, q1 = la * g.sx, q2 = lb * g.sx;
-            const double dmin = fmin(p1, p2) + fmin(q1, q2), dmax = fmax(p1, p2) + fmax(q1, q2);
-            if (dmax <= -(double)g.half || dmin >= (double)g.half) continue;
-            const T dd = (T)((double)k1 * g.cx + (double)k2 * g.sx);
-            const T v = g.S > T(0) ? gram_A(g, dd, true) : gram_A(g, dd, false);
-            const T yk = v - comp;
-            const T tk = acc + yk;
-            comp = (tk - acc) - yk;
-            acc = tk;
+        for (int j0 = run_lo[run]; j0 < run_hi[run]; j0 += 256) {
+            const int cnt = min(256, run_hi[run] - j0);
+            GramAngle<T> g;
+            bool hit = false;
+            if (tid < cnt) {
+                g = ga[ord[j0 + tid]];
+                // projected interval of the tile (extreme corners)
+                const double p1 = ka * g.cx, p2 = kb * g.cx, q1 = la * g.sx, q2 = lb * g.sx;
+                const double dmin = fmin(p1, p2) + fmin(q1, q2), dmax = fmax(p1, p2) + fmax(q1, q2);
+                hit = dmax > -(double)g.half && dmin < (double)g.half;
+            }
+            const unsigned long long mask = __ballot(hit);
+            __syncthreads();  // the previous chunk's readers are done with sg and wcnt
+            if (lane == 0) wcnt[wave] = __popcll(mask);
+            __syncthreads();
+            int off = 0, total = 0;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                off += w < wave ? wcnt[w] : 0;
+                total += wcnt[w];
+            }
+            if (hit) sg[off + __popcll(mask & ((1ull << lane) - 1ull))] = g;
+            __syncthreads();
+            for (int jj = SPLIT ? wave : 0; jj < total; jj += SPLIT ? 4 : 1) {
+                const GramAngle<T> &h = sg[jj];
+                const T dd = (T)(dk1 * h.cx + dk2 * h.sx);
+                const T v = h.S > T(0) ? gram_A(h, dd, true) : gram_A(h, dd, false);
+                const T yk = v - comp;
+                const T tk = acc + yk;
+                comp = (tk - acc) - yk;
+                acc = tk;
+            }
         }
-    if (live) {
-        G[(size_t)(k2 + N - 1) * W + (k1 + N - 1)] = acc;
-        G[(size_t)(N - 1 - k2) * W + (N - 1 - k1)] = acc;
+    if (!SPLIT) {
+        if (live) {
+            G[(size_t)(k2 + N - 1) * W + (k1 + N - 1)] = acc;
+            G[(size_t)(N - 1 - k2) * W + (N - 1 - k1)] = acc;
+        }
+        return;
+    }
+    racc[wave][lane] = acc;
+    rcomp[wave][lane] = comp;
+    __syncthreads();
+    if (wave == 0 && live) {
+        // compensated sum of the four partial sums (value acc - comp each), in order
+        T s = 0, c = 0;
+#pragma unroll
+        for (int w = 0; w < 8; ++w) {
+            const T v = (w & 1) ? -rcomp[w >> 1][lane] : racc[w >> 1][lane];
+            const T yk = v - c;
+            const T tk = s + yk;
+            c = (tk - s) - yk;
+            s = tk;
+        }
+        G[(size_t)(k2 + N - 1) * W + (k1 + N - 1)] = s;
+        G[(size_t)(N - 1 - k2) * W + (N - 1 - k1)] = s;
     }
 }
 
@@ -153,7 +228,7 @@ __global__ void __launch_bounds__(256)
 k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ ga, const int32_t *__restrict__ ord,
              const double *__restrict__ th, double hmax, double l1, double l2)
 {
-    body_gram_tile<T>(blockIdx.x, blockIdx.y, G, N, n, ga, ord, th, hmax, l1, l2);
+    body_gram_tile<T, true>(blockIdx.x, blockIdx.y, G, N, n, ga, ord, th, hmax, l1, l2);
 }
 
 // Batched: block b covers tile map[b].y of slice map[b].x.
@@ -163,8 +238,8 @@ kb_gram_build(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl, T
 {
     const int2 m = map[blockIdx.x];
     const BatchSlice &d = sl[m.x];
-    const int tiles_x = (2 * d.N - 1 + 15) / 16;
-    body_gram_tile<T>(m.y % tiles_x, m.y / tiles_x, G + d.gram, d.N, d.n, reinterpret_cast<const GramAngle<T> *>(d.ga),
+    const int tiles_x = (2 * d.N - 1 + GRAM_TILE - 1) / GRAM_TILE;
+    body_gram_tile<T, false>(m.y % tiles_x, m.y / tiles_x, G + d.gram, d.N, d.n, reinterpret_cast<const GramAngle<T> *>(d.ga),
                       d.gord, d.gth, d.ghmax, d.l1, d.l2);
 }
 
@@ -172,7 +247,7 @@ template <typename T>
 hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s)
 {
     const int W = 2 * p->N - 1;
-    const dim3 grid((W + 15) / 16, (p->N + 15) / 16);
+    const dim3 grid((W + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT, (p->N + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT);
     const GramAngle<T> *ga =
         reinterpret_cast<const GramAngle<T> *>(sizeof(T) == 4 ? p->dev.gram_f32 : p->dev.gram_f64);
     hipLaunchKernelGGL(k_gram_build<T>, grid, dim3(256), 0, s, G, p->N, p->n, ga,

@@ -60,8 +60,12 @@ def test_batch_gram_build_and_apply_match_oracle(batch_setup, dt):
 
 
 def test_batch_apply_bitwise_equals_single_slice(batch_setup):
-    """Same device bodies and tile shapes: the batched apply reproduces the
-    single-slice apply bit for bit (before autotuning)."""
+    """Same device bodies and tile shapes: from the same Gram filter the
+    batched spectrum and apply reproduce the single-slice ones bit for bit
+    (before autotuning).  The Gram builds themselves use different tile
+    shapes (the single-slice build splits each tile's angles over the block's
+    waves), so their sums are ordered differently and agree to FP32
+    rounding."""
     gct, B, plans, ogs = batch_setup
     dt = torch.float32
     G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
@@ -75,9 +79,10 @@ def test_batch_apply_bitwise_equals_single_slice(batch_setup):
         Gi = torch.empty(P.info.gram_elems, dtype=dt, device="cuda")
         gct.gram_build(P, Gi)
         o = int(B.gram_offsets[i])
-        assert torch.equal(Gi, G[o:o + P.info.gram_elems])
+        Gb = G[o:o + P.info.gram_elems]
+        assert normwise(Gi.double().cpu().numpy(), Gb.double().cpu().numpy()) <= 1e-6
         Gh = torch.empty(P.info.spectrum_elems, dtype=dt, device="cuda")
-        gct.gram_spectrum(P, Gi, Gh, P.workspace(gct.OP_GRAM_SPECTRUM, dt))
+        gct.gram_spectrum(P, Gb.contiguous(), Gh, P.workspace(gct.OP_GRAM_SPECTRUM, dt))
         so = int(B.spectrum_offsets[i])
         assert torch.equal(Gh, Ghat[so:so + P.info.spectrum_elems])
         yi = torch.empty(P.N * P.N, dtype=dt, device="cuda")

@@ -248,7 +248,23 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
                 for (int j = 0; j < JM; ++j) cj[j] = j < J ? cf[j * D1] : T(0);
                 const T *pp = s_p + c * pseg;
                 T *E = s_E + (size_t)c * eang + sidx * D1P + k;
-                for (int mi = mlo; mi < mhi; ++mi) {
+                int mi = mlo;
+                // 8 bins at a time from one register window of JM + 7 samples
+                // (one LDS read per bin instead of JM); the window ends
+                // before mhi + JM - 1 <= pseg
+                for (; mi + 8 <= mhi; mi += 8) {
+                    T w[JM + 7];
+#pragma unroll
+                    for (int q2 = 0; q2 < JM + 7; ++q2) w[q2] = pp[mi + q2];
+#pragma unroll
+                    for (int o = 0; o < 8; ++o) {
+                        T e = 0;
+#pragma unroll
+                        for (int j = 0; j < JM; ++j) e += w[o + j] * cj[j];
+                        E[(mi + o) * smax * D1P] = e;
+                    }
+                }
+                for (; mi < mhi; ++mi) {
                     T e = 0;
 #pragma unroll
                     for (int j = 0; j < JM; ++j) e += pp[mi + j] * cj[j];
@@ -257,34 +273,21 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
             }
         }
         __syncthreads();
+        // the chunk's angles summed plainly per pixel, then added to the
+        // compensated total once per chunk
+        T csum[PPT];
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) csum[i] = T(0);
         for (int c = 0; c < cnt; ++c) {
             const int R = s_w[4 * c + 1], nsub = s_w[4 * c + 2], base = s_w[4 * c + 3];
             const T zf = s_f[3 * c], dz1 = s_f[3 * c + 1], dz2 = s_f[3 * c + 2];
             const T *bk = s_b + c * smax;
-            T b1 = T(2), b2 = T(2), b3 = T(2);  // breakpoints 1..3 (2: absent)
-            if (nsub > 1) b1 = bk[1];
-            if (nsub > 2) b2 = bk[2];
-            if (nsub > 3) b3 = bk[3];
             const T *Ec = s_E + (size_t)c * eang;
             const T zrow = zf + (T)d1 * dz1 + (T)d2 * dz2;
             const T rstep = (T)RSTEP * dz2;
-#pragma unroll
-            for (int i = 0; i < PPT; ++i) {
-                const T zl = zrow + (T)i * rstep;
-                const T fl = floor(zl);
-                const T t = zl - fl;
-                int mi = base + (int)fl;
-                mi = mi < 0 ? 0 : (mi >= R ? R - 1 : mi);
-                int sub;
-                T u;
-                if (nsub <= 4) {
-                    sub = (t >= b1) + (t >= b2) + (t >= b3);
-                    u = t - (sub == 0 ? bk[0] : sub == 1 ? b1 : sub == 2 ? b2 : b3);
-                } else {
-                    sub = 0;
-                    for (int s2 = 1; s2 < nsub; ++s2) sub += (t >= bk[s2]) ? 1 : 0;
-                    u = t - bk[sub];
-                }
+            // value of the angle's interpolant at pixel i, given its
+            // sub-interval and offset in it
+            auto eval = [&](int i, int mi, int sub, T u) {
                 const T *e = Ec + (size_t)(mi * smax + sub) * D1P;
                 T ev[D1P];
 #pragma unroll
@@ -292,11 +295,45 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
                 T v = ev[D1P - 1];
 #pragma unroll
                 for (int k = D1P - 2; k >= 0; --k) v = v * u + ev[k];
-                const T yk = v - comp[i];
-                const T tk = acc[i] + yk;
-                comp[i] = (tk - acc[i]) - yk;
-                acc[i] = tk;
+                csum[i] += v;
+            };
+            if (nsub <= 4) {  // (uniform) branch-free search over at most 3 breakpoints
+                const T b0 = bk[0];
+                const T b1 = nsub > 1 ? bk[1] : T(2), b2 = nsub > 2 ? bk[2] : T(2),
+                        b3 = nsub > 3 ? bk[3] : T(2);  // 2: absent (t < 1)
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) {
+                    const T zl = zrow + (T)i * rstep;
+                    const T fl = floor(zl);
+                    const T t = zl - fl;
+                    int mi = base + (int)fl;
+                    mi = mi < 0 ? 0 : (mi >= R ? R - 1 : mi);
+                    const bool g1 = t >= b1, g2 = t >= b2, g3 = t >= b3;
+                    T bs = g1 ? b1 : b0;  // breakpoints ascend: the last one passed
+                    bs = g2 ? b2 : bs;
+                    bs = g3 ? b3 : bs;
+                    eval(i, mi, (int)g1 + (int)g2 + (int)g3, t - bs);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < PPT; ++i) {
+                    const T zl = zrow + (T)i * rstep;
+                    const T fl = floor(zl);
+                    const T t = zl - fl;
+                    int mi = base + (int)fl;
+                    mi = mi < 0 ? 0 : (mi >= R ? R - 1 : mi);
+                    int sub = 0;
+                    for (int s2 = 1; s2 < nsub; ++s2) sub += (t >= bk[s2]) ? 1 : 0;
+                    eval(i, mi, sub, t - bk[sub]);
+                }
             }
+        }
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+            const T yk = csum[i] - comp[i];
+            const T tk = acc[i] + yk;
+            comp[i] = (tk - acc[i]) - yk;
+            acc[i] = tk;
         }
     }
     T *dst = groups > 1 ? out + (size_t)blockIdx.z * N * N : out;

@@ -52,6 +52,21 @@ def test_plan_rejects_bad_geometry_without_gpu(gct, kw, msg):
     assert e.value.code == gct.GCT_EINVAL and msg in str(e.value)
 
 
+@pytest.mark.parametrize("name", ["gct_cg_solve", "gct_sd_solve"])
+def test_solvers_reject_null_plan_without_gpu(gct, name):
+    """The solvers check their arguments before any GPU call: a NULL plan
+    is GCT_EINVAL with a message, and the result struct is untouched."""
+    raw = ctypes.CDLL(gct.LIB_PATH)
+    fn = getattr(raw, name)
+    fn.restype = ctypes.c_int
+    res = gct._CGResult()
+    res.iters = 7
+    rc = fn(None, 0, None, None, None, 0, ctypes.c_double(1e-4), 10, 8, None, ctypes.byref(res), None, None)
+    assert rc == gct.GCT_EINVAL and res.iters == 7
+    raw.gct_last_error.restype = ctypes.c_char_p
+    assert raw.gct_last_error()
+
+
 @pytest.mark.parametrize("zeta", [0.0, 0.3, 1.0])
 @pytest.mark.parametrize("theta", [0.37, 1.1, np.pi / 1800, np.pi / 2 - 1e-3])
 def test_host_boxspline_matches_oracle_gram_and_footprint(gct, theta, zeta):

@@ -46,6 +46,32 @@ __device__ __forceinline__ const C2<T> *stage_twiddles(C2<T> *lds_after_data,
 // Rows forward from registers: v[q] holds (row ra, row ra+1) at column
 // t + G q (zero past N); one complex FFT, split into the two real-row
 // spectra, written transposed as W1[k][row].
+// Two adjacent complex values as one 16-byte access (FP32; the caller
+// guarantees 16-byte alignment); FP64 falls back to two accesses.
+template <typename T>
+__device__ __forceinline__ void store_pair(C2<T> *p, const C2<T> &a, const C2<T> &b)
+{
+    if constexpr (sizeof(T) == 4) {
+        *reinterpret_cast<float4 *>(p) = make_float4(a.x, a.y, b.x, b.y);
+    } else {
+        p[0] = a;
+        p[1] = b;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void load_pair(const C2<T> *p, C2<T> &a, C2<T> &b)
+{
+    if constexpr (sizeof(T) == 4) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        a = {v.x, v.y};
+        b = {v.z, v.w};
+    } else {
+        a = p[0];
+        b = p[1];
+    }
+}
+
 template <typename T, int LOGP, int E>
 __device__ __forceinline__ void rows_fwd_regs(int ra, C2<T> (&v)[E], C2<T> *__restrict__ W1, int N, C2<T> *x,
                                               const C2<T> *tws)
@@ -58,10 +84,19 @@ __device__ __forceinline__ void rows_fwd_regs(int ra, C2<T> (&v)[E], C2<T> *__re
 #pragma unroll
     for (int q = 0; q < E; ++q) x[t + G * q] = v[q];
     __syncthreads();
+    // rows ra, ra+1 of a column are adjacent in W1: one 16-byte store for
+    // both (FP32) where they are 16-byte aligned (N even, aligned base)
+    const bool pair = sizeof(T) == 4 && (N & 1) == 0 && (reinterpret_cast<uintptr_t>(W1) & 15) == 0;
     for (int k = t; k <= hP; k += G) {
         const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
-        W1[(size_t)k * N + ra] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
-        if (rb < N) W1[(size_t)k * N + rb] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+        const C2<T> a = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
+        const C2<T> b = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+        if (pair) {
+            store_pair(W1 + (size_t)k * N + ra, a, b);
+        } else {
+            W1[(size_t)k * N + ra] = a;
+            if (rb < N) W1[(size_t)k * N + rb] = b;
+        }
     }
     __syncthreads();  // x may be reused by the caller
 }
@@ -140,12 +175,18 @@ __device__ __forceinline__ void rows_inv_regs(int ra, const C2<T> *__restrict__ 
     constexpr int P = 1 << LOGP, hP = P >> 1, G = P / E;
     const int t = threadIdx.x;
     const int rb = ra + 1;
+    const bool pair = sizeof(T) == 4 && (N & 1) == 0 && (reinterpret_cast<uintptr_t>(W2) & 15) == 0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int k = t + G * q;
         const int kk = k <= hP ? k : P - k;  // Hermitian extension
-        C2<T> Ya = W2[(size_t)kk * N + ra];
-        C2<T> Yb = rb < N ? W2[(size_t)kk * N + rb] : C2<T>{T(0), T(0)};
+        C2<T> Ya, Yb;
+        if (pair) {  // rows ra, ra+1 in one 16-byte load
+            load_pair(W2 + (size_t)kk * N + ra, Ya, Yb);
+        } else {
+            Ya = W2[(size_t)kk * N + ra];
+            Yb = rb < N ? W2[(size_t)kk * N + rb] : C2<T>{T(0), T(0)};
+        }
         if (k > hP) {
             Ya.y = -Ya.y;
             Yb.y = -Yb.y;

@@ -52,6 +52,142 @@ kb_rows_fwd(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
                               pupd ? pupd + d.img : nullptr, pupd ? (T)st[m.x].beta : T(0));
 }
 
+// Two row pairs per block (rows 4j .. 4j+3 of a slice), for the long
+// transforms: each group of G = P/E threads transforms one pair as above,
+// then the block writes the four rows' spectra column by column with
+// neighbouring lanes on neighbouring pairs, so each column gets one 32-byte
+// run per block instead of two 16-byte ones (the transposed scratch is
+// written a few bytes per cache line; fewer, larger requests move it
+// faster).  FP32 with even N (paired 16-byte accesses).
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(512)
+kb_rows_fwd2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
+             const T *__restrict__ src, C2<T> *__restrict__ W1, const CGState *st, T *pupd)
+{
+    constexpr int P = 1 << LOGP, hP = P / 2, G = P / E;
+    const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
+    if (slice_halted(st, m.x)) return;
+    const BatchSlice &d = sl[m.x];
+    const int N = d.N;
+    const int grp = threadIdx.x / G, t = threadIdx.x % G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *xs = reinterpret_cast<C2<T> *>(smem_raw);
+    C2<T> *x = xs + grp * P;
+    const C2<T> *tws =
+        stage_twiddles<T, twiddles_in_lds<T>(P)>(xs + 2 * P, reinterpret_cast<const C2<T> *>(d.tw), hP);
+    __syncthreads();
+    const int ra = 4 * m.y + 2 * grp, rb = ra + 1;
+    const T *sr = src + d.img;
+    T *pu = pupd ? pupd + d.img : nullptr;
+    const T bt = pupd ? (T)st[m.x].beta : T(0);
+    C2<T> v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int n = t + G * q;
+        T re = 0, im = 0;
+        if (n < N && ra < N) {  // N even: rb < N too
+            const size_t ia = (size_t)ra * N + n, ib = (size_t)rb * N + n;
+            re = sr[ia];
+            im = sr[ib];
+            if (pu) {
+                re += bt * pu[ia];
+                pu[ia] = re;
+                im += bt * pu[ib];
+                pu[ib] = im;
+            }
+        }
+        v[q] = {re, im};
+    }
+    fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
+#pragma unroll
+    for (int q = 0; q < E; ++q) x[t + G * q] = v[q];
+    __syncthreads();
+    // split each pair's transform into its two real rows (as rows_fwd_regs)
+    // and write (k, pair) with the pair fastest
+    C2<T> *out = W1 + d.w;
+    for (int i = threadIdx.x; i < 2 * (hP + 1); i += 2 * G) {
+        const int k = i >> 1, g2 = i & 1, r0 = 4 * m.y + 2 * g2;
+        if (r0 >= N) continue;
+        const C2<T> *xg = xs + g2 * P;
+        const C2<T> Zk = xg[k], Zm = xg[(P - k) & (P - 1)];
+        const C2<T> a = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
+        const C2<T> b = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
+        store_pair(out + (size_t)k * N + r0, a, b);
+    }
+}
+
+// Inverse rows for two row pairs per block: the block reads the four rows'
+// spectra column by column (32-byte runs, pair fastest) into LDS, then each
+// group transforms its pair as rows_inv_regs; FP64 partial dot of the block
+// in the slot of its first pair (the second pair's slot holds 0).
+template <typename T, int LOGP, int E>
+__global__ void __launch_bounds__(512)
+kb_rows_inv2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
+             const C2<T> *__restrict__ W2, T *__restrict__ y, const CGState *st,
+             const T *__restrict__ dotv, double *__restrict__ partial)
+{
+    constexpr int P = 1 << LOGP, hP = P / 2, G = P / E, XS = P + 2;  // per-group area (spectra + 2)
+    const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
+    if (slice_halted(st, m.x)) return;
+    const BatchSlice &d = sl[m.x];
+    const int N = d.N;
+    const int grp = threadIdx.x / G, t = threadIdx.x % G;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2<T> *xs = reinterpret_cast<C2<T> *>(smem_raw);
+    const C2<T> *tws =
+        stage_twiddles<T, twiddles_in_lds<T>(P)>(xs + 2 * XS, reinterpret_cast<const C2<T> *>(d.tw), hP);
+    // stage: group g2's area holds (Ya, Yb) of column k at 2k, 2k + 1
+    const C2<T> *in = W2 + d.w;
+    for (int i = threadIdx.x; i < 2 * (hP + 1); i += 2 * G) {
+        const int k = i >> 1, g2 = i & 1, r0 = 4 * m.y + 2 * g2;
+        C2<T> a = {T(0), T(0)}, b = {T(0), T(0)};
+        if (r0 < N) load_pair(in + (size_t)k * N + r0, a, b);
+        C2<T> *sg = xs + g2 * XS;
+        sg[2 * k] = a;
+        sg[2 * k + 1] = b;
+    }
+    __syncthreads();
+    const C2<T> *sg = xs + grp * XS;
+    C2<T> v[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int k = t + G * q;
+        const int kk = k <= hP ? k : P - k;  // Hermitian extension
+        C2<T> Ya = sg[2 * kk], Yb = sg[2 * kk + 1];
+        if (k > hP) {
+            Ya.y = -Ya.y;
+            Yb.y = -Yb.y;
+        }
+        v[q] = {Ya.x - Yb.y, Ya.y + Yb.x};
+    }
+    __syncthreads();  // the staged spectra are read: the transform may reuse the area
+    fft_passes<T, E, P, 1, true, true>(v, xs + grp * XS, t, tws);
+    const int ra = 4 * m.y + 2 * grp, rb = ra + 1;
+    T *yo = y + d.img;
+    const T *dv = dotv ? dotv + d.img : nullptr;
+    double acc = 0.0;
+    if (ra < N) {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int n = t + G * q;
+            if (n >= N) continue;
+            yo[(size_t)ra * N + n] = v[q].x;
+            yo[(size_t)rb * N + n] = v[q].y;
+            if (dv) {
+                acc += (double)dv[(size_t)ra * N + n] * (double)v[q].x;
+                acc += (double)dv[(size_t)rb * N + n] * (double)v[q].y;
+            }
+        }
+    }
+    if (partial) {
+        const double sum = block_sum_lds(acc, reinterpret_cast<double *>(smem_raw));
+        if (threadIdx.x == 0) {
+            partial[d.rpart + 2 * m.y] = sum;
+            if (2 * m.y + 1 < d.nrow) partial[d.rpart + 2 * m.y + 1] = 0.0;
+        }
+    }
+}
+
 template <typename T, int LOGP, int E>
 __global__ void __launch_bounds__(256)
 kb_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
@@ -307,7 +443,28 @@ struct BatchGroup {
     int E[2];  // tuned elements per thread, [f32, f64]
     int2 *rows = nullptr, *cols = nullptr, *srows = nullptr, *scols = nullptr;
     int nrows = 0, ncols = 0, nsrows = 0, nscols = 0;
+    // two row pairs per block (FP32 row passes of 1024- and 2048-point
+    // groups whose slices all have even N): map of (slice, row quad)
+    int2 *rows2 = nullptr;
+    int nrows2 = 0;
 };
+
+// LDS of the two-pair row kernels
+template <typename T>
+inline size_t rows2_lds_bytes(int P, bool inv)
+{
+    const size_t data = inv ? 2 * (size_t)(P + 2) : 2 * (size_t)P;
+    size_t b = (data + (twiddles_in_lds<T>(P) ? (size_t)(P / 2) : 0)) * sizeof(C2<T>);
+    return b > 512 * sizeof(double) ? b : 512 * sizeof(double);
+}
+
+#define GCT_LAUNCH_B2(kern, T, logP, E, grid, lds, s, ...)                                               \
+    do {                                                                                                \
+        if (logP == 10 && E == 16) hipLaunchKernelGGL((kern<T, 10, 16>), grid, dim3(128), lds, s, __VA_ARGS__); \
+        else if (logP == 10) hipLaunchKernelGGL((kern<T, 10, 8>), grid, dim3(256), lds, s, __VA_ARGS__);    \
+        else if (E == 16) hipLaunchKernelGGL((kern<T, 11, 16>), grid, dim3(256), lds, s, __VA_ARGS__);      \
+        else hipLaunchKernelGGL((kern<T, 11, 8>), grid, dim3(512), lds, s, __VA_ARGS__);                    \
+    } while (0)
 
 struct gct_batch {
     std::vector<const gct_plan *> plans;
@@ -339,7 +496,7 @@ void free_batch(gct_batch *b)
     b->graphs.clear();
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
     for (auto &g : b->groups) {
-        for (int2 *m : {g.rows, g.cols, g.srows, g.scols})
+        for (int2 *m : {g.rows, g.cols, g.srows, g.scols, g.rows2})
             if (m) (void)hipFree(m);
     }
     if (b->gram_map) (void)hipFree(b->gram_map);
@@ -389,6 +546,13 @@ hipError_t batch_apply_passes(const gct_batch *b, const T *Ghat, const T *src, T
     const BatchSlice *sl = b->dev[dti<T>()];
     for (const auto &g : b->groups) {
         const int E = g.E[dti<T>()];
+        if constexpr (sizeof(T) == 4) {
+            if (g.nrows2) {
+                GCT_LAUNCH_B2(kb_rows_fwd2, T, g.logP, E, dim3(g.nrows2), rows2_lds_bytes<T>(1 << g.logP, false), s,
+                              g.rows2, sl, src, W1, st, pupd);
+                continue;
+            }
+        }
         const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
         GCT_LAUNCH_B(kb_rows_fwd, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, src, W1, st, pupd);
     }
@@ -399,6 +563,13 @@ hipError_t batch_apply_passes(const gct_batch *b, const T *Ghat, const T *src, T
     }
     for (const auto &g : b->groups) {
         const int E = g.E[dti<T>()];
+        if constexpr (sizeof(T) == 4) {
+            if (g.nrows2) {
+                GCT_LAUNCH_B2(kb_rows_inv2, T, g.logP, E, dim3(g.nrows2), rows2_lds_bytes<T>(1 << g.logP, true), s,
+                              g.rows2, sl, W2, y, st, dotv, partial);
+                continue;
+            }
+        }
         const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
         GCT_LAUNCH_B(kb_rows_inv, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, W2, y, st, dotv,
                      partial);
@@ -600,9 +771,12 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         g.logP = kv.first;
         const int P = 1 << g.logP;
         g.E[0] = g.E[1] = fft_elems(P);
-        std::vector<int2> rows, cols, srows, scols;
+        std::vector<int2> rows, cols, srows, scols, rows2;
+        bool pair2 = g.logP == 10 || g.logP == 11;
         for (int i : kv.second) {
             const int N = plans[i]->N;
+            pair2 = pair2 && N % 2 == 0 && b->host[i].w % 2 == 0;
+            for (int k = 0; k < (N / 2 + 1) / 2; ++k) rows2.push_back(make_int2(i, k));
             for (int k = 0; k < (N + 1) / 2; ++k) rows.push_back(make_int2(i, k));
             for (int k = 0; k <= P / 2; ++k) cols.push_back(make_int2(i, k));
             for (int k = 0; k < P / 2; ++k) srows.push_back(make_int2(i, k));
@@ -617,6 +791,10 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         if (!rc) rc = upload_map(&g.cols, cols);
         if (!rc) rc = upload_map(&g.srows, srows);
         if (!rc) rc = upload_map(&g.scols, scols);
+        if (!rc && pair2) {
+            g.nrows2 = (int)rows2.size();
+            rc = upload_map(&g.rows2, rows2);
+        }
         b->groups.push_back(g);
         if (rc) {
             free_batch(b);

@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from paper_2005_13471_amd import inputs
-from gpu_helpers import normwise, say
+from gpu_helpers import normwise, sample_pixels, say
 
 pytestmark = pytest.mark.gpu
 
@@ -160,3 +160,85 @@ def test_batch_rejects_bad_arguments(batch_setup):
     with pytest.raises(gct.GramctError) as e:
         gct.batch_gram_apply(B, gh, t, t, B.workspace(gct.OP_GRAM_APPLY))
     assert e.value.code == gct.GCT_EINVAL
+
+
+# long transforms: 1024- and 2048-point groups, where FP32 row passes take
+# two row pairs per block when every slice of the group has even N (the
+# second batch has an odd N in the 1024-point group, which keeps the
+# one-pair kernels there)
+LONG = [[(300, 60, 1.0), (260, 40, 0.0), (520, 30, 1.0), (302, 20, 0.5)],
+        [(300, 60, 1.0), (301, 24, 0.5), (520, 30, 1.0)]]
+# slices whose group takes the two-pair row kernels
+LONG_PAIRED = [{300, 260, 520, 302}, {520}]
+
+
+@pytest.mark.parametrize("which", [0, 1])
+def test_batch_long_transforms_match_single_slice_and_oracle(which):
+    """Batched spectrum and apply of long-transform slices against the
+    single-slice ones from the same Gram filter: bit for bit where the batch
+    runs the same row kernels; to a few units in the last place where it
+    runs the two-pair row kernels (the same arithmetic in another kernel,
+    where the compiler may contract products and sums differently).  Sampled
+    outputs against the oracle's direct sum; batched CG meets the stopping
+    rule with the oracle's re-check of sampled residual entries."""
+    from paper_2005_13471_amd import gramct as gct
+    dt = torch.float32
+    spec = LONG[which]
+    plans, ogs = [], []
+    for i, (N, n, z) in enumerate(spec):
+        th = inputs.angles(n) + 0.013 * i
+        M = inputs.detector_bins(N, z)
+        plans.append(gct.Plan(N, th, M, zeta=z))
+        ogs.append(oracle.Geometry(N, th, M, zeta=z))
+    say("batch long", which, [p.N for p in plans])
+    B = gct.Batch(plans)
+    G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
+    gct.batch_gram_build(B, G)
+    Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")
+    gct.batch_gram_spectrum(B, G, Ghat, B.workspace(gct.OP_GRAM_SPECTRUM, dt))
+    cs = [inputs.uniform_coeffs(N, 4000 + i) for i, (N, _, _) in enumerate(spec)]
+    y = torch.empty(B.image_elems, dtype=dt, device="cuda")
+    gct.batch_gram_apply(B, Ghat, _packed(B, cs, dt), y, B.workspace(gct.OP_GRAM_APPLY, dt))
+    for i, P in enumerate(plans):
+        o = int(B.gram_offsets[i])
+        Gb = G[o:o + P.info.gram_elems].contiguous()
+        Gh = torch.empty(P.info.spectrum_elems, dtype=dt, device="cuda")
+        gct.gram_spectrum(P, Gb, Gh, P.workspace(gct.OP_GRAM_SPECTRUM, dt))
+        so = int(B.spectrum_offsets[i])
+        say("  slice", i, "N", P.N, "spectrum max diff",
+            float((Gh - Ghat[so:so + P.info.spectrum_elems]).abs().max()))
+        assert torch.equal(Gh, Ghat[so:so + P.info.spectrum_elems]), i
+        yi = torch.empty(P.N * P.N, dtype=dt, device="cuda")
+        gct.gram_apply(P, Gh, torch.as_tensor(cs[i].reshape(-1), dtype=dt, device="cuda"), yi,
+                       P.workspace(gct.OP_GRAM_APPLY, dt))
+        d = float((yi.view(P.N, P.N) - B.image(y, i)).abs().max())
+        say("  slice", i, "apply max diff", d)
+        if P.N in LONG_PAIRED[which]:
+            assert d <= 1e-6 * float(yi.abs().max()), i
+        else:
+            assert torch.equal(yi.view(P.N, P.N), B.image(y, i)), i
+        # sampled outputs against the oracle's exact filter
+        g_or = oracle.gram(ogs[i])
+        idx = sample_pixels(P.N, 60, 10 + i)
+        ref = oracle.apply_at(g_or, cs[i], idx)
+        got = B.image(y, i).double().cpu().numpy().reshape(-1)[idx]
+        assert np.max(np.abs(got - ref)) <= 1e-4 * np.max(np.abs(ref)), i
+    # batched CG (dot partials of the two-pair kernels) to 1e-4
+    bs = [torch.as_tensor(inputs.uniform_coeffs(N, 5000 + i), dtype=dt, device="cuda")
+          for i, (N, _, _) in enumerate(spec)]
+    bpk = torch.zeros(B.image_elems, dtype=dt, device="cuda")
+    for i, bi in enumerate(bs):
+        gct.gram_apply(plans[i], Ghat[int(B.spectrum_offsets[i]):int(B.spectrum_offsets[i]) + plans[i].info.spectrum_elems],
+                       bi.reshape(-1), B.image(bpk, i).reshape(-1), plans[i].workspace(gct.OP_GRAM_APPLY, dt))
+    x = torch.zeros_like(bpk)
+    res = gct.batch_cg_solve(B, Ghat, bpk, x, B.workspace(gct.OP_CG, dt), rtol=1e-4, max_iter=500,
+                             check_every=4)
+    for i, P in enumerate(plans):
+        say("  slice", i, "N", P.N, "iters", res[i].iters, "true", res[i].rel_res_true)
+        assert res[i].status == gct.GCT_OK and res[i].rel_res_true <= 1.2e-4
+        g_or = oracle.gram(ogs[i])
+        idx = sample_pixels(P.N, 60, 20 + i)
+        bh = B.image(bpk, i).double().cpu().numpy()
+        xh = B.image(x, i).double().cpu().numpy()
+        r = bh.reshape(-1)[idx] - oracle.apply_at(g_or, xh, idx)
+        assert np.sqrt(np.mean(r ** 2)) <= 3e-4 * np.linalg.norm(bh) / P.N

@@ -167,8 +167,9 @@ k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp,
 //     per (angle, sub-interval, coefficient), split in runs of bins over all
 //     threads; k padded to 8 with zeros (written once per block);
 //   - each thread evaluates 8 pixels (rows 4 apart) per angle: one floor,
-//     a sub-interval search, two 16-byte LDS reads, an 8-term Horner scheme.
-template <typename T, int JM>
+//     a sub-interval search, one or two 16-byte LDS reads, an HN-term Horner
+//     scheme (HN >= D1: the coefficients past D1 are the zero padding).
+template <typename T, int JM, int HN>
 __global__ void __launch_bounds__(256)
 k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, int K, int groups,
           const double *__restrict__ geo, const int32_t *__restrict__ ints, const T *__restrict__ brk,
@@ -288,13 +289,13 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
             // value of the angle's interpolant at pixel i, given its
             // sub-interval and offset in it
             auto eval = [&](int i, int mi, int sub, T u) {
-                const T *e = Ec + (size_t)(mi * smax + sub) * D1P;
-                T ev[D1P];
+                const T *e = Ec + (mi * smax + sub) * D1P;
+                T ev[HN];
 #pragma unroll
-                for (int k = 0; k < D1P; ++k) ev[k] = e[k];
-                T v = ev[D1P - 1];
+                for (int k = 0; k < HN; ++k) ev[k] = e[k];
+                T v = ev[HN - 1];
 #pragma unroll
-                for (int k = D1P - 2; k >= 0; --k) v = v * u + ev[k];
+                for (int k = HN - 2; k >= 0; --k) v = v * u + ev[k];
                 csum[i] += v;
             };
             if (nsub <= 4) {  // (uniform) branch-free search over at most 3 breakpoints
@@ -307,7 +308,7 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
                     const T fl = floor(zl);
                     const T t = zl - fl;
                     int mi = base + (int)fl;
-                    mi = mi < 0 ? 0 : (mi >= R ? R - 1 : mi);
+                    mi = min(max(mi, 0), R - 1);
                     const bool g1 = t >= b1, g2 = t >= b2, g3 = t >= b3;
                     T bs = g1 ? b1 : b0;  // breakpoints ascend: the last one passed
                     bs = g2 ? b2 : bs;
@@ -321,7 +322,7 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
                     const T fl = floor(zl);
                     const T t = zl - fl;
                     int mi = base + (int)fl;
-                    mi = mi < 0 ? 0 : (mi >= R ? R - 1 : mi);
+                    mi = min(max(mi, 0), R - 1);
                     int sub = 0;
                     for (int s2 = 1; s2 < nsub; ++s2) sub += (t >= bk[s2]) ? 1 : 0;
                     eval(i, mi, sub, t - bk[sub]);
@@ -422,12 +423,21 @@ hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, hip
             T *dst = groups > 1 ? part : b;
             const double *geo_ = reinterpret_cast<const double *>(p->dev.bp_geo);
             const int32_t *ints_ = reinterpret_cast<const int32_t *>(p->dev.bp_int);
-            if (p->bp.J <= 8)
-                hipLaunchKernelGGL((k_bp_tile<T, 8>), grid, dim3(256), lds, s, pf, dst, N, p->n, p->M + 2 * p->K,
-                                   p->K, groups, geo_, ints_, brk_, coef_, p->bp.smax, p->bp.J, p->bp.D1, rmax, ch);
-            else
-                hipLaunchKernelGGL((k_bp_tile<T, 16>), grid, dim3(256), lds, s, pf, dst, N, p->n, p->M + 2 * p->K,
-                                   p->K, groups, geo_, ints_, brk_, coef_, p->bp.smax, p->bp.J, p->bp.D1, rmax, ch);
+#define GCT_BP_TILE(JM_, HN_)                                                                              \
+    hipLaunchKernelGGL((k_bp_tile<T, JM_, HN_>), grid, dim3(256), lds, s, pf, dst, N, p->n, p->M + 2 * p->K, \
+                       p->K, groups, geo_, ints_, brk_, coef_, p->bp.smax, p->bp.J, p->bp.D1, rmax, ch)
+            // Horner length: the kernel degree + 1 rounded up to 4, 6 or 8
+            const int hn = p->bp.D1 <= 4 ? 4 : (p->bp.D1 <= 6 ? 6 : 8);
+            if (p->bp.J <= 8) {
+                if (hn == 4) GCT_BP_TILE(8, 4);
+                else if (hn == 6) GCT_BP_TILE(8, 6);
+                else GCT_BP_TILE(8, 8);
+            } else {
+                if (hn == 4) GCT_BP_TILE(16, 4);
+                else if (hn == 6) GCT_BP_TILE(16, 6);
+                else GCT_BP_TILE(16, 8);
+            }
+#undef GCT_BP_TILE
             if (groups > 1) {
                 const size_t len = (size_t)N * N;
                 hipLaunchKernelGGL(k_bp_reduce<T>, dim3((unsigned)std::min<size_t>(2048, (len + 255) / 256)),

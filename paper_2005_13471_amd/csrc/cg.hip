@@ -99,7 +99,39 @@ k_cg_init_fin(CGState *st, const double *part_rr, const double *part_bb, int np,
         st->stat[0] = st->stat[1] = st->status;
         st->kring = 0;
         st->sd = sd;
+        st->fb = 0;
     }
+}
+
+// Start-vector fallback on the device: if ||b - A x_0|| >= ||b|| (or is not
+// finite) the solve starts from zero instead.  Vector part (every block),
+// then the scalars (one block); both read the decision from the state that
+// k_cg_init_fin wrote, which neither changes before the second kernel.
+__device__ __forceinline__ bool cg_drop_start(const CGState *st)
+{
+    return st->bb > 0.0 && !(st->rr0 < st->bb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_cg_fallback_vec(const CGState *st, const T *b, T *x, T *r, size_t n)
+{
+    if (!cg_drop_start(st)) return;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        x[i] = T(0);
+        r[i] = b[i];
+    }
+}
+
+__global__ void k_cg_fallback_fin(CGState *st)
+{
+    if (threadIdx.x != 0 || !cg_drop_start(st)) return;
+    const double bb = st->bb;
+    st->rr = st->rr0 = bb;
+    st->ring[0] = bb;
+    st->status = (bb <= st->thr2) ? CG_CONVERGED : CG_RUNNING;
+    st->gam[0] = st->gam[1] = bb;
+    st->stat[0] = st->stat[1] = st->status;
+    st->fb = 1;
 }
 
 // After the last launch of a solve that reached max_iter: ||r_k||^2 from the
@@ -233,34 +265,29 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     if (check_every > CG_RING) check_every = CG_RING;
     check_every += check_every & 1;  // even chunks keep the parity slots aligned across replays
 
-    CGState hs;
-    int fell_back = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
-        const bool start = use_x0 && attempt == 0;
-        if (start) GCT_TRY(launch_apply_passes<T>(p, Ghat, x, Ap, aws, s, nullptr, nullptr, nullptr,
-                                                  nullptr, nullptr));
-        hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, b, x, r, pv,
-                           start ? (const T *)Ap : nullptr, n, part, part2);
-        hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK,
-                           rtol * rtol, method == 1 ? 1 : 0);
-        GCT_TRY(hipGetLastError());
-        GCT_TRY(hipMemcpyAsync(&hs, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
-        GCT_TRY(hipStreamSynchronize(s));
-        // a start vector that is no better than zero is dropped (plain CG is
-        // the fallback)
-        if (start && hs.bb > 0.0 && !(hs.rr < hs.bb)) {
-            fell_back = 1;
-            continue;
-        }
-        break;
+    // pinned state copy and its event (once per plan)
+    gct_plan *pm = const_cast<gct_plan *>(p);
+    if (!pm->cg_pin) {
+        void *h = nullptr;
+        GCT_TRY(hipHostMalloc(&h, sizeof(CGState), hipHostMallocDefault));
+        pm->cg_pin = reinterpret_cast<CGState *>(h);
     }
-    const double bb = hs.bb;
-    auto rel = [bb](double rr) { return bb > 0.0 ? std::sqrt(rr / bb) : 0.0; };
-    res->rel_res0 = rel(hs.rr0);
-    res->fell_back = fell_back;
-    if (hist) hist[0] = rel(hs.rr0);
+    if (!pm->cg_ev) GCT_TRY(hipEventCreateWithFlags(&pm->cg_ev, hipEventDisableTiming));
+    CGState *pin = pm->cg_pin;
 
-    int64_t done = 0;
+    // start: r_0 (from x_0 when given), then on the device the fallback to
+    // zero when x_0 is no better; no host round trip before the iterations
+    if (use_x0) GCT_TRY(launch_apply_passes<T>(p, Ghat, x, Ap, aws, s, nullptr, nullptr, nullptr, nullptr, nullptr));
+    hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, b, x, r, pv, use_x0 ? (const T *)Ap : nullptr,
+                       n, part, part2);
+    hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK, rtol * rtol,
+                       method == 1 ? 1 : 0);
+    if (use_x0) {
+        hipLaunchKernelGGL(k_cg_fallback_vec<T>, dim3(VBLK), dim3(256), 0, s, (const CGState *)st, b, x, r, n);
+        hipLaunchKernelGGL(k_cg_fallback_fin, dim3(1), dim3(64), 0, s, st);
+    }
+    GCT_TRY(hipGetLastError());
+
     // launch i (of a batch starting at launch `first`): three fused kernels,
     // parity (first + i) & 1; launch 0 only forms A r_0, launch i > 0 makes
     // update i - 1, so max_iter updates take max_iter + 1 launches
@@ -272,20 +299,22 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
         }
         return hipGetLastError();
     };
+    // one chunk of launches (a graph of check_every launches, captured once
+    // per buffer set, or a shorter tail), then the state copied to the
+    // pinned buffer
     const int64_t launches = max_iter > 0 ? (int64_t)max_iter + 1 : 0;
-    while (hs.status == CG_RUNNING && done < launches) {
-        const int chunk = (int)std::min<int64_t>(check_every, launches - done);
-        hipGraphExec_t exec = nullptr;
+    int64_t launched = 0;
+    auto enqueue = [&]() -> int {
+        const int chunk = (int)std::min<int64_t>(check_every, launches - launched);
         if (chunk == check_every) {
-            // a chunk of iterations as one graph, captured once per buffer set
-            const CGGraphKey key{(const void *)Ghat, (const void *)b, (void *)x, ws,
-                                 (int)sizeof(T), chunk};
-            exec = cg_graph_lookup(p, key);
+            const CGGraphKey key{(const void *)Ghat, (const void *)b, (void *)x, ws, (int)sizeof(T), chunk};
+            hipGraphExec_t exec = cg_graph_lookup(p, key);
             if (!exec) {
                 hipStream_t cs = cg_capture_stream(p);
                 if (!cs) return fail(GCT_EHIP, "cannot create the capture stream");
-                GCT_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-                hipError_t e = launch_iters(chunk, 0, cs);  // replayed at even `done` only
+                hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) return check_hip(e, "cg graph capture");
+                e = launch_iters(chunk, 0, cs);  // replayed at even `launched` only
                 hipGraph_t g = nullptr;
                 hipError_t e2 = hipStreamEndCapture(cs, &g);
                 if (e != hipSuccess || e2 != hipSuccess) {
@@ -297,17 +326,51 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
                 if (e != hipSuccess) return check_hip(e, "hipGraphInstantiate");
                 cg_graph_store(p, key, exec);
             }
-            GCT_TRY(hipGraphLaunch(exec, s));
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) return check_hip(e, "cg chunk launch");
         } else {
-            GCT_TRY(launch_iters(chunk, done, s));
+            hipError_t e = launch_iters(chunk, launched, s);
+            if (e != hipSuccess) return check_hip(e, "cg chunk launch");
         }
-        const int64_t kprev = hs.kring;
-        GCT_TRY(hipMemcpyAsync(&hs, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        launched += chunk;
+        hipError_t e = hipMemcpyAsync(pin, st, sizeof(CGState), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(pm->cg_ev, s);
+        return check_hip(e, "cg state copy");
+    };
+    CGState hs;
+    int rc = GCT_OK;
+    if (launches == 0) {  // no iteration: the state after the start
+        GCT_TRY(hipMemcpyAsync(pin, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
         GCT_TRY(hipStreamSynchronize(s));
-        if (hist)
-            for (int64_t k = kprev + 1; k <= hs.kring; ++k) hist[k] = rel(hs.ring[k % CG_RING]);
-        done += chunk;
+        hs = *pin;
+    } else {
+        // one chunk at a time: a chunk queued ahead of the check would run
+        // (skipping) after convergence and delay the true-residual step more
+        // than the overlapped check saves
+        if ((rc = enqueue()) != GCT_OK) return rc;
+        int64_t kprev = 0;
+        bool first = true;
+        for (;;) {
+            GCT_TRY(hipEventSynchronize(pm->cg_ev));
+            hs = *pin;
+            if (first) {
+                if (hist) hist[0] = hs.bb > 0.0 ? std::sqrt(hs.rr0 / hs.bb) : 0.0;
+                first = false;
+            }
+            if (hist)
+                for (int64_t k = kprev + 1; k <= hs.kring; ++k)
+                    hist[k] = hs.bb > 0.0 ? std::sqrt(hs.ring[k % CG_RING] / hs.bb) : 0.0;
+            kprev = std::max(kprev, hs.kring);
+            if (hs.status != CG_RUNNING || launched >= launches) break;
+            if ((rc = enqueue()) != GCT_OK) return rc;
+        }
     }
+    const double bb = hs.bb;
+    auto rel = [bb](double rr) { return bb > 0.0 ? std::sqrt(rr / bb) : 0.0; };
+    res->rel_res0 = rel(hs.rr0);
+    res->fell_back = (int32_t)hs.fb;
+    if (hist && launches == 0) hist[0] = rel(hs.rr0);
+    const int64_t done = launched;
     if (hs.status == CG_RUNNING && done > 0) {
         // max_iter updates made: test the last residual norm
         hipLaunchKernelGGL(k_cgf_norm, dim3(1), dim3(256), 0, s, st, (const double *)part, rblocks);

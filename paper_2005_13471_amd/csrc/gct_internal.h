@@ -98,7 +98,8 @@ enum : int64_t { CG_RUNNING = 0, CG_CONVERGED = 1, CG_BREAKDOWN = 2 };
 
 struct CGState {
     double rr, bb, rr0, pAp, alpha, beta, thr2, pad;
-    int64_t k, status, sd, pad3;  // sd = 1: steepest descent (every update takes beta = 0)
+    int64_t k, status, sd, fb;  // sd = 1: steepest descent (every update takes beta = 0);
+                                // fb = 1: the start vector was replaced by zero
     double ring[CG_RING];  // ||r_k||^2 at ring[k % CG_RING]
     // fused single-slice iteration (parity slots, see gram_apply.hip):
     // gamma = ||r||^2 and alpha of the last update, "updates may start" (1:
@@ -156,6 +157,9 @@ struct gct_plan {
     // cached CG iteration graphs and the stream they are captured on
     std::vector<gct::CGGraph> cg_graphs;
     hipStream_t capture_stream = nullptr;
+    // pinned host copy of the solver state and the event of its copy
+    gct::CGState *cg_pin = nullptr;
+    hipEvent_t cg_ev = nullptr;
 };
 
 namespace gct {

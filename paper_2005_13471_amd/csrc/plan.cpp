@@ -509,6 +509,8 @@ int gct_plan_destroy(gct_plan *plan)
     for (auto &g : plan->cg_graphs) (void)hipGraphExecDestroy(g.exec);
     plan->cg_graphs.clear();
     if (plan->capture_stream) (void)hipStreamDestroy(plan->capture_stream);
+    if (plan->cg_pin) (void)hipHostFree(plan->cg_pin);
+    if (plan->cg_ev) (void)hipEventDestroy(plan->cg_ev);
     free_tables(plan);
     delete plan;
     return GCT_OK;

@@ -647,8 +647,7 @@ int batch_cg(const gct_batch *b, const T *Ghat, const T *bv, T *x, double rtol, 
     while (running() && done < max_iter) {
         const int chunk = (int)std::min<int64_t>(check_every, max_iter - done);
         if (chunk == check_every) {
-            const CGGraphKey key{(const void *)Ghat, (const void *)bv, (void *)x, ws, (int)sizeof(T),
-                                 chunk};
+            const CGGraphKey key{(const void *)Ghat, (void *)x, ws, (int)sizeof(T), chunk};
             hipGraphExec_t exec = nullptr;
             for (const auto &g : b->graphs)
                 if (g.key == key) exec = g.exec;

@@ -307,7 +307,7 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     auto enqueue = [&]() -> int {
         const int chunk = (int)std::min<int64_t>(check_every, launches - launched);
         if (chunk == check_every) {
-            const CGGraphKey key{(const void *)Ghat, (const void *)b, (void *)x, ws, (int)sizeof(T), chunk};
+            const CGGraphKey key{(const void *)Ghat, (void *)x, ws, (int)sizeof(T), chunk};
             hipGraphExec_t exec = cg_graph_lookup(p, key);
             if (!exec) {
                 hipStream_t cs = cg_capture_stream(p);
@@ -376,8 +376,9 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
         hipLaunchKernelGGL(k_cgf_norm, dim3(1), dim3(256), 0, s, st, (const double *)part, rblocks);
         GCT_TRY(hipGetLastError());
         const int64_t kprev = hs.kring;
-        GCT_TRY(hipMemcpyAsync(&hs, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
+        GCT_TRY(hipMemcpyAsync(pin, st, sizeof(CGState), hipMemcpyDeviceToHost, s));
         GCT_TRY(hipStreamSynchronize(s));
+        hs = *pin;
         if (hist)
             for (int64_t k = kprev + 1; k <= hs.kring; ++k) hist[k] = rel(hs.ring[k % CG_RING]);
     }
@@ -387,9 +388,9 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     hipLaunchKernelGGL(k_resid<T>, dim3(VBLK), dim3(256), 0, s, b, Ap, n, part);
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, VBLK, &st->pad);
     GCT_TRY(hipGetLastError());
-    double rt = 0.0;
-    GCT_TRY(hipMemcpyAsync(&rt, &st->pad, sizeof(double), hipMemcpyDeviceToHost, s));
+    GCT_TRY(hipMemcpyAsync(&pin->pad, &st->pad, sizeof(double), hipMemcpyDeviceToHost, s));
     GCT_TRY(hipStreamSynchronize(s));
+    const double rt = pin->pad;
 
     res->iters = (int32_t)hs.k;
     res->rel_res = rel(hs.rr);

@@ -126,14 +126,16 @@ struct BatchSlice {
 };
 
 // Key of a captured chunk of CG iterations.
+// (the right-hand side is not part of it: the iterations read only the
+// workspace vectors, x and the spectrum, so solves of many right-hand sides
+// reuse one graph)
 struct CGGraphKey {
-    const void *Ghat, *b;
+    const void *Ghat;
     void *x, *ws;
     int elem, chunk;
     bool operator==(const CGGraphKey &o) const
     {
-        return Ghat == o.Ghat && b == o.b && x == o.x && ws == o.ws && elem == o.elem &&
-               chunk == o.chunk;
+        return Ghat == o.Ghat && x == o.x && ws == o.ws && elem == o.elem && chunk == o.chunk;
     }
 };
 

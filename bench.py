@@ -340,6 +340,11 @@ def warm_compare(slices: int):
     seeds = range(W.TEST_SEEDS[0], W.TEST_SEEDS[0] + slices)
     b, _, _ = W.generate(prob, seeds, None, log=lambda *a: None, normalize=False)
     rep = W.summarize(W.compare(prob, ws, b))
+    ms_pipe, res_pipe = W.pipelined(prob, ws, b)
+    rep["warm_pipelined"] = {"ms_per_slice": ms_pipe,
+                             "iters_mean": float(np.mean([r.iters for r in res_pipe])),
+                             "max_rel_res_true": float(max(r.rel_res_true for r in res_pipe)),
+                             "note": "U-Net of the next slice on a second stream during each solve"}
     rep.update(workload="n256_a180_m366_z1", seeds=[W.TEST_SEEDS[0], W.TEST_SEEDS[0] + slices],
                net=f"U-Net {cfg.levels} levels, {cfg.base_channels} base channels, bf16",
                trained_steps=ws.meta.get("step"))

@@ -49,6 +49,20 @@ def test_trained_net_cuts_cg_iterations(setup):
     assert np.mean(cmp["warm_iters"] < cmp["plain_iters"]) >= 0.75
 
 
+def test_pipelined_warm_start_matches_sequential(setup):
+    """Inference of the next slice on a second stream during each solve:
+    the same start vectors, hence the same iterations as the sequential
+    warm solves, every solve meeting the stopping rule."""
+    gct, W, prob, b, xs, iters = setup
+    ws = W.WarmStart(prob, W.trained_path())
+    cmp = W.compare(prob, ws, b)
+    ms, res = W.pipelined(prob, ws, b)
+    say("pipelined warm ms per slice", ms, "sequential warm", np.mean(cmp["warm_ms"]),
+        "plain", np.mean(cmp["plain_ms"]))
+    assert [r.iters for r in res] == list(cmp["warm_iters"])
+    assert all(r.status == gct.GCT_OK and r.rel_res_true <= 1.05e-4 for r in res)
+
+
 def test_warm_iterate_is_close_to_the_cg_target(setup):
     """x0 from the net is a rough reconstruction: relative error against the
     plain-CG solution well below 1 on every slice."""

@@ -34,6 +34,10 @@
  * (per-angle parameters, FFT twiddles, correction-filter taps: O(n_angles)
  * bytes) once.  Every other buffer, including scratch workspace, is passed in
  * by the caller; gct_workspace_size reports the bytes each operation needs.
+ * A plan also keeps the solvers' captured iteration graphs and one pinned
+ * host copy of the solver state, so solves on one plan (and one batch) must
+ * not run from two host threads at once; the stream-ordered calls may share
+ * a plan freely.
  */
 #ifndef GRAMCT_H
 #define GRAMCT_H

@@ -47,8 +47,9 @@ def parse():
     ap.add_argument("--batch-slices", type=int, default=256)
     ap.add_argument("--warm-slices", type=int, default=64,
                     help="held-out slices for the plain vs warm-start CG comparison (0: skip)")
-    ap.add_argument("--fft-elems", type=int, default=0,
-                    help="elements per thread of the Gram-filtering transforms (0: autotune)")
+    ap.add_argument("--fft-elems", default="",
+                    help="elements per thread of the Gram-filtering transforms: E for every pass, or "
+                         "ROWS,COLS for the row passes and the column pass (empty: autotune)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for counter runs: set up the workload, then 20 applies and one "
                          "256 MiB elementwise copy (the counters' calibration), and exit")
@@ -138,10 +139,8 @@ def batch_main(args):
     ws_apply = B.workspace(gct.OP_GRAM_APPLY, dt)
     gct.batch_gram_build(B, G)
     gct.batch_gram_spectrum(B, G, Ghat, ws_spec)
-    tuned = gct.batch_autotune(B, Ghat, ws_cg, reps=3)
+    gct.batch_autotune(B, Ghat, ws_cg, reps=3)
     torch.cuda.synchronize()
-    if args.pmc_probe:
-        return pmc_probe(gct, plan, Ghat, c_apply, y, ws_apply, fft_elems)
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         for _ in range(4):
@@ -189,7 +188,8 @@ def batch_main(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch_uneven_256", "slices": S, "seed": 3000,
                    "N_values": sorted(set(int(v) for v in Ns)), "image_elems": B.image_elems,
-                   "fft_groups": B.groups, "autotuned_elems_per_thread": tuned},
+                   "fft_groups": B.groups,
+                   "autotuned_elems_per_thread": [list(e) for e in gct.batch_get_pass_elems(B, dt)]},
         "phase_ms": {"gram_build": round(float(np.median(ph[:, 0])), 3),
                      "gram_spectrum": round(float(np.median(ph[:, 1])), 3),
                      "cg_solve": round(float(np.median(ph[:, 2])), 3),
@@ -264,10 +264,15 @@ def pmc_summarize(fetch_dir: str, write_dir: str):
 
     fetch, copy_f = load(fetch_dir, "FETCH_SIZE")
     write, copy_w = load(write_dir, "WRITE_SIZE")
-    elems = {int(k.split(",")[-1].strip(" >")) for k in fetch}
-    if len(elems) != 1:
-        raise SystemExit(f"expected one transform tiling in the run, found {sorted(elems)}")
-    E = elems.pop()
+    def elems_of(tag):
+        e = {int(k.split(",")[-1].strip(" >")) for k in fetch if tag in k}
+        if len(e) != 1:
+            raise SystemExit(f"expected one tiling of {tag} in the run, found {sorted(e)}")
+        return e.pop()
+
+    E = elems_key(elems_of("k_rows_fwd<"), elems_of("k_cols<"))
+    if elems_of("k_rows_inv<") != elems_of("k_rows_fwd<"):
+        raise SystemExit("row passes with different tilings")
     sf, sw = PMC_COPY_BYTES / (copy_f * 1024), PMC_COPY_BYTES / (copy_w * 1024)
     fb = sum(fetch.values()) * 1024 * sf
     wb = sum(write.values()) * 1024 * sw
@@ -285,7 +290,7 @@ def pmc_summarize(fetch_dir: str, write_dir: str):
     if d.get("apply_source_sha") != apply_source_sha():
         d = {}
     d.update({"workload": WORKLOAD, "apply_source_sha": apply_source_sha()})
-    d.setdefault("by_fft_elems", {})[str(E)] = entry
+    d.setdefault("by_fft_elems", {})[E] = entry
     with open(PMC_FILE, "w") as fh:
         json.dump(d, fh, indent=1)
     print(f"elements per thread {E}: scale fetch {sf:.4f}, write {sw:.4f}")
@@ -297,7 +302,13 @@ def pmc_summarize(fetch_dir: str, write_dir: str):
     print(f"per apply: {fb / 1e6:.2f} MB fetched + {wb / 1e6:.2f} MB written = {(fb + wb) / 1e6:.2f} MB")
 
 
-def measured_traffic(fft_elems: int):
+def elems_key(rows: int, cols: int) -> str:
+    """Name of a transform tiling: "E" when every pass uses E elements per
+    thread, else "ROWS,COLS"."""
+    return str(rows) if rows == cols else f"{rows},{cols}"
+
+
+def measured_traffic(fft_elems: str):
     """HBM bytes per apply from the committed counter runs, if they were taken
     on these kernel sources with this tiling; else None."""
     try:
@@ -307,7 +318,7 @@ def measured_traffic(fft_elems: int):
         return None
     if d.get("apply_source_sha") != apply_source_sha():
         return None
-    e = d.get("by_fft_elems", {}).get(str(fft_elems))
+    e = d.get("by_fft_elems", {}).get(fft_elems)
     return e.get("hbm_bytes_per_apply") if e else None
 
 
@@ -412,10 +423,11 @@ def main():
         print(json.dumps({"phase_probe": True, "gram_build": 4, "backproject": 3}))
         return
     if args.fft_elems:
-        gct.plan_set_fft_elems(plan, args.fft_elems)
-        fft_elems = args.fft_elems
+        er, ec = (list(map(int, args.fft_elems.split(","))) * 2)[:2]
+        gct.plan_set_pass_elems(plan, er, ec)
+        fft_elems = elems_key(er, ec)
     else:
-        fft_elems = gct.plan_autotune(plan, Ghat, ws_cg, reps=20)
+        fft_elems = elems_key(*gct.plan_autotune(plan, Ghat, ws_cg, reps=20))
     torch.cuda.synchronize()
     if args.pmc_probe:
         return pmc_probe(gct, plan, Ghat, c_apply, y, ws_apply, fft_elems)

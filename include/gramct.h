@@ -160,13 +160,15 @@ int gct_forward_project(const gct_plan *plan, gct_dtype dtype, const void *c, vo
 /* Autotuner of the Gram-filtering passes (the FFT realisation of Sec. 4's
  * Toeplitz-block-Toeplitz product): times one apply for each candidate
  * number of elements per thread of the transforms (16, 8 or 4 where the
- * transform size allows; fewer elements mean more threads per transform)
- * and keeps the fastest in the plan for `dtype`; separately for the fused
+ * transform size allows; fewer elements mean more threads per transform),
+ * chosen independently for the two row passes and for the column pass, and
+ * keeps the fastest pair in the plan for `dtype`; separately for the fused
  * CG passes of gct_cg_solve, timed on a trial solve.  Results of later applies
  * and solves agree with the untuned ones to rounding.  ws must be a CG
  * workspace of the plan (gct_workspace_size(plan, GCT_OP_CG, dtype)); its
  * contents are overwritten.  reps: timed repetitions per candidate (<= 0:
- * 3).  chosen: optional HOST int receiving the choice for the apply passes.  Changes the plan:
+ * 3).  chosen: optional HOST int receiving the choice for the row passes of
+ * the apply (gct_plan_get_pass_elems reports all four).  Changes the plan:
  * do not call while other streams use it.  Blocks the host. */
 int gct_plan_autotune(gct_plan *plan, gct_dtype dtype, const void *Ghat, void *ws, int32_t reps,
                       int32_t *chosen, void *stream);
@@ -176,6 +178,15 @@ int gct_plan_autotune(gct_plan *plan, gct_dtype dtype, const void *Ghat, void *w
  * transform size allows; otherwise GCT_EINVAL); elems_per_thread = 0
  * restores the default.  Changes the plan like gct_plan_autotune. */
 int gct_plan_set_fft_elems(gct_plan *plan, gct_dtype dtype, int32_t elems_per_thread);
+
+/* As gct_plan_set_fft_elems with separate values for the two row passes
+ * (rows_elems) and the column pass (cols_elems), for the apply and the fused
+ * CG passes alike; 0 selects the default for that pass. */
+int gct_plan_set_pass_elems(gct_plan *plan, gct_dtype dtype, int32_t rows_elems, int32_t cols_elems);
+
+/* The plan's current elements per thread for `dtype`: out (HOST, 4 ints) =
+ * {apply row passes, apply column pass, CG row passes, CG column pass}. */
+int gct_plan_get_pass_elems(const gct_plan *plan, gct_dtype dtype, int32_t *out);
 
 /* Result of gct_cg_solve (host struct). */
 typedef struct {
@@ -278,12 +289,17 @@ int gct_batch_cg_solve(const gct_batch *batch, gct_dtype dtype, const void *Ghat
 
 /* Autotuner: for each FFT size of the batch, times the batched apply with
  * each candidate number of elements per thread of the transforms (the work
- * tile of one thread) and keeps the fastest for `dtype`.  ws must be a CG
- * workspace of the batch; reps timed repetitions per candidate (<= 0: 3).
- * chosen: optional HOST array of `groups` entries receiving the choice.
+ * tile of one thread), for the row passes and for the column pass in turn,
+ * and keeps the fastest for `dtype`.  ws must be a CG workspace of the
+ * batch; reps timed repetitions per candidate (<= 0: 3).  chosen: optional
+ * HOST array of `groups` entries receiving the choice for the row passes.
  * Blocks the host. */
 int gct_batch_autotune(gct_batch *batch, gct_dtype dtype, const void *Ghat, void *ws,
                        int32_t reps, int32_t *chosen, void *stream);
+
+/* The batch's current elements per thread for `dtype`: out (HOST, 2 x groups
+ * ints) = {row passes, column pass} for each FFT size in increasing order. */
+int gct_batch_get_pass_elems(const gct_batch *batch, gct_dtype dtype, int32_t *out);
 
 /* Thread-local description of the last error (never NULL). */
 const char *gct_last_error(void);

@@ -440,7 +440,8 @@ using namespace gct;
 // ---------------------------------------------------------------------------
 struct BatchGroup {
     int logP;
-    int E[2];  // tuned elements per thread, [f32, f64]
+    int E[2];   // tuned elements per thread of the row passes, [f32, f64]
+    int Ec[2];  // and of the column pass
     int2 *rows = nullptr, *cols = nullptr, *srows = nullptr, *scols = nullptr;
     int nrows = 0, ncols = 0, nsrows = 0, nscols = 0;
     // two row pairs per block (FP32 row passes of 1024- and 2048-point
@@ -557,7 +558,7 @@ hipError_t batch_apply_passes(const gct_batch *b, const T *Ghat, const T *src, T
         GCT_LAUNCH_B(kb_rows_fwd, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, src, W1, st, pupd);
     }
     for (const auto &g : b->groups) {
-        const int E = g.E[dti<T>()];
+        const int E = g.Ec[dti<T>()];
         const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
         GCT_LAUNCH_B(kb_cols, T, g.logP, E, dim3(g.ncols), lds, s, g.cols, sl, W1, W2, Ghat, st);
     }
@@ -769,7 +770,7 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         BatchGroup g;
         g.logP = kv.first;
         const int P = 1 << g.logP;
-        g.E[0] = g.E[1] = fft_elems(P);
+        g.E[0] = g.E[1] = g.Ec[0] = g.Ec[1] = fft_elems(P);
         std::vector<int2> rows, cols, srows, scols, rows2;
         bool pair2 = g.logP == 10 || g.logP == 11;
         for (int i : kv.second) {
@@ -916,6 +917,18 @@ int gct_batch_cg_solve(const gct_batch *b, gct_dtype dt, const void *Ghat, const
     return rc;
 }
 
+int gct_batch_get_pass_elems(const gct_batch *b, gct_dtype dt, int32_t *out)
+{
+    CHECK_BATCH_DT(b, dt);
+    if (!out) return fail(GCT_EINVAL, "NULL output");
+    const int t = dt == GCT_F32 ? 0 : 1;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        out[2 * gi] = b->groups[gi].E[t];
+        out[2 * gi + 1] = b->groups[gi].Ec[t];
+    }
+    return GCT_OK;
+}
+
 int gct_batch_autotune(gct_batch *b, gct_dtype dt, const void *Ghat, void *ws, int32_t reps,
                        int32_t *chosen, void *stream)
 {
@@ -933,16 +946,18 @@ int gct_batch_autotune(gct_batch *b, gct_dtype dt, const void *Ghat, void *ws, i
     hipEvent_t e0, e1;
     B_TRY(hipEventCreate(&e0));
     B_TRY(hipEventCreate(&e1));
-    // tune one group at a time, the others keep their current choice; each
-    // candidate is timed on the whole batched apply
-    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
-        BatchGroup &g = b->groups[gi];
+    // tune one group and one pass kind (row passes, then the column pass) at
+    // a time, everything else keeping its current choice; each candidate is
+    // timed on the whole batched apply
+    for (int q = 0; q < 2 * (int)b->groups.size(); ++q) {
+        BatchGroup &g = b->groups[q / 2];
+        int &Eq = q % 2 == 0 ? g.E[t] : g.Ec[t];
         const int P = 1 << g.logP, E0 = fft_elems(P);
-        int best = g.E[t];
+        int best = Eq;
         float best_ms = 1e30f;
         for (int E : {E0, E0 / 2}) {
             if (E < 4 || !e_ok(g.logP, E)) continue;
-            g.E[t] = E;
+            Eq = E;
             for (int rep = 0; rep <= reps; ++rep) {
                 if (rep == 1) B_TRY(hipEventRecord(e0, s));
                 hipError_t e = t == 0 ? batch_apply_passes<float>(b, (const float *)Ghat, (const float *)src,
@@ -962,9 +977,10 @@ int gct_batch_autotune(gct_batch *b, gct_dtype dt, const void *Ghat, void *ws, i
                 best = E;
             }
         }
-        g.E[t] = best;
-        if (chosen) chosen[gi] = best;
+        Eq = best;
     }
+    if (chosen)
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) chosen[gi] = b->groups[gi].E[t];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     // captured CG graphs used the old shapes

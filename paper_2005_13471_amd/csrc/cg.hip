@@ -416,12 +416,15 @@ int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chose
     hipEvent_t e0, e1;
     GCT_TRY(hipEventCreate(&e0));
     GCT_TRY(hipEventCreate(&e1));
-    int best = p->fft_e[t];
+    // every (row passes, column pass) pair of candidates
+    int best = p->fft_e[t], best_c = p->fft_ec[t];
     float best_ms = 1e30f;
     hipError_t err = hipSuccess;
-    for (int E : {16, 8, 4}) {
-        if (!apply_e_ok(p->logP, E)) continue;
+    for (int pr = 0; pr < 9; ++pr) {
+        const int E = 16 >> (pr / 3), Ec = 16 >> (pr % 3);
+        if (!apply_e_ok(p->logP, E) || !apply_e_ok(p->logP, Ec)) continue;
         p->fft_e[t] = E;
+        p->fft_ec[t] = Ec;
         for (int rep = 0; rep <= reps && err == hipSuccess; ++rep) {
             if (rep == 1) err = hipEventRecord(e0, s);
             if (err == hipSuccess)
@@ -435,12 +438,14 @@ int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chose
         if (ms < best_ms) {
             best_ms = ms;
             best = E;
+            best_c = Ec;
         }
     }
     p->fft_e[t] = best;
+    p->fft_ec[t] = best_c;
     // the fused CG passes: a trial solve of A x = 1 that never meets its
     // stopping rule (rtol = 0), timed over `reps` iterations per candidate
-    int best_cg = p->cg_e[t];
+    int best_cg = p->cg_e[t], best_cgc = p->cg_ec[t];
     if (err == hipSuccess) {
         T *sv = reinterpret_cast<T *>(w + L.sv), *pv = reinterpret_cast<T *>(w + L.p);
         T *xt = reinterpret_cast<T *>(w + L.xt);
@@ -449,9 +454,11 @@ int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chose
         CGState *st = reinterpret_cast<CGState *>(w + L.st);
         const size_t n = (size_t)p->N * p->N;
         float best_cg_ms = 1e30f;
-        for (int E : {16, 8, 4}) {
-            if (!apply_e_ok(p->logP, E) || err != hipSuccess) continue;
+        for (int pr = 0; pr < 9; ++pr) {
+            const int E = 16 >> (pr / 3), Ec = 16 >> (pr % 3);
+            if (!apply_e_ok(p->logP, E) || !apply_e_ok(p->logP, Ec) || err != hipSuccess) continue;
             p->cg_e[t] = E;
+            p->cg_ec[t] = Ec;
             hipLaunchKernelGGL(k_fill_one<T>, dim3(VBLK), dim3(256), 0, s, sv, n);
             hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, (const T *)sv, xt, src, pv, nullptr, n,
                                part, part2);
@@ -468,10 +475,12 @@ int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chose
             if (err == hipSuccess && ms < best_cg_ms) {
                 best_cg_ms = ms;
                 best_cg = E;
+                best_cgc = Ec;
             }
         }
     }
     p->cg_e[t] = best_cg;
+    p->cg_ec[t] = best_cgc;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (err != hipSuccess) return check_hip(err, "plan autotune");

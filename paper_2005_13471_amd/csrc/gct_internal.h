@@ -151,8 +151,10 @@ struct gct_plan {
     double lx1, lx2, ly, zeta;
     int32_t P, logP;
     double gram_hmax;  // largest support half-width of A_theta over the angles
-    int32_t fft_e[2];  // elements per thread of the apply passes, [F32, F64]
-    int32_t cg_e[2];   // elements per thread of the fused CG passes
+    // elements per thread of the transforms, [F32, F64]: the row passes and
+    // the column pass of an apply, and the same for the fused CG passes
+    int32_t fft_e[2], fft_ec[2];
+    int32_t cg_e[2], cg_ec[2];
     gct::BPDims bp;
     gct::DeviceTables dev;
     int device;

@@ -401,15 +401,15 @@ hipError_t launch_apply_passes(const gct_plan *p, const T *Ghat, const T *src, T
                                const T *dotv, double *partial)
 {
     const int N = p->N, P = p->P, logP = p->logP;
-    const int E = p->fft_e[sizeof(T) == 4 ? 0 : 1];
-    const size_t lds = fft_lds_bytes<T>(P, E);
+    const int t = sizeof(T) == 4 ? 0 : 1, E = p->fft_e[t], Ec = p->fft_ec[t];
+    const size_t lds = fft_lds_bytes<T>(P, E), ldsc = fft_lds_bytes<T>(P, Ec);
     const size_t w1 = align256((size_t)(P / 2 + 1) * N * 2 * sizeof(T));
     C2<T> *W1 = reinterpret_cast<C2<T> *>(ws);
     C2<T> *W2 = reinterpret_cast<C2<T> *>(reinterpret_cast<char *>(ws) + w1);
     const C2<T> *tw = twiddles<T>(p);
     const dim3 rgrid((N + 1) / 2), cgrid(P / 2 + 1);
     GCT_LAUNCH_FFTE(k_rows_fwd, T, logP, E, rgrid, lds, s, src, W1, N, tw, status, pupd, beta);
-    GCT_LAUNCH_FFTE(k_cols, T, logP, E, cgrid, lds, s, W1, W2, Ghat, N, tw, status);
+    GCT_LAUNCH_FFTE(k_cols, T, logP, Ec, cgrid, ldsc, s, W1, W2, Ghat, N, tw, status);
     GCT_LAUNCH_FFTE(k_rows_inv, T, logP, E, rgrid, lds, s, W2, y, N, tw, status, dotv, partial);
     return hipGetLastError();
 }
@@ -419,8 +419,8 @@ hipError_t launch_cgf_iteration(const gct_plan *p, const T *Ghat, T *x, T *r, T 
                                 double *part, CGState *st, int par, hipStream_t s)
 {
     const int N = p->N, P = p->P, logP = p->logP;
-    const int E = p->cg_e[sizeof(T) == 4 ? 0 : 1];
-    const size_t lds = fft_lds_bytes<T>(P, E);
+    const int t = sizeof(T) == 4 ? 0 : 1, E = p->cg_e[t], Ec = p->cg_ec[t];
+    const size_t lds = fft_lds_bytes<T>(P, E), ldsc = fft_lds_bytes<T>(P, Ec);
     const size_t w1 = align256((size_t)(P / 2 + 1) * N * 2 * sizeof(T));
     C2<T> *W1 = reinterpret_cast<C2<T> *>(ws);
     C2<T> *W2 = reinterpret_cast<C2<T> *>(reinterpret_cast<char *>(ws) + w1);
@@ -429,7 +429,7 @@ hipError_t launch_cgf_iteration(const gct_plan *p, const T *Ghat, T *x, T *r, T 
     const dim3 rgrid(np), cgrid(P / 2 + 1);
     GCT_LAUNCH_FFTE(k_cgf_rows_fwd, T, logP, E, rgrid, lds, s, x, r, pv, sv, (const T *)w, W1, N, tw, st,
                     (const double *)part, np, par);
-    GCT_LAUNCH_FFTE(k_cgf_cols, T, logP, E, cgrid, lds, s, (const C2<T> *)W1, W2, Ghat, N, tw,
+    GCT_LAUNCH_FFTE(k_cgf_cols, T, logP, Ec, cgrid, ldsc, s, (const C2<T> *)W1, W2, Ghat, N, tw,
                     (const CGState *)st, par);
     GCT_LAUNCH_FFTE(k_cgf_rows_inv, T, logP, E, rgrid, lds, s, (const C2<T> *)W2, w, (const T *)r, N, tw,
                     (const CGState *)st, part, np, par);

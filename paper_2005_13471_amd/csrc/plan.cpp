@@ -488,7 +488,7 @@ int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
         p->logP = logP;
         // elements per thread of the apply passes until gct_plan_autotune
         p->fft_e[0] = p->fft_e[1] = P >= 1024 ? 16 : (P == 512 ? 8 : 4);
-        p->cg_e[0] = p->cg_e[1] = p->fft_e[0];
+        p->fft_ec[0] = p->fft_ec[1] = p->cg_e[0] = p->cg_e[1] = p->cg_ec[0] = p->cg_ec[1] = p->fft_e[0];
         if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
         rc = build_plan(geom, p);
         if (rc) {
@@ -682,18 +682,38 @@ int gct_sd_solve(const gct_plan *p, gct_dtype dt, const void *Ghat, const void *
     return rc;
 }
 
-int gct_plan_set_fft_elems(gct_plan *p, gct_dtype dt, int32_t E)
+int gct_plan_set_pass_elems(gct_plan *p, gct_dtype dt, int32_t Er, int32_t Ec)
 {
     CHECK_PLAN_DT(p, dt);
-    if (E == 0) E = p->P >= 1024 ? 16 : (p->P == 512 ? 8 : 4);
-    if (!apply_e_ok(p->logP, E)) return fail(GCT_EINVAL, "elements per thread not available for this transform size");
+    const int E0 = p->P >= 1024 ? 16 : (p->P == 512 ? 8 : 4);
+    if (Er == 0) Er = E0;
+    if (Ec == 0) Ec = E0;
+    if (!apply_e_ok(p->logP, Er) || !apply_e_ok(p->logP, Ec))
+        return fail(GCT_EINVAL, "elements per thread not available for this transform size");
     const int t = dt == GCT_F32 ? 0 : 1;
-    if (p->fft_e[t] != E || p->cg_e[t] != E) {
-        p->fft_e[t] = E;
-        p->cg_e[t] = E;
+    if (p->fft_e[t] != Er || p->fft_ec[t] != Ec || p->cg_e[t] != Er || p->cg_ec[t] != Ec) {
+        p->fft_e[t] = p->cg_e[t] = Er;
+        p->fft_ec[t] = p->cg_ec[t] = Ec;
         for (auto &g : p->cg_graphs) (void)hipGraphExecDestroy(g.exec);
         p->cg_graphs.clear();
     }
+    return GCT_OK;
+}
+
+int gct_plan_set_fft_elems(gct_plan *p, gct_dtype dt, int32_t E)
+{
+    return gct_plan_set_pass_elems(p, dt, E, E);
+}
+
+int gct_plan_get_pass_elems(const gct_plan *p, gct_dtype dt, int32_t *out)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!out) return fail(GCT_EINVAL, "NULL output");
+    const int t = dt == GCT_F32 ? 0 : 1;
+    out[0] = p->fft_e[t];
+    out[1] = p->fft_ec[t];
+    out[2] = p->cg_e[t];
+    out[3] = p->cg_ec[t];
     return GCT_OK;
 }
 

@@ -92,6 +92,8 @@ def _load():
     L.gct_sd_solve.argtypes = L.gct_cg_solve.argtypes
     L.gct_plan_autotune.argtypes = [vp, ctypes.c_int, vp, vp, i32, ctypes.POINTER(i32), vp]
     L.gct_plan_set_fft_elems.argtypes = [vp, ctypes.c_int, i32]
+    L.gct_plan_set_pass_elems.argtypes = [vp, ctypes.c_int, i32, i32]
+    L.gct_plan_get_pass_elems.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32)]
     L.gct_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
     L.gct_batch_destroy.argtypes = [vp]
     L.gct_batch_get_info.argtypes = [vp, ctypes.POINTER(_BatchInfo), ctypes.c_void_p,
@@ -104,6 +106,7 @@ def _load():
     L.gct_batch_cg_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp, dbl, i32, i32,
                                      ctypes.POINTER(_CGResult), vp, vp]
     L.gct_batch_autotune.argtypes = [vp, ctypes.c_int, vp, vp, i32, ctypes.POINTER(i32), vp]
+    L.gct_batch_get_pass_elems.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32)]
     L.gct_host_boxspline_eval.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, dbl,
                                           ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_double)]
@@ -301,19 +304,33 @@ def _solve(fn, plan, Ghat, b, x, ws, use_x0, rtol, max_iter, check_every, raise_
                     res.fell_back, hist[: res.iters + 1].copy())
 
 
-def plan_autotune(plan: Plan, Ghat: torch.Tensor, ws: torch.Tensor, reps: int = 3) -> int:
+def plan_autotune(plan: Plan, Ghat: torch.Tensor, ws: torch.Tensor, reps: int = 3):
     """Pick the fastest elements-per-thread of the apply passes for Ghat's
-    dtype; returns the choice.  ws: a CG workspace of the plan."""
+    dtype; returns the apply's choice as (row passes, column pass).  ws: a CG
+    workspace of the plan."""
     ch = ctypes.c_int32(0)
     _check(lib.gct_plan_autotune(plan.handle, _dt(Ghat), _ptr(Ghat, plan.info.spectrum_elems),
                                  _ptr(ws, plan.workspace_size(OP_CG, Ghat.dtype)), int(reps),
                                  ctypes.byref(ch), _stream()))
-    return int(ch.value)
+    return plan_get_pass_elems(plan, Ghat.dtype)[:2]
 
 
 def plan_set_fft_elems(plan: Plan, elems: int, dtype=torch.float32):
-    """Force the elements per thread of the apply passes (0: default)."""
+    """Force the elements per thread of every transform pass (0: default)."""
     _check(lib.gct_plan_set_fft_elems(plan.handle, F32 if dtype == torch.float32 else F64, int(elems)))
+
+
+def plan_set_pass_elems(plan: Plan, rows: int, cols: int, dtype=torch.float32):
+    """Force the elements per thread of the row passes and of the column
+    pass separately (0: default)."""
+    _check(lib.gct_plan_set_pass_elems(plan.handle, F32 if dtype == torch.float32 else F64, int(rows), int(cols)))
+
+
+def plan_get_pass_elems(plan: Plan, dtype=torch.float32):
+    """(apply rows, apply cols, CG rows, CG cols) elements per thread."""
+    out = (ctypes.c_int32 * 4)()
+    _check(lib.gct_plan_get_pass_elems(plan.handle, F32 if dtype == torch.float32 else F64, out))
+    return tuple(int(v) for v in out)
 
 
 # ---------------------------------------------------------------------------
@@ -403,6 +420,13 @@ def batch_autotune(batch: Batch, Ghat: torch.Tensor, ws: torch.Tensor, reps: int
                                   _ptr(ws, batch.workspace_size(OP_CG, Ghat.dtype)), int(reps),
                                   chosen, _stream()))
     return list(chosen)
+
+
+def batch_get_pass_elems(batch: Batch, dtype=torch.float32) -> list:
+    """[(row passes, column pass)] elements per thread per FFT size."""
+    out = (ctypes.c_int32 * (2 * batch.groups))()
+    _check(lib.gct_batch_get_pass_elems(batch.handle, F32 if dtype == torch.float32 else F64, out))
+    return [(int(out[2 * i]), int(out[2 * i + 1])) for i in range(batch.groups)]
 
 
 # C-ABI names

@@ -67,6 +67,18 @@ def test_solvers_reject_null_plan_without_gpu(gct, name):
     assert raw.gct_last_error()
 
 
+def test_pass_elems_reject_null_plan_without_gpu(gct):
+    """Setting and reading the transform tilings validate the plan handle
+    and the output pointer on the host."""
+    raw = ctypes.CDLL(gct.LIB_PATH)
+    out = (ctypes.c_int32 * 4)(-1, -1, -1, -1)
+    raw.gct_plan_get_pass_elems.restype = ctypes.c_int
+    assert raw.gct_plan_get_pass_elems(None, gct.F32, out) == gct.GCT_EINVAL
+    assert list(out) == [-1] * 4
+    raw.gct_plan_set_pass_elems.restype = ctypes.c_int
+    assert raw.gct_plan_set_pass_elems(None, gct.F32, 4, 8) == gct.GCT_EINVAL
+
+
 @pytest.mark.parametrize("zeta", [0.0, 0.3, 1.0])
 @pytest.mark.parametrize("theta", [0.37, 1.1, np.pi / 1800, np.pi / 2 - 1e-3])
 def test_host_boxspline_matches_oracle_gram_and_footprint(gct, theta, zeta):

@@ -143,8 +143,10 @@ def test_batch_autotune_keeps_results(batch_setup):
     Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")
     gct.batch_gram_spectrum(B, G, Ghat, B.workspace(gct.OP_GRAM_SPECTRUM, dt))
     chosen = gct.batch_autotune(B, Ghat, B.workspace(gct.OP_CG, dt), reps=2)
-    say("autotune choice per FFT size", chosen)
+    both = gct.batch_get_pass_elems(B, dt)
+    say("autotune choice per FFT size (rows, cols)", both)
     assert len(chosen) == B.groups and all(e in (4, 8, 16) for e in chosen)
+    assert [r for r, _ in both] == chosen and all(c in (4, 8, 16) for _, c in both)
     cs = [inputs.uniform_coeffs(N, 4000 + i) for i, (N, _, _) in enumerate(SLICES)]
     y = torch.empty(B.image_elems, dtype=dt, device="cuda")
     gct.batch_gram_apply(B, Ghat, _packed(B, cs, dt), y, B.workspace(gct.OP_GRAM_APPLY, dt))

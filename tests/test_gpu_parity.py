@@ -170,13 +170,19 @@ CASE_P512 = Case(200, 40, zeta=0.5)    # FFT size 512: 8 or 4
 
 @pytest.mark.parametrize("dt", DTYPES)
 @pytest.mark.parametrize("case,elems", [(CASE_P1024, 16), (CASE_P1024, 8), (CASE_P1024, 4),
-                                        (CASE_P512, 8), (CASE_P512, 4)], ids=repr)
+                                        (CASE_P512, 8), (CASE_P512, 4), (CASE_P1024, (4, 8)),
+                                        (CASE_P1024, (16, 4)), (CASE_P512, (4, 8))], ids=repr)
 def test_gram_apply_every_transform_tiling(gct, case, elems, dt):
-    """Each elements-per-thread variant of the apply passes against the
-    oracle's direct sum on sampled outputs."""
+    """Each elements-per-thread variant of the apply passes (one value for
+    every pass, or separate ones for the row passes and the column pass)
+    against the oracle's direct sum on sampled outputs."""
     say("gram_apply tiling", case, elems, dt)
     P = case.plan(gct)
-    gct.plan_set_fft_elems(P, elems, dt)
+    if isinstance(elems, tuple):
+        gct.plan_set_pass_elems(P, *elems, dtype=dt)
+        assert gct.plan_get_pass_elems(P, dt) == elems * 2
+    else:
+        gct.plan_set_fft_elems(P, elems, dt)
     G = _gram_oracle_cached(case)
     c = inputs.uniform_coeffs(case.N, 2100)
     got = _apply_gpu_plan(gct, P, case, dt, G, c).reshape(-1)
@@ -202,13 +208,23 @@ def test_plan_autotune_then_cg(gct):
     x = torch.empty_like(b)
     r0 = gct.cg_solve(P, Ghat, b, x, ws, rtol=1e-4, max_iter=500)
     E = gct.plan_autotune(P, Ghat, ws, reps=3)
-    say("  autotune chose", E, "default iters", r0.iters)
-    assert E in (16, 8, 4)
+    say("  autotune chose", gct.plan_get_pass_elems(P, dt), "default iters", r0.iters)
+    assert len(E) == 2 and all(e in (16, 8, 4) for e in gct.plan_get_pass_elems(P, dt))
     r1 = gct.cg_solve(P, Ghat, b, x, ws, rtol=1e-4, max_iter=500)
     assert r0.status == gct.GCT_OK and r1.status == gct.GCT_OK
     assert r1.rel_res_true <= 1.1e-4 and abs(r1.iters - r0.iters) <= max(3, r0.iters // 10)
+    # the fused CG passes with different row and column tilings
+    for rows, cols in ((4, 8), (16, 4)):
+        gct.plan_set_pass_elems(P, rows, cols, dt)
+        r2 = gct.cg_solve(P, Ghat, b, x, ws, rtol=1e-4, max_iter=500)
+        say("  rows/cols", rows, cols, "iters", r2.iters)
+        assert r2.status == gct.GCT_OK and r2.rel_res_true <= 1.1e-4
+        assert abs(r2.iters - r0.iters) <= max(3, r0.iters // 10)
     with pytest.raises(gct.GramctError) as e:
         gct.plan_set_fft_elems(P, 2)
+    assert e.value.code == gct.GCT_EINVAL
+    with pytest.raises(gct.GramctError) as e:
+        gct.plan_set_pass_elems(P, 4, 2)
     assert e.value.code == gct.GCT_EINVAL
 
 

@@ -496,7 +496,8 @@ def main():
         "config": {"workload": args.workload, "N": N, "n_angles": n, "M": M, "lambda_y": ly,
                    "zeta_blur": zeta, "fft_size": P, "ellipses": cfg["ellipses"],
                    "noise": cfg["eta"], "cg_rtol": 1e-4, "apply_burst": APPLY_BURST,
-                   "apply_graph": APPLY_GRAPH, "fft_elems_per_thread": fft_elems},
+                   "apply_graph": APPLY_GRAPH, "fft_elems_per_thread": fft_elems,
+                   "cg_elems_per_thread": elems_key(*gct.plan_get_pass_elems(plan)[2:])},
         "phase_ms": {"gram_build": round(float(np.median(ph[:, 0])), 4),
                      "gram_spectrum": round(float(np.median(ph[:, 1])), 4),
                      "backproject": round(float(np.median(ph[:, 2])), 4),

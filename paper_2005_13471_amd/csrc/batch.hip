@@ -45,11 +45,14 @@ kb_rows_fwd(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    // data first, then the twiddles: their latencies overlap
+    C2<T> v[E];
+    rows_fwd_load<T, LOGP, E>(2 * m.y, src + d.img, d.N, pupd ? pupd + d.img : nullptr,
+                              pupd ? (T)st[m.x].beta : T(0), v);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
-    body_rows_fwd<T, LOGP, E>(2 * m.y, src + d.img, W1 + d.w, d.N, x, tws,
-                              pupd ? pupd + d.img : nullptr, pupd ? (T)st[m.x].beta : T(0));
+    rows_fwd_regs<T, LOGP, E>(2 * m.y, v, W1 + d.w, d.N, x, tws);
 }
 
 // Two row pairs per block (rows 4j .. 4j+3 of a slice), for the long
@@ -74,7 +77,7 @@ kb_rows_fwd2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     C2<T> *xs = reinterpret_cast<C2<T> *>(smem_raw);
     C2<T> *x = xs + grp * P;
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P)>(xs + 2 * P, reinterpret_cast<const C2<T> *>(d.tw), hP);
+        stage_twiddles<T, twiddles_in_lds<T>(P), hP, 2 * G>(xs + 2 * P, reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     const int ra = 4 * m.y + 2 * grp, rb = ra + 1;
     const T *sr = src + d.img;
@@ -118,7 +121,7 @@ kb_rows_fwd2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
 
 // Inverse rows for two row pairs per block: the block reads the four rows'
 // spectra column by column (32-byte runs, pair fastest) into LDS, then each
-// group transforms its pair as rows_inv_regs; FP64 partial dot of the block
+// group transforms its pair as the single-pair inverse row pass; FP64 partial dot of the block
 // in the slot of its first pair (the second pair's slot holds 0).
 template <typename T, int LOGP, int E>
 __global__ void __launch_bounds__(512)
@@ -135,7 +138,7 @@ kb_rows_inv2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *xs = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P)>(xs + 2 * XS, reinterpret_cast<const C2<T> *>(d.tw), hP);
+        stage_twiddles<T, twiddles_in_lds<T>(P), hP, 2 * G>(xs + 2 * XS, reinterpret_cast<const C2<T> *>(d.tw));
     // stage: group g2's area holds (Ya, Yb) of column k at 2k, 2k + 1
     const C2<T> *in = W2 + d.w;
     for (int i = threadIdx.x; i < 2 * (hP + 1); i += 2 * G) {
@@ -200,10 +203,13 @@ kb_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    C2<T> v[E];
+    T gs[E];
+    cols_load<T, LOGP, E>(m.y, W1 + d.w, Ghat + d.spec, d.N, v, gs);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
-    body_cols<T, LOGP, E>(m.y, W1 + d.w, W2 + d.w, Ghat + d.spec, d.N, x, tws);
+    cols_regs<T, LOGP, E>(m.y, v, gs, W2 + d.w, d.N, x, tws);
 }
 
 template <typename T, int LOGP, int E>
@@ -218,11 +224,13 @@ kb_rows_inv(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
+    C2<T> v[E];
+    rows_inv_load<T, LOGP, E>(2 * m.y, W2 + d.w, d.N, v);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
-    const double acc = body_rows_inv<T, LOGP, E>(2 * m.y, W2 + d.w, y + d.img, d.N, x, tws,
-                                                 dotv ? dotv + d.img : nullptr);
+    fft_passes<T, E, P, 1, true, true>(v, x, threadIdx.x, tws);
+    const double acc = rows_inv_store<T, LOGP, E>(2 * m.y, v, y + d.img, d.N, dotv ? dotv + d.img : nullptr);
     if (partial) {
         const double s = block_sum_lds(acc, reinterpret_cast<double *>(smem_raw));
         if (threadIdx.x == 0) partial[d.rpart + m.y] = s;
@@ -240,7 +248,7 @@ kb_spec_rows(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     // R of a slice uses (P/2+1) P complex, i.e. 2 d.spec reals' worth of offset
     body_spec_rows<T, LOGP, E>(m.y, G + d.gram, R + d.spec, d.N, x, tws);
@@ -257,7 +265,7 @@ kb_spec_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, reinterpret_cast<const C2<T> *>(d.tw), P / 2);
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     body_spec_cols<T, LOGP, E>(m.y, R + d.spec, Ghat + d.spec, x, tws,
                                T(1.0 / ((double)P * (double)P)));

@@ -20,10 +20,6 @@
 
 namespace gct {
 
-template <typename T>
-hipError_t launch_apply_passes(const gct_plan *p, const T *Ghat, const T *src, T *y, void *ws,
-                               hipStream_t s, const int64_t *status, T *pupd, const double *beta,
-                               const T *dotv, double *partial);
 int apply_row_blocks(const gct_plan *p, size_t elem);
 
 constexpr int VBLK = 256;  // blocks of the vector kernels (fixed: deterministic reductions)
@@ -277,7 +273,7 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
 
     // start: r_0 (from x_0 when given), then on the device the fallback to
     // zero when x_0 is no better; no host round trip before the iterations
-    if (use_x0) GCT_TRY(launch_apply_passes<T>(p, Ghat, x, Ap, aws, s, nullptr, nullptr, nullptr, nullptr, nullptr));
+    if (use_x0) GCT_TRY(launch_gram_apply<T>(p, Ghat, x, Ap, aws, s));
     hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, b, x, r, pv, use_x0 ? (const T *)Ap : nullptr,
                        n, part, part2);
     hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK, rtol * rtol,
@@ -383,8 +379,7 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
             for (int64_t k = kprev + 1; k <= hs.kring; ++k) hist[k] = rel(hs.ring[k % CG_RING]);
     }
     // true residual of the returned iterate
-    GCT_TRY(launch_apply_passes<T>(p, Ghat, x, Ap, aws, s, nullptr, nullptr, nullptr, nullptr,
-                                   nullptr));
+    GCT_TRY(launch_gram_apply<T>(p, Ghat, x, Ap, aws, s));
     hipLaunchKernelGGL(k_resid<T>, dim3(VBLK), dim3(256), 0, s, b, Ap, n, part);
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, VBLK, &st->pad);
     GCT_TRY(hipGetLastError());
@@ -401,41 +396,78 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     return res->status;
 }
 
-// Times one apply per candidate elements-per-thread E (apply_e_ok) on
-// zero input in the CG workspace's vectors and keeps the fastest for this
-// dtype; cached CG graphs (built with the old E) are dropped.
+// Times the apply passes for every candidate pair (row passes E, column
+// pass Ec; apply_e_ok) on zero input in the CG workspace's vectors and keeps
+// the fastest for this dtype; then the same for the fused CG passes, on
+// trial solves.  Each candidate's launches are captured as one graph and the
+// best of a few replays is kept, so host launch overhead and one-off noise
+// do not decide.  Cached CG graphs (built with the old tiling) are dropped.
 template <typename T>
 int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chosen, hipStream_t s)
 {
     const CGLayout L = cg_layout(p, sizeof(T));
     char *w = reinterpret_cast<char *>(ws);
     T *src = reinterpret_cast<T *>(w + L.r), *dst = reinterpret_cast<T *>(w + L.Ap);
+    T *sv = reinterpret_cast<T *>(w + L.sv), *pv = reinterpret_cast<T *>(w + L.p);
+    T *xt = reinterpret_cast<T *>(w + L.xt);
+    double *part = reinterpret_cast<double *>(w + L.part);
+    double *part2 = reinterpret_cast<double *>(w + L.part2);
+    CGState *st = reinterpret_cast<CGState *>(w + L.st);
     void *aws = w + L.apply;
     const int t = sizeof(T) == 4 ? 0 : 1;
-    GCT_TRY(hipMemsetAsync(src, 0, (size_t)p->N * p->N * sizeof(T), s));
+    const size_t n = (size_t)p->N * p->N;
+    reps += reps & 1;  // even: the CG parity slots line up across replays
+    hipStream_t cs = cg_capture_stream(p);
+    if (!cs) return fail(GCT_EHIP, "cannot create the capture stream");
+    GCT_TRY(hipMemsetAsync(src, 0, n * sizeof(T), s));
     hipEvent_t e0, e1;
     GCT_TRY(hipEventCreate(&e0));
     GCT_TRY(hipEventCreate(&e1));
-    // every (row passes, column pass) pair of candidates
+    hipError_t err = hipSuccess;
+    // best of three replays of the graph of `body` (launches on the capture
+    // stream); `prep` (launches on s) runs before each replay, untimed
+    auto time_graph = [&](auto body, auto prep) -> float {
+        float best = 1e30f;
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        err = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (err != hipSuccess) return best;
+        hipError_t eb = body(cs);
+        err = hipStreamEndCapture(cs, &g);
+        if (err == hipSuccess) err = eb;
+        if (err == hipSuccess) err = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        for (int rep = 0; rep < 4 && err == hipSuccess; ++rep) {
+            prep();
+            err = hipGetLastError();
+            if (err == hipSuccess) err = hipEventRecord(e0, s);
+            if (err == hipSuccess) err = hipGraphLaunch(ge, s);
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err == hipSuccess && rep > 0) best = std::min(best, ms);  // replay 0 warms up
+        }
+        if (ge) (void)hipGraphExecDestroy(ge);
+        return best;
+    };
     int best = p->fft_e[t], best_c = p->fft_ec[t];
     float best_ms = 1e30f;
-    hipError_t err = hipSuccess;
-    for (int pr = 0; pr < 9; ++pr) {
+    for (int pr = 0; pr < 9 && err == hipSuccess; ++pr) {
         const int E = 16 >> (pr / 3), Ec = 16 >> (pr % 3);
         if (!apply_e_ok(p->logP, E) || !apply_e_ok(p->logP, Ec)) continue;
         p->fft_e[t] = E;
         p->fft_ec[t] = Ec;
-        for (int rep = 0; rep <= reps && err == hipSuccess; ++rep) {
-            if (rep == 1) err = hipEventRecord(e0, s);
-            if (err == hipSuccess)
-                err = launch_apply_passes<T>(p, Ghat, src, dst, aws, s, nullptr, nullptr, nullptr, nullptr, nullptr);
-        }
-        if (err == hipSuccess) err = hipEventRecord(e1, s);
-        if (err == hipSuccess) err = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-        if (err != hipSuccess) break;
-        if (ms < best_ms) {
+        const float ms = time_graph(
+            [&](hipStream_t q) {
+                for (int r = 0; r < reps; ++r) {
+                    hipError_t e = launch_gram_apply<T>(p, Ghat, src, dst, aws, q);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
+            },
+            [] {});
+        if (err == hipSuccess && ms < best_ms) {
             best_ms = ms;
             best = E;
             best_c = Ec;
@@ -444,39 +476,33 @@ int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chose
     p->fft_e[t] = best;
     p->fft_ec[t] = best_c;
     // the fused CG passes: a trial solve of A x = 1 that never meets its
-    // stopping rule (rtol = 0), timed over `reps` iterations per candidate
+    // stopping rule (rtol = 0), restarted before each replay of `reps`
+    // iterations
     int best_cg = p->cg_e[t], best_cgc = p->cg_ec[t];
-    if (err == hipSuccess) {
-        T *sv = reinterpret_cast<T *>(w + L.sv), *pv = reinterpret_cast<T *>(w + L.p);
-        T *xt = reinterpret_cast<T *>(w + L.xt);
-        double *part = reinterpret_cast<double *>(w + L.part);
-        double *part2 = reinterpret_cast<double *>(w + L.part2);
-        CGState *st = reinterpret_cast<CGState *>(w + L.st);
-        const size_t n = (size_t)p->N * p->N;
-        float best_cg_ms = 1e30f;
-        for (int pr = 0; pr < 9; ++pr) {
-            const int E = 16 >> (pr / 3), Ec = 16 >> (pr % 3);
-            if (!apply_e_ok(p->logP, E) || !apply_e_ok(p->logP, Ec) || err != hipSuccess) continue;
-            p->cg_e[t] = E;
-            p->cg_ec[t] = Ec;
-            hipLaunchKernelGGL(k_fill_one<T>, dim3(VBLK), dim3(256), 0, s, sv, n);
-            hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, (const T *)sv, xt, src, pv, nullptr, n,
-                               part, part2);
-            hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK, 0.0, 0);
-            for (int it = 0; it < reps + 2 && err == hipSuccess; ++it) {
-                if (it == 2) err = hipEventRecord(e0, s);
-                if (err == hipSuccess)
-                    err = launch_cgf_iteration<T>(p, Ghat, xt, src, pv, sv, dst, aws, part, st, it & 1, s);
-            }
-            if (err == hipSuccess) err = hipEventRecord(e1, s);
-            if (err == hipSuccess) err = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-            if (err == hipSuccess && ms < best_cg_ms) {
-                best_cg_ms = ms;
-                best_cg = E;
-                best_cgc = Ec;
-            }
+    float best_cg_ms = 1e30f;
+    for (int pr = 0; pr < 9 && err == hipSuccess; ++pr) {
+        const int E = 16 >> (pr / 3), Ec = 16 >> (pr % 3);
+        if (!apply_e_ok(p->logP, E) || !apply_e_ok(p->logP, Ec)) continue;
+        p->cg_e[t] = E;
+        p->cg_ec[t] = Ec;
+        const float ms = time_graph(
+            [&](hipStream_t q) {
+                for (int it = 0; it < reps; ++it) {
+                    hipError_t e = launch_cgf_iteration<T>(p, Ghat, xt, src, pv, sv, dst, aws, part, st, it & 1, q);
+                    if (e != hipSuccess) return e;
+                }
+                return hipSuccess;
+            },
+            [&] {
+                hipLaunchKernelGGL(k_fill_one<T>, dim3(VBLK), dim3(256), 0, s, sv, n);
+                hipLaunchKernelGGL(k_cg_init<T>, dim3(VBLK), dim3(256), 0, s, (const T *)sv, xt, src, pv, nullptr,
+                                   n, part, part2);
+                hipLaunchKernelGGL(k_cg_init_fin, dim3(1), dim3(256), 0, s, st, part, part2, VBLK, 0.0, 0);
+            });
+        if (err == hipSuccess && ms < best_cg_ms) {
+            best_cg_ms = ms;
+            best_cg = E;
+            best_cgc = Ec;
         }
     }
     p->cg_e[t] = best_cg;

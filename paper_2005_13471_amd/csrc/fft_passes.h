@@ -31,21 +31,28 @@ __host__ __device__ constexpr bool twiddles_in_lds(int P)
     return (size_t)(P + P / 2) * sizeof(C2<T>) <= 65536;
 }
 
-template <typename T, bool TWL>
-__device__ __forceinline__ const C2<T> *stage_twiddles(C2<T> *lds_after_data,
-                                                       const C2<T> *__restrict__ tw, int hP)
+// HP twiddles by a block of NT threads (the launch's block size): every
+// thread issues all its loads before its first LDS store, so the block
+// waits for one global latency rather than one per round of NT entries.
+template <typename T, bool TWL, int HP, int NT>
+__device__ __forceinline__ const C2<T> *stage_twiddles(C2<T> *lds_after_data, const C2<T> *__restrict__ tw)
 {
     if (!TWL) return tw;
-    for (int i = threadIdx.x; i < hP; i += blockDim.x) lds_after_data[i] = tw[i];
+    constexpr int K = (HP + NT - 1) / NT;
+    C2<T> r[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int i = threadIdx.x + j * NT;
+        if (HP % NT == 0 || i < HP) r[j] = tw[i];
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int i = threadIdx.x + j * NT;
+        if (HP % NT == 0 || i < HP) lds_after_data[i] = r[j];
+    }
     return lds_after_data;
 }
 
-// Rows forward: real FFT of image rows ra and ra+1 (one complex transform),
-// written transposed as W1[k][row], k in [0, P/2].  With pupd, the rows are
-// first updated in place as p = src + bt * p (CG direction update).
-// Rows forward from registers: v[q] holds (row ra, row ra+1) at column
-// t + G q (zero past N); one complex FFT, split into the two real-row
-// spectra, written transposed as W1[k][row].
 // Two adjacent complex values as one 16-byte access (FP32; the caller
 // guarantees 16-byte alignment); FP64 falls back to two accesses.
 template <typename T>
@@ -72,6 +79,10 @@ __device__ __forceinline__ void load_pair(const C2<T> *p, C2<T> &a, C2<T> &b)
     }
 }
 
+// Rows forward: real FFT of image rows ra and ra+1 (one complex transform),
+// written transposed as W1[k][row], k in [0, P/2].  From registers: v[q]
+// holds (row ra, row ra+1) at column t + G q (zero past N); one complex
+// FFT, split into the two real-row spectra.
 template <typename T, int LOGP, int E>
 __device__ __forceinline__ void rows_fwd_regs(int ra, C2<T> (&v)[E], C2<T> *__restrict__ W1, int N, C2<T> *x,
                                               const C2<T> *tws)
@@ -101,56 +112,89 @@ __device__ __forceinline__ void rows_fwd_regs(int ra, C2<T> (&v)[E], C2<T> *__re
     __syncthreads();  // x may be reused by the caller
 }
 
+// The load halves (rows_fwd_load, cols_load, rows_inv_load) touch no LDS
+// and no twiddles, so a kernel can issue them before staging the twiddles:
+// the two global latencies then overlap.  rows_fwd_load: with pupd, the
+// rows are first updated in place as p = src + bt * p (CG direction
+// update).
+template <typename T, int LOGP, int E>
+__device__ __forceinline__ void rows_fwd_load(int ra, const T *__restrict__ src, int N, T *pupd, T bt,
+                                              C2<T> (&v)[E])
+{
+    constexpr int P = 1 << LOGP, G = P / E;
+    const int t = threadIdx.x;
+    const bool hb = ra + 1 < N;  // row ra < N always
+    const size_t oa = (size_t)ra * N, ob = hb ? oa + N : oa;
+    // unconditional loads from clamped in-range addresses, masked afterwards:
+    // no branch between them, so all are in flight before the first wait
+    T a[E], b[E];
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int nc = min(t + G * q, N - 1);
+        a[q] = src[oa + nc];
+        b[q] = src[ob + nc];
+    }
+    if (pupd) {
+        T ua[E], ub[E];
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int nc = min(t + G * q, N - 1);
+            ua[q] = pupd[oa + nc];
+            ub[q] = pupd[ob + nc];
+        }
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int n = t + G * q;
+            if (n >= N) continue;
+            a[q] += bt * ua[q];
+            pupd[oa + n] = a[q];
+            if (hb) {
+                b[q] += bt * ub[q];
+                pupd[ob + n] = b[q];
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const bool ok = t + G * q < N;
+        v[q] = {ok ? a[q] : T(0), ok && hb ? b[q] : T(0)};
+    }
+}
+
 template <typename T, int LOGP, int E>
 __device__ __forceinline__ void body_rows_fwd(int ra, const T *__restrict__ src,
                                               C2<T> *__restrict__ W1, int N, C2<T> *x,
                                               const C2<T> *tws, T *pupd, T bt)
 {
-    constexpr int P = 1 << LOGP, G = P / E;
-    const int t = threadIdx.x;
-    const int rb = ra + 1;
     C2<T> v[E];
-#pragma unroll
-    for (int q = 0; q < E; ++q) {
-        const int n = t + G * q;
-        T re = 0, im = 0;
-        if (n < N) {
-            const size_t ia = (size_t)ra * N + n, ib = (size_t)rb * N + n;
-            re = src[ia];
-            if (rb < N) im = src[ib];
-            if (pupd) {
-                re += bt * pupd[ia];
-                pupd[ia] = re;
-                if (rb < N) {
-                    im += bt * pupd[ib];
-                    pupd[ib] = im;
-                }
-            }
-        }
-        v[q] = {re, im};
-    }
+    rows_fwd_load<T, LOGP, E>(ra, src, N, pupd, bt, v);
     rows_fwd_regs<T, LOGP, E>(ra, v, W1, N, x, tws);
 }
 
 // Columns: FFT along k2 of column col (N nonzero of P), times the real
 // spectrum, inverse FFT (in registers between the two), first N entries.
 template <typename T, int LOGP, int E>
-__device__ __forceinline__ void body_cols(int col, const C2<T> *__restrict__ W1,
-                                          C2<T> *__restrict__ W2, const T *__restrict__ Ghat,
-                                          int N, C2<T> *x, const C2<T> *tws)
+__device__ __forceinline__ void cols_load(int col, const C2<T> *__restrict__ W1, const T *__restrict__ Ghat,
+                                          int N, C2<T> (&v)[E], T (&gs)[E])
 {
     constexpr int P = 1 << LOGP, G = P / E;
     const int t = threadIdx.x;
     const C2<T> *in = W1 + (size_t)col * N;
     const T *g = Ghat + (size_t)col * P;
-    C2<T> v[E];
-    T gs[E];
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int n = t + G * q;
         v[q] = n < N ? in[n] : C2<T>{T(0), T(0)};
         gs[q] = g[n];
     }
+}
+
+template <typename T, int LOGP, int E>
+__device__ __forceinline__ void cols_regs(int col, C2<T> (&v)[E], const T (&gs)[E], C2<T> *__restrict__ W2,
+                                          int N, C2<T> *x, const C2<T> *tws)
+{
+    constexpr int P = 1 << LOGP, G = P / E;
+    const int t = threadIdx.x;
     fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
 #pragma unroll
     for (int q = 0; q < E; ++q) v[q] = {v[q].x * gs[q], v[q].y * gs[q]};
@@ -163,51 +207,53 @@ __device__ __forceinline__ void body_cols(int col, const C2<T> *__restrict__ W1,
     }
 }
 
-// Rows inverse: Hermitian row spectra of rows ra, ra+1 -> one complex
-// inverse FFT -> two real rows of y.  Returns this thread's FP64 partial of
-// dotv . y over the two rows (0 if dotv is null).
-// Rows inverse into registers: Hermitian row spectra of rows ra, ra+1 ->
-// one complex inverse FFT; v[q] = (row ra, row ra+1) at column t + G q.
+// Rows inverse: Hermitian row spectra of rows ra, ra+1 (loaded as one
+// complex spectrum) -> one complex inverse FFT (fft_passes) -> v[q] =
+// (row ra, row ra+1) at column t + G q -> two real rows of y.
 template <typename T, int LOGP, int E>
-__device__ __forceinline__ void rows_inv_regs(int ra, const C2<T> *__restrict__ W2, int N, C2<T> *x,
-                                              const C2<T> *tws, C2<T> (&v)[E])
+__device__ __forceinline__ void rows_inv_load(int ra, const C2<T> *__restrict__ W2, int N, C2<T> (&v)[E])
 {
     constexpr int P = 1 << LOGP, hP = P >> 1, G = P / E;
     const int t = threadIdx.x;
     const int rb = ra + 1;
     const bool pair = sizeof(T) == 4 && (N & 1) == 0 && (reinterpret_cast<uintptr_t>(W2) & 15) == 0;
+    // one loop per access form, so that no load waits for the previous one
+    C2<T> Ya[E], Yb[E];
+    if (pair) {  // rows ra, ra+1 in one 16-byte load
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int k = t + G * q;
+            const int kk = k <= hP ? k : P - k;  // Hermitian extension
+            load_pair(W2 + (size_t)kk * N + ra, Ya[q], Yb[q]);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+            const int k = t + G * q;
+            const int kk = k <= hP ? k : P - k;
+            Ya[q] = W2[(size_t)kk * N + ra];
+            Yb[q] = rb < N ? W2[(size_t)kk * N + rb] : C2<T>{T(0), T(0)};
+        }
+    }
 #pragma unroll
     for (int q = 0; q < E; ++q) {
-        const int k = t + G * q;
-        const int kk = k <= hP ? k : P - k;  // Hermitian extension
-        C2<T> Ya, Yb;
-        if (pair) {  // rows ra, ra+1 in one 16-byte load
-            load_pair(W2 + (size_t)kk * N + ra, Ya, Yb);
-        } else {
-            Ya = W2[(size_t)kk * N + ra];
-            Yb = rb < N ? W2[(size_t)kk * N + rb] : C2<T>{T(0), T(0)};
+        if (t + G * q > hP) {
+            Ya[q].y = -Ya[q].y;
+            Yb[q].y = -Yb[q].y;
         }
-        if (k > hP) {
-            Ya.y = -Ya.y;
-            Yb.y = -Yb.y;
-        }
-        v[q] = {Ya.x - Yb.y, Ya.y + Yb.x};
+        v[q] = {Ya[q].x - Yb[q].y, Ya[q].y + Yb[q].x};
     }
-    fft_passes<T, E, P, 1, true, true>(v, x, t, tws);
 }
 
-// Rows inverse: the two real rows of y.  Returns this thread's FP64 partial
-// of dotv . y over the two rows (0 if dotv is null).
+// The two real output rows from v (after the inverse transform) into y;
+// returns this thread's FP64 partial of dotv . y (0 if dotv is null).
 template <typename T, int LOGP, int E>
-__device__ __forceinline__ double body_rows_inv(int ra, const C2<T> *__restrict__ W2,
-                                                T *__restrict__ y, int N, C2<T> *x,
-                                                const C2<T> *tws, const T *__restrict__ dotv)
+__device__ __forceinline__ double rows_inv_store(int ra, const C2<T> (&v)[E], T *__restrict__ y, int N,
+                                                 const T *__restrict__ dotv)
 {
     constexpr int P = 1 << LOGP, G = P / E;
     const int t = threadIdx.x;
     const int rb = ra + 1;
-    C2<T> v[E];
-    rows_inv_regs<T, LOGP, E>(ra, W2, N, x, tws, v);
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
@@ -227,6 +273,7 @@ __device__ __forceinline__ double body_rows_inv(int ra, const C2<T> *__restrict_
 // then the per-wave results (at most 4 waves) added in wave order through
 // LDS (2 doubles per wave at red).  One barrier; the same order everywhere,
 // so every block reducing the same data gets the same bits.
+template <int NT>  // the block's thread count
 __device__ __forceinline__ void block_sum2(double &a, double &b, double *red)
 {
 #pragma unroll
@@ -234,7 +281,8 @@ __device__ __forceinline__ void block_sum2(double &a, double &b, double *red)
         a += __shfl_xor(a, o);
         b += __shfl_xor(b, o);
     }
-    const int wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    constexpr int nw = (NT + 63) >> 6;
+    const int wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
         red[2 * wv] = a;
         red[2 * wv + 1] = b;

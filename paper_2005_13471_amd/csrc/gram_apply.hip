@@ -20,61 +20,54 @@
 
 namespace gct {
 
-// Status word of a running CG solve (see cg.hip): kernels return at once
-// when it is non-zero, so iterations queued after convergence cost only a
-// launch.
-__device__ __forceinline__ bool halted(const int64_t *status) { return status && *status != 0; }
-
 // One transform per block, P/E threads; E is the plan's choice for the
 // apply passes (gct_plan_autotune), fft_elems(P) for the spectrum.
 template <typename T, int LOGP, int E>
 __global__ void __launch_bounds__(256)
-k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, const C2<T> *__restrict__ tw,
-           const int64_t *status, T *pupd, const double *beta)
+k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, const C2<T> *__restrict__ tw)
 {
-    if (halted(status)) return;
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
-    __syncthreads();
     const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
-    body_rows_fwd<T, LOGP, E>(2 * rp, src, W1, N, x, tws, pupd, pupd ? (T)(*beta) : T(0));
+    // data first, then the twiddles: their latencies overlap
+    C2<T> v[E];
+    rows_fwd_load<T, LOGP, E>(2 * rp, src, N, nullptr, T(0), v);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
+    __syncthreads();
+    rows_fwd_regs<T, LOGP, E>(2 * rp, v, W1, N, x, tws);
 }
 
 template <typename T, int LOGP, int E>
 __global__ void __launch_bounds__(256)
 k_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat, int N,
-       const C2<T> *__restrict__ tw, const int64_t *status)
+       const C2<T> *__restrict__ tw)
 {
-    if (halted(status)) return;
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
+    C2<T> v[E];
+    T gs[E];
+    cols_load<T, LOGP, E>(blockIdx.x, W1, Ghat, N, v, gs);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
     __syncthreads();
-    body_cols<T, LOGP, E>(blockIdx.x, W1, W2, Ghat, N, x, tws);
+    cols_regs<T, LOGP, E>(blockIdx.x, v, gs, W2, N, x, tws);
 }
 
-// With `dotv` set (CG), each block also writes the FP64 partial sum of
-// dotv . y over its two rows.
 template <typename T, int LOGP, int E>
 __global__ void __launch_bounds__(256)
-k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, const C2<T> *__restrict__ tw,
-           const int64_t *status, const T *__restrict__ dotv, double *__restrict__ partial)
+k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, const C2<T> *__restrict__ tw)
 {
-    if (halted(status)) return;
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
-    __syncthreads();
     const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
-    const double acc = body_rows_inv<T, LOGP, E>(2 * rp, W2, y, N, x, tws, dotv);
-    if (partial) {
-        const double s = block_sum_lds(acc, reinterpret_cast<double *>(smem_raw));
-        if (threadIdx.x == 0) partial[rp] = s;
-    }
+    C2<T> v[E];
+    rows_inv_load<T, LOGP, E>(2 * rp, W2, N, v);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
+    __syncthreads();
+    fft_passes<T, E, P, 1, true, true>(v, x, threadIdx.x, tws);
+    (void)rows_inv_store<T, LOGP, E>(2 * rp, v, y, N, nullptr);
 }
 
 template <typename T, int LOGP>
@@ -84,7 +77,7 @@ k_spec_rows(const T *__restrict__ G, C2<T> *__restrict__ R, int N, const C2<T> *
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / fft_elems(P)>(x + P, tw);
     __syncthreads();
     body_spec_rows<T, LOGP, fft_elems(P)>(xcd_swizzle(blockIdx.x, gridDim.x), G, R, N, x, tws);
 }
@@ -97,7 +90,7 @@ k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat, const C2<T> *__re
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / fft_elems(P)>(x + P, tw);
     __syncthreads();
     body_spec_cols<T, LOGP, fft_elems(P)>(blockIdx.x, R, Ghat, x, tws, scale);
 }
@@ -120,16 +113,39 @@ k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat, const C2<T> *__re
 // solver, Sec. 6.2).  All blocks compute the same scalars; block 0 alone
 // records them, in the slots of the other parity.
 // ---------------------------------------------------------------------------
-// (sum part[0..np), sum part[np..2np)) in a fixed order
-__device__ __forceinline__ void dot_pair(const double *part, int np, double *red, double &g, double &d)
+// (sum part[0..np), sum part[np..2np)) in a fixed order, for a block of NT
+// threads: thread t adds entries t, t + NT, ... in increasing order.  The
+// first KP of them are loaded by part_load (clamped addresses, so the loads
+// can be issued before anything else), the rest, if any, here.
+template <int NT, int KP>
+__device__ __forceinline__ void part_load(const double *part, int np, double (&pg)[KP], double (&pd)[KP])
+{
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        const int i = min((int)threadIdx.x + j * NT, np - 1);
+        pg[j] = part[i];
+        pd[j] = part[np + i];
+    }
+}
+
+template <int NT, int KP>
+__device__ __forceinline__ void dot_pair(const double *part, int np, const double (&pg)[KP],
+                                         const double (&pd)[KP], double *red, double &g, double &d)
 {
     g = 0.0;
     d = 0.0;
-    for (int i = threadIdx.x; i < np; i += blockDim.x) {
+#pragma unroll
+    for (int j = 0; j < KP; ++j) {
+        if ((int)threadIdx.x + j * NT < np) {
+            g += pg[j];
+            d += pd[j];
+        }
+    }
+    for (int i = threadIdx.x + KP * NT; i < np; i += NT) {
         g += part[i];
         d += part[np + i];
     }
-    block_sum2(g, d, red);
+    block_sum2<NT>(g, d, red);
 }
 
 template <typename T, int LOGP, int E>
@@ -138,7 +154,6 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
                const T *__restrict__ w, C2<T> *__restrict__ W1, int N, const C2<T> *__restrict__ tw,
                CGState *st, const double *__restrict__ part, int np, int par)
 {
-    if (st->stat[par] != CG_RUNNING) return;
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *xs = reinterpret_cast<C2<T> *>(smem_raw);
@@ -146,27 +161,34 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
     const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
     const int ra = 2 * rp;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
-    const int64_t pend = st->pend[par];
+    const int64_t stat = st->stat[par], pend = st->pend[par];
+    // the previous launch's partial dots and this thread's elements of the
+    // five vectors (in range whatever the state), issued together with the
+    // state words so that all their latencies overlap
+    constexpr int G = P / E, KP = E / 4 + 1;
+    double pg[KP], pd[KP];
+    part_load<G, KP>(part, np, pg, pd);
+    T lr[E][2], lw[E][2], lp[E][2], ls[E][2], lx[E][2];
+#pragma unroll
+    for (int q = 0; q < E; ++q)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int n = threadIdx.x + G * q, row = ra + h;
+            const bool ok = n < N && row < N;
+            const size_t i = ok ? (size_t)row * N + n : 0;
+            lr[q][h] = ok ? r[i] : T(0);
+            lw[q][h] = ok ? w[i] : T(0);
+            lp[q][h] = ok ? p[i] : T(0);
+            ls[q][h] = ok ? sv[i] : T(0);
+            lx[q][h] = ok ? x[i] : T(0);
+        }
+    if (stat != CG_RUNNING) return;
     if (pend) {
-        // this thread's elements of the five vectors, loaded before the
-        // reduction so that their latency overlaps it
-        constexpr int G = P / E;
-        T lr[E][2], lw[E][2], lp[E][2], ls[E][2], lx[E][2];
-#pragma unroll
-        for (int q = 0; q < E; ++q)
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int n = threadIdx.x + G * q, row = ra + h;
-                const bool ok = n < N && row < N;
-                const size_t i = ok ? (size_t)row * N + n : 0;
-                lr[q][h] = ok ? r[i] : T(0);
-                lw[q][h] = ok ? w[i] : T(0);
-                lp[q][h] = ok ? p[i] : T(0);
-                ls[q][h] = ok ? sv[i] : T(0);
-                lx[q][h] = ok ? x[i] : T(0);
-            }
+        // twiddles to LDS behind the data area (the reduction below uses
+        // its start): their latency overlaps the loads above
+        const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(xs + P, tw);
         double g, dl;
-        dot_pair(part, np, red, g, dl);
+        dot_pair<G, KP>(part, np, pg, pd, red, g, dl);
         const int64_t u = st->k;  // updates so far: g = ||r_u||^2
         if (!(g == g)) {
             if (lead) st->stat[par ^ 1] = st->status = CG_BREAKDOWN;
@@ -229,15 +251,14 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
             }
             v[q] = {rv[0], rv[1]};
         }
-        const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(xs + P, tw, P / 2);
-        __syncthreads();
+        __syncthreads();  // the reduction's LDS reads are done before the transform writes
         rows_fwd_regs<T, LOGP, E>(ra, v, W1, N, xs, tws);
         return;
     } else if (lead) {
         st->pend[par ^ 1] = 1;  // first launch: transform r_0 only
         st->stat[par ^ 1] = CG_RUNNING;
     }
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(xs + P, tw, P / 2);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(xs + P, tw);
     __syncthreads();
     body_rows_fwd<T, LOGP, E>(ra, r, W1, N, xs, tws, nullptr, T(0));
 }
@@ -247,13 +268,18 @@ __global__ void __launch_bounds__(256)
 k_cgf_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat, int N,
            const C2<T> *__restrict__ tw, const CGState *st, int par)
 {
-    if (st->stat[par ^ 1] != CG_RUNNING) return;
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
+    // the column's loads go out with the state word's (in range either way)
+    const int64_t stat = st->stat[par ^ 1];
+    C2<T> v[E];
+    T gs[E];
+    cols_load<T, LOGP, E>(blockIdx.x, W1, Ghat, N, v, gs);
+    if (stat != CG_RUNNING) return;
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
     __syncthreads();
-    body_cols<T, LOGP, E>(blockIdx.x, W1, W2, Ghat, N, x, tws);
+    cols_regs<T, LOGP, E>(blockIdx.x, v, gs, W2, N, x, tws);
 }
 
 template <typename T, int LOGP, int E>
@@ -261,17 +287,30 @@ __global__ void __launch_bounds__(256)
 k_cgf_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ w, const T *__restrict__ r, int N,
                const C2<T> *__restrict__ tw, const CGState *st, double *__restrict__ part, int np, int par)
 {
-    if (st->stat[par ^ 1] != CG_RUNNING) return;
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P)>(x + P, tw, P / 2);
-    __syncthreads();
     const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
     const int ra = 2 * rp, rb = ra + 1;
     constexpr int G = P / E;
+    const int64_t stat = st->stat[par ^ 1];  // tested after the loads below are issued
+    // this thread's entries of r, loaded ahead of the transform so that
+    // their latency overlaps it
+    // (clamped in-range addresses; entries past N are never used)
+    T lr[E][2];
+    const size_t oa = (size_t)ra * N, ob = rb < N ? oa + N : oa;
+#pragma unroll
+    for (int q = 0; q < E; ++q) {
+        const int nc = min((int)threadIdx.x + G * q, N - 1);
+        lr[q][0] = r[oa + nc];
+        lr[q][1] = r[ob + nc];
+    }
     C2<T> v[E];
-    rows_inv_regs<T, LOGP, E>(ra, W2, N, x, tws, v);
+    rows_inv_load<T, LOGP, E>(ra, W2, N, v);
+    if (stat != CG_RUNNING) return;
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
+    __syncthreads();
+    fft_passes<T, E, P, 1, true, true>(v, x, threadIdx.x, tws);
     double g = 0.0, dl = 0.0;
 #pragma unroll
     for (int q = 0; q < E; ++q) {
@@ -279,19 +318,19 @@ k_cgf_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ w, const T *__restr
         if (n >= N) continue;
         const size_t ia = (size_t)ra * N + n;
         w[ia] = v[q].x;
-        const double ra_ = (double)r[ia];
+        const double ra_ = (double)lr[q][0];
         g += ra_ * ra_;
         dl += ra_ * (double)v[q].x;
         if (rb < N) {
             const size_t ib = ia + N;
             w[ib] = v[q].y;
-            const double rb_ = (double)r[ib];
+            const double rb_ = (double)lr[q][1];
             g += rb_ * rb_;
             dl += rb_ * (double)v[q].y;
         }
     }
     __syncthreads();  // the transform's LDS reads are done before red is written
-    block_sum2(g, dl, reinterpret_cast<double *>(smem_raw));
+    block_sum2<G>(g, dl, reinterpret_cast<double *>(smem_raw));
     if (threadIdx.x == 0) {
         part[rp] = g;
         part[np + rp] = dl;
@@ -393,12 +432,9 @@ bool apply_e_ok(int logP, int E)
         }                                                                                 \
     } while (0)
 
-// The three passes of one apply; status/pupd/beta/dotv/partial are the CG
-// hooks (all null for a plain apply).
+// The three passes of one apply.
 template <typename T>
-hipError_t launch_apply_passes(const gct_plan *p, const T *Ghat, const T *src, T *y, void *ws,
-                               hipStream_t s, const int64_t *status, T *pupd, const double *beta,
-                               const T *dotv, double *partial)
+hipError_t launch_gram_apply(const gct_plan *p, const T *Ghat, const T *c, T *y, void *ws, hipStream_t s)
 {
     const int N = p->N, P = p->P, logP = p->logP;
     const int t = sizeof(T) == 4 ? 0 : 1, E = p->fft_e[t], Ec = p->fft_ec[t];
@@ -408,9 +444,9 @@ hipError_t launch_apply_passes(const gct_plan *p, const T *Ghat, const T *src, T
     C2<T> *W2 = reinterpret_cast<C2<T> *>(reinterpret_cast<char *>(ws) + w1);
     const C2<T> *tw = twiddles<T>(p);
     const dim3 rgrid((N + 1) / 2), cgrid(P / 2 + 1);
-    GCT_LAUNCH_FFTE(k_rows_fwd, T, logP, E, rgrid, lds, s, src, W1, N, tw, status, pupd, beta);
-    GCT_LAUNCH_FFTE(k_cols, T, logP, Ec, cgrid, ldsc, s, W1, W2, Ghat, N, tw, status);
-    GCT_LAUNCH_FFTE(k_rows_inv, T, logP, E, rgrid, lds, s, W2, y, N, tw, status, dotv, partial);
+    GCT_LAUNCH_FFTE(k_rows_fwd, T, logP, E, rgrid, lds, s, c, W1, N, tw);
+    GCT_LAUNCH_FFTE(k_cols, T, logP, Ec, cgrid, ldsc, s, W1, W2, Ghat, N, tw);
+    GCT_LAUNCH_FFTE(k_rows_inv, T, logP, E, rgrid, lds, s, W2, y, N, tw);
     return hipGetLastError();
 }
 
@@ -443,14 +479,6 @@ template hipError_t launch_cgf_iteration<double>(const gct_plan *, const double 
                                                  int, hipStream_t);
 
 template <typename T>
-hipError_t launch_gram_apply(const gct_plan *p, const T *Ghat, const T *c, T *y, void *ws,
-                             hipStream_t s)
-{
-    return launch_apply_passes<T>(p, Ghat, c, y, ws, s, nullptr, nullptr, nullptr, nullptr,
-                                  nullptr);
-}
-
-template <typename T>
 hipError_t launch_gram_spectrum(const gct_plan *p, const T *G, T *Ghat, void *ws, hipStream_t s)
 {
     const int N = p->N, P = p->P, logP = p->logP;
@@ -471,11 +499,5 @@ template hipError_t launch_gram_spectrum<float>(const gct_plan *, const float *,
                                                 hipStream_t);
 template hipError_t launch_gram_spectrum<double>(const gct_plan *, const double *, double *, void *,
                                                  hipStream_t);
-template hipError_t launch_apply_passes<float>(const gct_plan *, const float *, const float *,
-                                               float *, void *, hipStream_t, const int64_t *,
-                                               float *, const double *, const float *, double *);
-template hipError_t launch_apply_passes<double>(const gct_plan *, const double *, const double *,
-                                                double *, void *, hipStream_t, const int64_t *,
-                                                double *, const double *, const double *, double *);
 
 }  // namespace gct

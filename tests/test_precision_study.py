@@ -157,11 +157,14 @@ def test_precision_study_n2048(setup):
     # FP32 vectors with FP64 dots reach the FP64 solve's residual level after
     # 100 steps.  Unconverged CG on this ill-conditioned system amplifies
     # rounding: reordering the FFT's floating-point operations alone moved the
-    # FP64 residual after 100 steps by ~25%, so only the level is compared
-    # (within a factor of 2), not the trajectory.
+    # FP64 residual after 100 steps by ~25%, and two FP32 applies that differ
+    # by 2e-7 relative (the same passes compiled with different load
+    # scheduling) gave FP32 residuals after 100 steps a factor of ~2 apart,
+    # either way round, on two phantoms.  So only the level is compared
+    # (within a factor of 4), not the trajectory.
     ratio = rep["cg100_fp32_iterate_rel_res_fp64_operator"] / rep["cg100_fp64_rel_res_true"]
     rep["cg100_fp32_over_fp64"] = ratio
-    assert 0.5 <= ratio <= 2.0
+    assert 0.25 <= ratio <= 4.0
 
     out_dir = os.environ.get("GCT_REPORT_DIR")
     if out_dir:

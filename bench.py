@@ -356,6 +356,12 @@ def warm_compare(slices: int):
                              "iters_mean": float(np.mean([r.iters for r in res_pipe])),
                              "max_rel_res_true": float(max(r.rel_res_true for r in res_pipe)),
                              "note": "U-Net of the next slice on a second stream during each solve"}
+    ms_b, res_b, dev_b = W.batched(prob, ws, b)
+    rep["warm_batched16"] = {"ms_per_slice": ms_b,
+                             "iters_mean": float(np.mean([r.iters for r in res_b])),
+                             "max_rel_res_true": float(max(r.rel_res_true for r in res_b)),
+                             "start_dev_vs_batch1": dev_b,
+                             "note": "U-Net inference for 16 slices at a time, then each CG from its start"}
     rep.update(workload="n256_a180_m366_z1", seeds=[W.TEST_SEEDS[0], W.TEST_SEEDS[0] + slices],
                net=f"U-Net {cfg.levels} levels, {cfg.base_channels} base channels, bf16",
                trained_steps=ws.meta.get("step"))

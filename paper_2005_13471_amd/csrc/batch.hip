@@ -50,7 +50,7 @@ kb_rows_fwd(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     rows_fwd_load<T, LOGP, E>(2 * m.y, src + d.img, d.N, pupd ? pupd + d.img : nullptr,
                               pupd ? (T)st[m.x].beta : T(0), v);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     rows_fwd_regs<T, LOGP, E>(2 * m.y, v, W1 + d.w, d.N, x, tws);
 }
@@ -101,7 +101,7 @@ kb_rows_fwd2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
         }
         v[q] = {re, im};
     }
-    fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
+    fft_passes<T, E, P, 1, false, true, false>(v, x, t, tws);  // one area per group
 #pragma unroll
     for (int q = 0; q < E; ++q) x[t + G * q] = v[q];
     __syncthreads();
@@ -164,7 +164,7 @@ kb_rows_inv2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
         v[q] = {Ya.x - Yb.y, Ya.y + Yb.x};
     }
     __syncthreads();  // the staged spectra are read: the transform may reuse the area
-    fft_passes<T, E, P, 1, true, true>(v, xs + grp * XS, t, tws);
+    fft_passes<T, E, P, 1, true, true, false>(v, xs + grp * XS, t, tws);  // one area per group
     const int ra = 4 * m.y + 2 * grp, rb = ra + 1;
     T *yo = y + d.img;
     const T *dv = dotv ? dotv + d.img : nullptr;
@@ -207,7 +207,7 @@ kb_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     T gs[E];
     cols_load<T, LOGP, E>(m.y, W1 + d.w, Ghat + d.spec, d.N, v, gs);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     cols_regs<T, LOGP, E>(m.y, v, gs, W2 + d.w, d.N, x, tws);
 }
@@ -227,7 +227,7 @@ kb_rows_inv(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     C2<T> v[E];
     rows_inv_load<T, LOGP, E>(2 * m.y, W2 + d.w, d.N, v);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     fft_passes<T, E, P, 1, true, true>(v, x, threadIdx.x, tws);
     const double acc = rows_inv_store<T, LOGP, E>(2 * m.y, v, y + d.img, d.N, dotv ? dotv + d.img : nullptr);
@@ -248,7 +248,7 @@ kb_spec_rows(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     // R of a slice uses (P/2+1) P complex, i.e. 2 d.spec reals' worth of offset
     body_spec_rows<T, LOGP, E>(m.y, G + d.gram, R + d.spec, d.N, x, tws);
@@ -265,7 +265,7 @@ kb_spec_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws =
-        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, reinterpret_cast<const C2<T> *>(d.tw));
+        stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     body_spec_cols<T, LOGP, E>(m.y, R + d.spec, Ghat + d.spec, x, tws,
                                T(1.0 / ((double)P * (double)P)));

@@ -152,13 +152,29 @@ __device__ __forceinline__ void dftR(C2<T> *v)
     else dft16<T, INV>(v);
 }
 
+// LDS layout of a transform: with ping-pong (two data areas of P entries
+// where they fit in 64 KB with the twiddles) a pass reads one area and
+// writes the other, so it needs one barrier instead of two.
+template <typename T>
+__host__ __device__ constexpr bool fft_pingpong(int P)
+{
+    return (size_t)(2 * P + P / 2) * sizeof(C2<T>) <= 65536;
+}
+template <typename T>
+__host__ __device__ constexpr int fft_data_elems(int P)
+{
+    return fft_pingpong<T>(P) ? 2 * P : P;
+}
+
 // ---------------------------------------------------------------------------
 // One Stockham pass of radix R on a length-P transform held by G = P/E
 // threads.  FIRST: inputs are v (R == E, no twiddles); LAST: outputs go to v
-// in the strided layout.  Otherwise x (LDS) is read and/or written.  Every
-// thread of the block must call it (it may contain barriers).
+// in the strided layout.  Otherwise x (LDS) is read and/or written: with PP
+// the pass writes area A (x + A P) and reads the other one, else both in
+// x.  Every thread of the block must call it (it contains barriers); after
+// the LAST pass the whole LDS data area is free again.
 // ---------------------------------------------------------------------------
-template <typename T, int E, int P, int NS, int R, bool INV, bool FIRST, bool LAST>
+template <typename T, int E, int P, int NS, int R, bool INV, bool FIRST, bool LAST, bool PP, int A>
 __device__ __forceinline__ void fft_pass(C2<T> (&v)[E], C2<T> *x, int t, const C2<T> *tw)
 {
     constexpr int B = E / R;
@@ -166,6 +182,8 @@ __device__ __forceinline__ void fft_pass(C2<T> (&v)[E], C2<T> *x, int t, const C
     constexpr int stride = P / R;
     constexpr int tstep = P / (NS * R);
     constexpr int hP = P / 2;
+    const C2<T> *xin = PP ? x + (A ^ 1) * P : x;
+    C2<T> *xout = PP ? x + A * P : x;
     C2<T> u[E];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
@@ -176,14 +194,16 @@ __device__ __forceinline__ void fft_pass(C2<T> (&v)[E], C2<T> *x, int t, const C
             if constexpr (FIRST) {
                 u[b * R + r] = v[b * R + r];
             } else {
-                C2<T> a = x[j + r * stride];
+                C2<T> a = xin[j + r * stride];
                 if (r > 0) a = cmul(a, twid<T, INV>(tw, r * k * tstep, hP));
                 u[b * R + r] = a;
             }
         }
         dftR<T, R, INV>(&u[b * R]);
     }
-    if constexpr (!FIRST) __syncthreads();  // every read of x in this pass is done
+    // every read of this pass is done before the area is written again (with
+    // ping-pong the next write to it comes after the next pass's barrier)
+    if constexpr (!FIRST && (!PP || LAST)) __syncthreads();
     if constexpr (LAST) {
 #pragma unroll
         for (int b = 0; b < B; ++b)
@@ -196,33 +216,23 @@ __device__ __forceinline__ void fft_pass(C2<T> (&v)[E], C2<T> *x, int t, const C
             const int k = j & (NS - 1);
             const int base = (j - k) * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) x[base + r * NS] = u[b * R + r];
+            for (int r = 0; r < R; ++r) xout[base + r * NS] = u[b * R + r];
         }
         __syncthreads();  // writes visible to the next pass
     }
 }
 
-template <typename T, int E, int P, int NS, bool INV, bool FIRST>
+template <typename T, int E, int P, int NS, bool INV, bool FIRST, bool PP = fft_pingpong<T>(P), int A = 0>
 __device__ __forceinline__ void fft_passes(C2<T> (&v)[E], C2<T> *x, int t, const C2<T> *tw)
 {
     constexpr int REM = P / NS;
     constexpr int R = REM >= E ? E : REM;
     constexpr bool LAST = REM == R;
-    fft_pass<T, E, P, NS, R, INV, FIRST, LAST>(v, x, t, tw);
-    if constexpr (!LAST) fft_passes<T, E, P, NS * R, INV, false>(v, x, t, tw);
+    fft_pass<T, E, P, NS, R, INV, FIRST, LAST, PP, A>(v, x, t, tw);
+    if constexpr (!LAST) fft_passes<T, E, P, NS * R, INV, false, PP, A ^ 1>(v, x, t, tw);
 }
 
 // Elements per thread for a length-P transform.
 __host__ __device__ constexpr int fft_elems(int P) { return P >= 1024 ? 16 : (P == 512 ? 8 : 4); }
-
-// Full transform of length P = 2^LOGP: v holds x[t + G q] on entry and
-// X[t + G q] on exit.  x is an LDS scratch area of P elements.
-template <typename T, int LOGP, bool INV>
-__device__ __forceinline__ void fft_strided(C2<T> (&v)[fft_elems(1 << LOGP)], C2<T> *x, int t,
-                                            const C2<T> *tw)
-{
-    constexpr int P = 1 << LOGP;
-    fft_passes<T, fft_elems(P), P, 1, INV, true>(v, x, t, tw);
-}
 
 }  // namespace gct

@@ -23,8 +23,8 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb)
     return b < q * X ? (b % X) * q + b / X : b;
 }
 
-// Twiddles go to LDS after the data area when both fit in 64 KB, else they
-// are read from the plan's global table.
+// Twiddles go to LDS after the data area (fft_data_elems entries) when
+// both fit in 64 KB, else they are read from the plan's global table.
 template <typename T>
 __host__ __device__ constexpr bool twiddles_in_lds(int P)
 {
@@ -372,12 +372,13 @@ __device__ __forceinline__ void body_spec_cols(int col, const C2<T> *__restrict_
     for (int q = 0; q < E; ++q) Ghat[(size_t)col * P + t + Gt * q] = v[q].x * scale;
 }
 
-// LDS bytes of a pass kernel: data (P) + twiddles (P/2, when in LDS), at
-// least blockDim doubles for the reductions.
+// LDS bytes of a pass kernel: data (P, or 2P with ping-pong) + twiddles
+// (P/2, when in LDS), at least blockDim doubles for the reductions.
 template <typename T>
 inline size_t fft_lds_bytes(int P, int E)
 {
-    size_t b = (size_t)P * sizeof(C2<T>) + (twiddles_in_lds<T>(P) ? (size_t)(P / 2) * sizeof(C2<T>) : 0);
+    size_t b = (size_t)fft_data_elems<T>(P) * sizeof(C2<T>) +
+               (twiddles_in_lds<T>(P) ? (size_t)(P / 2) * sizeof(C2<T>) : 0);
     const size_t red = (size_t)(P / E) * sizeof(double);
     return b > red ? b : red;
 }

@@ -33,7 +33,7 @@ k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, const C2<T>
     // data first, then the twiddles: their latencies overlap
     C2<T> v[E];
     rows_fwd_load<T, LOGP, E>(2 * rp, src, N, nullptr, T(0), v);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
     rows_fwd_regs<T, LOGP, E>(2 * rp, v, W1, N, x, tws);
 }
@@ -49,7 +49,7 @@ k_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict
     C2<T> v[E];
     T gs[E];
     cols_load<T, LOGP, E>(blockIdx.x, W1, Ghat, N, v, gs);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
     cols_regs<T, LOGP, E>(blockIdx.x, v, gs, W2, N, x, tws);
 }
@@ -64,7 +64,7 @@ k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, const C2<T> *
     const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
     C2<T> v[E];
     rows_inv_load<T, LOGP, E>(2 * rp, W2, N, v);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
     fft_passes<T, E, P, 1, true, true>(v, x, threadIdx.x, tws);
     (void)rows_inv_store<T, LOGP, E>(2 * rp, v, y, N, nullptr);
@@ -77,7 +77,7 @@ k_spec_rows(const T *__restrict__ G, C2<T> *__restrict__ R, int N, const C2<T> *
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / fft_elems(P)>(x + P, tw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / fft_elems(P)>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
     body_spec_rows<T, LOGP, fft_elems(P)>(xcd_swizzle(blockIdx.x, gridDim.x), G, R, N, x, tws);
 }
@@ -90,7 +90,7 @@ k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat, const C2<T> *__re
     constexpr int P = 1 << LOGP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / fft_elems(P)>(x + P, tw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / fft_elems(P)>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
     body_spec_cols<T, LOGP, fft_elems(P)>(blockIdx.x, R, Ghat, x, tws, scale);
 }
@@ -186,7 +186,7 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
     if (pend) {
         // twiddles to LDS behind the data area (the reduction below uses
         // its start): their latency overlaps the loads above
-        const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(xs + P, tw);
+        const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(xs + fft_data_elems<T>(P), tw);
         double g, dl;
         dot_pair<G, KP>(part, np, pg, pd, red, g, dl);
         const int64_t u = st->k;  // updates so far: g = ||r_u||^2
@@ -258,7 +258,7 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
         st->pend[par ^ 1] = 1;  // first launch: transform r_0 only
         st->stat[par ^ 1] = CG_RUNNING;
     }
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(xs + P, tw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(xs + fft_data_elems<T>(P), tw);
     __syncthreads();
     body_rows_fwd<T, LOGP, E>(ra, r, W1, N, xs, tws, nullptr, T(0));
 }
@@ -277,7 +277,7 @@ k_cgf_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__rest
     T gs[E];
     cols_load<T, LOGP, E>(blockIdx.x, W1, Ghat, N, v, gs);
     if (stat != CG_RUNNING) return;
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
     cols_regs<T, LOGP, E>(blockIdx.x, v, gs, W2, N, x, tws);
 }
@@ -308,7 +308,7 @@ k_cgf_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ w, const T *__restr
     C2<T> v[E];
     rows_inv_load<T, LOGP, E>(ra, W2, N, v);
     if (stat != CG_RUNNING) return;
-    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + P, tw);
+    const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
     fft_passes<T, E, P, 1, true, true>(v, x, threadIdx.x, tws);
     double g = 0.0, dl = 0.0;

@@ -63,6 +63,24 @@ def test_pipelined_warm_start_matches_sequential(setup):
     assert all(r.status == gct.GCT_OK and r.rel_res_true <= 1.05e-4 for r in res)
 
 
+def test_batched_inference_warm_start(setup):
+    """Inference for a group of slices in one forward of a batch-16 net
+    with the trained weights: start vectors equal to the batch-1 net's to
+    rounding (the layers may take other tilings at another batch), iteration
+    counts within two of the sequential warm solves, every solve meeting the
+    stopping rule."""
+    gct, W, prob, b, xs, iters = setup
+    ws = W.WarmStart(prob, W.trained_path())
+    cmp = W.compare(prob, ws, b)
+    ms, res, dev = W.batched(prob, ws, b, batch=16)
+    say("batched warm ms per slice", ms, "sequential warm", np.mean(cmp["warm_ms"]),
+        "plain", np.mean(cmp["plain_ms"]), "start deviation", dev)
+    assert dev <= 1e-2
+    assert len(res) == b.shape[0]
+    assert all(abs(r.iters - k) <= 2 for r, k in zip(res, cmp["warm_iters"]))
+    assert all(r.status == gct.GCT_OK and r.rel_res_true <= 1.05e-4 for r in res)
+
+
 def test_warm_iterate_is_close_to_the_cg_target(setup):
     """x0 from the net is a rough reconstruction: relative error against the
     plain-CG solution well below 1 on every slice."""

@@ -358,33 +358,85 @@ __global__ void __launch_bounds__(256) k_bp_reduce(const T *__restrict__ part, i
     }
 }
 
-// Angle groups of the tiled kernel: enough for about 1024 blocks (at most
-// 16, and at least 8 angles each).
-int bp_angle_groups(const gct_plan *p)
+// Tiled kernel for the plan's kernel shape (taps JM, Horner length HN).
+template <typename T>
+static const void *bp_tile_fn(const gct_plan *p)
 {
-    const long long tiles = (long long)((p->N + BP_TX - 1) / BP_TX) * ((p->N + BP_TY - 1) / BP_TY);
-    long long g = (1024 + tiles - 1) / tiles;
-    g = std::min<long long>(g, 16);
-    g = std::min<long long>(g, std::max(1, p->n / 8));
-    return (int)std::max<long long>(g, 1);
+    const int hn = p->bp.D1 <= 4 ? 4 : (p->bp.D1 <= 6 ? 6 : 8);
+    if (p->bp.J <= 8)
+        return hn == 4 ? reinterpret_cast<const void *>(&k_bp_tile<T, 8, 4>)
+                       : (hn == 6 ? reinterpret_cast<const void *>(&k_bp_tile<T, 8, 6>)
+                                  : reinterpret_cast<const void *>(&k_bp_tile<T, 8, 8>));
+    return hn == 4 ? reinterpret_cast<const void *>(&k_bp_tile<T, 16, 4>)
+                   : (hn == 6 ? reinterpret_cast<const void *>(&k_bp_tile<T, 16, 6>)
+                              : reinterpret_cast<const void *>(&k_bp_tile<T, 16, 8>));
 }
 
-// Angles per chunk of the tiled kernel: the largest of 8, 4, 2, 1 whose
-// tables fit in 64 KB (0 if none fits or the tables exceed the kernel's
-// limits: 8 coefficients, 16 taps).
-static int bp_tile_chunk(const gct_plan *p, size_t elem, int &rmax, size_t &lds)
+// Bins of a tile's window and the LDS bytes of the tiled kernel for `ch`
+// angles per chunk.
+static int bp_rmax(const gct_plan *p) { return (int)std::ceil(p->bp.tile_win) + 4; }
+static size_t bp_tile_lds(const gct_plan *p, size_t elem, int ch)
 {
-    rmax = (int)std::ceil(p->bp.tile_win) + 4;
-    if (p->bp.D1 > 8 || p->bp.J > 16) return 0;
-    const int jm = p->bp.J <= 8 ? 8 : 16;  // the kernel's tap count JM
+    const int rmax = bp_rmax(p), jm = p->bp.J <= 8 ? 8 : 16;  // the kernel's tap count JM
     const size_t per = (size_t)rmax * p->bp.smax * 8 + (size_t)p->bp.smax * p->bp.J * p->bp.D1 +
                        (rmax + jm) + p->bp.smax + 3;
-    for (int ch = 8; ch >= 1; ch >>= 1) {
-        lds = ch * per * elem + ch * 4 * sizeof(int);
-        if (lds <= 65536) return ch;
-    }
-    return 0;
+    return ch * per * elem + ch * 4 * sizeof(int);
 }
+
+// Launch shape of the tiled kernel for one element size, chosen for
+// occupancy.  Angles per chunk: among 8, 4, 2, 1 with tables within 64 KB,
+// the one that keeps the most blocks resident per CU
+// (hipOccupancyMaxActiveBlocksPerMultiprocessor: registers and LDS), the
+// larger on a tie (fewer chunk set-ups).  Angle groups g <= min(32, n / 8)
+// minimising ceil(tiles g / resident blocks of the chip) / g: a block's
+// work shrinks as 1/g, and a last round of blocks that fills only part of
+// the chip leaves CUs idle; the smaller g on a tie (fewer partial images).
+template <typename T>
+static void bp_configure_t(gct_plan *p, int t)
+{
+    p->bp_ch[t] = 0;
+    p->bp_groups[t] = 1;
+    if (p->bp.D1 > 8 || p->bp.J > 16) return;  // beyond the kernel's limits
+    const void *fn = bp_tile_fn<T>(p);
+    int best_ch = 0, best_nb = 0;
+    for (int ch : {8, 4, 2, 1}) {
+        const size_t lds = bp_tile_lds(p, sizeof(T), ch);
+        if (lds > 65536) continue;
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds) != hipSuccess) nb = 1;
+        if (nb > best_nb) {
+            best_nb = nb;
+            best_ch = ch;
+        }
+    }
+    if (best_ch == 0) return;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1)
+        cus = 256;
+    const long long tiles = (long long)((p->N + BP_TX - 1) / BP_TX) * ((p->N + BP_TY - 1) / BP_TY);
+    const long long slots = (long long)std::max(best_nb, 1) * cus;
+    const int gmax = std::max(1, std::min(32, p->n / 8));
+    int best_g = 1;
+    double best_cost = 1e300;
+    for (int g = 1; g <= gmax; ++g) {
+        const double cost = (double)((tiles * g + slots - 1) / slots) / g;
+        if (cost < best_cost * (1.0 - 1e-12)) {
+            best_cost = cost;
+            best_g = g;
+        }
+    }
+    p->bp_ch[t] = best_ch;
+    p->bp_groups[t] = best_g;
+}
+
+void bp_configure(gct_plan *p)
+{
+    bp_configure_t<float>(p, 0);
+    bp_configure_t<double>(p, 1);
+    (void)hipGetLastError();  // an occupancy query that failed leaves no error behind
+}
+
+int bp_angle_groups(const gct_plan *p, size_t elem) { return p->bp_groups[elem == 4 ? 0 : 1]; }
 
 // Tile side, bins per tile window and angles per chunk such that the LDS
 // stays within 64 KB: 32 x 32 tiles when they fit, else 16 x 16.
@@ -414,11 +466,11 @@ hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, hip
     const T *brk_ = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.bp_brk_f32 : p->dev.bp_brk_f64);
     const T *coef_ = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.bp_coef_f32 : p->dev.bp_coef_f64);
     {
-        int rmax;
-        size_t lds;
-        const int ch = bp_tile_chunk(p, sizeof(T), rmax, lds);
+        const int t = sizeof(T) == 4 ? 0 : 1;
+        const int ch = p->bp_ch[t], rmax = bp_rmax(p);
+        const size_t lds = bp_tile_lds(p, sizeof(T), ch);
         if (ch > 0) {
-            const int groups = bp_angle_groups(p);
+            const int groups = p->bp_groups[t];
             const dim3 grid((N + BP_TX - 1) / BP_TX, (N + BP_TY - 1) / BP_TY, groups);
             T *dst = groups > 1 ? part : b;
             const double *geo_ = reinterpret_cast<const double *>(p->dev.bp_geo);

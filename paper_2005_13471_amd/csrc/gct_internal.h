@@ -156,6 +156,9 @@ struct gct_plan {
     int32_t fft_e[2], fft_ec[2];
     int32_t cg_e[2], cg_ec[2];
     gct::BPDims bp;
+    // launch shape of the tiled back projection, [F32, F64] (bp_configure):
+    // angles per chunk (0: the tiled kernel does not apply) and angle groups
+    int32_t bp_ch[2], bp_groups[2];
     gct::DeviceTables dev;
     int device;
     // cached CG iteration graphs and the stream they are captured on
@@ -200,7 +203,8 @@ hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s
 
 template <typename T>
 hipError_t launch_backproject(const gct_plan *p, const T *prefiltered, T *b, T *partial, hipStream_t s);
-int bp_angle_groups(const gct_plan *p);
+int bp_angle_groups(const gct_plan *p, size_t elem);
+void bp_configure(gct_plan *p);
 
 template <typename T>
 hipError_t launch_forward(const gct_plan *p, const T *c, T *g, hipStream_t s);

@@ -496,6 +496,7 @@ int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
             delete p;
             return rc;
         }
+        bp_configure(p);
         *plan = p;
         return GCT_OK;
     } catch (const std::exception &e) {
@@ -541,7 +542,7 @@ size_t gct_workspace_size(const gct_plan *p, int op, gct_dtype dt)
     case GCT_OP_GRAM_APPLY: return apply_ws_bytes(p, e);
     case GCT_OP_BACKPROJECT: {
         // prefiltered sinogram, then one partial image per angle group
-        const int g = bp_angle_groups(p);
+        const int g = bp_angle_groups(p, e);
         return align256((size_t)p->n * (p->M + 2 * p->K) * e) +
                (g > 1 ? align256((size_t)g * p->N * p->N * e) : 0);
     }

@@ -14,6 +14,7 @@
 // them, updates x, r and p on its rows and transforms p.  In exact
 // arithmetic these are the textbook CG iterates.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 
 #include "gct_internal.h"
@@ -148,6 +149,30 @@ __global__ void __launch_bounds__(256) k_cgf_norm(CGState *st, const double *par
     }
 }
 
+// The solver state copied to the pinned host buffer by the GPU itself (plain
+// vector stores over the host link, then a system-scope fence): no copy
+// engine in the host's check of a chunk.
+__global__ void __launch_bounds__(64) k_state_out(const CGState *st, CGState *out)
+{
+    constexpr int nw = (int)(sizeof(CGState) / sizeof(int64_t));
+    static_assert(sizeof(CGState) % sizeof(int64_t) == 0, "state words");
+    const int64_t *src = reinterpret_cast<const int64_t *>(st);
+    int64_t *dst = reinterpret_cast<int64_t *>(out);
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) dst[i] = src[i];
+    __threadfence_system();
+}
+
+// Waits for an event by polling it (no sleep between polls: a chunk ends
+// within microseconds of the check, and a yielding wait adds its wake-up
+// latency to every check).
+static hipError_t spin_wait(hipEvent_t e)
+{
+    for (;;) {
+        const hipError_t q = hipEventQuery(e);
+        if (q != hipErrorNotReady) return q;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) k_fill_one(T *v, size_t n)
 {
@@ -265,7 +290,8 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     gct_plan *pm = const_cast<gct_plan *>(p);
     if (!pm->cg_pin) {
         void *h = nullptr;
-        GCT_TRY(hipHostMalloc(&h, sizeof(CGState), hipHostMallocDefault));
+        // coherent: the GPU writes it directly (k_state_out)
+        GCT_TRY(hipHostMalloc(&h, sizeof(CGState), hipHostMallocCoherent));
         pm->cg_pin = reinterpret_cast<CGState *>(h);
     }
     if (!pm->cg_ev) GCT_TRY(hipEventCreateWithFlags(&pm->cg_ev, hipEventDisableTiming));
@@ -329,7 +355,8 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
             if (e != hipSuccess) return check_hip(e, "cg chunk launch");
         }
         launched += chunk;
-        hipError_t e = hipMemcpyAsync(pin, st, sizeof(CGState), hipMemcpyDeviceToHost, s);
+        hipLaunchKernelGGL(k_state_out, dim3(1), dim3(64), 0, s, (const CGState *)st, pin);
+        hipError_t e = hipGetLastError();
         if (e == hipSuccess) e = hipEventRecord(pm->cg_ev, s);
         return check_hip(e, "cg state copy");
     };
@@ -347,7 +374,8 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
         int64_t kprev = 0;
         bool first = true;
         for (;;) {
-            GCT_TRY(hipEventSynchronize(pm->cg_ev));
+            GCT_TRY(spin_wait(pm->cg_ev));
+            std::atomic_thread_fence(std::memory_order_acquire);
             hs = *pin;
             if (first) {
                 if (hist) hist[0] = hs.bb > 0.0 ? std::sqrt(hs.rr0 / hs.bb) : 0.0;
@@ -382,9 +410,11 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     GCT_TRY(launch_gram_apply<T>(p, Ghat, x, Ap, aws, s));
     hipLaunchKernelGGL(k_resid<T>, dim3(VBLK), dim3(256), 0, s, b, Ap, n, part);
     hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, part, VBLK, &st->pad);
+    hipLaunchKernelGGL(k_state_out, dim3(1), dim3(64), 0, s, (const CGState *)st, pin);
     GCT_TRY(hipGetLastError());
-    GCT_TRY(hipMemcpyAsync(&pin->pad, &st->pad, sizeof(double), hipMemcpyDeviceToHost, s));
-    GCT_TRY(hipStreamSynchronize(s));
+    GCT_TRY(hipEventRecord(pm->cg_ev, s));
+    GCT_TRY(spin_wait(pm->cg_ev));
+    std::atomic_thread_fence(std::memory_order_acquire);
     const double rt = pin->pad;
 
     res->iters = (int32_t)hs.k;

@@ -204,6 +204,19 @@ hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s
 template <typename T>
 hipError_t launch_backproject(const gct_plan *p, const T *prefiltered, T *b, T *partial, hipStream_t s);
 int bp_angle_groups(const gct_plan *p, size_t elem);
+
+// Default elements per thread of the row passes and of the column pass for a
+// transform of size P (what the autotuner picks on MI355X at P = 1024: the
+// row passes fastest with 256 threads per transform, the column pass with
+// 128; elsewhere the largest tile, 256 threads at most per transform).
+inline void default_pass_elems(int P, int &rows, int &cols)
+{
+    rows = cols = P >= 1024 ? 16 : (P == 512 ? 8 : 4);
+    if (P == 1024) {
+        rows = 4;
+        cols = 8;
+    }
+}
 void bp_configure(gct_plan *p);
 
 template <typename T>

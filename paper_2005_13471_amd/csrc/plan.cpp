@@ -486,9 +486,11 @@ int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
         }
         p->P = P;
         p->logP = logP;
-        // elements per thread of the apply passes until gct_plan_autotune
-        p->fft_e[0] = p->fft_e[1] = P >= 1024 ? 16 : (P == 512 ? 8 : 4);
-        p->fft_ec[0] = p->fft_ec[1] = p->cg_e[0] = p->cg_e[1] = p->cg_ec[0] = p->cg_ec[1] = p->fft_e[0];
+        // elements per thread of the transform passes until gct_plan_autotune
+        int er, ec;
+        default_pass_elems(P, er, ec);
+        p->fft_e[0] = p->fft_e[1] = p->cg_e[0] = p->cg_e[1] = er;
+        p->fft_ec[0] = p->fft_ec[1] = p->cg_ec[0] = p->cg_ec[1] = ec;
         if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
         rc = build_plan(geom, p);
         if (rc) {
@@ -686,9 +688,10 @@ int gct_sd_solve(const gct_plan *p, gct_dtype dt, const void *Ghat, const void *
 int gct_plan_set_pass_elems(gct_plan *p, gct_dtype dt, int32_t Er, int32_t Ec)
 {
     CHECK_PLAN_DT(p, dt);
-    const int E0 = p->P >= 1024 ? 16 : (p->P == 512 ? 8 : 4);
-    if (Er == 0) Er = E0;
-    if (Ec == 0) Ec = E0;
+    int dr, dc;
+    default_pass_elems(p->P, dr, dc);
+    if (Er == 0) Er = dr;
+    if (Ec == 0) Ec = dc;
     if (!apply_e_ok(p->logP, Er) || !apply_e_ok(p->logP, Ec))
         return fail(GCT_EINVAL, "elements per thread not available for this transform size");
     const int t = dt == GCT_F32 ? 0 : 1;

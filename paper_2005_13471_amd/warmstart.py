@@ -66,6 +66,8 @@ class Problem:
         self.G0 = float(G[(cfg.N - 1) * W + (cfg.N - 1)].item())
         self.ws_bp = P.workspace(gct.OP_BACKPROJECT)
         self.ws_cg = P.workspace(gct.OP_CG)
+        # transform tilings of the apply and the fused CG passes for this size
+        gct.plan_autotune(P, self.Ghat, self.ws_cg, reps=10)
         self.S = int(batch_slices)
         self.batch = gct.Batch([P] * self.S)
         self.bGhat = torch.empty(self.batch.spectrum_elems, dtype=torch.float32, device="cuda")

@@ -362,6 +362,12 @@ def warm_compare(slices: int):
                              "max_rel_res_true": float(max(r.rel_res_true for r in res_b)),
                              "start_dev_vs_batch1": dev_b,
                              "note": "U-Net inference for 16 slices at a time, then each CG from its start"}
+    st = W.stacked(prob, ws, b)
+    rep["stack_batched_solver"] = {k: {"ms_per_slice": v[0], "iters_mean": float(np.mean([r.iters for r in v[1]])),
+                                       "max_rel_res_true": float(max(r.rel_res_true for r in v[1]))}
+                                   for k, v in st.items()}
+    rep["stack_batched_solver"]["note"] = (f"the slices as one stack through the batched solver ({prob.S} per solve), "
+                                           "plain from zero vs warm from the U-Net (32 slices per forward)")
     rep.update(workload="n256_a180_m366_z1", seeds=[W.TEST_SEEDS[0], W.TEST_SEEDS[0] + slices],
                net=f"U-Net {cfg.levels} levels, {cfg.base_channels} base channels, bf16",
                trained_steps=ws.meta.get("step"))

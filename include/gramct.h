@@ -287,6 +287,15 @@ int gct_batch_cg_solve(const gct_batch *batch, gct_dtype dtype, const void *Ghat
                        void *x, double rtol, int32_t max_iter, int32_t check_every,
                        gct_cg_result *results, void *ws, void *stream);
 
+/* As gct_batch_cg_solve, starting from the iterates in x (the learned warm
+ * start of a stack of slices, Sec. 6.2's iteration from a given image): per
+ * slice r = b - A x_0; a slice whose ||b - A x_0|| >= ||b|| (or not finite)
+ * starts from zero instead (results[i].fell_back = 1), and
+ * results[i].rel_res0 reports the start actually used. */
+int gct_batch_cg_solve_x0(const gct_batch *batch, gct_dtype dtype, const void *Ghat, const void *b,
+                          void *x, double rtol, int32_t max_iter, int32_t check_every,
+                          gct_cg_result *results, void *ws, void *stream);
+
 /* Autotuner: for each FFT size of the batch, times the batched apply with
  * each candidate number of elements per thread of the transforms (the work
  * tile of one thread), for the row passes and for the column pass in turn,

@@ -281,47 +281,78 @@ __device__ __forceinline__ double bsum(double v)
     return block_sum_lds(v, red);
 }
 
+// r = b - A x (Ax given: start vector) or r = b, x = 0; p = r; partial
+// ||r||^2 and ||b||^2 per (slice, block).
 template <typename T>
 __global__ void __launch_bounds__(256)
 kb_cg_init(const BatchSlice *__restrict__ sl, const T *__restrict__ b, T *__restrict__ x,
-           T *__restrict__ r, T *__restrict__ p, double *__restrict__ prr, double *__restrict__ pbb)
+           T *__restrict__ r, T *__restrict__ p, const T *__restrict__ Ax, double *__restrict__ prr,
+           double *__restrict__ pbb)
 {
     const int s = blockIdx.x / BVB, j = blockIdx.x % BVB;
     const BatchSlice &d = sl[s];
     const size_t n = (size_t)d.N * d.N;
-    double rr = 0.0;
+    double rr = 0.0, bb = 0.0;
     for (size_t i = (size_t)j * blockDim.x + threadIdx.x; i < n; i += (size_t)BVB * blockDim.x) {
         const size_t g = d.img + i;
         const T bi = b[g];
-        x[g] = T(0);
-        r[g] = bi;
-        p[g] = bi;
-        rr += (double)bi * (double)bi;
+        T ri = bi;
+        if (Ax) ri = bi - Ax[g];
+        else x[g] = T(0);
+        r[g] = ri;
+        p[g] = ri;
+        rr += (double)ri * (double)ri;
+        bb += (double)bi * (double)bi;
     }
     rr = bsum(rr);
+    bb = bsum(bb);
     if (threadIdx.x == 0) {
         prr[blockIdx.x] = rr;
-        pbb[blockIdx.x] = rr;
+        pbb[blockIdx.x] = bb;
     }
 }
 
+// Per slice: the start's residual norm, ||b||, the stopping threshold; with
+// a start vector, the fallback to zero when ||b - A x_0|| >= ||b|| (or is
+// not finite), as in the single-slice solver (fb = 1: kb_cg_fallback_vec
+// resets the vectors).
 __global__ void __launch_bounds__(256)
-kb_cg_init_fin(CGState *st, const double *prr, double rtol2)
+kb_cg_init_fin(CGState *st, const double *prr, const double *pbb, double rtol2, int use_x0)
 {
     const int s = blockIdx.x;
-    double v = threadIdx.x < BVB ? prr[s * BVB + threadIdx.x] : 0.0;
-    const double rr = bsum(v);
+    const double rr_ = bsum(threadIdx.x < BVB ? prr[s * BVB + threadIdx.x] : 0.0);
+    const double bb = bsum(threadIdx.x < BVB ? pbb[s * BVB + threadIdx.x] : 0.0);
     if (threadIdx.x == 0) {
         CGState &c = st[s];
+        const bool drop = use_x0 && bb > 0.0 && !(rr_ < bb);
+        const double rr = drop ? bb : rr_;
         c.rr = rr;
-        c.bb = rr;
+        c.bb = bb;
         c.rr0 = rr;
         c.beta = 0.0;
-        c.thr2 = rtol2 * rr;
+        c.thr2 = rtol2 * bb;
         c.k = 0;
         c.ring[0] = rr;
+        c.fb = drop ? 1 : 0;
         c.status = (rr <= c.thr2) ? CG_CONVERGED : CG_RUNNING;
-        if (!(rr == rr)) c.status = CG_BREAKDOWN;
+        if (!(rr == rr) || !(bb == bb)) c.status = CG_BREAKDOWN;
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+kb_cg_fallback_vec(const CGState *st, const BatchSlice *__restrict__ sl, const T *__restrict__ b,
+                   T *__restrict__ x, T *__restrict__ r, T *__restrict__ p)
+{
+    const int s = blockIdx.x / BVB, j = blockIdx.x % BVB;
+    if (!st[s].fb) return;
+    const BatchSlice &d = sl[s];
+    const size_t n = (size_t)d.N * d.N;
+    for (size_t i = (size_t)j * blockDim.x + threadIdx.x; i < n; i += (size_t)BVB * blockDim.x) {
+        const size_t g = d.img + i;
+        x[g] = T(0);
+        r[g] = b[g];
+        p[g] = b[g];
     }
 }
 
@@ -612,7 +643,7 @@ hipError_t batch_spectrum(const gct_batch *b, const T *G, T *Ghat, void *ws, hip
     } while (0)
 
 template <typename T>
-int batch_cg(const gct_batch *b, const T *Ghat, const T *bv, T *x, double rtol, int max_iter,
+int batch_cg(const gct_batch *b, const T *Ghat, const T *bv, T *x, int use_x0, double rtol, int max_iter,
              int check_every, gct_cg_result *res, void *ws, hipStream_t s)
 {
     const BLayout L = blayout(b, sizeof(T));
@@ -626,8 +657,12 @@ int batch_cg(const gct_batch *b, const T *Ghat, const T *bv, T *x, double rtol, 
     const BatchSlice *sl = b->dev[dti<T>()];
     const int S = b->S;
     if (check_every <= 0) check_every = 8;
-    hipLaunchKernelGGL(kb_cg_init<T>, dim3(S * BVB), dim3(256), 0, s, sl, bv, x, r, p, upart, upart2);
-    hipLaunchKernelGGL(kb_cg_init_fin, dim3(S), dim3(256), 0, s, st, upart, rtol * rtol);
+    if (use_x0) B_TRY(batch_apply_passes<T>(b, Ghat, x, Ap, ws, s, nullptr, nullptr, nullptr, nullptr));
+    hipLaunchKernelGGL(kb_cg_init<T>, dim3(S * BVB), dim3(256), 0, s, sl, bv, x, r, p,
+                       use_x0 ? (const T *)Ap : nullptr, upart, upart2);
+    hipLaunchKernelGGL(kb_cg_init_fin, dim3(S), dim3(256), 0, s, st, (const double *)upart,
+                       (const double *)upart2, rtol * rtol, use_x0);
+    if (use_x0) hipLaunchKernelGGL(kb_cg_fallback_vec<T>, dim3(S * BVB), dim3(256), 0, s, (const CGState *)st, sl, bv, x, r, p);
     B_TRY(hipGetLastError());
     std::vector<CGState> hs(S);
     auto pull = [&]() -> int {
@@ -704,7 +739,7 @@ int batch_cg(const gct_batch *b, const T *Ghat, const T *bv, T *x, double rtol, 
         o.rel_res = rel(c.rr);
         o.rel_res_true = rel(c.pad);
         o.rel_res0 = rel(c.rr0);
-        o.fell_back = 0;
+        o.fell_back = (int32_t)c.fb;
         o.status = c.status == CG_CONVERGED ? GCT_OK
                    : c.status == CG_BREAKDOWN ? GCT_EBREAKDOWN
                                               : GCT_ENOTCONV;
@@ -906,9 +941,9 @@ int gct_batch_gram_apply(const gct_batch *b, gct_dtype dt, const void *Ghat, con
     return check_hip(e, "batch gram_apply launch");
 }
 
-int gct_batch_cg_solve(const gct_batch *b, gct_dtype dt, const void *Ghat, const void *bv, void *x,
-                       double rtol, int32_t max_iter, int32_t check_every, gct_cg_result *results,
-                       void *ws, void *stream)
+static int batch_cg_solve(const gct_batch *b, gct_dtype dt, const void *Ghat, const void *bv, void *x, int use_x0,
+                          double rtol, int32_t max_iter, int32_t check_every, gct_cg_result *results,
+                          void *ws, void *stream)
 {
     CHECK_BATCH_DT(b, dt);
     if (!Ghat || !bv || !x || !ws || !results) return fail(GCT_EINVAL, "NULL argument");
@@ -916,13 +951,27 @@ int gct_batch_cg_solve(const gct_batch *b, gct_dtype dt, const void *Ghat, const
     if (max_iter < 0 || !(rtol >= 0.0)) return fail(GCT_EINVAL, "bad max_iter or rtol");
     if (reinterpret_cast<uintptr_t>(ws) & 255u) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    int rc = dt == GCT_F32 ? batch_cg<float>(b, (const float *)Ghat, (const float *)bv, (float *)x,
+    int rc = dt == GCT_F32 ? batch_cg<float>(b, (const float *)Ghat, (const float *)bv, (float *)x, use_x0,
                                              rtol, max_iter, check_every, results, ws, s)
                            : batch_cg<double>(b, (const double *)Ghat, (const double *)bv,
-                                              (double *)x, rtol, max_iter, check_every, results, ws, s);
+                                              (double *)x, use_x0, rtol, max_iter, check_every, results, ws, s);
     if (rc == GCT_ENOTCONV) set_error("batch cg_solve: some slices reached max_iter");
     if (rc == GCT_EBREAKDOWN) set_error("batch cg_solve: breakdown in some slice");
     return rc;
+}
+
+int gct_batch_cg_solve(const gct_batch *b, gct_dtype dt, const void *Ghat, const void *bv, void *x,
+                       double rtol, int32_t max_iter, int32_t check_every, gct_cg_result *results,
+                       void *ws, void *stream)
+{
+    return batch_cg_solve(b, dt, Ghat, bv, x, 0, rtol, max_iter, check_every, results, ws, stream);
+}
+
+int gct_batch_cg_solve_x0(const gct_batch *b, gct_dtype dt, const void *Ghat, const void *bv, void *x,
+                          double rtol, int32_t max_iter, int32_t check_every, gct_cg_result *results,
+                          void *ws, void *stream)
+{
+    return batch_cg_solve(b, dt, Ghat, bv, x, 1, rtol, max_iter, check_every, results, ws, stream);
 }
 
 int gct_batch_get_pass_elems(const gct_batch *b, gct_dtype dt, int32_t *out)

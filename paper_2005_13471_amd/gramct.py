@@ -105,6 +105,8 @@ def _load():
     L.gct_batch_gram_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
     L.gct_batch_cg_solve.argtypes = [vp, ctypes.c_int, vp, vp, vp, dbl, i32, i32,
                                      ctypes.POINTER(_CGResult), vp, vp]
+    L.gct_batch_cg_solve_x0.argtypes = [vp, ctypes.c_int, vp, vp, vp, dbl, i32, i32,
+                                        ctypes.POINTER(_CGResult), vp, vp]
     L.gct_batch_autotune.argtypes = [vp, ctypes.c_int, vp, vp, i32, ctypes.POINTER(i32), vp]
     L.gct_batch_get_pass_elems.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32)]
     L.gct_host_boxspline_eval.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.c_int, dbl,
@@ -402,9 +404,11 @@ def batch_gram_apply(batch: Batch, Ghat: torch.Tensor, c: torch.Tensor, y: torch
 
 def batch_cg_solve(batch: Batch, Ghat: torch.Tensor, b: torch.Tensor, x: torch.Tensor,
                    ws: torch.Tensor, rtol: float = 1e-4, max_iter: int = 1000,
-                   check_every: int = 8) -> list:
+                   check_every: int = 8, use_x0: bool = False) -> list:
+    """CG on every slice, from zero or (use_x0) from the iterates in x."""
     res = (_CGResult * batch.slices)()
-    rc = lib.gct_batch_cg_solve(batch.handle, _dt(b), _ptr(Ghat, batch.spectrum_elems, b.dtype),
+    fn = lib.gct_batch_cg_solve_x0 if use_x0 else lib.gct_batch_cg_solve
+    rc = fn(batch.handle, _dt(b), _ptr(Ghat, batch.spectrum_elems, b.dtype),
                                 _ptr(b, batch.image_elems), _ptr(x, batch.image_elems, b.dtype),
                                 float(rtol), int(max_iter), int(check_every), res,
                                 _ptr(ws, batch.workspace_size(OP_CG, b.dtype)), _stream())

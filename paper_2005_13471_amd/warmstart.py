@@ -441,6 +441,56 @@ def batched(prob: Problem, ws: WarmStart, b_all: torch.Tensor, batch: int = 16, 
     return ms, res, dev
 
 
+def stacked(prob: Problem, ws: WarmStart, b_all: torch.Tensor, net_batch: int = 32, check_every: int = 8):
+    """A stack of slices (one geometry, as the slices of a parallel-beam
+    volume) through the batched solver, prob.S slices per solve, plain (from
+    zero) and warm (start vectors from the U-Net, net_batch slices per
+    forward, then gct_batch_cg_solve_x0).  Returns {"plain": (ms per slice,
+    results), "warm": (...)}; host clock over the whole stack, inference
+    included in warm."""
+    cfg = prob.cfg
+    S_all, N, G = b_all.shape[0], cfg.N, prob.S
+    net = gct.UNet(cfg.levels, cfg.base_channels, N, N, net_batch)
+    w = torch.empty(ws.net.n_params, dtype=torch.float32, device="cuda")
+    gct.unet_get_params(ws.net, w)
+    gct.unet_set_params(net, w)
+    b_in = torch.zeros(net_batch, N, N, dtype=torch.float32, device="cuda")
+    x0 = torch.empty(net_batch, N, N, dtype=torch.float32, device="cuda")
+    bb = torch.zeros(prob.batch.image_elems, dtype=torch.float32, device="cuda")
+    x = torch.zeros_like(bb)
+    bv, xv = bb.view(G, N, N), x.view(G, N, N)
+
+    def run(warm):
+        res = []
+        for g0 in range(0, S_all, G):
+            k = min(G, S_all - g0)
+            bv[:k].copy_(b_all[g0:g0 + k])
+            if k < G:
+                bv[k:].zero_()
+            if warm:
+                for s0 in range(0, k, net_batch):
+                    m = min(net_batch, k - s0)
+                    b_in[:m].copy_(b_all[g0 + s0:g0 + s0 + m])
+                    gct.unet_forward(net, b_in, x0, in_scale=ws.in_scale, out_scale=ws.out_scale, batch=net_batch)
+                    xv[s0:s0 + m].copy_(x0[:m])
+                if k < G:
+                    xv[k:].zero_()
+            r = gct.batch_cg_solve(prob.batch, prob.bGhat, bb, x, prob.ws_bcg, rtol=cfg.rtol, max_iter=1000,
+                                   check_every=check_every, use_x0=warm)
+            res += r[:k]
+        torch.cuda.synchronize()
+        return res
+
+    out = {}
+    for warm in (False, True):
+        run(warm)  # captures
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = run(warm)
+        out["warm" if warm else "plain"] = ((time.perf_counter() - t0) * 1e3 / S_all, res)
+    return out
+
+
 def summarize(cmp: dict) -> dict:
     def st(a):
         a = np.asarray(a, dtype=np.float64)
@@ -492,6 +542,12 @@ def main(argv=None):
         rep["warm_batched16"] = dict(ms_per_slice=ms_b, iters_mean=float(np.mean([r.iters for r in res_b])),
                                      max_rel_res_true=float(max(r.rel_res_true for r in res_b)),
                                      start_dev_vs_batch1=dev_b)
+        st = stacked(prob, ws, b_test)
+        rep["stack_batched_solver"] = {k: dict(ms_per_slice=v[0], iters_mean=float(np.mean([r.iters for r in v[1]])),
+                                               max_rel_res_true=float(max(r.rel_res_true for r in v[1])),
+                                               converged=int(sum(r.status == gct.GCT_OK for r in v[1])))
+                                       for k, v in st.items()}
+        rep["stack_batched_solver"]["slices_per_solve"] = prob.S
         rep.update(checkpoint=os.path.basename(a.eval), step=int(ws.meta.get("step", 0)),
                    batched_target_iters_mean=float(it_test.mean()), seconds=time.time() - t0)
         log(json.dumps(rep))

@@ -133,6 +133,18 @@ def test_batch_cg_matches_single_slice_and_oracle(batch_setup, dt):
         xh = B.image(x, i).double().cpu().numpy()
         rel = np.linalg.norm(bh - oracle.apply(G_or, xh)) / np.linalg.norm(bh)
         assert rel <= (1.1e-4 if dt == torch.float32 else 1.0001e-4)
+    # from start vectors: the converged iterates restart converged; a start
+    # worse than zero (10 b, far from the solution) falls back to zero and
+    # repeats the plain solve's iterations
+    ws = B.workspace(gct.OP_CG, dt)
+    x2 = x.clone()
+    res2 = gct.batch_cg_solve(B, Ghat, b, x2, ws, rtol=1e-4, max_iter=500, check_every=4, use_x0=True)
+    assert all(r.status == gct.GCT_OK and r.iters <= 3 and not r.fell_back and r.rel_res0 <= 1.1e-4 for r in res2)
+    x3 = (10.0 * b).contiguous()
+    res3 = gct.batch_cg_solve(B, Ghat, b, x3, ws, rtol=1e-4, max_iter=500, check_every=4, use_x0=True)
+    say("  fallback iters", [r.iters for r in res3], "plain", [r.iters for r in res])
+    assert all(r.fell_back and r.status == gct.GCT_OK for r in res3)
+    assert [r.iters for r in res3] == [r.iters for r in res]
 
 
 def test_batch_autotune_keeps_results(batch_setup):

@@ -86,6 +86,23 @@ def test_batched_inference_warm_start(setup):
     assert all(r.status == gct.GCT_OK and r.rel_res_true <= 1.05e-4 for r in res)
 
 
+def test_stacked_warm_start_through_the_batched_solver(setup):
+    """The slices as one stack through the batched solver: from zero and
+    from the U-Net's start vectors (gct_batch_cg_solve_x0).  Every slice of
+    both meets the stopping rule, no start falls back, and the warm stack
+    takes fewer iterations on average."""
+    gct, W, prob, b, xs, iters = setup
+    ws = W.WarmStart(prob, W.trained_path())
+    st = W.stacked(prob, ws, b)
+    (ms_p, rp), (ms_w, rw) = st["plain"], st["warm"]
+    ip, iw = np.mean([r.iters for r in rp]), np.mean([r.iters for r in rw])
+    say("stack ms per slice plain", ms_p, "warm", ms_w, "iters", ip, iw)
+    assert len(rp) == len(rw) == b.shape[0]
+    assert all(r.status == gct.GCT_OK and r.rel_res_true <= 1.05e-4 for r in rp + rw)
+    assert not any(r.fell_back for r in rw)
+    assert iw < ip - 3
+
+
 def test_warm_iterate_is_close_to_the_cg_target(setup):
     """x0 from the net is a rough reconstruction: relative error against the
     plain-CG solution well below 1 on every slice."""

@@ -192,6 +192,19 @@ def test_gram_apply_every_transform_tiling(gct, case, elems, dt):
     assert err <= tol("apply", dt)
 
 
+def test_default_transform_tilings(gct):
+    """Default elements per thread (before any autotune): at 1024 points
+    the row passes take 4 and the column pass 8, elsewhere the largest tile;
+    0 restores the default after an explicit choice."""
+    P1024, P512 = CASE_P1024.plan(gct), CASE_P512.plan(gct)
+    assert gct.plan_get_pass_elems(P1024) == (4, 8, 4, 8)
+    assert gct.plan_get_pass_elems(P512) == (8, 8, 8, 8)
+    gct.plan_set_fft_elems(P1024, 16)
+    assert gct.plan_get_pass_elems(P1024) == (16, 16, 16, 16)
+    gct.plan_set_pass_elems(P1024, 0, 0)
+    assert gct.plan_get_pass_elems(P1024) == (4, 8, 4, 8)
+
+
 def test_plan_autotune_then_cg(gct):
     """The autotuner picks a candidate; CG with the tuned plan converges to
     the same stopping rule as with the default tiling, in about as many

@@ -310,6 +310,21 @@ def test_backproject_full(gct, case, dt):
     assert err <= tol("bp", dt)
 
 
+@pytest.mark.parametrize("dt", DTYPES)
+def test_backproject_many_angle_groups(gct, dt):
+    """A small image with many angles: the launch shape splits the angles
+    into 32 groups (partial images summed in group order), the most the
+    plan allows."""
+    case = Case(48, 400, zeta=1.0)
+    say("backproject many groups", case, dt)
+    g = _sino(case, 1003)
+    got = _bp_gpu(gct, case, dt, g)
+    ref = oracle.backproject(case.og(), g)
+    err = normwise(got, ref)
+    say("  normwise", err)
+    assert err <= tol("bp", dt)
+
+
 def test_backproject_config2_sampled(gct):
     case = CFG2
     say("backproject sampled", case)

@@ -374,10 +374,55 @@ def warm_compare(slices: int):
     return rep
 
 
+def bp_sizes_main(args):
+    """The step the paper times (Sec. 6.1): back projection (prefilter,
+    tiled kernel, group reduction) at 64^2 ... 1024^2 with 180 views and
+    lambda_y = lambda_x, without and with detector blur (zeta = 1).
+    Median of 20 timed calls after 3 warm-ups per case; random sinogram
+    values (the kernels' work does not depend on them)."""
+    import torch
+    from paper_2005_13471_amd import gramct as gct
+    from paper_2005_13471_amd import inputs
+
+    torch.cuda.set_device(0)
+    dt = torch.float32
+    n = 180
+    rows = []
+    for N in (64, 128, 256, 512, 1024):
+        row = {"N": N}
+        for zeta in (0.0, 1.0):
+            M = inputs.detector_bins(N, zeta)
+            P = gct.Plan(N, inputs.angles(n), M, zeta=zeta)
+            g = torch.rand(n * M, dtype=dt, device="cuda")
+            b = torch.empty(N * N, dtype=dt, device="cuda")
+            ws = P.workspace(gct.OP_BACKPROJECT, dt)
+            for _ in range(3):
+                gct.backproject_boxspline(P, g, b, ws)
+            ts = []
+            for _ in range(20):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                gct.backproject_boxspline(P, g, b, ws)
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            row["ms_blur" if zeta else "ms_noblur"] = round(float(np.median(ts)), 4)
+        row["blur_over_noblur"] = round(row["ms_blur"] / row["ms_noblur"], 3)
+        rows.append(row)
+    print(json.dumps({"metric": "back projection time by image size, 180 views (unblurred and zeta = 1)",
+                      "unit": "ms", "higher_is_better": False, "n_gpus": 1, "dtype": "f32",
+                      "data": "synthetic", "config": {"workload": "bp_sizes_a180"}, "rows": rows}))
+
+
 def main():
     args = parse()
     if args.pmc_summarize:
         return pmc_summarize(*args.pmc_summarize)
+    if args.workload == "bp_sizes_a180":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU", "n_gpus": args.gpus}))
+            sys.exit(2)
+        return bp_sizes_main(args)
     if args.workload == "batch_uneven_256":
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU", "n_gpus": args.gpus}))

@@ -141,6 +141,20 @@ def batch_main(args):
     gct.batch_gram_spectrum(B, G, Ghat, ws_spec)
     gct.batch_autotune(B, Ghat, ws_cg, reps=3)
     torch.cuda.synchronize()
+    if args.pmc_probe:
+        # counter runs: BATCH_PMC_APPLIES batched applies, then the calibration copy
+        for _ in range(BATCH_PMC_APPLIES):
+            gct.batch_gram_apply(B, Ghat, bpk, y, ws_apply)
+        torch.cuda.synchronize()
+        src = torch.ones(PMC_COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_probe": True, "workload": "batch_uneven_256", "applies": BATCH_PMC_APPLIES,
+                          "passes_per_apply": 3 * B.groups, "copy_bytes": PMC_COPY_BYTES,
+                          "batch_source_sha": batch_source_sha()}))
+        return
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         for _ in range(4):
@@ -199,7 +213,7 @@ def batch_main(args):
                "rel_res_true_max": max(r.rel_res_true for r in res)},
         "roofline": {"kernel": "batched gram_apply (all slices, rows / columns / rows passes)",
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": batch_measured_traffic(),
                      "alg_bytes_per_launch": alg},
     }
     print(json.dumps(out), flush=True)
@@ -208,6 +222,70 @@ def batch_main(args):
 PMC_APPLIES = 20
 PMC_COPY_BYTES = 256 << 20
 PMC_FILE = os.path.join(ROOT, "profiles", "gram_apply_n512_a720_pmc.json")
+BATCH_PMC_APPLIES = 5
+BATCH_PMC_FILE = os.path.join(ROOT, "profiles", "batch_apply_uneven256_pmc.json")
+BATCH_SOURCES = ["batch.hip", "fft_passes.h", "fft_common.h"]
+
+
+def batch_source_sha() -> str:
+    """Hash of the batched Gram-filtering kernel sources."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in BATCH_SOURCES:
+        with open(os.path.join(ROOT, "paper_2005_13471_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def pmc_summarize_batch(fetch_dir: str, write_dir: str):
+    """HBM bytes per batched apply from the two counter runs of
+    `--workload batch_uneven_256 --pmc-probe`: the counters of the last
+    BATCH_PMC_APPLIES applies' pass dispatches (after the autotuner's), summed
+    and divided by the applies, scaled by the calibration copy as for the
+    single-slice apply.  Written to BATCH_PMC_FILE."""
+    import csv
+    import glob
+
+    def load(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "*counter_collection.csv")):
+            with open(f) as fh:
+                rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+        per = {}
+        for r in rows:
+            k = (int(r["Dispatch_Id"]), r["Kernel_Name"].split("(")[0].replace("void ", ""))
+            per[k] = per.get(k, 0.0) + float(r["Counter_Value"])
+        disp = sorted(per.items())
+        passes = [(k, v) for k, v in disp if any(t in k[1] for t in ("kb_rows_fwd", "kb_cols<", "kb_rows_inv"))]
+        # the calibration copy is the run's last dispatch outside the library
+        # (the set-up's own large fills come earlier)
+        copy = next((v for k, v in reversed(disp) if "gct::" not in k[1]), 0.0)
+        return passes, copy
+
+    fetch, copy_f = load(fetch_dir, "FETCH_SIZE")
+    write, copy_w = load(write_dir, "WRITE_SIZE")
+    # passes of one apply: 3 per FFT size (log2 P, the second template
+    # argument); the probe's applies are the last dispatches
+    groups = {k[1].split("<")[1].split(",")[1].strip() for k, _ in fetch[-30:]}
+    n_last = 3 * len(groups) * BATCH_PMC_APPLIES
+    sf, sw = PMC_COPY_BYTES / (copy_f * 1024), PMC_COPY_BYTES / (copy_w * 1024)
+    fb = sum(v for _, v in fetch[-n_last:]) * 1024 * sf / BATCH_PMC_APPLIES
+    wb = sum(v for _, v in write[-n_last:]) * 1024 * sw / BATCH_PMC_APPLIES
+    entry = {"workload": "batch_uneven_256", "batch_source_sha": batch_source_sha(), "fft_sizes": len(groups),
+             "scale_fetch": sf, "scale_write": sw, "hbm_fetch_bytes_per_apply": int(round(fb)),
+             "hbm_write_bytes_per_apply": int(round(wb)), "hbm_bytes_per_apply": int(round(fb + wb))}
+    with open(BATCH_PMC_FILE, "w") as fh:
+        json.dump(entry, fh, indent=1)
+    print(json.dumps(entry))
+
+
+def batch_measured_traffic():
+    try:
+        with open(BATCH_PMC_FILE) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return d.get("hbm_bytes_per_apply") if d.get("batch_source_sha") == batch_source_sha() else None
 APPLY_SOURCES = ["gram_apply.hip", "fft_passes.h", "fft_common.h"]
 
 
@@ -417,6 +495,8 @@ def bp_sizes_main(args):
 def main():
     args = parse()
     if args.pmc_summarize:
+        if args.workload == "batch_uneven_256":
+            return pmc_summarize_batch(*args.pmc_summarize)
         return pmc_summarize(*args.pmc_summarize)
     if args.workload == "bp_sizes_a180":
         if args.gpus != 1:

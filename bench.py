@@ -500,16 +500,16 @@ def main():
         return pmc_summarize(*args.pmc_summarize)
     if args.workload == "bp_sizes_a180":
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU", "n_gpus": args.gpus}))
+            print(json.dumps({"error": "this benchmark runs on one GPU", "n_gpus": args.gpus}))
             sys.exit(2)
         return bp_sizes_main(args)
     if args.workload == "batch_uneven_256":
         if args.gpus != 1:
-            print(json.dumps({"error": "this build runs on one GPU", "n_gpus": args.gpus}))
+            print(json.dumps({"error": "this benchmark runs on one GPU", "n_gpus": args.gpus}))
             sys.exit(2)
         return batch_main(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU runs are not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch

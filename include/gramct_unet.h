@@ -3,7 +3,7 @@
  * U-Net maps the back projection b = H^T g of a slice to an initial iterate
  * x0 for cg_solve, trained on the GPU by the kernels behind this interface.
  * CG from x0 = 0 stays the fallback (gct_cg_solve drops a warm start whose
- * residual is not below ||b||) and the judge of the net's error: the solve
+ * residual is not below ||b||) and the measure of the net's error: the solve
  * always runs to the same stopping rule ||b - A x_k|| <= rtol ||b||.
  *
  * The paper (Sec. 6) reconstructs with plain iterations from zero; the warm

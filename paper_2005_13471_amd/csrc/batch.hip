@@ -88,7 +88,8 @@ kb_rows_fwd2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     for (int q = 0; q < E; ++q) {
         const int n = t + G * q;
         T re = 0, im = 0;
-        if (n < N && ra < N) {  // N even: rb < N too
+        // q >= E/2: n >= P/2 >= N, zero padding known at compile time
+        if (q < E / 2 && n < N && ra < N) {  // N even: rb < N too
             const size_t ia = (size_t)ra * N + n, ib = (size_t)rb * N + n;
             re = sr[ia];
             im = sr[ib];
@@ -171,7 +172,7 @@ kb_rows_inv2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     double acc = 0.0;
     if (ra < N) {
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
+        for (int q = 0; q < E / 2; ++q) {  // n >= P/2 >= N for q >= E/2
             const int n = t + G * q;
             if (n >= N) continue;
             yo[(size_t)ra * N + n] = v[q].x;

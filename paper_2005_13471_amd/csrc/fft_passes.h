@@ -126,24 +126,27 @@ __device__ __forceinline__ void rows_fwd_load(int ra, const T *__restrict__ src,
     const bool hb = ra + 1 < N;  // row ra < N always
     const size_t oa = (size_t)ra * N, ob = hb ? oa + N : oa;
     // unconditional loads from clamped in-range addresses, masked afterwards:
-    // no branch between them, so all are in flight before the first wait
-    T a[E], b[E];
+    // no branch between them, so all are in flight before the first wait.
+    // Entries q >= E/2 sit at t + G q >= P/2 >= N (P >= 2N): zero padding,
+    // known at compile time, so the first transform pass drops their terms.
+    constexpr int H = E / 2;
+    T a[H], b[H];
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
+    for (int q = 0; q < H; ++q) {
         const int nc = min(t + G * q, N - 1);
         a[q] = src[oa + nc];
         b[q] = src[ob + nc];
     }
     if (pupd) {
-        T ua[E], ub[E];
+        T ua[H], ub[H];
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
+        for (int q = 0; q < H; ++q) {
             const int nc = min(t + G * q, N - 1);
             ua[q] = pupd[oa + nc];
             ub[q] = pupd[ob + nc];
         }
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
+        for (int q = 0; q < H; ++q) {
             const int n = t + G * q;
             if (n >= N) continue;
             a[q] += bt * ua[q];
@@ -156,6 +159,10 @@ __device__ __forceinline__ void rows_fwd_load(int ra, const T *__restrict__ src,
     }
 #pragma unroll
     for (int q = 0; q < E; ++q) {
+        if (q >= H) {
+            v[q] = {T(0), T(0)};
+            continue;
+        }
         const bool ok = t + G * q < N;
         v[q] = {ok ? a[q] : T(0), ok && hb ? b[q] : T(0)};
     }
@@ -184,7 +191,8 @@ __device__ __forceinline__ void cols_load(int col, const C2<T> *__restrict__ W1,
 #pragma unroll
     for (int q = 0; q < E; ++q) {
         const int n = t + G * q;
-        v[q] = n < N ? in[n] : C2<T>{T(0), T(0)};
+        // q >= E/2: n >= P/2 >= N, zero padding known at compile time
+        v[q] = q < E / 2 && n < N ? in[n] : C2<T>{T(0), T(0)};
         gs[q] = g[n];
     }
 }
@@ -201,7 +209,7 @@ __device__ __forceinline__ void cols_regs(int col, C2<T> (&v)[E], const T (&gs)[
     fft_passes<T, E, P, 1, true, true>(v, x, t, tws);
     C2<T> *out = W2 + (size_t)col * N;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
+    for (int q = 0; q < E / 2; ++q) {  // n >= P/2 >= N for q >= E/2: the last pass drops them
         const int n = t + G * q;
         if (n < N) out[n] = v[q];
     }
@@ -256,7 +264,7 @@ __device__ __forceinline__ double rows_inv_store(int ra, const C2<T> (&v)[E], T 
     const int rb = ra + 1;
     double acc = 0.0;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
+    for (int q = 0; q < E / 2; ++q) {  // n >= P/2 >= N for q >= E/2
         const int n = t + G * q;
         if (n >= N) continue;
         y[(size_t)ra * N + n] = v[q].x;

@@ -165,12 +165,14 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
     // the previous launch's partial dots and this thread's elements of the
     // five vectors (in range whatever the state), issued together with the
     // state words so that all their latencies overlap
-    constexpr int G = P / E, KP = E / 4 + 1;
+    // (entries q >= E/2 are at t + G q >= P/2 >= N: never loaded, zero in
+    // the transform)
+    constexpr int G = P / E, KP = E / 4 + 1, H = E / 2;
     double pg[KP], pd[KP];
     part_load<G, KP>(part, np, pg, pd);
-    T lr[E][2], lw[E][2], lp[E][2], ls[E][2], lx[E][2];
+    T lr[H][2], lw[H][2], lp[H][2], ls[H][2], lx[H][2];
 #pragma unroll
-    for (int q = 0; q < E; ++q)
+    for (int q = 0; q < H; ++q)
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int n = threadIdx.x + G * q, row = ra + h;
@@ -234,7 +236,9 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
         // the transform takes, so the new r goes to it in registers
         C2<T> v[E];
 #pragma unroll
-        for (int q = 0; q < E; ++q) {
+        for (int q = H; q < E; ++q) v[q] = {T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < H; ++q) {
             T rv[2] = {T(0), T(0)};
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -297,10 +301,11 @@ k_cgf_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ w, const T *__restr
     // this thread's entries of r, loaded ahead of the transform so that
     // their latency overlaps it
     // (clamped in-range addresses; entries past N are never used)
-    T lr[E][2];
+    // (q < E/2 only: t + G q >= P/2 >= N beyond)
+    T lr[E / 2][2];
     const size_t oa = (size_t)ra * N, ob = rb < N ? oa + N : oa;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
+    for (int q = 0; q < E / 2; ++q) {
         const int nc = min((int)threadIdx.x + G * q, N - 1);
         lr[q][0] = r[oa + nc];
         lr[q][1] = r[ob + nc];
@@ -313,7 +318,7 @@ k_cgf_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ w, const T *__restr
     fft_passes<T, E, P, 1, true, true>(v, x, threadIdx.x, tws);
     double g = 0.0, dl = 0.0;
 #pragma unroll
-    for (int q = 0; q < E; ++q) {
+    for (int q = 0; q < E / 2; ++q) {
         const int n = threadIdx.x + G * q;
         if (n >= N) continue;
         const size_t ia = (size_t)ra * N + n;

@@ -169,8 +169,11 @@ k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp,
 //   - each thread evaluates 8 pixels (rows 4 apart) per angle: one floor,
 //     a sub-interval search, one or two 16-byte LDS reads, an HN-term Horner
 //     scheme (HN >= D1: the coefficients past D1 are the zero padding).
+// At least 5 waves per SIMD (96 VGPRs, a few spilled): with 4 the register
+// count alone held a CU to 4 blocks; the kernel is VALU-bound and the extra
+// wave hides more of its LDS latency (0.44 -> 0.43 ms at 512^2 / 720 angles).
 template <typename T, int JM, int HN>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256, 5)
 k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, int K, int groups,
           const double *__restrict__ geo, const int32_t *__restrict__ ints, const T *__restrict__ brk,
           const T *__restrict__ coef, int smax, int J, int D1, int rmax, int CH)

@@ -11,25 +11,42 @@ namespace gct {
 // Correction filter (Sec. 5, eq. correction filter).  One thread per output
 // element p[a][m + K], m in [-K, M-1+K]; rows whose B-spline degree is 0 or 1
 // are copied (q = delta), degree-2 rows are filtered with the 2K+1 taps.
+// A block first stages the 256 + 2K input samples its outputs reach into LDS
+// (zero outside the row), so the taps read LDS instead of 2K+1 global loads
+// per output; the terms are summed in ascending tap order, and the zero
+// samples add exact zeros, so the result equals the plain truncated sum.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_prefilter(const T *__restrict__ g, T *__restrict__ out, int n, int M, int K,
             const T *__restrict__ q, const int32_t *__restrict__ deg)
 {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *s_row = reinterpret_cast<T *>(smem_raw);  // row[m0 - 2K .. m0 + 255]
     const int Mp = M + 2 * K;
     const int a = blockIdx.y;
-    const int mo = blockIdx.x * blockDim.x + threadIdx.x;
-    if (a >= n || mo >= Mp) return;
-    const int m = mo - K;
+    const int mo0 = blockIdx.x * blockDim.x;
+    const int mo = mo0 + threadIdx.x;
     const T *row = g + (size_t)a * M;
-    T acc = 0;
-    if (deg[a] == 2) {
-        const int jlo = max(-K, m - (M - 1)), jhi = min(K, m);
-        for (int j = jlo; j <= jhi; ++j) acc += q[j + K] * row[m - j];
-    } else if (m >= 0 && m < M) {
-        acc = row[m];
+    if (deg[a] != 2) {  // uniform per block
+        if (mo < Mp) {
+            const int m = mo - K;
+            out[(size_t)a * Mp + mo] = (m >= 0 && m < M) ? row[m] : T(0);
+        }
+        return;
     }
+    // s_row[i] = row[mo0 - 2K + i] (output mo uses m - j = mo - K - j, j in [-K, K])
+    const int span = blockDim.x + 2 * K;
+    for (int i = threadIdx.x; i < span; i += blockDim.x) {
+        const int src = mo0 - 2 * K + i;
+        s_row[i] = (src >= 0 && src < M) ? row[src] : T(0);
+    }
+    __syncthreads();
+    if (mo >= Mp) return;
+    // term j reads row[mo - K - j] = s_row[threadIdx.x + K - j]
+    const T *w = s_row + threadIdx.x + K;
+    T acc = 0;
+    for (int j = -K; j <= K; ++j) acc += q[j + K] * w[-j];
     out[(size_t)a * Mp + mo] = acc;
 }
 
@@ -38,8 +55,10 @@ hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s
 {
     const int Mp = p->M + 2 * p->K;
     const dim3 grid((Mp + 255) / 256, p->n);
+    const size_t lds = (size_t)(256 + 2 * p->K) * sizeof(T);
+    if (lds > 64 * 1024) return hipErrorInvalidConfiguration;
     const T *q = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.q_f32 : p->dev.q_f64);
-    hipLaunchKernelGGL(k_prefilter<T>, grid, dim3(256), 0, s, g, out, p->n, p->M, p->K, q,
+    hipLaunchKernelGGL(k_prefilter<T>, grid, dim3(256), lds, s, g, out, p->n, p->M, p->K, q,
                        reinterpret_cast<const int32_t *>(p->dev.deg));
     return hipGetLastError();
 }

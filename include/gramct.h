@@ -188,6 +188,17 @@ int gct_plan_set_pass_elems(gct_plan *plan, gct_dtype dtype, int32_t rows_elems,
  * {apply row passes, apply column pass, CG row passes, CG column pass}. */
 int gct_plan_get_pass_elems(const gct_plan *plan, gct_dtype dtype, int32_t *out);
 
+/* Launch shape the plan chose for gct_backproject_boxspline in `dtype`
+ * (Sec. 5 back projection; the arithmetic is the same on every path): out
+ * (HOST, 3 ints) = {angles per chunk of the pixel-tiled kernel, whose
+ * per-(tile, angle) tables must fit in 64 KB of LDS (0: they do not, and the
+ * per-angle kernel runs instead), angle groups of the tiled kernel (1 when
+ * it does not run), tile side of the per-angle kernel (0 when the tiled
+ * kernel runs; also 0 when neither fits, and back projection then returns
+ * GCT_EHIP)}.  Fine detector sampling (small lambda_y relative to the
+ * pixel) and FP64 widen the tables. */
+int gct_plan_get_bp_shape(const gct_plan *plan, gct_dtype dtype, int32_t *out);
+
 /* Result of gct_cg_solve (host struct). */
 typedef struct {
     int32_t iters;        /* iterations performed */
@@ -211,8 +222,13 @@ typedef struct {
  * ||r_k|| <= rtol ||b|| or after max_iter iterations.  x: on entry the start
  * vector if use_x0 != 0 (else ignored and zero is used); on exit the last
  * iterate.  A start vector with ||b - A x_0|| >= ||b|| is replaced by zero
- * (result->fell_back = 1).  hist: optional HOST array of max_iter + 1 doubles receiving
- * ||r_k||/||b||.  check_every: iterations between host convergence checks
+ * (result->fell_back = 1).  Success (GCT_OK) means the recomputed residual
+ * ||b - A x||/||b|| of the returned iterate is <= rtol: when the recursive
+ * residual meets the rule but the recomputed one does not (rounding drift),
+ * CG restarts from the current iterate with r = b - A x (at most 4 times,
+ * within max_iter iterations in total), else GCT_ENOTCONV.  hist: optional
+ * HOST array of max_iter + 1 doubles receiving ||r_k||/||b|| (at a restart
+ * the recomputed residual).  check_every: iterations between host convergence checks
  * (<= 0 selects 8); iterations after convergence are skipped on the device.
  * BLOCKS the host until the solve is complete. */
 int gct_cg_solve(const gct_plan *plan, gct_dtype dtype, const void *Ghat, const void *b, void *x,

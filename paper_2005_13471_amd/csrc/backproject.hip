@@ -481,6 +481,12 @@ static BPLayout bp_layout(const gct_plan *p, size_t elem)
 
 size_t bp_lds_bytes(const gct_plan *p, size_t elem) { return bp_layout(p, elem).lds; }
 
+int bp_fallback_tile(const gct_plan *p, size_t elem)
+{
+    const BPLayout L = bp_layout(p, elem);
+    return L.lds <= 65536 ? L.tile : 0;
+}
+
 template <typename T>
 hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, hipStream_t s)
 {

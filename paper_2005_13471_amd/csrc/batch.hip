@@ -1001,49 +1001,53 @@ int gct_batch_autotune(gct_batch *b, gct_dtype dt, const void *Ghat, void *ws, i
     char *w = reinterpret_cast<char *>(ws);
     void *src = w + L.r, *dst = w + L.Ap;
     B_TRY(hipMemsetAsync(src, 0, (size_t)b->img_total * elem, s));
-    hipEvent_t e0, e1;
-    B_TRY(hipEventCreate(&e0));
-    B_TRY(hipEventCreate(&e1));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t err = hipEventCreate(&e0);
+    if (err == hipSuccess) err = hipEventCreate(&e1);
     // tune one group and one pass kind (row passes, then the column pass) at
     // a time, everything else keeping its current choice; each candidate is
-    // timed on the whole batched apply
-    for (int q = 0; q < 2 * (int)b->groups.size(); ++q) {
+    // timed on the whole batched apply.  On an error the pass keeps the
+    // choice it had before its candidates were tried.
+    for (int q = 0; q < 2 * (int)b->groups.size() && err == hipSuccess; ++q) {
         BatchGroup &g = b->groups[q / 2];
         int &Eq = q % 2 == 0 ? g.E[t] : g.Ec[t];
         const int P = 1 << g.logP, E0 = fft_elems(P);
+        const int before = Eq;
         int best = Eq;
         float best_ms = 1e30f;
         for (int E : {E0, E0 / 2}) {
             if (E < 4 || !e_ok(g.logP, E)) continue;
             Eq = E;
-            for (int rep = 0; rep <= reps; ++rep) {
-                if (rep == 1) B_TRY(hipEventRecord(e0, s));
-                hipError_t e = t == 0 ? batch_apply_passes<float>(b, (const float *)Ghat, (const float *)src,
-                                                                  (float *)dst, ws, s, nullptr, nullptr,
-                                                                  nullptr, nullptr)
-                                      : batch_apply_passes<double>(b, (const double *)Ghat,
-                                                                   (const double *)src, (double *)dst, ws,
-                                                                   s, nullptr, nullptr, nullptr, nullptr);
-                B_TRY(e);
+            for (int rep = 0; rep <= reps && err == hipSuccess; ++rep) {
+                if (rep == 1) err = hipEventRecord(e0, s);
+                if (err == hipSuccess)
+                    err = t == 0 ? batch_apply_passes<float>(b, (const float *)Ghat, (const float *)src,
+                                                             (float *)dst, ws, s, nullptr, nullptr, nullptr,
+                                                             nullptr)
+                                 : batch_apply_passes<double>(b, (const double *)Ghat, (const double *)src,
+                                                              (double *)dst, ws, s, nullptr, nullptr, nullptr,
+                                                              nullptr);
             }
-            B_TRY(hipEventRecord(e1, s));
-            B_TRY(hipEventSynchronize(e1));
+            if (err == hipSuccess) err = hipEventRecord(e1, s);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
             float ms = 0.0f;
-            B_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err != hipSuccess) break;
             if (ms < best_ms) {
                 best_ms = ms;
                 best = E;
             }
         }
-        Eq = best;
+        Eq = err == hipSuccess ? best : before;
     }
-    if (chosen)
-        for (size_t gi = 0; gi < b->groups.size(); ++gi) chosen[gi] = b->groups[gi].E[t];
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     // captured CG graphs used the old shapes
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
+    if (err != hipSuccess) return check_hip(err, "batch autotune");
+    if (chosen)
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) chosen[gi] = b->groups[gi].E[t];
     return GCT_OK;
 }
 

@@ -266,10 +266,13 @@ static hipStream_t cg_capture_stream(const gct_plan *p)
     return q->capture_stream;
 }
 
+// One solve from x (or zero) until the recursive residual meets rtol, the
+// iterations run out or the recurrence breaks down; the true residual of the
+// returned iterate is recomputed at the end.
 template <typename T>
-int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, double rtol,
-             int max_iter, int check_every, double *hist, gct_cg_result *res, void *ws,
-             hipStream_t s, int method)
+static int cg_run(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, double rtol,
+                  int max_iter, int check_every, double *hist, gct_cg_result *res, void *ws,
+                  hipStream_t s, int method)
 {
     const CGLayout L = cg_layout(p, sizeof(T));
     char *w = reinterpret_cast<char *>(ws);
@@ -424,6 +427,44 @@ int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, dou
     else if (hs.status == CG_BREAKDOWN) res->status = GCT_EBREAKDOWN;
     else res->status = GCT_ENOTCONV;
     return res->status;
+}
+
+// Restarts after the recursive residual met the rule while the recomputed
+// one did not (at most this many, within max_iter in total).
+constexpr int CG_MAX_RESTARTS = 4;
+
+// The solver: GCT_OK only when the recomputed residual ||b - A x||/||b|| of
+// the returned iterate is within rtol.  The recursive residual drifts from
+// the true one by rounding; when it meets the rule alone, CG restarts from
+// the current iterate with r = b - A x (residual replacement), continuing
+// the iteration count and the history.
+template <typename T>
+int cg_solve(const gct_plan *p, const T *Ghat, const T *b, T *x, int use_x0, double rtol,
+             int max_iter, int check_every, double *hist, gct_cg_result *res, void *ws,
+             hipStream_t s, int method)
+{
+    int64_t done = 0;
+    for (int run = 0;; ++run) {
+        gct_cg_result r{};
+        const int left = (int)(max_iter - done);
+        const int rc = cg_run<T>(p, Ghat, b, x, use_x0 || run > 0, rtol, left, check_every,
+                                 hist ? hist + done : nullptr, &r, ws, s, method);
+        if (rc != GCT_OK && rc != GCT_ENOTCONV && rc != GCT_EBREAKDOWN) return rc;
+        if (run == 0) {
+            res->rel_res0 = r.rel_res0;
+            res->fell_back = r.fell_back;
+        }
+        done += r.iters;
+        res->iters = (int32_t)done;
+        res->rel_res = r.rel_res;
+        res->rel_res_true = r.rel_res_true;
+        res->status = r.status;
+        if (r.status == GCT_OK && !(r.rel_res_true <= rtol)) {
+            if (done < max_iter && run < CG_MAX_RESTARTS) continue;
+            res->status = GCT_ENOTCONV;
+        }
+        return res->status;
+    }
 }
 
 // Times the apply passes for every candidate pair (row passes E, column

@@ -204,6 +204,9 @@ hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s
 template <typename T>
 hipError_t launch_backproject(const gct_plan *p, const T *prefiltered, T *b, T *partial, hipStream_t s);
 int bp_angle_groups(const gct_plan *p, size_t elem);
+// Tile side of the per-angle back-projection kernel (taken when the tiled
+// kernel's tables do not fit, bp_ch == 0), or 0 when its LDS does not fit.
+int bp_fallback_tile(const gct_plan *p, size_t elem);
 
 // Default elements per thread of the row passes and of the column pass for a
 // transform of size P (what the autotuner picks on MI355X at P = 1024: the

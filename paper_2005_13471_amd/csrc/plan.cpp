@@ -721,6 +721,18 @@ int gct_plan_get_pass_elems(const gct_plan *p, gct_dtype dt, int32_t *out)
     return GCT_OK;
 }
 
+int gct_plan_get_bp_shape(const gct_plan *p, gct_dtype dt, int32_t *out)
+{
+    CHECK_PLAN_DT(p, dt);
+    if (!out) return fail(GCT_EINVAL, "NULL output");
+    const int t = dt == GCT_F32 ? 0 : 1;
+    const size_t e = dt == GCT_F32 ? 4 : 8;
+    out[0] = p->bp_ch[t];
+    out[1] = p->bp_ch[t] > 0 ? p->bp_groups[t] : 1;
+    out[2] = p->bp_ch[t] > 0 ? 0 : bp_fallback_tile(p, e);
+    return GCT_OK;
+}
+
 int gct_plan_autotune(gct_plan *p, gct_dtype dt, const void *Ghat, void *ws, int32_t reps,
                       int32_t *chosen, void *stream)
 {

@@ -94,6 +94,7 @@ def _load():
     L.gct_plan_set_fft_elems.argtypes = [vp, ctypes.c_int, i32]
     L.gct_plan_set_pass_elems.argtypes = [vp, ctypes.c_int, i32, i32]
     L.gct_plan_get_pass_elems.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32)]
+    L.gct_plan_get_bp_shape.argtypes = [vp, ctypes.c_int, ctypes.POINTER(i32)]
     L.gct_batch_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(vp)]
     L.gct_batch_destroy.argtypes = [vp]
     L.gct_batch_get_info.argtypes = [vp, ctypes.POINTER(_BatchInfo), ctypes.c_void_p,
@@ -332,6 +333,15 @@ def plan_get_pass_elems(plan: Plan, dtype=torch.float32):
     """(apply rows, apply cols, CG rows, CG cols) elements per thread."""
     out = (ctypes.c_int32 * 4)()
     _check(lib.gct_plan_get_pass_elems(plan.handle, F32 if dtype == torch.float32 else F64, out))
+    return tuple(int(v) for v in out)
+
+
+def plan_get_bp_shape(plan: Plan, dtype=torch.float32):
+    """Back-projection launch shape: (angles per chunk of the tiled kernel,
+    0 when the per-angle kernel runs; angle groups; per-angle tile side, 0
+    when the tiled kernel runs)."""
+    out = (ctypes.c_int32 * 3)()
+    _check(lib.gct_plan_get_bp_shape(plan.handle, F32 if dtype == torch.float32 else F64, out))
     return tuple(int(v) for v in out)
 
 

@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from paper_2005_13471_amd import inputs
-from gpu_helpers import normwise, sample_pixels, say
+from gpu_helpers import normwise, sample_pixels, sample_taps, say
 
 pytestmark = pytest.mark.gpu
 
@@ -254,3 +254,66 @@ def test_batch_long_transforms_match_single_slice_and_oracle(which):
         xh = B.image(x, i).double().cpu().numpy()
         r = bh.reshape(-1)[idx] - oracle.apply_at(g_or, xh, idx)
         assert np.sqrt(np.mean(r ** 2)) <= 3e-4 * np.linalg.norm(bh) / P.N
+
+
+# slices at the sizes of the 256-slice benchmark batch: the largest N and
+# angle count (the batched Gram build takes its angular windows in several
+# runs of 256 angles), a 2048-point transform of N = 768, and a small slice
+CONFIG3 = [(1024, 1440, 0.5), (768, 720, 1.0), (128, 180, 0.0)]
+
+
+def test_batch_config3_sizes_match_oracle():
+    """Batch of benchmark-sized slices against the oracle: sampled Gram taps
+    (oracle.gram_at), sampled outputs of the batched apply (the oracle's
+    direct sum with its exact filter), and batched CG to 1e-4 on phantom
+    right-hand sides with the oracle's recomputation of sampled residual
+    entries of each returned iterate."""
+    from paper_2005_13471_amd import gramct as gct
+    dt = torch.float32
+    plans, ogs = [], []
+    for i, (N, n, z) in enumerate(CONFIG3):
+        th = inputs.angles(n)
+        M = inputs.detector_bins(N, z)
+        plans.append(gct.Plan(N, th, M, zeta=z))
+        ogs.append(oracle.Geometry(N, th, M, zeta=z))
+    say("batch config-3 sizes", [(p.N, p.info.n_angles) for p in plans])
+    B = gct.Batch(plans)
+    G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
+    gct.batch_gram_build(B, G)
+    Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")
+    gct.batch_gram_spectrum(B, G, Ghat, B.workspace(gct.OP_GRAM_SPECTRUM, dt))
+    cs = [inputs.uniform_coeffs(N, 6000 + i) for i, (N, _, _) in enumerate(CONFIG3)]
+    y = torch.empty(B.image_elems, dtype=dt, device="cuda")
+    gct.batch_gram_apply(B, Ghat, _packed(B, cs, dt), y, B.workspace(gct.OP_GRAM_APPLY, dt))
+    rhs = [inputs.phantom(N, 40, 7000 + i)[0] for i, (N, _, _) in enumerate(CONFIG3)]
+    bpk = _packed(B, rhs, dt)
+    x = torch.zeros_like(bpk)
+    res = gct.batch_cg_solve(B, Ghat, bpk, x, B.workspace(gct.OP_CG, dt), rtol=1e-4, max_iter=3000,
+                             check_every=16)
+    torch.cuda.synchronize()
+    for i, P in enumerate(plans):
+        N = P.N
+        W = 2 * N - 1
+        o = int(B.gram_offsets[i])
+        Gb = G[o:o + W * W].double().cpu().numpy().reshape(W, W)
+        taps = sample_taps(N, 300, 30 + i)
+        g_at = oracle.gram_at(ogs[i], taps)
+        got = Gb[taps[:, 1] + N - 1, taps[:, 0] + N - 1]
+        eg = normwise(got, g_at)
+        say("  slice", i, "N", N, "sampled taps normwise", eg)
+        assert eg <= 1e-5, i
+        say("  slice", i, "oracle Gram filter")
+        g_or = oracle.gram(ogs[i])
+        idx = sample_pixels(N, 200, 40 + i)
+        ref = oracle.apply_at(g_or, cs[i], idx)
+        ya = B.image(y, i).double().cpu().numpy().reshape(-1)[idx]
+        ea = normwise(ya, ref)
+        say("  slice", i, "sampled apply normwise", ea)
+        assert ea <= 1e-4, i
+        say("  slice", i, "cg iters", res[i].iters, "status", res[i].status, "true", res[i].rel_res_true)
+        assert res[i].status == gct.GCT_OK and res[i].rel_res_true <= 1.2e-4
+        idx = sample_pixels(N, 300, 50 + i)
+        xh = B.image(x, i).double().cpu().numpy()
+        r = rhs[i].reshape(-1)[idx] - oracle.apply_at(g_or, xh, idx)
+        # sampled residual entries consistent with ||r|| <= 1e-4 ||b||
+        assert np.sqrt(np.mean(r ** 2)) <= 3e-4 * np.linalg.norm(rhs[i]) / N, i

@@ -325,6 +325,54 @@ def test_backproject_many_angle_groups(gct, dt):
     assert err <= tol("bp", dt)
 
 
+def _bins(N, zeta, ly):
+    """Smallest even bin count whose detector covers the image's shadow
+    (N sqrt(2) + zeta wide) at sampling step ly, plus two bins."""
+    m = int(np.ceil((N * np.sqrt(2.0) + zeta) / ly)) + 2
+    return m + (m & 1)
+
+
+# Fine detector sampling (lambda_y < lambda_x, Sec. 6 sampling-rate sweep):
+# the tiled kernel's per-(tile, angle) tables outgrow its 64 KB of LDS (FP64
+# at lambda_y = 0.25; FP32 at 0.125 without blur) or its 16-tap limit (FP32
+# at 0.125 with blur), so the per-angle kernel runs (tile side 16 or 32).
+PER_ANGLE = [(Case(48, 30, M=_bins(48, 1.0, 0.25), zeta=1.0, ly=0.25), torch.float64),
+             (Case(48, 30, M=_bins(48, 1.0, 0.125), zeta=1.0, ly=0.125), torch.float32),
+             (Case(40, 26, M=_bins(40, 0.0, 0.125), zeta=0.0, ly=0.125), torch.float32)]
+
+
+@pytest.mark.parametrize("case,dt", PER_ANGLE, ids=lambda v: repr(v))
+def test_backproject_per_angle_kernel(gct, case, dt):
+    """The per-angle back-projection kernel against the oracle on the whole
+    image; the plan reports that this kernel is the one that runs."""
+    P = case.plan(gct)
+    shape = gct.plan_get_bp_shape(P, dt)
+    say("backproject per-angle", case, dt, "shape", shape)
+    assert shape[0] == 0 and shape[2] in (16, 32), shape
+    g = _sino(case, 1004)
+    got = _bp_gpu(gct, case, dt, g)
+    ref = oracle.backproject(case.og(), g)
+    err = normwise(got, ref)
+    say("  normwise", err)
+    assert err <= tol("bp", dt)
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+def test_backproject_rate_quarter(gct, dt):
+    """lambda_y = lambda_x / 4 with blur, the finest rate of the sampling
+    sweep, at its image size: whichever kernel the plan picks, the whole
+    image against the oracle."""
+    case = Case(64, 45, M=_bins(64, 1.0, 0.25), zeta=1.0, ly=0.25)
+    P = case.plan(gct)
+    say("backproject rate 1/4", case, dt, "shape", gct.plan_get_bp_shape(P, dt))
+    g = _sino(case, 1005)
+    got = _bp_gpu(gct, case, dt, g)
+    ref = oracle.backproject(case.og(), g)
+    err = normwise(got, ref)
+    say("  normwise", err)
+    assert err <= tol("bp", dt)
+
+
 def test_backproject_config2_sampled(gct):
     case = CFG2
     say("backproject sampled", case)
@@ -466,12 +514,14 @@ def test_cg_config1_converges_like_oracle(gct, dt):
     assert abs(res.iters - it_ref) <= max(3, 0.15 * it_ref)
     xg = host(x).reshape(case.N, case.N)
     true_rel = np.linalg.norm(b - oracle.apply(G, xg)) / np.linalg.norm(b)
-    assert true_rel <= (1.1e-4 if dt == torch.float32 else 1.0001e-4)
+    # success means the solver's own recomputed residual met rtol; the oracle's
+    # exact operator differs from the FP32 product by rounding (~1e-7 relative)
+    assert true_rel <= (1.01e-4 if dt == torch.float32 else 1.0001e-4)
 
 
 def test_cg_config2_converges(gct):
-    """Config 2 scale: CG to 1e-4; the oracle re-checks sampled residual
-    entries of the returned iterate."""
+    """Config 2 scale: CG to 1e-4; the oracle recomputes the whole residual
+    of the returned iterate (direct sum, 2.7e11 multiply-adds)."""
     case = CFG2
     dt = torch.float32
     say("cg config2", case)
@@ -487,15 +537,15 @@ def test_cg_config2_converges(gct):
     res = gct.cg_solve(P, Ghat, b, x, P.workspace(gct.OP_CG, dt), rtol=1e-4, max_iter=2000)
     say("  iters", res.iters, "rel", res.rel_res, "true", res.rel_res_true, "status", res.status)
     assert res.status == gct.GCT_OK
-    assert res.rel_res <= 1e-4 and res.rel_res_true <= 1.2e-4
+    assert res.rel_res_true <= 1e-4
     bh, xh = host(b), host(x).reshape(case.N, case.N)
-    idx = sample_pixels(case.N, 400, 5)
-    r_or = bh[idx] - oracle.apply_at(G, xh, idx)
-    torch.cuda.synchronize()
-    # residual entries recomputed by the oracle: consistent with ||r|| <= 1e-4 ||b||
-    rms_sample = np.sqrt(np.mean(r_or ** 2))
-    rms_b = np.linalg.norm(bh) / case.N
-    assert rms_sample <= 3e-4 * rms_b
+    # the whole residual recomputed by the oracle (direct sum with its exact
+    # filter): the solver's success rule holds for the exact operator up to
+    # the FP32 rounding of the iterate's product (~1e-7 relative to ||A x||)
+    r_or = bh.reshape(case.N, case.N) - oracle.apply(G, xh)
+    rel = np.linalg.norm(r_or) / np.linalg.norm(bh)
+    say("  oracle residual", rel)
+    assert rel <= 1.02e-4
 
 
 @pytest.mark.parametrize("dt", DTYPES)
@@ -550,12 +600,14 @@ def test_sd_config1_converges_like_oracle(gct, dt):
     assert res.iters > 3 * rc.iters
     xg = host(x).reshape(case.N, case.N)
     true_rel = np.linalg.norm(b - oracle.apply(G, xg)) / np.linalg.norm(b)
-    assert true_rel <= (1.1e-4 if dt == torch.float32 else 1.0001e-4)
+    # success means the solver's own recomputed residual met rtol; the oracle's
+    # exact operator differs from the FP32 product by rounding (~1e-7 relative)
+    assert true_rel <= (1.01e-4 if dt == torch.float32 else 1.0001e-4)
 
 
 def test_sd_config2_converges(gct):
-    """Config 2 scale: steepest descent to 1e-4 (FP32); the oracle re-checks
-    sampled residual entries of the returned iterate."""
+    """Config 2 scale: steepest descent to 1e-4 (FP32); the oracle recomputes
+    the whole residual of the returned iterate."""
     case = CFG2
     dt = torch.float32
     say("sd config2", case)
@@ -572,11 +624,41 @@ def test_sd_config2_converges(gct):
                        check_every=64)
     say("  iters", res.iters, "rel", res.rel_res, "true", res.rel_res_true, "status", res.status)
     assert res.status == gct.GCT_OK
-    assert res.rel_res <= 1e-4 and res.rel_res_true <= 1.2e-4
+    assert res.rel_res_true <= 1e-4
     bh, xh = host(b), host(x).reshape(case.N, case.N)
-    idx = sample_pixels(case.N, 400, 6)
-    r_or = bh[idx] - oracle.apply_at(G, xh, idx)
-    assert np.sqrt(np.mean(r_or ** 2)) <= 3e-4 * np.linalg.norm(bh) / case.N
+    r_or = bh.reshape(case.N, case.N) - oracle.apply(G, xh)
+    rel = np.linalg.norm(r_or) / np.linalg.norm(bh)
+    say("  oracle residual", rel)
+    assert rel <= 1.02e-4
+
+
+@pytest.mark.parametrize("dt,rtol", [(torch.float32, 1e-7), (torch.float64, 1e-10)])
+def test_cg_success_means_true_residual(gct, dt, rtol):
+    """Success is judged on the recomputed residual ||b - A x||/||b||: far
+    below FP32's attainable accuracy the recursive residual keeps falling
+    while the true one stalls, so the solver restarts from its iterate and
+    finally reports GCT_ENOTCONV rather than success; in FP64 the same
+    tolerance is reached and reported as success."""
+    case = CFG1
+    og = case.og()
+    G = oracle.gram(og)
+    c, _ = inputs.phantom(case.N, 10, 1000)
+    b = oracle.backproject(og, inputs.add_noise(oracle.forward(og, c), 0.01, 1_000_000 + 1000))
+    P, Ghat = _cg_setup(gct, case, dt, G)
+    x = torch.zeros(case.N ** 2, dtype=dt, device="cuda")
+    res = gct.cg_solve(P, Ghat, dev(b.reshape(-1), dt), x, P.workspace(gct.OP_CG, dt), rtol=rtol,
+                       max_iter=600)
+    say("  cg rtol", rtol, dt, "status", res.status, "iters", res.iters, "rel", res.rel_res,
+        "true", res.rel_res_true)
+    assert res.iters <= 600 and res.history.size == res.iters + 1
+    assert res.status in (gct.GCT_OK, gct.GCT_ENOTCONV)
+    if res.status == gct.GCT_OK:
+        assert res.rel_res_true <= rtol
+    if dt == torch.float64:
+        assert res.status == gct.GCT_OK
+        xg = host(x).reshape(case.N, case.N)
+        true_rel = np.linalg.norm(b - oracle.apply(G, xg)) / np.linalg.norm(b)
+        assert true_rel <= 1.001 * rtol
 
 
 def test_cg_warm_start_and_fallback(gct):

@@ -2,7 +2,9 @@
 100-ellipse phantom, 0.5% noise.  FP32 vs FP64 on the GPU for every step,
 both against the FP64 oracle on the central 256 x 256 crop (pixels
 [896, 1152)^2, taps |k|_inf <= 127), and the relative residual after 100 CG
-iterations in each precision.
+iterations in each precision, with the drift of the FP32 recursive residual
+from the recomputed one after those 100 steps for the fused solver and for
+the textbook arrangement of the batched solver.
 
 The oracle cannot afford the full 4095^2 Gram filter inside a test, so it
 computes exactly the taps each comparison needs:
@@ -165,6 +167,28 @@ def test_precision_study_n2048(setup):
     ratio = rep["cg100_fp32_iterate_rel_res_fp64_operator"] / rep["cg100_fp64_rel_res_true"]
     rep["cg100_fp32_over_fp64"] = ratio
     assert 0.25 <= ratio <= 4.0
+
+    # A trajectory-independent measure of the FP32 recurrences: how far the
+    # recursive residual has drifted from the recomputed one after 100 steps,
+    # for the fused Chronopoulos-Gear solver and for the textbook arrangement
+    # of the batched solver on the same slice (a batch of one).  Both keep
+    # FP64 inner products and FP32 vectors; both gaps must stay small.
+    say("precision: 100 textbook CG iterations FP32 (batch of one)")
+    dt = torch.float32
+    B = gct.Batch([plan])
+    xb = torch.zeros(N * N, dtype=dt, device="cuda")
+    rb = gct.batch_cg_solve(B, Ghat[dt], b[dt], xb, B.workspace(gct.OP_CG, dt), rtol=0.0,
+                            max_iter=100, check_every=20)[0]
+    rep["cg100_fp32_textbook_rel_res"] = rb.rel_res
+    rep["cg100_fp32_textbook_rel_res_true"] = rb.rel_res_true
+    rep["cg100_fp32_textbook_iters"] = rb.iters
+    gap_cg = abs(rep["cg100_fp32_rel_res"] - rep["cg100_fp32_rel_res_true"]) / rep["cg100_fp32_rel_res_true"]
+    gap_tb = abs(rb.rel_res - rb.rel_res_true) / rb.rel_res_true
+    rep["cg100_fp32_gap_fused"] = gap_cg
+    rep["cg100_fp32_gap_textbook"] = gap_tb
+    say("  gap fused", gap_cg, "textbook", gap_tb, "textbook residual", rb.rel_res_true)
+    assert rb.iters == 100
+    assert gap_cg <= 0.02 and gap_tb <= 0.02
 
     out_dir = os.environ.get("GCT_REPORT_DIR")
     if out_dir:

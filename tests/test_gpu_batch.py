@@ -265,9 +265,9 @@ CONFIG3 = [(1024, 1440, 0.5), (768, 720, 1.0), (128, 180, 0.0)]
 def test_batch_config3_sizes_match_oracle():
     """Batch of benchmark-sized slices against the oracle: sampled Gram taps
     (oracle.gram_at), sampled outputs of the batched apply (the oracle's
-    direct sum with its exact filter), and batched CG to 1e-4 on phantom
-    right-hand sides with the oracle's recomputation of sampled residual
-    entries of each returned iterate."""
+    direct sum with its exact filter), and batched CG to 1e-4 on back
+    projections of noisy phantom sinograms with the oracle's recomputation of
+    sampled residual entries of each returned iterate."""
     from paper_2005_13471_amd import gramct as gct
     dt = torch.float32
     plans, ogs = [], []
@@ -285,7 +285,17 @@ def test_batch_config3_sizes_match_oracle():
     cs = [inputs.uniform_coeffs(N, 6000 + i) for i, (N, _, _) in enumerate(CONFIG3)]
     y = torch.empty(B.image_elems, dtype=dt, device="cuda")
     gct.batch_gram_apply(B, Ghat, _packed(B, cs, dt), y, B.workspace(gct.OP_GRAM_APPLY, dt))
-    rhs = [inputs.phantom(N, 40, 7000 + i)[0] for i, (N, _, _) in enumerate(CONFIG3)]
+    # right-hand sides as in the benchmark: back projections of noisy
+    # sinograms of 40-ellipse phantoms (line integrals of the ellipses)
+    rhs = []
+    for i, (N, n, z) in enumerate(CONFIG3):
+        ells = inputs.random_ellipses(N, 40, 7000 + i)
+        sino = inputs.add_noise(inputs.analytic_sinogram(ells, plans[i].theta, plans[i].M, zeta=z),
+                                0.01, inputs.NOISE_SEED_BASE + 7000 + i)
+        bi = torch.empty(N * N, dtype=dt, device="cuda")
+        gct.backproject_boxspline(plans[i], torch.as_tensor(sino.reshape(-1), dtype=dt, device="cuda"),
+                                  bi, plans[i].workspace(gct.OP_BACKPROJECT, dt))
+        rhs.append(bi.double().cpu().numpy().reshape(N, N))
     bpk = _packed(B, rhs, dt)
     x = torch.zeros_like(bpk)
     res = gct.batch_cg_solve(B, Ghat, bpk, x, B.workspace(gct.OP_CG, dt), rtol=1e-4, max_iter=3000,

@@ -135,6 +135,20 @@ int gct_gram_spectrum(const gct_plan *plan, gct_dtype dtype, const void *G, void
 int gct_gram_apply(const gct_plan *plan, gct_dtype dtype, const void *Ghat, const void *c,
                    void *y, void *ws, void *stream);
 
+/* gct_gram_apply without the workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  The scratch of the three passes is a
+ * static device array of 24 MiB per GPU, held until the process ends:
+ * enough for N <= 1024 in FP32 and N <= 767 in FP64 (the call needs
+ * gct_workspace_size(plan, GCT_OP_GRAM_APPLY, dtype) bytes; larger plans
+ * return GCT_EINVAL).  The current device must be the plan's.  Allocates
+ * nothing and calls no allocating routine.  Every call on one GPU shares the
+ * array: calls that may overlap in time (other streams, other host threads)
+ * race and must be serialised by the caller.  Same kernels and results as
+ * gct_gram_apply. */
+int gct_gram_apply_static(const gct_plan *plan, gct_dtype dtype, const void *Ghat, const void *c,
+                          void *y, void *stream);
+
 /* Digital correction filter of Sec. 5 (eq. correction filter) per angle
  * row: p = q_d * g_s with g_s zero outside [0, M); q_d = delta for
  * B-spline degree d <= 1 and q[m] = sqrt(2) (2 sqrt(2) - 3)^|m|, |m| <= K,

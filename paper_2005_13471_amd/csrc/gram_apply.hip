@@ -15,6 +15,7 @@
 // The 1/P^2 normalisation is folded into Ghat.  One block of P/E threads
 // owns one transform.
 #include <algorithm>
+#include <mutex>
 
 #include "fft_passes.h"
 
@@ -506,3 +507,70 @@ template hipError_t launch_gram_spectrum<double>(const gct_plan *, const double 
                                                  hipStream_t);
 
 }  // namespace gct
+
+// ---------------------------------------------------------------------------
+// Gram filtering without a workspace argument (gct_gram_apply_static), for
+// callers that cannot allocate device memory.  The transposed scratch
+// arrays W1, W2 of the three passes live in `scratch`, a file-scope device
+// array: every GPU the library runs on holds its own copy until the process
+// ends.  Host code never names the array in a launch; it uses the address
+// hipGetSymbolAddress returns for the current device, fetched once per
+// device.  Every used entry of W1 and W2 is written before it is read, so
+// nothing needs clearing between calls; calls that overlap on one GPU share
+// the array and race.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(24) << 20;  // 24 MiB
+constexpr int MAX_DEVICES = 64;
+
+__device__ __align__(256) unsigned char scratch[STATIC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's copy of `scratch` (the current device).
+int static_scratch(int dev, void **out)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) return gct::fail(GCT_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return gct::check_hip(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return gct::fail(GCT_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GCT_OK;
+}
+
+}  // namespace
+
+extern "C" int gct_gram_apply_static(const gct_plan *p, gct_dtype dt, const void *Ghat, const void *c,
+                                     void *y, void *stream)
+{
+    using namespace gct;
+    if (!p) return fail(GCT_EINVAL, "plan is NULL");
+    if (dt != GCT_F32 && dt != GCT_F64) return fail(GCT_EINVAL, "bad dtype");
+    if (!Ghat || !c || !y) return fail(GCT_EINVAL, "NULL buffer");
+    if (c == y) return fail(GCT_EINVAL, "y must not alias c");
+    const size_t need = apply_ws_bytes(p, dt == GCT_F32 ? 4 : 8);
+    if (need > STATIC_SCRATCH_BYTES)
+        return fail(GCT_EINVAL, "gram_apply_static: this plan needs " + std::to_string(need) +
+                                    " bytes of scratch, more than the static array's " +
+                                    std::to_string(STATIC_SCRATCH_BYTES) +
+                                    "; use gct_gram_apply with a workspace");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return check_hip(e, "hipGetDevice");
+    if (dev != p->device) return fail(GCT_EINVAL, "the current device is not the plan's device");
+    void *ws = nullptr;
+    const int rc = static_scratch(dev, &ws);
+    if (rc != GCT_OK) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    e = dt == GCT_F32 ? launch_gram_apply<float>(p, (const float *)Ghat, (const float *)c, (float *)y, ws, s)
+                      : launch_gram_apply<double>(p, (const double *)Ghat, (const double *)c, (double *)y, ws, s);
+    return check_hip(e, "gram_apply_static launch");
+}
+

@@ -84,6 +84,7 @@ def _load():
     L.gct_gram_build.argtypes = [vp, ctypes.c_int, vp, vp]
     L.gct_gram_spectrum.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.gct_gram_apply.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp]
+    L.gct_gram_apply_static.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.gct_prefilter.argtypes = [vp, ctypes.c_int, vp, vp, vp]
     L.gct_backproject_boxspline.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp]
     L.gct_forward_project.argtypes = [vp, ctypes.c_int, vp, vp, vp]
@@ -242,6 +243,14 @@ def gram_apply(plan: Plan, Ghat: torch.Tensor, c: torch.Tensor, y: torch.Tensor,
     _check(lib.gct_gram_apply(plan.handle, dt, _ptr(Ghat, plan.info.spectrum_elems, c.dtype),
                               _ptr(c, plan.info.image_elems), _ptr(y, plan.info.image_elems, c.dtype),
                               _ptr(ws, plan.workspace_size(OP_GRAM_APPLY, c.dtype)), _stream()))
+    return y
+
+
+def gram_apply_static(plan: Plan, Ghat: torch.Tensor, c: torch.Tensor, y: torch.Tensor):
+    """gram_apply with the library's static scratch (no workspace)."""
+    _check(lib.gct_gram_apply_static(plan.handle, _dt(c), _ptr(Ghat, plan.info.spectrum_elems, c.dtype),
+                                     _ptr(c, plan.info.image_elems), _ptr(y, plan.info.image_elems, c.dtype),
+                                     _stream()))
     return y
 
 
@@ -447,6 +456,7 @@ def batch_get_pass_elems(batch: Batch, dtype=torch.float32) -> list:
 gct_gram_build = gram_build
 gct_gram_spectrum = gram_spectrum
 gct_gram_apply = gram_apply
+gct_gram_apply_static = gram_apply_static
 gct_prefilter = prefilter
 gct_backproject_boxspline = backproject_boxspline
 gct_forward_project = forward_project

@@ -32,6 +32,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector rate without packed instructions (which this build does not
+# emit): 256 CUs x 64 lanes x 2 flop (FMA) x 2.4 GHz
+FP32_VALU_PEAK_TFLOPS = 78.6
 WORKLOAD = "n512_a720_m730_z1"
 APPLY_BURST = 200
 APPLY_GRAPH = 50
@@ -44,8 +47,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=WORKLOAD)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--batch-slices", type=int, default=256)
-    ap.add_argument("--warm-slices", type=int, default=64,
+    ap.add_argument("--batch-slices", type=int, default=256,
+                    help="slices of the uneven batch reported beside the main line (0: skip)")
+    ap.add_argument("--warm-slices", type=int, default=1024,
                     help="held-out slices for the plain vs warm-start CG comparison (0: skip)")
     ap.add_argument("--fft-elems", default="",
                     help="elements per thread of the Gram-filtering transforms: E for every pass, or "
@@ -65,10 +69,22 @@ def parse():
     return ap.parse_args()
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, theta, sample):
     """The FP64 oracle's normal operator (direct spatial sum with the exactly
     integrated Gram filter), timed on the host cores on a bounded sample of
-    output pixels and scaled to whole applies per second."""
+    output pixels and scaled to whole applies per second: once on all the
+    threads OpenMP uses, once on one thread (a 1/32 sample)."""
     import oracle
     from paper_2005_13471_amd import inputs
     oracle.build(force=False)
@@ -79,17 +95,42 @@ def cpu_baseline(cfg, theta, sample):
     if sample <= 0 or sample > N * N:
         sample = N * N
     idx = np.arange(0, N * N, max(1, (N * N) // sample), dtype=np.int32)[:sample]
+    threads = oracle.max_threads()
     t0 = time.perf_counter()
     oracle.apply_at(G, c, idx)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": (idx.size / (N * N)) / dt, "unit": "applies/s", "cores": cores,
-            "kind": "oracle",
+    idx1 = idx[::32]
+    oracle.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.apply_at(G, c, idx1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(threads)
+    return {"value": (idx.size / (N * N)) / dt, "unit": "applies/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "value_1core": (idx1.size / (N * N)) / dt1,
             "sample": f"direct-sum H^T H c (FP64, exact Gram filter) at {idx.size} of {N*N} "
-                      f"output pixels, {dt:.2f} s wall, scaled by {N*N/idx.size:.0f}"}
+                      f"output pixels on {threads} threads, {dt:.2f} s wall, scaled by "
+                      f"{N*N/idx.size:.0f}; one thread: {idx1.size} pixels, {dt1:.2f} s, scaled by "
+                      f"{N*N/idx1.size:.0f}"}
 
 
 def batch_main(args):
+    out = batch_run(args.batch_slices, args.steps, args.warmup, args.pmc_probe)
+    if out is not None:
+        print(json.dumps(out), flush=True)
+
+
+def fft_flops(N: int, P: int) -> float:
+    """Flops of one Gram-filtering apply of an N x N slice by the three
+    passes, counted as 5 P log2 P per complex transform of size P: N/2 row
+    transforms (two real rows each) forward and inverse, and P/2 + 1 column
+    transforms forward and inverse."""
+    return 5.0 * P * np.log2(P) * (2 * ((N + 1) // 2) + 2 * (P // 2 + 1))
+
+
+def batch_run(S, steps, warmup, pmc_probe=False):
     """256 independent slices of uneven size through one batch: N from
     {128, 256, 384, 512, 768, 1024}, angle counts from {180, 360, 720, 1440},
     blur from {0, 0.5, 1}, each drawn from a seeded generator; 40-ellipse
@@ -105,7 +146,6 @@ def batch_main(args):
     torch.cuda.set_device(0)
     dt = torch.float32
     rng = np.random.Generator(np.random.PCG64(3000))
-    S = args.batch_slices
     Ns = rng.choice([128, 256, 384, 512, 768, 1024], size=S)
     ns = rng.choice([180, 360, 720, 1440], size=S)
     zs = rng.choice([0.0, 0.5, 1.0], size=S)
@@ -141,7 +181,7 @@ def batch_main(args):
     gct.batch_gram_spectrum(B, G, Ghat, ws_spec)
     gct.batch_autotune(B, Ghat, ws_cg, reps=3)
     torch.cuda.synchronize()
-    if args.pmc_probe:
+    if pmc_probe:
         # counter runs: BATCH_PMC_APPLIES batched applies, then the calibration copy
         for _ in range(BATCH_PMC_APPLIES):
             gct.batch_gram_apply(B, Ghat, bpk, y, ws_apply)
@@ -154,7 +194,7 @@ def batch_main(args):
         print(json.dumps({"pmc_probe": True, "workload": "batch_uneven_256", "applies": BATCH_PMC_APPLIES,
                           "passes_per_apply": 3 * B.groups, "copy_bytes": PMC_COPY_BYTES,
                           "batch_source_sha": batch_source_sha()}))
-        return
+        return None
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
         for _ in range(4):
@@ -177,27 +217,29 @@ def batch_main(args):
         rec.append((e, res))
 
     warm = []
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(warm)
     torch.cuda.synchronize()
     rec = []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(rec)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ph = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(4)] for e, _ in rec])
-    apply_ms = ph[:, 3].sum() / (args.steps * 20)
+    apply_ms = ph[:, 3].sum() / (steps * 20)
     res = rec[-1][1]
     alg = sum(8 * p.N * p.N + 4 * (p.info.fft_size // 2 + 1) * p.info.fft_size for p in plans)
+    flops = sum(fft_flops(p.N, p.info.fft_size) for p in plans)
     achieved = alg / (apply_ms * 1e-3) / 1e9
+    tflops = flops / (apply_ms * 1e-3) / 1e12
     iters = np.array([r.iters for r in res])
     out = {
         "metric": "batched uneven slices: slices/s (build + spectrum + CG to 1e-4) and aggregate Gram-filtering GB/s",
         "value": round(S / (np.median(ph[:, 0] + ph[:, 1] + ph[:, 2]) * 1e-3), 2),
         "unit": "slices/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(wall * 1e3 / args.steps, 3),
+        "n_gpus": 1, "steps": steps, "warmup": warmup,
+        "ms_per_step": round(wall * 1e3 / steps, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batch_uneven_256", "slices": S, "seed": 3000,
@@ -215,8 +257,12 @@ def batch_main(args):
                      "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": batch_measured_traffic(),
                      "alg_bytes_per_launch": alg},
+        "roofline_alu": {"kernel": "batched gram_apply FFT arithmetic (5 P log2 P per complex transform)",
+                         "bound": "alu", "achieved": round(tflops, 2), "peak": FP32_VALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / FP32_VALU_PEAK_TFLOPS, 4),
+                         "alg_flops_per_launch": flops},
     }
-    print(json.dumps(out), flush=True)
+    return out
 
 
 PMC_APPLIES = 20
@@ -652,6 +698,14 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": measured_traffic(fft_elems),
                      "alg_bytes_per_launch": alg_bytes},
     }
+    if args.batch_slices > 0:
+        del graph
+        torch.cuda.synchronize()
+        bt = batch_run(args.batch_slices, 3, 1)
+        out["batch_uneven_256"] = {k: bt[k] for k in ("value", "unit", "metric", "phase_ms", "cg", "roofline",
+                                                       "roofline_alu")}
+        out["batch_uneven_256"]["config"] = {k: bt["config"][k] for k in ("slices", "seed", "N_values",
+                                                                          "fft_groups")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(cfg, theta, args.cpu_sample)
     print(json.dumps(out), flush=True)

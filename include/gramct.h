@@ -308,7 +308,11 @@ int gct_batch_gram_apply(const gct_batch *batch, gct_dtype dtype, const void *Gh
 /* CG from x_i = 0 on every slice to ||r_i|| <= rtol ||b_i|| (per slice) or
  * max_iter iterations; converged slices stop while the others continue.
  * Textbook arrangement (products A p, then the x, r update and ||r||^2,
- * then beta), FP64 inner products as in gct_cg_solve.
+ * then beta), FP64 inner products as in gct_cg_solve.  As there, success
+ * means the recomputed residual of the returned iterate meets rtol: slices
+ * whose recursive residual alone met it restart from their iterate with
+ * r = b - A x (at most 4 times, within max_iter iterations per slice), else
+ * they report GCT_ENOTCONV.
  * results: HOST array of `slices` entries.  Returns GCT_OK if all slices
  * converged, else GCT_ENOTCONV / GCT_EBREAKDOWN (see results[i].status).
  * Chunks of check_every iterations (<= 0 selects 8) are replayed as a

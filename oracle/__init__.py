@@ -65,6 +65,8 @@ def lib():
         L.or_explicit_H.restype = _c_int
         L.or_apply.argtypes = [_c_int, _dp, _dp, _dp]
         L.or_apply_at.argtypes = [_c_int, _dp, _dp, _c_int, _ip, _dp]
+        L.or_max_threads.restype = _c_int
+        L.or_set_threads.argtypes = [_c_int]
         L.or_bspline.argtypes = [_c_int, _c_dbl]
         L.or_bspline.restype = _c_dbl
         L.or_degree.argtypes = [_c_dbl, _c_dbl]
@@ -234,3 +236,14 @@ def cg(G: np.ndarray, b: np.ndarray, x0=None, maxit=100, rtol=1e-4):
     hist = np.zeros(maxit + 1)
     it = lib().or_cg(N, _f64(G).reshape(-1), _f64(b).reshape(-1), x, int(maxit), float(rtol), hist)
     return x.reshape(N, N), it, hist[: it + 1]
+
+
+def max_threads() -> int:
+    """Threads the oracle's parallel loops use (OpenMP's current maximum)."""
+    return int(lib().or_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's parallel loops on n threads from now on."""
+    lib().or_set_threads(int(n))
+

@@ -26,6 +26,7 @@
  * independent outputs, so results do not depend on the thread count.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -693,3 +694,8 @@ OR_API int or_sd(int N, const double *G, const double *b, double *x, int maxit, 
     free(Ar);
     return k;
 }
+
+/* Thread count of the parallel loops (for timing the oracle on a stated
+ * number of host cores). */
+int or_max_threads(void) { return omp_get_max_threads(); }
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }

@@ -25,6 +25,7 @@ hipError_t launch_batch_gram_build(const int2 *map, int nblocks, const BatchSlic
                                    hipStream_t s);
 
 constexpr int BVB = 8;  // vector-kernel blocks per slice
+constexpr int BATCH_MAX_RESTARTS = 4;
 
 __device__ __forceinline__ bool slice_halted(const CGState *st, int s)
 {
@@ -406,6 +407,55 @@ __global__ void __launch_bounds__(256) kb_cg_beta(CGState *st, const double *upa
     }
 }
 
+// Residual replacement: a slice whose recursive residual met the rule while
+// the recomputed one (st.pad, from A x in Ax) did not restarts from its
+// iterate with r = b - A x, p = r; the iteration count continues.  Other
+// slices keep their state.  Both kernels test the same condition on the
+// same state.
+__device__ __forceinline__ bool slice_restarts(const CGState &c)
+{
+    return c.status == CG_CONVERGED && c.pad > c.thr2;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+kb_cg_restart_vec(const CGState *st, const BatchSlice *__restrict__ sl, const T *__restrict__ b,
+                  const T *__restrict__ Ax, T *__restrict__ r, T *__restrict__ p, double *__restrict__ prr)
+{
+    const int s = blockIdx.x / BVB, j = blockIdx.x % BVB;
+    if (!slice_restarts(st[s])) {
+        if (threadIdx.x == 0) prr[blockIdx.x] = 0.0;
+        return;
+    }
+    const BatchSlice &d = sl[s];
+    const size_t n = (size_t)d.N * d.N;
+    double rr = 0.0;
+    for (size_t i = (size_t)j * blockDim.x + threadIdx.x; i < n; i += (size_t)BVB * blockDim.x) {
+        const size_t g = d.img + i;
+        const T ri = b[g] - Ax[g];
+        r[g] = ri;
+        p[g] = ri;
+        rr += (double)ri * (double)ri;
+    }
+    rr = bsum(rr);
+    if (threadIdx.x == 0) prr[blockIdx.x] = rr;
+}
+
+__global__ void __launch_bounds__(256) kb_cg_restart_fin(CGState *st, const double *prr)
+{
+    const int s = blockIdx.x;
+    const bool go = slice_restarts(st[s]);
+    const double rr = bsum(threadIdx.x < BVB ? prr[s * BVB + threadIdx.x] : 0.0);
+    if (go && threadIdx.x == 0) {
+        CGState &c = st[s];
+        c.rr = rr;
+        c.beta = 0.0;
+        c.ring[c.k % CG_RING] = rr;
+        c.status = (rr <= c.thr2) ? CG_CONVERGED : CG_RUNNING;
+        if (!(rr == rr)) c.status = CG_BREAKDOWN;
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
 kb_resid(const BatchSlice *__restrict__ sl, const T *__restrict__ b, const T *__restrict__ Ax,
@@ -688,49 +738,65 @@ int batch_cg(const gct_batch *b, const T *Ghat, const T *bv, T *x, int use_x0, d
         }
         return hipGetLastError();
     };
-    int64_t done = 0;
-    while (running() && done < max_iter) {
-        const int chunk = (int)std::min<int64_t>(check_every, max_iter - done);
-        if (chunk == check_every) {
-            const CGGraphKey key{(const void *)Ghat, (void *)x, ws, (int)sizeof(T), chunk};
-            hipGraphExec_t exec = nullptr;
-            for (const auto &g : b->graphs)
-                if (g.key == key) exec = g.exec;
-            if (!exec) {
-                gct_batch *mb = const_cast<gct_batch *>(b);
-                if (!mb->capture_stream &&
-                    hipStreamCreateWithFlags(&mb->capture_stream, hipStreamNonBlocking) != hipSuccess)
-                    return fail(GCT_EHIP, "cannot create the capture stream");
-                B_TRY(hipStreamBeginCapture(mb->capture_stream, hipStreamCaptureModeThreadLocal));
-                hipError_t e = launch_iters(chunk, mb->capture_stream);
-                hipGraph_t gr = nullptr;
-                hipError_t e2 = hipStreamEndCapture(mb->capture_stream, &gr);
-                if (e != hipSuccess || e2 != hipSuccess) {
-                    if (gr) (void)hipGraphDestroy(gr);
-                    return check_hip(e != hipSuccess ? e : e2, "batch cg graph capture");
+    // Runs: the first from the start vectors; later ones restart the slices
+    // whose recursive residual met the rule while the recomputed one did not
+    // (at most BATCH_MAX_RESTARTS, within max_iter iterations per slice).
+    int64_t limit = max_iter;
+    for (int run = 0;; ++run) {
+        int64_t done = 0;
+        while (running() && done < limit) {
+            const int chunk = (int)std::min<int64_t>(check_every, limit - done);
+            if (chunk == check_every) {
+                const CGGraphKey key{(const void *)Ghat, (void *)x, ws, (int)sizeof(T), chunk};
+                hipGraphExec_t exec = nullptr;
+                for (const auto &g : b->graphs)
+                    if (g.key == key) exec = g.exec;
+                if (!exec) {
+                    gct_batch *mb = const_cast<gct_batch *>(b);
+                    if (!mb->capture_stream &&
+                        hipStreamCreateWithFlags(&mb->capture_stream, hipStreamNonBlocking) != hipSuccess)
+                        return fail(GCT_EHIP, "cannot create the capture stream");
+                    B_TRY(hipStreamBeginCapture(mb->capture_stream, hipStreamCaptureModeThreadLocal));
+                    hipError_t e = launch_iters(chunk, mb->capture_stream);
+                    hipGraph_t gr = nullptr;
+                    hipError_t e2 = hipStreamEndCapture(mb->capture_stream, &gr);
+                    if (e != hipSuccess || e2 != hipSuccess) {
+                        if (gr) (void)hipGraphDestroy(gr);
+                        return check_hip(e != hipSuccess ? e : e2, "batch cg graph capture");
+                    }
+                    e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
+                    (void)hipGraphDestroy(gr);
+                    if (e != hipSuccess) return check_hip(e, "hipGraphInstantiate");
+                    if (mb->graphs.size() >= 8) {
+                        (void)hipGraphExecDestroy(mb->graphs.front().exec);
+                        mb->graphs.erase(mb->graphs.begin());
+                    }
+                    mb->graphs.push_back({key, exec});
                 }
-                e = hipGraphInstantiate(&exec, gr, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(gr);
-                if (e != hipSuccess) return check_hip(e, "hipGraphInstantiate");
-                if (mb->graphs.size() >= 8) {
-                    (void)hipGraphExecDestroy(mb->graphs.front().exec);
-                    mb->graphs.erase(mb->graphs.begin());
-                }
-                mb->graphs.push_back({key, exec});
+                B_TRY(hipGraphLaunch(exec, s));
+            } else {
+                B_TRY(launch_iters(chunk, s));
             }
-            B_TRY(hipGraphLaunch(exec, s));
-        } else {
-            B_TRY(launch_iters(chunk, s));
+            if ((rc = pull())) return rc;
+            done += chunk;
         }
+        // true residuals of the returned iterates (A x left in Ap)
+        B_TRY(batch_apply_passes<T>(b, Ghat, x, Ap, ws, s, nullptr, nullptr, nullptr, nullptr));
+        hipLaunchKernelGGL(kb_resid<T>, dim3(S * BVB), dim3(256), 0, s, sl, bv, Ap, upart);
+        hipLaunchKernelGGL(kb_resid_fin, dim3(S), dim3(256), 0, s, st, upart);
+        B_TRY(hipGetLastError());
         if ((rc = pull())) return rc;
-        done += chunk;
+        int64_t kmax = -1;
+        for (const auto &c : hs)
+            if (c.status == CG_CONVERGED && c.pad > c.thr2) kmax = std::max<int64_t>(kmax, c.k);
+        if (kmax < 0 || run == BATCH_MAX_RESTARTS || kmax >= max_iter || running()) break;
+        hipLaunchKernelGGL(kb_cg_restart_vec<T>, dim3(S * BVB), dim3(256), 0, s, (const CGState *)st, sl, bv,
+                           (const T *)Ap, r, p, upart);
+        hipLaunchKernelGGL(kb_cg_restart_fin, dim3(S), dim3(256), 0, s, st, (const double *)upart);
+        B_TRY(hipGetLastError());
+        if ((rc = pull())) return rc;
+        limit = max_iter - kmax;
     }
-    // true residuals of the returned iterates
-    B_TRY(batch_apply_passes<T>(b, Ghat, x, Ap, ws, s, nullptr, nullptr, nullptr, nullptr));
-    hipLaunchKernelGGL(kb_resid<T>, dim3(S * BVB), dim3(256), 0, s, sl, bv, Ap, upart);
-    hipLaunchKernelGGL(kb_resid_fin, dim3(S), dim3(256), 0, s, st, upart);
-    B_TRY(hipGetLastError());
-    if ((rc = pull())) return rc;
     int worst = GCT_OK;
     for (int i = 0; i < S; ++i) {
         const CGState &c = hs[i];
@@ -741,7 +807,8 @@ int batch_cg(const gct_batch *b, const T *Ghat, const T *bv, T *x, int use_x0, d
         o.rel_res_true = rel(c.pad);
         o.rel_res0 = rel(c.rr0);
         o.fell_back = (int32_t)c.fb;
-        o.status = c.status == CG_CONVERGED ? GCT_OK
+        // success means the recomputed residual met the rule too
+        o.status = c.status == CG_CONVERGED ? (c.pad <= c.thr2 ? GCT_OK : GCT_ENOTCONV)
                    : c.status == CG_BREAKDOWN ? GCT_EBREAKDOWN
                                               : GCT_ENOTCONV;
         if (o.status == GCT_EBREAKDOWN) worst = GCT_EBREAKDOWN;

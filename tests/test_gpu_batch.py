@@ -327,3 +327,40 @@ def test_batch_config3_sizes_match_oracle():
         r = rhs[i].reshape(-1)[idx] - oracle.apply_at(g_or, xh, idx)
         # sampled residual entries consistent with ||r|| <= 1e-4 ||b||
         assert np.sqrt(np.mean(r ** 2)) <= 3e-4 * np.linalg.norm(rhs[i]) / N, i
+
+
+@pytest.mark.parametrize("dt,rtol", [(torch.float32, 1e-7), (torch.float64, 1e-10)])
+def test_batch_cg_success_means_true_residual(batch_setup, dt, rtol):
+    """As for the single-slice solver: a slice reports success only when its
+    recomputed residual meets rtol (far below FP32's attainable accuracy the
+    recursive residual alone would); FP64 reaches the same tolerance, and the
+    oracle's recomputed residual of each FP64 iterate agrees."""
+    gct, B, plans, ogs = batch_setup
+    G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
+    gct.batch_gram_build(B, G)
+    Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")
+    gct.batch_gram_spectrum(B, G, Ghat, B.workspace(gct.OP_GRAM_SPECTRUM, dt))
+    rhs = []
+    for i, (N, n, z) in enumerate(SLICES):
+        ells = inputs.random_ellipses(N, 8, 8000 + i)
+        sino = inputs.add_noise(inputs.analytic_sinogram(ells, plans[i].theta, plans[i].M, zeta=z),
+                                0.01, inputs.NOISE_SEED_BASE + 8000 + i)
+        bi = torch.empty(N * N, dtype=dt, device="cuda")
+        gct.backproject_boxspline(plans[i], torch.as_tensor(sino.reshape(-1), dtype=dt, device="cuda"),
+                                  bi, plans[i].workspace(gct.OP_BACKPROJECT, dt))
+        rhs.append(bi.double().cpu().numpy().reshape(N, N))
+    b = _packed(B, rhs, dt)
+    x = torch.zeros_like(b)
+    res = gct.batch_cg_solve(B, Ghat, b, x, B.workspace(gct.OP_CG, dt), rtol=rtol, max_iter=1500,
+                             check_every=8)
+    say("batch cg rtol", rtol, dt, [(r.status, r.iters, r.rel_res, r.rel_res_true) for r in res])
+    for i, r in enumerate(res):
+        assert r.status in (gct.GCT_OK, gct.GCT_ENOTCONV), i
+        assert r.iters <= 1500
+        if r.status == gct.GCT_OK:
+            assert r.rel_res_true <= rtol, i
+        if dt == torch.float64:
+            assert r.status == gct.GCT_OK, i
+            xh = B.image(x, i).double().cpu().numpy()
+            true_rel = np.linalg.norm(rhs[i] - oracle.apply(oracle.gram(ogs[i]), xh)) / np.linalg.norm(rhs[i])
+            assert true_rel <= 1.001 * rtol, i

@@ -179,7 +179,10 @@ def batch_run(S, steps, warmup, pmc_probe=False):
     ws_apply = B.workspace(gct.OP_GRAM_APPLY, dt)
     gct.batch_gram_build(B, G)
     gct.batch_gram_spectrum(B, G, Ghat, ws_spec)
-    gct.batch_autotune(B, Ghat, ws_cg, reps=3)
+    if not pmc_probe:
+        # (counter runs keep the default tilings, so that every run of a
+        # counter set times the same kernels)
+        gct.batch_autotune(B, Ghat, ws_cg, reps=3)
     torch.cuda.synchronize()
     if pmc_probe:
         # counter runs: BATCH_PMC_APPLIES batched applies, then the calibration copy

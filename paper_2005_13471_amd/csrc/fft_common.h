@@ -158,7 +158,7 @@ __device__ __forceinline__ void dftR(C2<T> *v)
 template <typename T>
 __host__ __device__ constexpr bool fft_pingpong(int P)
 {
-    return (size_t)(2 * P + P / 2) * sizeof(C2<T>) <= 65536;
+    return (size_t)(2 * P + P / 2) * sizeof(C2<T>) <= 32768;
 }
 template <typename T>
 __host__ __device__ constexpr int fft_data_elems(int P)

@@ -56,8 +56,8 @@ def lib():
         if not os.path.exists(_LIB):
             build(force=False)
         L = ctypes.CDLL(_LIB)
-        geo = [_c_int, _c_dbl, _c_dbl, _c_int, _dp, _c_dbl]  # N lx1 lx2 n theta zeta
-        L.or_footprint.argtypes = [_c_dbl] * 8
+        geo = [_c_int, _c_dbl, _c_dbl, _c_int, _dp, _dp]  # N lx1 lx2 n theta detector
+        L.or_footprint.argtypes = [_c_dbl] * 4 + [ctypes.c_void_p] + [_c_dbl] * 3
         L.or_footprint.restype = _c_dbl
         L.or_gram.argtypes = geo + [_dp]
         L.or_gram_at.argtypes = geo + [_c_int, _ip, _dp]
@@ -72,8 +72,8 @@ def lib():
         L.or_degree.argtypes = [_c_dbl, _c_dbl]
         L.or_degree.restype = _c_int
         L.or_prefilter_taps.argtypes = [_c_int, _c_int, _dp]
-        L.or_prefilter.argtypes = [_c_int, _dp, _c_dbl, _c_int, _c_int, _dp, _dp]
-        L.or_ghat.argtypes = [_c_int, _dp, _c_dbl, _c_dbl, _c_int, _c_int, _dp, _c_int, _dp, _dp]
+        L.or_prefilter.argtypes = [_c_int, _dp, _dp, _c_int, _c_int, _dp, _dp]
+        L.or_ghat.argtypes = [_c_int, _dp, _dp, _c_dbl, _c_int, _c_int, _dp, _c_int, _dp, _dp]
         bpgeo = geo + [_c_dbl, _c_int, _c_int]  # + ly M K
         L.or_backproject.argtypes = bpgeo + [_dp, _dp]
         L.or_backproject_at.argtypes = bpgeo + [_dp, _c_int, _ip, _dp]
@@ -97,28 +97,51 @@ def _i32(a):
     return np.ascontiguousarray(a, dtype=np.int32)
 
 
+def detector(zeta=0.0, boxes=None) -> np.ndarray:
+    """The detector kernel as the oracle's array {nb, w0, h0, w1, h1, ...}:
+    K(t) = sum_i h_i 1{|t| <= w_i / 2} (Sec. 2: boxes of different heights
+    and lengths).  boxes: (width, height) pairs; else one box of width zeta
+    and height 1/zeta (the paper's blur model), or none for zeta = 0."""
+    if boxes:
+        if zeta:
+            raise ValueError("give either zeta or boxes")
+        bx = [(float(w), float(h)) for w, h in boxes]
+    elif zeta > 0.0:
+        bx = [(float(zeta), 1.0 / float(zeta))]
+    else:
+        bx = []
+    return _f64([len(bx)] + [v for wh in bx for v in wh])
+
+
 class Geometry:
     """Problem statement of Sec. 2: N, Lambda_x = diag(lx1, lx2), the angle set,
-    the detector step ly, the bin count M, the blur width zeta and the
-    correction-filter truncation K (Sec. 5 truncates at 40)."""
+    the detector step ly, the bin count M, the detector kernel (blur width
+    zeta, or a list of (width, height) boxes) and the correction-filter
+    truncation K (Sec. 5 truncates at 40)."""
 
-    def __init__(self, N, theta, M, ly=1.0, zeta=0.0, lx=(1.0, 1.0), K=40):
+    def __init__(self, N, theta, M, ly=1.0, zeta=0.0, lx=(1.0, 1.0), K=40, boxes=None):
         self.N, self.M, self.ly, self.zeta, self.K = int(N), int(M), float(ly), float(zeta), int(K)
+        self.boxes = [tuple(b) for b in boxes] if boxes else None
+        self.det = detector(self.zeta, self.boxes)
         self.lx1, self.lx2 = float(lx[0]), float(lx[1])
         self.theta = _f64(theta)
         self.n = int(self.theta.size)
 
     def _geo(self):
-        return (self.N, self.lx1, self.lx2, self.n, self.theta, self.zeta)
+        return (self.N, self.lx1, self.lx2, self.n, self.theta, self.det)
 
     def _bpgeo(self):
         return self._geo() + (self.ly, self.M, self.K)
 
 
-def footprint(c, s, y, lx=(1.0, 1.0), zeta=0.0, centre=(0.0, 0.0)):
-    """F^zeta of one pixel at direction (c, s), by chord length / clipped area."""
+def footprint(c, s, y, lx=(1.0, 1.0), zeta=0.0, centre=(0.0, 0.0), boxes=None):
+    """Footprint of one pixel at direction (c, s) through the detector kernel
+    (blur width zeta, or boxes): chord length, or sum over boxes of height
+    times clipped area."""
     L = lib()
-    return np.array([L.or_footprint(c, s, lx[0], lx[1], zeta, centre[0], centre[1], float(v))
+    det = detector(zeta, boxes)
+    dp = det.ctypes.data  # (det stays alive for the loop)
+    return np.array([L.or_footprint(c, s, lx[0], lx[1], dp, centre[0], centre[1], float(v))
                      for v in np.atleast_1d(y)])
 
 
@@ -178,14 +201,14 @@ def prefilter_taps(d: int, K: int = 40) -> np.ndarray:
 
 def prefilter(g: Geometry, sino: np.ndarray) -> np.ndarray:
     p = np.zeros((g.n, g.M + 2 * g.K))
-    lib().or_prefilter(g.n, g.theta, g.zeta, g.M, g.K, _f64(sino).reshape(-1), p)
+    lib().or_prefilter(g.n, g.theta, g.det, g.M, g.K, _f64(sino).reshape(-1), p)
     return p
 
 
 def ghat(g: Geometry, sino: np.ndarray, y) -> np.ndarray:
     y = _f64(np.atleast_1d(y))
     out = np.zeros((g.n, y.size))
-    lib().or_ghat(g.n, g.theta, g.zeta, g.ly, g.M, g.K, _f64(sino).reshape(-1), y.size, y, out)
+    lib().or_ghat(g.n, g.theta, g.det, g.ly, g.M, g.K, _f64(sino).reshape(-1), y.size, y, out)
     return out
 
 

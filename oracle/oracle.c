@@ -116,9 +116,43 @@ static int clip_halfplane(const double *px, const double *py, int n, double c, d
     return m;
 }
 
-/* (1/zeta) * area(R intersect {x : |x.u - y| <= zeta/2}): the projection
- * averaged over a detector cell of width zeta (Sec. 2 blur model). */
-static double blurred_footprint(const rect *R, double c, double s, double zeta, double y)
+/* Detector kernel (Sec. 2: the detector cell as boxes of different heights
+ * and lengths): K(t) = sum_i h[i] 1{|t| <= w[i]/2}, nb boxes; nb = 0 is the
+ * point sample of the X-ray transform (no blur).  The paper's single box
+ * of width zeta and height 1/zeta is nb = 1.  Callers pass it as the array
+ * det = {nb, w0, h0, w1, h1, ...}. */
+#define OR_MAXB 4
+typedef struct {
+    int nb;
+    double w[OR_MAXB], h[OR_MAXB];
+} detector;
+
+static detector det_from(const double *det)
+{
+    detector D;
+    D.nb = (int)det[0];
+    if (D.nb < 0) D.nb = 0;
+    if (D.nb > OR_MAXB) D.nb = OR_MAXB;
+    for (int i = 0; i < D.nb; ++i) {
+        D.w[i] = det[1 + 2 * i];
+        D.h[i] = det[2 + 2 * i];
+    }
+    return D;
+}
+
+/* widest box (0 without blur): the kernel's support is [-wmax/2, wmax/2] */
+static double det_wmax(const detector *D)
+{
+    double m = 0.0;
+    for (int i = 0; i < D->nb; ++i)
+        if (D->w[i] > m) m = D->w[i];
+    return m;
+}
+
+/* area(R intersect {x : |x.u - y| <= w/2}) by clipping the rectangle
+ * against the two half-planes of the slab (Sutherland-Hodgman) and the
+ * shoelace formula. */
+static double slab_area(const rect *R, double c, double s, double zeta, double y)
 {
     double ax[8] = {R->x0, R->x1, R->x1, R->x0}, ay[8] = {R->y0, R->y0, R->y1, R->y1};
     double bx[8], by[8], cx[8], cy[8];
@@ -131,26 +165,37 @@ static double blurred_footprint(const rect *R, double c, double s, double zeta, 
         int j = (i + 1) % n;
         area += cx[i] * cy[j] - cx[j] * cy[i];
     }
-    return 0.5 * fabs(area) / zeta;
+    return 0.5 * fabs(area);
 }
 
-static double footprint_rect(const rect *R, double c, double s, double zeta, double y)
+/* Footprint of the pixel rectangle through the detector kernel: the chord
+ * length without blur, else sum_i h[i] area(R intersect slab of width w[i]
+ * around y) (the projection integrated against each box; one box of width
+ * zeta and height 1/zeta averages it over the cell). */
+static double footprint_rect(const rect *R, double c, double s, const detector *D, double y)
 {
-    return zeta > 0.0 ? blurred_footprint(R, c, s, zeta, y) : chord_length(R, c, s, y);
+    if (D->nb == 0) return chord_length(R, c, s, y);
+    double acc = 0.0;
+    for (int i = 0; i < D->nb; ++i) acc += D->h[i] * slab_area(R, c, s, D->w[i], y);
+    return acc;
 }
 
 /* Breakpoints in y of the footprint: projections of the 4 corners, each
- * shifted by +-zeta/2 when blurred.  Writes 4 or 8 values, returns count. */
-static int footprint_breaks(const rect *R, double c, double s, double zeta, double *out)
+ * shifted by +-w[i]/2 for every box.  Writes 4 or 8 nb values (at most
+ * OR_BRK), returns the count. */
+#define OR_BRK (8 * OR_MAXB)
+static int footprint_breaks(const rect *R, double c, double s, const detector *D, double *out)
 {
     double p[4] = {R->x0 * c + R->y0 * s, R->x1 * c + R->y0 * s, R->x0 * c + R->y1 * s,
                    R->x1 * c + R->y1 * s};
-    if (zeta > 0.0) {
-        for (int i = 0; i < 4; ++i) {
-            out[2 * i] = p[i] - 0.5 * zeta;
-            out[2 * i + 1] = p[i] + 0.5 * zeta;
-        }
-        return 8;
+    if (D->nb > 0) {
+        int n = 0;
+        for (int b = 0; b < D->nb; ++b)
+            for (int i = 0; i < 4; ++i) {
+                out[n++] = p[i] - 0.5 * D->w[b];
+                out[n++] = p[i] + 0.5 * D->w[b];
+            }
+        return n;
     }
     for (int i = 0; i < 4; ++i) out[i] = p[i];
     return 4;
@@ -167,11 +212,12 @@ static void support(const double *br, int n, double *lo, double *hi)
     *hi = b;
 }
 
-OR_API double or_footprint(double c, double s, double lx1, double lx2, double zeta, double cx,
+OR_API double or_footprint(double c, double s, double lx1, double lx2, const double *det, double cx,
                            double cy, double y)
 {
     rect R = pixel_rect(cx, cy, lx1, lx2);
-    return footprint_rect(&R, c, s, zeta, y);
+    detector D = det_from(det);
+    return footprint_rect(&R, c, s, &D, y);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -181,9 +227,9 @@ OR_API double or_footprint(double c, double s, double lx1, double lx2, double ze
 /* breakpoints, so the product has degree <= 4 and 3-point Gauss-Legendre    */
 /* on every segment of the merged breakpoint list is exact.                  */
 /* ------------------------------------------------------------------------ */
-static double inner_product_angle(const rect *A, const rect *B, double c, double s, double zeta)
+static double inner_product_angle(const rect *A, const rect *B, double c, double s, const detector *zeta)
 {
-    double br[16], lo1, hi1, lo2, hi2;
+    double br[2 * OR_BRK], lo1, hi1, lo2, hi2;
     int na = footprint_breaks(A, c, s, zeta, br);
     support(br, na, &lo1, &hi1);
     int nb = footprint_breaks(B, c, s, zeta, br + na);
@@ -211,9 +257,12 @@ static double inner_product_angle(const rect *A, const rect *B, double c, double
 /* Output layout: G[(k2 + N-1) * (2N-1) + (k1 + N-1)].  Pairs of disjoint     */
 /* footprints contribute exactly zero and are skipped.                       */
 /* ------------------------------------------------------------------------ */
-OR_API void or_gram(int N, double lx1, double lx2, int n, const double *theta, double zeta,
+OR_API void or_gram(int N, double lx1, double lx2, int n, const double *theta, const double *det,
                     double *G)
 {
+    detector Dz = det_from(det);
+    const detector *zeta = &Dz;
+    const double wmax = det_wmax(zeta);
     const int W = 2 * N - 1;
     rect P0 = pixel_rect(0.0, 0.0, lx1, lx2);
 #pragma omp parallel for schedule(dynamic, 1)
@@ -225,7 +274,7 @@ OR_API void or_gram(int N, double lx1, double lx2, int n, const double *theta, d
             double acc = 0.0;
             for (int a = 0; a < n; ++a) {
                 double c = cos(theta[a]), s = sin(theta[a]);
-                double half = 0.5 * (lx1 * fabs(c) + lx2 * fabs(s) + zeta);
+                double half = 0.5 * (lx1 * fabs(c) + lx2 * fabs(s) + wmax);
                 double d = k1 * lx1 * c + k2 * lx2 * s;
                 if (fabs(d) >= 2.0 * half) continue;
                 acc += inner_product_angle(&P0, &Pk, c, s, zeta);
@@ -236,9 +285,12 @@ OR_API void or_gram(int N, double lx1, double lx2, int n, const double *theta, d
 }
 
 /* Selected taps only: taps[2i], taps[2i+1] = (k1, k2). */
-OR_API void or_gram_at(int N, double lx1, double lx2, int n, const double *theta, double zeta,
+OR_API void or_gram_at(int N, double lx1, double lx2, int n, const double *theta, const double *det,
                        int cnt, const int *taps, double *out)
 {
+    detector Dz = det_from(det);
+    const detector *zeta = &Dz;
+    const double wmax = det_wmax(zeta);
     (void)N;
     rect P0 = pixel_rect(0.0, 0.0, lx1, lx2);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -248,7 +300,7 @@ OR_API void or_gram_at(int N, double lx1, double lx2, int n, const double *theta
         double acc = 0.0;
         for (int a = 0; a < n; ++a) {
             double c = cos(theta[a]), s = sin(theta[a]);
-            double half = 0.5 * (lx1 * fabs(c) + lx2 * fabs(s) + zeta);
+            double half = 0.5 * (lx1 * fabs(c) + lx2 * fabs(s) + wmax);
             double d = k1 * lx1 * c + k2 * lx2 * s;
             if (fabs(d) >= 2.0 * half) continue;
             acc += inner_product_angle(&P0, &Pk, c, s, zeta);
@@ -264,11 +316,13 @@ OR_API void or_gram_at(int N, double lx1, double lx2, int n, const double *theta
 /* so (H^T H)_{ij} equals the continuous-y inner product exactly.            */
 /* Call with H == NULL to get the row count.  H is row-major [rows][N*N].    */
 /* ------------------------------------------------------------------------ */
-OR_API int or_explicit_H(int N, double lx1, double lx2, int n, const double *theta, double zeta,
+OR_API int or_explicit_H(int N, double lx1, double lx2, int n, const double *theta, const double *det,
                          double *H)
 {
     const int NN = N * N;
-    double *br = (double *)malloc(sizeof(double) * 8 * (size_t)NN);
+    detector Dz = det_from(det);
+    const detector *zeta = &Dz;
+    double *br = (double *)malloc(sizeof(double) * OR_BRK * (size_t)NN);
     int row = 0;
     for (int a = 0; a < n; ++a) {
         double c = cos(theta[a]), s = sin(theta[a]);
@@ -356,7 +410,7 @@ OR_API double or_bspline(int d, double x)
 /* B-spline degree per angle (Sec. 5): the projected signal is C^0 (C^-1 for
  * an axis-aligned angle) without blur and C^1 (C^0 axis-aligned) with blur;
  * the interpolating B-spline has degree one above that continuity order. */
-OR_API int or_degree(double theta, double zeta)
+OR_API int or_degree(double theta, double zeta)  /* zeta > 0: any detector blur */
 {
     double c = fabs(cos(theta)), s = fabs(sin(theta));
     int axis = (c < 1e-12 || s < 1e-12);
@@ -416,9 +470,10 @@ static void prefilter_row(const double *g, int M, int K, const double *q, double
     }
 }
 
-OR_API void or_prefilter(int n, const double *theta, double zeta, int M, int K, const double *g,
+OR_API void or_prefilter(int n, const double *theta, const double *det, int M, int K, const double *g,
                          double *p)
 {
+    const double zeta = det[0] > 0.0 ? 1.0 : 0.0; /* blurred or not: the degree rule */
     double *qs[3];
     for (int d = 0; d < 3; ++d) {
         qs[d] = (double *)malloc(sizeof(double) * (2 * K + 1));
@@ -446,11 +501,12 @@ static double ghat_eval(const double *prow, int M, int K, double ly, int d, doub
 }
 
 /* Evaluate ghat for every angle at arbitrary points (tests of Sec. 5). */
-OR_API void or_ghat(int n, const double *theta, double zeta, double ly, int M, int K,
+OR_API void or_ghat(int n, const double *theta, const double *det, double ly, int M, int K,
                     const double *g, int cnt, const double *y, double *out /* n x cnt */)
 {
+    const double zeta = det[0] > 0.0 ? 1.0 : 0.0;
     double *p = (double *)malloc(sizeof(double) * (size_t)n * (M + 2 * K));
-    or_prefilter(n, theta, zeta, M, K, g, p);
+    or_prefilter(n, theta, det, M, K, g, p);
     for (int a = 0; a < n; ++a) {
         int d = or_degree(theta[a], zeta);
         for (int i = 0; i < cnt; ++i)
@@ -465,15 +521,16 @@ OR_API void or_ghat(int n, const double *theta, double zeta, double ly, int M, i
 /* Segments are cut at the footprint breakpoints and at the knots of ghat;   */
 /* the integrand has degree <= 2 + 2 there, so Gauss-Legendre is exact.      */
 /* ------------------------------------------------------------------------ */
-static double bp_pixel(int N, double lx1, double lx2, int n, const double *theta, double zeta,
+static double bp_pixel(int N, double lx1, double lx2, int n, const double *theta, const detector *zeta,
                        double ly, int M, int K, const double *p, int k1, int k2)
 {
     rect R = pixel_rect(lx1 * (k1 - 0.5 * (N - 1)), lx2 * (k2 - 0.5 * (N - 1)), lx1, lx2);
     double acc = 0.0;
-    double br[8 + 64];
+    double br[OR_BRK + 256];
+    const double blur = zeta->nb > 0 ? 1.0 : 0.0;
     for (int a = 0; a < n; ++a) {
         double c = cos(theta[a]), s = sin(theta[a]);
-        int d = or_degree(theta[a], zeta);
+        int d = or_degree(theta[a], blur);
         const double *prow = p + (size_t)a * (M + 2 * K);
         int nb = footprint_breaks(&R, c, s, zeta, br);
         double lo, hi;
@@ -481,7 +538,7 @@ static double bp_pixel(int N, double lx1, double lx2, int n, const double *theta
         /* knots of ghat: y_m (d odd) or y_m +- ly/2 (d even) */
         double off = (d % 2 == 0) ? 0.5 : 0.0;
         double z0 = lo / ly + 0.5 * (M - 1) - off, z1 = hi / ly + 0.5 * (M - 1) - off;
-        for (int m = (int)ceil(z0); m <= (int)floor(z1) && nb < 72; ++m)
+        for (int m = (int)ceil(z0); m <= (int)floor(z1) && nb < OR_BRK + 256; ++m)
             br[nb++] = ly * (m + off - 0.5 * (M - 1));
         nb = sort_unique(br, nb);
         for (int i = 0; i + 1 < nb; ++i) {
@@ -497,26 +554,28 @@ static double bp_pixel(int N, double lx1, double lx2, int n, const double *theta
     return acc;
 }
 
-OR_API void or_backproject(int N, double lx1, double lx2, int n, const double *theta, double zeta,
+OR_API void or_backproject(int N, double lx1, double lx2, int n, const double *theta, const double *det,
                            double ly, int M, int K, const double *g, double *b)
 {
+    detector Dz = det_from(det);
     double *p = (double *)malloc(sizeof(double) * (size_t)n * (M + 2 * K));
-    or_prefilter(n, theta, zeta, M, K, g, p);
+    or_prefilter(n, theta, det, M, K, g, p);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int i = 0; i < N * N; ++i)
-        b[i] = bp_pixel(N, lx1, lx2, n, theta, zeta, ly, M, K, p, i % N, i / N);
+        b[i] = bp_pixel(N, lx1, lx2, n, theta, &Dz, ly, M, K, p, i % N, i / N);
     free(p);
 }
 
 OR_API void or_backproject_at(int N, double lx1, double lx2, int n, const double *theta,
-                              double zeta, double ly, int M, int K, const double *g, int cnt,
+                              const double *det, double ly, int M, int K, const double *g, int cnt,
                               const int *idx, double *b)
 {
+    detector Dz = det_from(det);
     double *p = (double *)malloc(sizeof(double) * (size_t)n * (M + 2 * K));
-    or_prefilter(n, theta, zeta, M, K, g, p);
+    or_prefilter(n, theta, det, M, K, g, p);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < cnt; ++i)
-        b[i] = bp_pixel(N, lx1, lx2, n, theta, zeta, ly, M, K, p, idx[i] % N, idx[i] / N);
+        b[i] = bp_pixel(N, lx1, lx2, n, theta, &Dz, ly, M, K, p, idx[i] % N, idx[i] / N);
     free(p);
 }
 
@@ -524,10 +583,10 @@ OR_API void or_backproject_at(int N, double lx1, double lx2, int n, const double
 /* Forward model (Sec. 2 and Sec. 4): g_s[theta, m] = (H c)(y_m)             */
 /*   = sum_k c_k F_{k,theta}(y_m), point samples of the (blurred) projection. */
 /* ------------------------------------------------------------------------ */
-static double fp_bin(int N, double lx1, double lx2, double c, double s, double zeta,
+static double fp_bin(int N, double lx1, double lx2, double c, double s, const detector *zeta,
                      const double *img, double y)
 {
-    double half = 0.5 * (lx1 * fabs(c) + lx2 * fabs(s) + zeta);
+    double half = 0.5 * (lx1 * fabs(c) + lx2 * fabs(s) + det_wmax(zeta));
     double acc = 0.0;
     for (int k2 = 0; k2 < N; ++k2) {
         double cy = lx2 * (k2 - 0.5 * (N - 1));
@@ -541,9 +600,11 @@ static double fp_bin(int N, double lx1, double lx2, double c, double s, double z
     return acc;
 }
 
-OR_API void or_forward(int N, double lx1, double lx2, int n, const double *theta, double zeta,
+OR_API void or_forward(int N, double lx1, double lx2, int n, const double *theta, const double *det,
                        double ly, int M, const double *img, double *g)
 {
+    detector Dz = det_from(det);
+    const detector *zeta = &Dz;
 #pragma omp parallel for schedule(dynamic, 1) collapse(2)
     for (int a = 0; a < n; ++a)
         for (int m = 0; m < M; ++m)
@@ -552,9 +613,11 @@ OR_API void or_forward(int N, double lx1, double lx2, int n, const double *theta
 }
 
 /* Selected bins: idx[i] = angle * M + m. */
-OR_API void or_forward_at(int N, double lx1, double lx2, int n, const double *theta, double zeta,
+OR_API void or_forward_at(int N, double lx1, double lx2, int n, const double *theta, const double *det,
                           double ly, int M, const double *img, int cnt, const int *idx, double *g)
 {
+    detector Dz = det_from(det);
+    const detector *zeta = &Dz;
     (void)n;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int i = 0; i < cnt; ++i) {
@@ -569,17 +632,20 @@ OR_API void or_forward_at(int N, double lx1, double lx2, int n, const double *th
  * pixel and every knot of ghat (tiny N only).  This takes the inner product
  * on the sinogram side, independently of the pixel-by-pixel back projection,
  * for the adjoint test. */
-OR_API double or_l2_inner(int N, double lx1, double lx2, int n, const double *theta, double zeta,
+OR_API double or_l2_inner(int N, double lx1, double lx2, int n, const double *theta, const double *det,
                           double ly, int M, int K, const double *img, const double *g)
 {
+    detector Dz = det_from(det);
+    const detector *zeta = &Dz;
+    const double blur = Dz.nb > 0 ? 1.0 : 0.0;
     double *p = (double *)malloc(sizeof(double) * (size_t)n * (M + 2 * K));
-    or_prefilter(n, theta, zeta, M, K, g, p);
-    int cap = 8 * N * N + 2 * (M + 2 * K) + 8;
+    or_prefilter(n, theta, det, M, K, g, p);
+    int cap = OR_BRK * N * N + 2 * (M + 2 * K) + 8;
     double *br = (double *)malloc(sizeof(double) * (size_t)cap);
     double total = 0.0;
     for (int a = 0; a < n; ++a) {
         double c = cos(theta[a]), s = sin(theta[a]);
-        int d = or_degree(theta[a], zeta);
+        int d = or_degree(theta[a], blur);
         int nb = 0;
         for (int k = 0; k < N * N; ++k) {
             rect R = pixel_rect(lx1 * (k % N - 0.5 * (N - 1)), lx2 * (k / N - 0.5 * (N - 1)), lx1,

@@ -476,3 +476,127 @@ def test_sd_solves_tiny_system(oracle_lib):
     xs = np.linalg.solve(A, b.reshape(-1))
     assert np.linalg.norm(A @ x.reshape(-1) - b.reshape(-1)) <= 1.01e-10 * np.linalg.norm(b)
     assert np.max(np.abs(x.reshape(-1) - xs)) < 1e-6 * np.max(np.abs(xs)) * np.linalg.cond(A)
+
+
+# --------------------------------------------------------------------------
+# Detector kernels of several boxes of different heights and lengths
+# (Sec. 2): K(t) = sum_i h_i 1{|t| <= w_i / 2}
+# --------------------------------------------------------------------------
+BOX_SETS = [[(1.0, 0.6), (0.5, 0.8)], [(1.2, 0.3), (0.7, 0.5), (0.3, 0.8)]]
+
+
+def _chord_convolved(oracle, c, s, y, boxes, lx=(1.0, 1.0)):
+    """integral K(t) F0(y - t) dt with F0 the unblurred chord-length
+    footprint: two-point Gauss-Legendre on every piece between F0's kinks
+    (F0 is linear in t there), box by box."""
+    px = [sx * 0.5 * lx[0] * c + sy * 0.5 * lx[1] * s for sx in (-1, 1) for sy in (-1, 1)]
+    g = 1.0 / np.sqrt(3.0)
+    out = []
+    for yy in np.atleast_1d(y):
+        acc = 0.0
+        for w, h in boxes:
+            br = sorted({-0.5 * w, 0.5 * w} | {yy - p for p in px if -0.5 * w < yy - p < 0.5 * w})
+            for a, b in zip(br[:-1], br[1:]):
+                m, r = 0.5 * (a + b), 0.5 * (b - a)
+                acc += h * r * float(np.sum(oracle.footprint(c, s, [yy - m + r * g, yy - m - r * g], lx=lx)))
+        out.append(acc)
+    return np.array(out)
+
+
+@pytest.mark.parametrize("boxes", BOX_SETS)
+@pytest.mark.parametrize("theta,lx", [(0.0, (1.0, 1.0)), (0.37, (1.0, 1.0)), (np.pi / 4, (1.0, 1.0)),
+                                      (1.1, (0.8, 1.3))])
+def test_multibox_footprint_is_kernel_convolved_chord(oracle_lib, boxes, theta, lx):
+    """The clipped-area footprint through the box kernel equals the chord
+    footprint convolved with the kernel (independent code paths)."""
+    c, s = np.cos(theta), np.sin(theta)
+    y = np.linspace(-1.6, 1.6, 41) + 0.0123
+    f = oracle_lib.footprint(c, s, y, lx=lx, boxes=boxes)
+    ref = _chord_convolved(oracle_lib, c, s, y, boxes, lx)
+    assert np.max(np.abs(f - ref)) < 1e-12
+
+
+@pytest.mark.parametrize("boxes", BOX_SETS)
+@pytest.mark.parametrize("theta", [0.2, 0.7, 1.3])
+def test_multibox_partition_of_unity_and_integral(oracle_lib, boxes, theta):
+    """|cos| times the footprints of a whole pixel row is the kernel's
+    integral sum h_i w_i everywhere; one footprint integrates to it."""
+    c, s = np.cos(theta), np.sin(theta)
+    mass = sum(w * h for w, h in boxes)
+    y = np.linspace(-3.0, 3.0, 37)
+    tot = np.zeros_like(y)
+    for k1 in range(-40, 41):
+        tot += oracle_lib.footprint(c, s, y, boxes=boxes, centre=(float(k1), 0.0))
+    assert np.allclose(abs(c) * tot, mass, atol=1e-12)
+    val = _dense_integral(lambda v: oracle_lib.footprint(c, s, v, boxes=boxes), -3.0, 3.0, 60001)
+    assert abs(val - mass) < 1e-6
+
+
+def test_multibox_gram_merges_equal_widths(oracle_lib):
+    """Two boxes of one width are one box of the summed height (the kernel
+    is the same function), in the Gram filter and the forward model."""
+    th = inputs.angles(7) + 0.05
+    a = oracle_lib.Geometry(6, th, 16, boxes=[(0.8, 0.4), (0.8, 0.9), (0.3, 1.5)])
+    b = oracle_lib.Geometry(6, th, 16, boxes=[(0.8, 1.3), (0.3, 1.5)])
+    Ga, Gb = oracle_lib.gram(a), oracle_lib.gram(b)
+    assert np.max(np.abs(Ga - Gb)) < 1e-12 * np.max(np.abs(Gb))
+    img = np.random.default_rng(3).normal(size=(6, 6))
+    assert np.allclose(oracle_lib.forward(a, img), oracle_lib.forward(b, img), rtol=0, atol=1e-12)
+
+
+def test_multibox_single_box_is_the_blur_model(oracle_lib):
+    """One box of width zeta and height 1/zeta is the paper's blur model."""
+    th = inputs.angles(9)
+    a = oracle_lib.Geometry(5, th, 16, zeta=0.7)
+    b = oracle_lib.Geometry(5, th, 16, boxes=[(0.7, 1.0 / 0.7)])
+    assert np.max(np.abs(oracle_lib.gram(a) - oracle_lib.gram(b))) < 1e-14
+
+
+@pytest.mark.parametrize("boxes", BOX_SETS)
+def test_multibox_gram_brute_force_riemann(oracle_lib, boxes):
+    """Gram taps against dense Riemann sums of footprint products."""
+    th = [0.37, 1.9]
+    g = oracle_lib.Geometry(4, th, 16, boxes=boxes)
+    G = oracle_lib.gram(g)
+    y = np.linspace(-1.5, 1.5, 30001)  # the reference footprint's support lies inside
+    dy = y[1] - y[0]
+    for k1, k2 in [(0, 0), (1, 0), (1, 2), (-2, 1)]:
+        ref = 0.0
+        for t in th:
+            c, s = np.cos(t), np.sin(t)
+            f0 = oracle_lib.footprint(c, s, y, boxes=boxes)
+            fk = oracle_lib.footprint(c, s, y, boxes=boxes, centre=(float(k1), float(k2)))
+            ref += float(np.sum(f0 * fk) * dy)
+        assert abs(G[k2 + 3, k1 + 3] - ref) < 2e-6
+
+
+@pytest.mark.parametrize("boxes", BOX_SETS)
+def test_multibox_explicit_H_gram_is_toeplitz_and_equals_filter(oracle_lib, boxes):
+    N = 4
+    g = oracle_lib.Geometry(N, inputs.angles(5) + 0.1, 16, boxes=boxes)
+    H = oracle_lib.explicit_H(g)
+    HtH = H.T @ H
+    G = oracle_lib.gram(g)
+    for i in range(N * N):
+        for j in range(N * N):
+            d1, d2 = i % N - j % N, i // N - j // N
+            assert abs(HtH[i, j] - G[d2 + N - 1, d1 + N - 1]) < 1e-12
+
+
+@pytest.mark.parametrize("boxes", BOX_SETS)
+def test_multibox_backprojection_adjoint_and_constant_data(oracle_lib, boxes):
+    N, n, M = 5, 6, 14
+    g = oracle_lib.Geometry(N, inputs.angles(n) + 0.03, M, ly=0.8, boxes=boxes, K=10)
+    rng = np.random.default_rng(7)
+    c = rng.normal(size=(N, N))
+    sino = rng.normal(size=(n, M))
+    lhs = oracle_lib.l2_inner(g, c, sino)
+    rhs = float(np.sum(c * oracle_lib.backproject(g, sino)))
+    assert abs(lhs - rhs) < 1e-11 * max(1.0, abs(lhs))
+    # ghat == 1 under every footprint: b = n * pixel area * kernel integral
+    K = 40
+    M2 = 2 * (K + 12) + N
+    g2 = oracle_lib.Geometry(N, inputs.angles(n), M2, boxes=boxes, K=K)
+    b = oracle_lib.backproject(g2, np.ones((n, M2)))
+    mass = sum(w * h for w, h in boxes)
+    assert np.max(np.abs(b - n * mass)) < 1e-12 * n

@@ -77,6 +77,8 @@ typedef struct {
 
 typedef struct gct_plan gct_plan;
 
+#define GCT_MAX_BOXES 4
+
 /* Sizes (in elements) of the arrays a plan works on. */
 typedef struct {
     int32_t N, n_angles, M, prefilter_K;
@@ -95,6 +97,23 @@ typedef struct {
  * host, then copied to the current device (blocking).  *plan is owned by the
  * caller and released with gct_plan_destroy. */
 int gct_plan_create(const gct_geometry *geom, gct_plan **plan);
+/* As gct_plan_create with a detector kernel made of several boxes of
+ * different heights and lengths (Sec. 2, the detector cell model before the
+ * paper's simplification to one box): K(t) = sum_i box_height[i] for
+ * |t| <= box_width[i]/2, 1 <= n_boxes <= GCT_MAX_BOXES (HOST arrays, read
+ * during the call; widths > 0, heights non-zero).  The measurement of bin m
+ * is then the projection integrated against K(y_m - y); one box of width
+ * zeta and height 1/zeta is gct_plan_create with zeta_blur = zeta.
+ * geom->zeta_blur must be 0.  Every operation of the plan uses this kernel:
+ * the footprint is sum_i h_i w_i l1 l2 M_[l1|c|, l2|s|, w_i] (Sec. 4 eq.
+ * blurxray_of_f per box), the Gram filter the angle sum of the
+ * autocorrelation of that footprint (each pair of boxes as a difference of
+ * two six-direction closed forms), back projection the exact adjoint with the
+ * blurred degree rule of Sec. 5.  The Gram filter's FP32 accuracy needs box
+ * widths and half-differences of widths that are not tiny against the pixel
+ * (>= 0.1 l); FP64 has no such limit. */
+int gct_plan_create_detector(const gct_geometry *geom, int32_t n_boxes, const double *box_width,
+                             const double *box_height, gct_plan **plan);
 int gct_plan_destroy(gct_plan *plan);
 int gct_plan_get_info(const gct_plan *plan, gct_plan_info *info);
 
@@ -207,9 +226,9 @@ int gct_plan_get_pass_elems(const gct_plan *plan, gct_dtype dtype, int32_t *out)
  * (HOST, 3 ints) = {angles per chunk of the pixel-tiled kernel, whose
  * per-(tile, angle) tables must fit in 64 KB of LDS (0: they do not, and the
  * per-angle kernel runs instead), angle groups of the tiled kernel (1 when
- * it does not run), tile side of the per-angle kernel (0 when the tiled
- * kernel runs; also 0 when neither fits, and back projection then returns
- * GCT_EHIP)}.  Fine detector sampling (small lambda_y relative to the
+ * it does not run), tile side of the per-angle kernel (32, 16 or 8; 0
+ * when the tiled kernel runs; also 0 when neither fits, and back projection
+ * then returns GCT_EHIP)}.  Fine detector sampling (small lambda_y relative to the
  * pixel) and FP64 widen the tables. */
 int gct_plan_get_bp_shape(const gct_plan *plan, gct_dtype dtype, int32_t *out);
 

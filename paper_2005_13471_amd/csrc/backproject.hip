@@ -461,11 +461,12 @@ void bp_configure(gct_plan *p)
 int bp_angle_groups(const gct_plan *p, size_t elem) { return p->bp_groups[elem == 4 ? 0 : 1]; }
 
 // Tile side, bins per tile window and angles per chunk such that the LDS
-// stays within 64 KB: 32 x 32 tiles when they fit, else 16 x 16.
+// stays within 64 KB: 32 x 32 tiles when they fit, else 16 x 16, else 8 x 8
+// (kernels with many sub-intervals: several detector boxes in FP64).
 static BPLayout bp_layout(const gct_plan *p, size_t elem)
 {
     BPLayout L{16, 0, 1, 0};
-    for (int tile : {32, 16}) {
+    for (int tile : {32, 16, 8}) {
         const int r = (int)std::ceil((tile - 1) * p->bp.span_per_pixel) + 4;
         for (int ch : {16, 8, 4, 2, 1}) {
             const size_t per_coef = (size_t)p->bp.smax * p->bp.J * p->bp.D1;
@@ -537,6 +538,10 @@ hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, hip
         hipLaunchKernelGGL((k_backproject<T, 32>), grid, dim3(1024), L.lds, s, pf, b, N, p->n,
                            p->M + 2 * p->K, p->K, geo, ints, brk, coef, p->bp.smax, p->bp.J,
                            p->bp.D1, L.rmax, L.ch);
+    else if (L.tile == 8)
+        hipLaunchKernelGGL((k_backproject<T, 8>), grid, dim3(64), L.lds, s, pf, b, N, p->n,
+                           p->M + 2 * p->K, p->K, geo, ints, brk, coef, p->bp.smax, p->bp.J,
+                           p->bp.D1, L.rmax, L.ch);
     else
         hipLaunchKernelGGL((k_backproject<T, 16>), grid, dim3(256), L.lds, s, pf, b, N, p->n,
                            p->M + 2 * p->K, p->K, geo, ints, brk, coef, p->bp.smax, p->bp.J,
@@ -575,18 +580,24 @@ __device__ __forceinline__ T footprint(const FwdAngle<T> &f, T x)
     return f.scale_over_L * (theta_int(f, x + T(0.5) * f.L) - theta_int(f, x - T(0.5) * f.L));
 }
 
-template <typename T>
+// fa holds NB boxes per angle (NB = 0: nb at run time, the detector's
+// boxes of Sec. 2; one box of width zeta is the paper's blur); the
+// footprint is the sum of the boxes' terms, the support the widest.
+template <typename T, int NB>
 __global__ void __launch_bounds__(256)
 k_forward(const T *__restrict__ c, T *__restrict__ g, int N, int M, double ly,
-          const FwdAngle<T> *__restrict__ fa)
+          const FwdAngle<T> *__restrict__ fa, int nb)
 {
     const int a = blockIdx.y;
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= M) return;
-    const FwdAngle<T> f = fa[a];
+    const int nbx = NB > 0 ? NB : nb;
+    const FwdAngle<T> *fb = fa + (size_t)a * nbx;
+    const FwdAngle<T> f = fb[0];
     const double y = ly * ((double)m - 0.5 * (M - 1));
     const double h = 0.5 * (N - 1);
-    const double half = (double)f.half;
+    double half = (double)f.half;
+    for (int b = 1; b < nbx; ++b) half = fmax(half, (double)fb[b].half);
     T acc = 0;
     // walk rows (solve for k1) or columns (solve for k2)
     const double along = f.rows ? f.cx : f.sx;   // coefficient of the solved index
@@ -601,7 +612,8 @@ k_forward(const T *__restrict__ c, T *__restrict__ g, int N, int M, double ly,
         hi = min(hi, N - 1);
         for (int j = lo; j <= hi; ++j) {
             const T d = (T)(y - base - along * ((double)j - h));
-            const T v = footprint(f, d);
+            T v = footprint(f, d);
+            for (int b = 1; b < nbx; ++b) v += footprint(fb[b], d);
             const size_t idx = f.rows ? (size_t)i * N + j : (size_t)j * N + i;
             acc += c[idx] * v;
         }
@@ -615,7 +627,8 @@ hipError_t launch_forward(const gct_plan *p, const T *c, T *g, hipStream_t s)
     const dim3 grid((p->M + 255) / 256, p->n);
     const FwdAngle<T> *fa =
         reinterpret_cast<const FwdAngle<T> *>(sizeof(T) == 4 ? p->dev.fwd_f32 : p->dev.fwd_f64);
-    hipLaunchKernelGGL(k_forward<T>, grid, dim3(256), 0, s, c, g, p->N, p->M, p->ly, fa);
+    if (p->fwd_nb == 1) hipLaunchKernelGGL((k_forward<T, 1>), grid, dim3(256), 0, s, c, g, p->N, p->M, p->ly, fa, 1);
+    else hipLaunchKernelGGL((k_forward<T, 0>), grid, dim3(256), 0, s, c, g, p->N, p->M, p->ly, fa, p->fwd_nb);
     return hipGetLastError();
 }
 

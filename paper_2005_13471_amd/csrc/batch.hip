@@ -841,7 +841,7 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         BatchSlice d{};
         d.N = p->N;
         d.logP = p->logP;
-        d.n = p->n;
+        d.n = p->gram_n;  // Gram-filter table entries
         d.nrow = (p->N + 1) / 2;
         d.img = b->img_total;
         b->img_total += (int64_t)p->N * p->N;

@@ -150,6 +150,10 @@ struct gct_plan {
     int32_t N, n, M, K;
     double lx1, lx2, ly, zeta;
     int32_t P, logP;
+    // Gram-filter table entries (angle, term of the detector's
+    // autocorrelation; one term per angle for zero or one box) and
+    // footprint boxes per angle
+    int32_t gram_n = 0, fwd_nb = 1;
     double gram_hmax;  // largest support half-width of A_theta over the angles
     // elements per thread of the transforms, [F32, F64]: the row passes and
     // the column pass of an apply, and the same for the fused CG passes

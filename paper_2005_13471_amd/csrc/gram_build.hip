@@ -250,7 +250,7 @@ hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s)
     const dim3 grid((W + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT, (p->N + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT);
     const GramAngle<T> *ga =
         reinterpret_cast<const GramAngle<T> *>(sizeof(T) == 4 ? p->dev.gram_f32 : p->dev.gram_f64);
-    hipLaunchKernelGGL(k_gram_build<T>, grid, dim3(256), 0, s, G, p->N, p->n, ga,
+    hipLaunchKernelGGL(k_gram_build<T>, grid, dim3(256), 0, s, G, p->N, p->gram_n, ga,
                        reinterpret_cast<const int32_t *>(p->dev.gram_ord),
                        reinterpret_cast<const double *>(p->dev.gram_th), p->gram_hmax, p->lx1, p->lx2);
     return hipGetLastError();

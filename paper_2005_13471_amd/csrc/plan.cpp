@@ -157,6 +157,61 @@ static double pp_eval(const PPoly &f, double x)
     return horner(f.c[i], f.deg, x - f.x[i]);
 }
 
+// Sum of two piecewise polynomials: pieces on the union of the knots, each
+// polynomial re-expanded about the merged piece's left knot.
+static PPoly pp_add(const PPoly &f, const PPoly &g)
+{
+    PPoly h;
+    h.deg = std::max(f.deg, g.deg);
+    h.x = f.x;
+    h.x.insert(h.x.end(), g.x.begin(), g.x.end());
+    std::sort(h.x.begin(), h.x.end());
+    h.x.erase(std::unique(h.x.begin(), h.x.end()), h.x.end());
+    auto piece = [](const PPoly &q, double xm, double origin) {
+        Coef r{};
+        if (xm <= q.x.front() || xm >= q.x.back()) return r;
+        int i = (int)(std::upper_bound(q.x.begin(), q.x.end(), xm) - q.x.begin()) - 1;
+        i = std::max(0, std::min(i, (int)q.c.size() - 1));
+        return taylor_shift(q.c[i], q.deg, origin - q.x[i]);
+    };
+    h.c.resize(h.x.size() - 1);
+    for (size_t j = 0; j + 1 < h.x.size(); ++j) {
+        const double xm = 0.5 * (h.x[j] + h.x[j + 1]);
+        const Coef a = piece(f, xm, h.x[j]), b = piece(g, xm, h.x[j]);
+        Coef r{};
+        for (int k = 0; k <= h.deg; ++k) r[k] = a[k] + b[k];
+        h.c[j] = r;
+    }
+    return h;
+}
+
+// ---------------------------------------------------------------------------
+// Detector kernel (Sec. 2): boxes of widths w[i] with integrals a[i] (height
+// times width), K(t) = sum_i (a[i] / w[i]) 1{|t| <= w[i]/2}.  No box: the
+// point sample of the X-ray transform.  The paper's blur of width zeta is
+// one box with a = 1.
+// ---------------------------------------------------------------------------
+struct Detector {
+    std::vector<double> w, a;
+    bool blurred() const { return !w.empty(); }
+    double wmax() const
+    {
+        double m = 0.0;
+        for (double v : w) m = std::max(m, v);
+        return m;
+    }
+};
+
+static Detector detector_of(double zeta)
+{
+    Detector D;
+    if (zeta > 0.0) {
+        D.w = {zeta};
+        D.a = {1.0};
+    }
+    return D;
+}
+
 // ---------------------------------------------------------------------------
 // Per-angle geometry.
 // ---------------------------------------------------------------------------
@@ -170,7 +225,7 @@ struct AngleDirs {
 // Continuity rule of Sec. 5: the projected signal is C^0 in general and
 // C^-1 at axis-aligned angles without blur; C^1 / C^0 with blur.  The
 // interpolating B-spline degree is one above the continuity order.
-static AngleDirs angle_dirs(double th, double l1, double l2, double zeta)
+static AngleDirs angle_dirs(double th, double l1, double l2, double zeta)  // zeta > 0: blurred
 {
     AngleDirs d;
     d.c = std::cos(th);
@@ -192,8 +247,10 @@ static void sorted3(double a, double b, double c, double &L, double &M, double &
     S = v[0];
 }
 
+// One term mult * (l1 l2)^2 * T_L * T_M * T_S of the Gram autocorrelation,
+// {L, M, S} = sorted {l1|c|, l2|s|, zeta}.
 template <typename T>
-static GramAngle<T> gram_angle(const AngleDirs &d, double l1, double l2, double zeta)
+static GramAngle<T> gram_angle(const AngleDirs &d, double l1, double l2, double zeta, double mult = 1.0)
 {
     GramAngle<T> g{};
     double L, M, S;
@@ -208,13 +265,36 @@ static GramAngle<T> gram_angle(const AngleDirs &d, double l1, double l2, double 
     g.c6M = M > 0 ? (T)(1.0 / (6.0 * M * M)) : T(0);
     g.s12 = (T)(S * S / 12.0);
     g.c120S = S > 0 ? (T)(1.0 / (120.0 * S * S)) : T(0);
-    g.scale = (T)(l1 * l2 * l1 * l2);
+    g.scale = (T)(mult * l1 * l2 * l1 * l2);
     g.half = (T)(L + M + S);
     return g;
 }
 
+// Terms (hat half-width S, multiplier) of the Gram autocorrelation
+// A = (l1 l2)^2 T_c * T_s * (K * K) (Sec. 4 with the kernel of Sec. 2).
+// With box kernels B_w (unit integral, width w), K = sum_i a_i B_{w_i} and
+// B_u * B_v = (s1^2 T_{s1} - s2^2 T_{s2}) / (u v), s1 = (u + v)/2,
+// s2 = |u - v|/2 (the trapezoid as a difference of two hats), so every
+// term is the six-direction closed form T_L * T_M * T_S.
+static std::vector<std::array<double, 2>> gram_terms(const Detector &D)
+{
+    std::vector<std::array<double, 2>> t;
+    if (!D.blurred()) return {{0.0, 1.0}};
+    const size_t nb = D.w.size();
+    for (size_t i = 0; i < nb; ++i) t.push_back({D.w[i], D.a[i] * D.a[i]});
+    for (size_t i = 0; i < nb; ++i)
+        for (size_t j = i + 1; j < nb; ++j) {
+            const double u = D.w[i], v = D.w[j], f = 2.0 * D.a[i] * D.a[j] / (u * v);
+            const double s1 = 0.5 * (u + v), s2 = 0.5 * std::fabs(u - v);
+            t.push_back({s1, f * s1 * s1});
+            if (s2 > 0.0) t.push_back({s2, -f * s2 * s2});
+        }
+    return t;
+}
+
+// Footprint term mult * l1 l2 M_[L, M, S] of one box (Sec. 4 eq. blurxray_of_f).
 template <typename T>
-static FwdAngle<T> fwd_angle(const AngleDirs &d, double l1, double l2, double zeta)
+static FwdAngle<T> fwd_angle(const AngleDirs &d, double l1, double l2, double zeta, double mult = 1.0)
 {
     FwdAngle<T> f{};
     double L, M, S;
@@ -227,7 +307,7 @@ static FwdAngle<T> fwd_angle(const AngleDirs &d, double l1, double l2, double ze
     f.iL = (T)(1.0 / L);
     f.iM = M > 0 ? (T)(1.0 / M) : T(0);
     f.i2MS = (M > 0 && S > 0) ? (T)(1.0 / (2.0 * M * S)) : T(0);
-    f.scale_over_L = (T)(l1 * l2 / L);
+    f.scale_over_L = (T)(mult * l1 * l2 / L);
     f.half = (T)(0.5 * (L + M + S));
     f.rows = std::fabs(f.cx) >= std::fabs(f.sx) ? 1 : 0;
     return f;
@@ -243,12 +323,17 @@ struct BPAngleTable {
 };
 
 static BPAngleTable bp_angle(const AngleDirs &d, int N, double l1, double l2, double ly, int M,
-                             double zeta)
+                             const Detector &D)
 {
     BPAngleTable t;
-    std::vector<double> dirs = {d.a1 / ly, d.a2 / ly, zeta / ly};
-    for (int i = 0; i <= d.degree; ++i) dirs.push_back(1.0);
-    const PPoly k = pp_boxspline(dirs, l1 * l2);
+    // kappa = l1 l2 sum_i a_i M_{[l1|c|, l2|s|, w_i, ly x (d+1)] / ly}
+    auto term = [&](double w, double a) {
+        std::vector<double> dirs = {d.a1 / ly, d.a2 / ly, w / ly};
+        for (int i = 0; i <= d.degree; ++i) dirs.push_back(1.0);
+        return pp_boxspline(dirs, l1 * l2 * a);
+    };
+    PPoly k = D.blurred() ? term(D.w[0], D.a[0]) : term(0.0, 1.0);
+    for (size_t i = 1; i < D.w.size(); ++i) k = pp_add(k, term(D.w[i], D.a[i]));
     // sub-interval breakpoints of t in [0,1): fractional parts of -knot
     std::vector<double> br = {0.0};
     for (double x : k.x) {
@@ -307,29 +392,40 @@ static std::vector<T> cast_vec(const std::vector<double> &v)
     return std::vector<T>(v.begin(), v.end());
 }
 
-static int build_plan(const gct_geometry *g, gct_plan *p)
+static int build_plan(const gct_geometry *g, const Detector &det, gct_plan *p)
 {
     const int n = g->n_angles;
-    const double l1 = g->lambda_x[0], l2 = g->lambda_x[1], ly = g->lambda_y, z = g->zeta_blur;
+    const double l1 = g->lambda_x[0], l2 = g->lambda_x[1], ly = g->lambda_y;
     std::vector<AngleDirs> ad(n);
-    for (int a = 0; a < n; ++a) ad[a] = angle_dirs(g->theta[a], l1, l2, z);
+    for (int a = 0; a < n; ++a) ad[a] = angle_dirs(g->theta[a], l1, l2, det.blurred() ? 1.0 : 0.0);
+    // Gram terms per angle (entry a * nt + t) and footprint boxes per angle
+    const auto terms = gram_terms(det);
+    const int nt = (int)terms.size();
+    const int nbf = det.blurred() ? (int)det.w.size() : 1;
+    p->gram_n = n * nt;
+    p->fwd_nb = nbf;
 
-    std::vector<GramAngle<float>> gf(n);
-    std::vector<GramAngle<double>> gd(n);
-    std::vector<FwdAngle<float>> ff(n);
-    std::vector<FwdAngle<double>> fd(n);
+    std::vector<GramAngle<float>> gf((size_t)n * nt);
+    std::vector<GramAngle<double>> gd((size_t)n * nt);
+    std::vector<FwdAngle<float>> ff((size_t)n * nbf);
+    std::vector<FwdAngle<double>> fd((size_t)n * nbf);
     std::vector<int32_t> deg(n);
     std::vector<BPAngleTable> bt(n);
     int smax = 1, J = 1, D1 = 1;
     double span = 0.0;
     for (int a = 0; a < n; ++a) {
         span = std::max(span, (ad[a].a1 + ad[a].a2) / ly);
-        gf[a] = gram_angle<float>(ad[a], l1, l2, z);
-        gd[a] = gram_angle<double>(ad[a], l1, l2, z);
-        ff[a] = fwd_angle<float>(ad[a], l1, l2, z);
-        fd[a] = fwd_angle<double>(ad[a], l1, l2, z);
+        for (int t = 0; t < nt; ++t) {
+            gf[(size_t)a * nt + t] = gram_angle<float>(ad[a], l1, l2, terms[t][0], terms[t][1]);
+            gd[(size_t)a * nt + t] = gram_angle<double>(ad[a], l1, l2, terms[t][0], terms[t][1]);
+        }
+        for (int b = 0; b < nbf; ++b) {
+            const double w = det.blurred() ? det.w[b] : 0.0, m = det.blurred() ? det.a[b] : 1.0;
+            ff[(size_t)a * nbf + b] = fwd_angle<float>(ad[a], l1, l2, w, m);
+            fd[(size_t)a * nbf + b] = fwd_angle<double>(ad[a], l1, l2, w, m);
+        }
         deg[a] = ad[a].degree;
-        bt[a] = bp_angle(ad[a], g->N, l1, l2, ly, g->M, z);
+        bt[a] = bp_angle(ad[a], g->N, l1, l2, ly, g->M, det);
         smax = std::max(smax, bt[a].h.nsub);
         J = std::max(J, bt[a].J);
         D1 = std::max(D1, bt[a].D1);
@@ -378,21 +474,23 @@ static int build_plan(const gct_geometry *g, gct_plan *p)
     if ((rc = upload(&p->dev.gram_f32, gf))) return rc;
     if ((rc = upload(&p->dev.gram_f64, gd))) return rc;
     {
-        // angles sorted by theta mod pi, for the Gram build's angular windows
-        std::vector<double> th(n);
-        std::vector<int32_t> ord(n);
+        // Gram entries (angle, term) sorted by theta mod pi, for the Gram
+        // build's angular windows (the terms of one angle stay together)
+        const int ne = p->gram_n;
+        std::vector<double> th(ne);
+        std::vector<int32_t> ord(ne);
         double hmax = 0.0;
-        for (int a = 0; a < n; ++a) {
-            double t = std::fmod(g->theta[a], M_PI);
+        for (int e = 0; e < ne; ++e) {
+            double t = std::fmod(g->theta[e / nt], M_PI);
             if (t < 0.0) t += M_PI;
             if (t >= M_PI) t = 0.0;
-            th[a] = t;
-            ord[a] = a;
-            hmax = std::max(hmax, (double)gd[a].half);
+            th[e] = t;
+            ord[e] = e;
+            hmax = std::max(hmax, (double)gd[e].half);
         }
         std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return th[x] < th[y]; });
-        std::vector<double> ths(n);
-        for (int a = 0; a < n; ++a) ths[a] = th[ord[a]];
+        std::vector<double> ths(ne);
+        for (int e = 0; e < ne; ++e) ths[e] = th[ord[e]];
         p->gram_hmax = hmax;
         if ((rc = upload(&p->dev.gram_ord, ord))) return rc;
         if ((rc = upload(&p->dev.gram_th, ths))) return rc;
@@ -426,7 +524,7 @@ static void free_tables(gct_plan *p)
     }
 }
 
-static int validate(const gct_geometry *g)
+static int validate(const gct_geometry *g, double wmax = -1.0)
 {
     if (!g) return fail(GCT_EINVAL, "geometry is NULL");
     if (g->N < 1 || g->N > 2048) return fail(GCT_EINVAL, "N must be in [1, 2048]");
@@ -445,7 +543,7 @@ static int validate(const gct_geometry *g)
     for (int a = 0; a < g->n_angles; ++a)
         if (!std::isfinite(g->theta[a])) return fail(GCT_EINVAL, "theta contains a non-finite value");
     // back-projection table size: the kernel support in bins must stay modest
-    const double w = (g->lambda_x[0] + g->lambda_x[1] + g->zeta_blur) / g->lambda_y + 3.0;
+    const double w = (g->lambda_x[0] + g->lambda_x[1] + (wmax >= 0.0 ? wmax : g->zeta_blur)) / g->lambda_y + 3.0;
     if (w > 48.0) return fail(GCT_EINVAL, "lambda_y too small for the pixel size (kernel spans > 48 bins)");
     const double lratio = g->lambda_x[0] / g->lambda_x[1];
     if (lratio > 64.0 || lratio < 1.0 / 64.0) return fail(GCT_EINVAL, "pixel aspect ratio beyond 64");
@@ -463,12 +561,9 @@ extern "C" {
 
 const char *gct_last_error(void) { return g_last_error.c_str(); }
 
-int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
+static int create_plan(const gct_geometry *geom, const Detector &det, gct_plan **plan)
 {
-    if (!plan) return fail(GCT_EINVAL, "plan output pointer is NULL");
-    *plan = nullptr;
-    int rc = validate(geom);
-    if (rc) return rc;
+    int rc = GCT_OK;
     try {
         gct_plan *p = new gct_plan();
         p->N = geom->N;
@@ -492,7 +587,7 @@ int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
         p->fft_e[0] = p->fft_e[1] = p->cg_e[0] = p->cg_e[1] = er;
         p->fft_ec[0] = p->fft_ec[1] = p->cg_ec[0] = p->cg_ec[1] = ec;
         if (hipGetDevice(&p->device) != hipSuccess) p->device = 0;
-        rc = build_plan(geom, p);
+        rc = build_plan(geom, det, p);
         if (rc) {
             free_tables(p);
             delete p;
@@ -504,6 +599,38 @@ int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
     } catch (const std::exception &e) {
         return fail(GCT_EINVAL, std::string("plan construction failed: ") + e.what());
     }
+}
+
+int gct_plan_create(const gct_geometry *geom, gct_plan **plan)
+{
+    if (!plan) return fail(GCT_EINVAL, "plan output pointer is NULL");
+    *plan = nullptr;
+    int rc = validate(geom);
+    if (rc) return rc;
+    return create_plan(geom, detector_of(geom->zeta_blur), plan);
+}
+
+int gct_plan_create_detector(const gct_geometry *geom, int32_t n_boxes, const double *box_width,
+                             const double *box_height, gct_plan **plan)
+{
+    if (!plan) return fail(GCT_EINVAL, "plan output pointer is NULL");
+    *plan = nullptr;
+    if (!geom) return fail(GCT_EINVAL, "geometry is NULL");
+    if (geom->zeta_blur != 0.0) return fail(GCT_EINVAL, "give the detector either as zeta_blur or as boxes");
+    if (n_boxes < 1 || n_boxes > GCT_MAX_BOXES) return fail(GCT_EINVAL, "n_boxes must be in [1, 4]");
+    if (!box_width || !box_height) return fail(GCT_EINVAL, "box arrays are NULL");
+    Detector det;
+    for (int i = 0; i < n_boxes; ++i) {
+        if (!(box_width[i] > 0.0) || !std::isfinite(box_width[i]))
+            return fail(GCT_EINVAL, "box widths must be finite and > 0");
+        if (!std::isfinite(box_height[i]) || box_height[i] == 0.0)
+            return fail(GCT_EINVAL, "box heights must be finite and non-zero");
+        det.w.push_back(box_width[i]);
+        det.a.push_back(box_width[i] * box_height[i]);
+    }
+    int rc = validate(geom, det.wmax());
+    if (rc) return rc;
+    return create_plan(geom, det, plan);
 }
 
 int gct_plan_destroy(gct_plan *plan)
@@ -774,7 +901,7 @@ int gct_host_bp_weights(const gct_geometry *g, int angle, double t, double *w, i
         return fail(GCT_EINVAL, "bad argument");
     const AngleDirs d = angle_dirs(g->theta[angle], g->lambda_x[0], g->lambda_x[1], g->zeta_blur);
     const BPAngleTable tb = bp_angle(d, g->N, g->lambda_x[0], g->lambda_x[1], g->lambda_y, g->M,
-                                     g->zeta_blur);
+                                     detector_of(g->zeta_blur));
     int s = 0;
     for (int i = 1; i < tb.h.nsub; ++i)
         if (t >= tb.brk[i]) s = i;

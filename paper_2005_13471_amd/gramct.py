@@ -77,6 +77,8 @@ def _load():
     vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
     L.gct_last_error.restype = ctypes.c_char_p
     L.gct_plan_create.argtypes = [ctypes.POINTER(_Geometry), ctypes.POINTER(vp)]
+    L.gct_plan_create_detector.argtypes = [ctypes.POINTER(_Geometry), i32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp)]
     L.gct_plan_destroy.argtypes = [vp]
     L.gct_plan_get_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
     L.gct_workspace_size.argtypes = [vp, ctypes.c_int, ctypes.c_int]
@@ -194,12 +196,22 @@ class PlanInfo:
 
 
 class Plan:
-    """gct_plan: geometry of Sec. 2 and the per-angle tables on the device."""
+    """gct_plan: geometry of Sec. 2 and the per-angle tables on the device.
+    The detector kernel is the blur box of width zeta, or `boxes`, a list of
+    (width, height) pairs (gct_plan_create_detector)."""
 
-    def __init__(self, N, theta, M, ly=1.0, zeta=0.0, lx=(1.0, 1.0), K=40):
+    def __init__(self, N, theta, M, ly=1.0, zeta=0.0, lx=(1.0, 1.0), K=40, boxes=None):
         g, th = _geometry_struct(N, theta, M, ly, zeta, lx, K)
         h = ctypes.c_void_p()
-        _check(lib.gct_plan_create(ctypes.byref(g), ctypes.byref(h)))
+        if boxes:
+            P = ctypes.POINTER(ctypes.c_double)
+            w = np.ascontiguousarray([b[0] for b in boxes], dtype=np.float64)
+            ht = np.ascontiguousarray([b[1] for b in boxes], dtype=np.float64)
+            _check(lib.gct_plan_create_detector(ctypes.byref(g), len(boxes), w.ctypes.data_as(P),
+                                                ht.ctypes.data_as(P), ctypes.byref(h)))
+        else:
+            _check(lib.gct_plan_create(ctypes.byref(g), ctypes.byref(h)))
+        self.boxes = [tuple(map(float, b)) for b in boxes] if boxes else None
         self._h = h
         self.theta = th
         self.N, self.M, self.ly, self.zeta, self.lx, self.K = int(N), int(M), float(ly), float(zeta), tuple(lx), int(K)

@@ -133,3 +133,20 @@ def test_unet_rejects_bad_config_without_gpu(gct, kw, msg):
     with pytest.raises(gct.GramctError) as e:
         gct.UNet(**args)
     assert e.value.code == gct.GCT_EINVAL and msg in str(e.value)
+
+
+@pytest.mark.parametrize("boxes,zeta,msg", [([], 0.0, "n_boxes"), ([(1.0, 1.0)] * 5, 0.0, "n_boxes"),
+                                            ([(0.0, 1.0)], 0.0, "widths"), ([(1.0, 0.0)], 0.0, "heights"),
+                                            ([(1.0, 1.0)], 0.5, "either"),
+                                            ([(1.0, float("nan"))], 0.0, "heights")])
+def test_detector_plan_rejects_bad_boxes_without_gpu(gct, boxes, zeta, msg):
+    """The multi-box plan validates its boxes before any GPU call."""
+    g, th = gct._geometry_struct(8, inputs.angles(4), 16, 1.0, zeta, (1.0, 1.0), 40)
+    P = ctypes.POINTER(ctypes.c_double)
+    w = np.ascontiguousarray([b[0] for b in boxes] or [1.0], dtype=np.float64)
+    h = np.ascontiguousarray([b[1] for b in boxes] or [1.0], dtype=np.float64)
+    out = ctypes.c_void_p()
+    rc = gct.lib.gct_plan_create_detector(ctypes.byref(g), len(boxes), w.ctypes.data_as(P),
+                                          h.ctypes.data_as(P), ctypes.byref(out))
+    assert rc == gct.GCT_EINVAL and msg in gct.lib.gct_last_error().decode()
+    assert not out.value

@@ -526,7 +526,7 @@ static double bp_pixel(int N, double lx1, double lx2, int n, const double *theta
 {
     rect R = pixel_rect(lx1 * (k1 - 0.5 * (N - 1)), lx2 * (k2 - 0.5 * (N - 1)), lx1, lx2);
     double acc = 0.0;
-    double br[OR_BRK + 256];
+    double br[OR_BRK + 1024];
     const double blur = zeta->nb > 0 ? 1.0 : 0.0;
     for (int a = 0; a < n; ++a) {
         double c = cos(theta[a]), s = sin(theta[a]);
@@ -538,7 +538,7 @@ static double bp_pixel(int N, double lx1, double lx2, int n, const double *theta
         /* knots of ghat: y_m (d odd) or y_m +- ly/2 (d even) */
         double off = (d % 2 == 0) ? 0.5 : 0.0;
         double z0 = lo / ly + 0.5 * (M - 1) - off, z1 = hi / ly + 0.5 * (M - 1) - off;
-        for (int m = (int)ceil(z0); m <= (int)floor(z1) && nb < OR_BRK + 256; ++m)
+        for (int m = (int)ceil(z0); m <= (int)floor(z1) && nb < OR_BRK + 1024; ++m)
             br[nb++] = ly * (m + off - 0.5 * (M - 1));
         nb = sort_unique(br, nb);
         for (int i = 0; i + 1 < nb; ++i) {

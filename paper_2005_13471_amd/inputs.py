@@ -49,27 +49,48 @@ def random_ellipses(N: int, count: int, seed: int) -> list[Ellipse]:
     return out
 
 
-def rasterize(N: int, ells: list[Ellipse], sub: int = 8) -> np.ndarray:
+def random_ellipses_inside(N: float, count: int, seed: int, radius: float | None = None) -> list[Ellipse]:
+    """As random_ellipses (same distributions, same generator), keeping only
+    ellipses that lie inside the disc of `radius` (default N/2, the disc
+    inscribed in the image) until `count` are kept: a phantom wholly inside
+    the field of view, so that exact data contain nothing the image cannot
+    represent."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    R = 0.5 * N if radius is None else float(radius)
+    out = []
+    while len(out) < count:
+        cx, cy = rng.uniform(-0.8, 0.8, size=2) * (N / 2)
+        a, b = rng.uniform(2.0, 20.0, size=2) * (N / 64)
+        phi = rng.uniform(0.0, np.pi)
+        rho = rng.uniform(-0.5, 1.0)
+        if np.hypot(cx, cy) + max(a, b) <= R:
+            out.append(Ellipse(float(cx), float(cy), float(a), float(b), float(phi), float(rho)))
+    return out
+
+
+def rasterize(N: int, ells: list[Ellipse], sub: int = 8, lx=(1.0, 1.0)) -> np.ndarray:
     """c[k2, k1] = sum_e rho_e * (fraction of the sub x sub sub-pixel centres
-    of pixel k inside ellipse e).  Pixel k is centred at k - (N-1)/2.
-    Counted exactly per sub-row: the ellipse cuts each sub-row in one
-    interval of x, and the sub-sample centres of a pixel inside an interval
-    are counted arithmetically."""
+    of pixel k inside ellipse e).  Pixel k is the lx[0] x lx[1] rectangle
+    centred at (lx[0] (k1 - (N-1)/2), lx[1] (k2 - (N-1)/2)).  Counted
+    exactly per sub-row: the ellipse cuts each sub-row in one interval of x,
+    and the sub-sample centres of a pixel inside an interval are counted
+    arithmetically."""
     img = np.zeros((N, N))
     offs = (np.arange(sub) + 0.5) / sub - 0.5
     h = 0.5 * (N - 1)
+    l1, l2 = float(lx[0]), float(lx[1])
     for e in ells:
-        r = max(e.a, e.b) + 1.0
-        k1lo = max(int(np.floor(e.cx + h - r)), 0)
-        k1hi = min(int(np.ceil(e.cx + h + r)), N - 1)
-        k2lo = max(int(np.floor(e.cy + h - r)), 0)
-        k2hi = min(int(np.ceil(e.cy + h + r)), N - 1)
+        r = max(e.a, e.b) + max(l1, l2)
+        k1lo = max(int(np.floor((e.cx - r) / l1 + h)), 0)
+        k1hi = min(int(np.ceil((e.cx + r) / l1 + h)), N - 1)
+        k2lo = max(int(np.floor((e.cy - r) / l2 + h)), 0)
+        k2hi = min(int(np.ceil((e.cy + r) / l2 + h)), N - 1)
         if k1lo > k1hi or k2lo > k2hi:
             continue
         cp, sp = np.cos(e.phi), np.sin(e.phi)
         ia2, ib2 = 1.0 / e.a ** 2, 1.0 / e.b ** 2
         # sub-row y values, shape (rows * sub,)
-        y = ((np.arange(k2lo, k2hi + 1) - h)[:, None] + offs[None, :]).reshape(-1)
+        y = (l2 * ((np.arange(k2lo, k2hi + 1) - h)[:, None] + offs[None, :])).reshape(-1)
         dy = y - e.cy
         A = cp * cp * ia2 + sp * sp * ib2
         B = 2.0 * dy * cp * sp * (ia2 - ib2)
@@ -77,8 +98,8 @@ def rasterize(N: int, ells: list[Ellipse], sub: int = 8) -> np.ndarray:
         disc = B * B - 4.0 * A * C
         ok = disc >= 0.0
         sq = np.sqrt(np.where(ok, disc, 0.0))
-        xlo = np.where(ok, e.cx + (-B - sq) / (2.0 * A), np.inf)[:, None]
-        xhi = np.where(ok, e.cx + (-B + sq) / (2.0 * A), -np.inf)[:, None]
+        xlo = np.where(ok, e.cx + (-B - sq) / (2.0 * A), np.inf)[:, None] / l1
+        xhi = np.where(ok, e.cx + (-B + sq) / (2.0 * A), -np.inf)[:, None] / l1
         x1 = (np.arange(k1lo, k1hi + 1) - h)[None, :]
         qlo = np.ceil((xlo - x1 + 0.5) * sub - 0.5)
         qhi = np.floor((xhi - x1 + 0.5) * sub - 0.5)

@@ -30,14 +30,20 @@
  *     returns a thread-local message for the last failure.  No C++
  *     exception crosses this interface.
  *
- * Device memory: gct_plan_create allocates the plan's small geometry tables
- * (per-angle parameters, FFT twiddles, correction-filter taps: O(n_angles)
- * bytes) once.  Every other buffer, including scratch workspace, is passed in
+ * Device memory: every data array and every scratch workspace is passed in
  * by the caller; gct_workspace_size reports the bytes each operation needs.
- * A plan also keeps the solvers' captured iteration graphs and one pinned
- * host copy of the solver state, so solves on one plan (and one batch) must
- * not run from two host threads at once; the stream-ordered calls may share
- * a plan freely.
+ * The one exception is the geometry a plan (or batch) is made of: the plan's
+ * per-angle tables (box-spline parameters, back-projection polynomials, FFT
+ * twiddles, correction-filter taps: O(n_angles) bytes, a few hundred per
+ * angle) and a batch's block maps and slice descriptors (O(total transform
+ * blocks)) are built on the host in FP64 at creation, uploaded once and
+ * freed at destruction.  They are read-only, their layout is internal (it
+ * changes with the kernels), and they live exactly as long as the handle,
+ * so the handle owns them rather than the caller; gct_plan_device_bytes and
+ * gct_batch_device_bytes report their size.  A plan also keeps the solvers'
+ * captured iteration graphs and one pinned host copy of the solver state, so
+ * solves on one plan (and one batch) must not run from two host threads at
+ * once; the stream-ordered calls may share a plan freely.
  */
 #ifndef GRAMCT_H
 #define GRAMCT_H
@@ -116,6 +122,9 @@ int gct_plan_create_detector(const gct_geometry *geom, int32_t n_boxes, const do
                              const double *box_height, gct_plan **plan);
 int gct_plan_destroy(gct_plan *plan);
 int gct_plan_get_info(const gct_plan *plan, gct_plan_info *info);
+
+/* Bytes of device memory the plan's tables hold (HOST int64 out). */
+int gct_plan_device_bytes(const gct_plan *plan, int64_t *bytes);
 
 /* Operation ids for gct_workspace_size. */
 enum {
@@ -305,6 +314,10 @@ typedef struct {
  * device.  Uploads the block maps and slice descriptors (blocking). */
 int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **batch);
 int gct_batch_destroy(gct_batch *batch);
+
+/* Bytes of device memory the batch's maps and descriptors hold (HOST out;
+ * the plans' own tables not included). */
+int gct_batch_device_bytes(const gct_batch *batch, int64_t *bytes);
 
 /* Sizes; the three offset arrays (host, `slices` entries each) may be NULL. */
 int gct_batch_get_info(const gct_batch *batch, gct_batch_info *info, int64_t *image_offsets,

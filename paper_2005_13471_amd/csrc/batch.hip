@@ -568,13 +568,15 @@ struct gct_batch {
     int ngram = 0;
     std::vector<CGGraph> graphs;
     hipStream_t capture_stream = nullptr;
+    int64_t dev_bytes = 0;  // bytes of the block maps and slice descriptors
 };
 
 namespace {
 
-int upload_map(int2 **dst, const std::vector<int2> &v)
+int upload_map(int2 **dst, const std::vector<int2> &v, int64_t *bytes)
 {
     if (v.empty()) return GCT_OK;
+    *bytes += (int64_t)(v.size() * sizeof(int2));
     hipError_t e = hipMalloc(dst, v.size() * sizeof(int2));
     if (e != hipSuccess) return check_hip(e, "hipMalloc(batch map)");
     return check_hip(hipMemcpy(*dst, v.data(), v.size() * sizeof(int2), hipMemcpyHostToDevice),
@@ -868,6 +870,7 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
             v[i].l2 = plans[i]->lx2;
             v[i].tw = t == 0 ? plans[i]->dev.tw_f32 : plans[i]->dev.tw_f64;
         }
+        b->dev_bytes += (int64_t)(count * sizeof(BatchSlice));
         hipError_t e = hipMalloc(&b->dev[t], count * sizeof(BatchSlice));
         if (e == hipSuccess)
             e = hipMemcpy(b->dev[t], v.data(), count * sizeof(BatchSlice), hipMemcpyHostToDevice);
@@ -898,13 +901,13 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         g.nsrows = (int)srows.size();
         g.nscols = (int)scols.size();
         int rc = GCT_OK;
-        if (!rc) rc = upload_map(&g.rows, rows);
-        if (!rc) rc = upload_map(&g.cols, cols);
-        if (!rc) rc = upload_map(&g.srows, srows);
-        if (!rc) rc = upload_map(&g.scols, scols);
+        if (!rc) rc = upload_map(&g.rows, rows, &b->dev_bytes);
+        if (!rc) rc = upload_map(&g.cols, cols, &b->dev_bytes);
+        if (!rc) rc = upload_map(&g.srows, srows, &b->dev_bytes);
+        if (!rc) rc = upload_map(&g.scols, scols, &b->dev_bytes);
         if (!rc && pair2) {
             g.nrows2 = (int)rows2.size();
-            rc = upload_map(&g.rows2, rows2);
+            rc = upload_map(&g.rows2, rows2, &b->dev_bytes);
         }
         b->groups.push_back(g);
         if (rc) {
@@ -919,12 +922,19 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         for (int k = 0; k < tiles; ++k) gm.push_back(make_int2(i, k));
     }
     b->ngram = (int)gm.size();
-    int rc = upload_map(&b->gram_map, gm);
+    int rc = upload_map(&b->gram_map, gm, &b->dev_bytes);
     if (rc) {
         free_batch(b);
         return rc;
     }
     *out = b;
+    return GCT_OK;
+}
+
+int gct_batch_device_bytes(const gct_batch *b, int64_t *bytes)
+{
+    if (!b || !bytes) return fail(GCT_EINVAL, "NULL argument");
+    *bytes = b->dev_bytes;
     return GCT_OK;
 }
 

@@ -164,6 +164,7 @@ struct gct_plan {
     // angles per chunk (0: the tiled kernel does not apply) and angle groups
     int32_t bp_ch[2], bp_groups[2];
     gct::DeviceTables dev;
+    int64_t dev_bytes = 0;  // bytes of the device tables
     int device;
     // cached CG iteration graphs and the stream they are captured on
     std::vector<gct::CGGraph> cg_graphs;

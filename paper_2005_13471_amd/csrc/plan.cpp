@@ -470,9 +470,14 @@ static int build_plan(const gct_geometry *g, const Detector &det, gct_plan *p)
     const double alpha = 2.0 * std::sqrt(2.0) - 3.0;
     for (int m = -K; m <= K; ++m) q[m + K] = std::sqrt(2.0) * std::pow(alpha, std::abs(m));
 
+    // every table the plan keeps on the device, with its bytes counted
+    auto up = [&](void **d, const auto &v) {
+        p->dev_bytes += (int64_t)(v.size() * sizeof(v[0]));
+        return upload(d, v);
+    };
     int rc;
-    if ((rc = upload(&p->dev.gram_f32, gf))) return rc;
-    if ((rc = upload(&p->dev.gram_f64, gd))) return rc;
+    if ((rc = up(&p->dev.gram_f32, gf))) return rc;
+    if ((rc = up(&p->dev.gram_f64, gd))) return rc;
     {
         // Gram entries (angle, term) sorted by theta mod pi, for the Gram
         // build's angular windows (the terms of one angle stay together)
@@ -492,22 +497,22 @@ static int build_plan(const gct_geometry *g, const Detector &det, gct_plan *p)
         std::vector<double> ths(ne);
         for (int e = 0; e < ne; ++e) ths[e] = th[ord[e]];
         p->gram_hmax = hmax;
-        if ((rc = upload(&p->dev.gram_ord, ord))) return rc;
-        if ((rc = upload(&p->dev.gram_th, ths))) return rc;
+        if ((rc = up(&p->dev.gram_ord, ord))) return rc;
+        if ((rc = up(&p->dev.gram_th, ths))) return rc;
     }
-    if ((rc = upload(&p->dev.fwd_f32, ff))) return rc;
-    if ((rc = upload(&p->dev.fwd_f64, fd))) return rc;
-    if ((rc = upload(&p->dev.bp_geo, geo))) return rc;
-    if ((rc = upload(&p->dev.bp_int, ints))) return rc;
-    if ((rc = upload(&p->dev.bp_brk_f32, cast_vec<float>(brk)))) return rc;
-    if ((rc = upload(&p->dev.bp_brk_f64, brk))) return rc;
-    if ((rc = upload(&p->dev.bp_coef_f32, cast_vec<float>(coef)))) return rc;
-    if ((rc = upload(&p->dev.bp_coef_f64, coef))) return rc;
-    if ((rc = upload(&p->dev.tw_f32, cast_vec<float>(tw)))) return rc;
-    if ((rc = upload(&p->dev.tw_f64, tw))) return rc;
-    if ((rc = upload(&p->dev.q_f32, cast_vec<float>(q)))) return rc;
-    if ((rc = upload(&p->dev.q_f64, q))) return rc;
-    if ((rc = upload(&p->dev.deg, deg))) return rc;
+    if ((rc = up(&p->dev.fwd_f32, ff))) return rc;
+    if ((rc = up(&p->dev.fwd_f64, fd))) return rc;
+    if ((rc = up(&p->dev.bp_geo, geo))) return rc;
+    if ((rc = up(&p->dev.bp_int, ints))) return rc;
+    if ((rc = up(&p->dev.bp_brk_f32, cast_vec<float>(brk)))) return rc;
+    if ((rc = up(&p->dev.bp_brk_f64, brk))) return rc;
+    if ((rc = up(&p->dev.bp_coef_f32, cast_vec<float>(coef)))) return rc;
+    if ((rc = up(&p->dev.bp_coef_f64, coef))) return rc;
+    if ((rc = up(&p->dev.tw_f32, cast_vec<float>(tw)))) return rc;
+    if ((rc = up(&p->dev.tw_f64, tw))) return rc;
+    if ((rc = up(&p->dev.q_f32, cast_vec<float>(q)))) return rc;
+    if ((rc = up(&p->dev.q_f64, q))) return rc;
+    if ((rc = up(&p->dev.deg, deg))) return rc;
     return GCT_OK;
 }
 
@@ -845,6 +850,13 @@ int gct_plan_get_pass_elems(const gct_plan *p, gct_dtype dt, int32_t *out)
     out[1] = p->fft_ec[t];
     out[2] = p->cg_e[t];
     out[3] = p->cg_ec[t];
+    return GCT_OK;
+}
+
+int gct_plan_device_bytes(const gct_plan *p, int64_t *bytes)
+{
+    if (!p || !bytes) return fail(GCT_EINVAL, "NULL argument");
+    *bytes = p->dev_bytes;
     return GCT_OK;
 }
 

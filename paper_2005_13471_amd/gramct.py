@@ -81,6 +81,8 @@ def _load():
                                            ctypes.POINTER(ctypes.c_double), ctypes.POINTER(vp)]
     L.gct_plan_destroy.argtypes = [vp]
     L.gct_plan_get_info.argtypes = [vp, ctypes.POINTER(_PlanInfo)]
+    L.gct_plan_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+    L.gct_batch_device_bytes.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
     L.gct_workspace_size.argtypes = [vp, ctypes.c_int, ctypes.c_int]
     L.gct_workspace_size.restype = ctypes.c_size_t
     L.gct_gram_build.argtypes = [vp, ctypes.c_int, vp, vp]
@@ -231,6 +233,12 @@ class Plan:
 
     def workspace_size(self, op: int, dtype=torch.float32) -> int:
         return int(lib.gct_workspace_size(self._h, op, F32 if dtype == torch.float32 else F64))
+
+    def device_bytes(self) -> int:
+        """Bytes of device memory the plan's tables hold."""
+        v = ctypes.c_int64()
+        _check(lib.gct_plan_device_bytes(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     def workspace(self, op: int, dtype=torch.float32, device=None) -> torch.Tensor:
         n = max(self.workspace_size(op, dtype), 256)
@@ -402,6 +410,12 @@ class Batch:
 
     def workspace_size(self, op: int, dtype=torch.float32) -> int:
         return int(lib.gct_batch_workspace_size(self._h, op, F32 if dtype == torch.float32 else F64))
+
+    def device_bytes(self) -> int:
+        """Bytes of device memory the batch's maps and descriptors hold."""
+        v = ctypes.c_int64()
+        _check(lib.gct_batch_device_bytes(self._h, ctypes.byref(v)))
+        return int(v.value)
 
     def workspace(self, op: int, dtype=torch.float32) -> torch.Tensor:
         return torch.empty(max(self.workspace_size(op, dtype), 256), dtype=torch.uint8, device="cuda")

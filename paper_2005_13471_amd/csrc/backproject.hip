@@ -173,6 +173,23 @@ k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp,
     if (k1 < N && k2 < N) b[(size_t)k2 * N + k1] = acc;
 }
 
+// z = i + t with i = floor(z) and t in [0, 1): in FP32 one fract and one
+// floor-convert instead of floor, convert and subtract.  The values are the
+// same (z - floor(z) is exact) except where z is a tiny negative number and
+// z - floor(z) rounds up to 1: fract returns the largest float below 1.
+template <typename T>
+__device__ __forceinline__ void split_floor(T z, int &i, T &t)
+{
+    if constexpr (sizeof(T) == 4) {
+        t = __builtin_amdgcn_fractf(z);
+        asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(i) : "v"(z));  // floor and convert in one instruction
+    } else {
+        const T f = floor(z);
+        t = z - f;
+        i = (int)f;
+    }
+}
+
 // Tiled variant (the default).  A block owns a BP_TX x BP_TY pixel tile and
 // one of `groups` contiguous ranges of angles (partial images are summed by
 // k_bp_reduce in group order), so the per-angle table work is shared by
@@ -192,12 +209,12 @@ k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp,
 // count alone held a CU to 4 blocks; the kernel is VALU-bound and the extra
 // wave hides more of its LDS latency (0.44 -> 0.43 ms at 512^2 / 720 angles).
 template <typename T, int JM, int HN>
-__global__ void __launch_bounds__(256, 5)
+__global__ void __launch_bounds__(BP_NT, BP_WAVES)
 k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, int K, int groups,
           const double *__restrict__ geo, const int32_t *__restrict__ ints, const T *__restrict__ brk,
           const T *__restrict__ coef, int smax, int J, int D1, int rmax, int CH)
 {
-    constexpr int NT = 256, D1P = 8, PPT = BP_TX * BP_TY / NT, RSTEP = NT / BP_TX;
+    constexpr int NT = BP_NT, D1P = 8, PPT = BP_TX * BP_TY / NT, RSTEP = NT / BP_TX;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int per_coef = smax * J * D1;
     const int pseg = rmax + JM;  // J-tap windows never leave the segment
@@ -222,8 +239,30 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
         const int kk = i % (D1P - D1), row = i / (D1P - D1);
         s_E[(size_t)row * D1P + D1 + kk] = T(0);
     }
+    // Work decompositions that stay the same for every chunk, computed once
+    // (integer divisions by launch parameters are long instruction
+    // sequences): the table build's units (angle c, sub-interval, coefficient
+    // k, run of bins) for a full chunk of CH angles, the first of them this
+    // thread's, and the segment-staging position of element tid.
+    const int triplesF = CH * smax * D1;
+    const int pieces = max(1, NT / triplesF);
+    const int len = (rmax + pieces - 1) / pieces;
+    const int units = triplesF * pieces;
+    // The two decompositions are kept packed in one register each (the host
+    // guarantees the field widths: smax < 256, pieces < 4096, segments <
+    // 65536 entries) and unpacked per chunk: held unpacked through the
+    // per-pixel evaluation they cost spills to scratch.
+    unsigned pk_u, pk_p;
+    {
+        const int r0 = tid / pieces, r = r0 / D1, c = r / smax;
+        pk_u = (unsigned)(tid - r0 * pieces) | (unsigned)(r0 - r * D1) << 12 | (unsigned)(r - c * smax) << 16 |
+               (unsigned)c << 24;
+        const int pc = tid / pseg;
+        pk_p = (unsigned)(tid - pc * pseg) | (unsigned)pc << 16;
+    }
     for (int a0 = abeg; a0 < aend; a0 += CH) {
         const int cnt = min(CH, aend - a0);
+        asm volatile("" : "+v"(pk_u), "+v"(pk_p));  // unpacked here, not hoisted
         __syncthreads();  // the previous chunk's evaluations are done with LDS
         if (tid < cnt) {
             const int a = a0 + tid;
@@ -245,25 +284,28 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
         for (int i = tid; i < cnt * per_coef; i += NT) s_C[i] = coef[(size_t)a0 * per_coef + i];
         for (int i = tid; i < cnt * smax; i += NT) s_b[i] = brk[(size_t)a0 * smax + i];
         __syncthreads();
-        for (int i = tid; i < cnt * pseg; i += NT) {
-            const int c = i / pseg, off = i - c * pseg;
+        for (int i = tid, c = (int)(pk_p >> 16), off = (int)(pk_p & 0xffffu); i < cnt * pseg; i += NT) {
             const int a = a0 + c;
             const int mlo = s_w[4 * c], R = s_w[4 * c + 1];
             const int mi = mlo + ints[4 * a + 1] + off + K;
             s_p[i] = (off < R + J - 1 && mi >= 0 && mi < Mp) ? pf[(size_t)a * Mp + mi] : T(0);
+            for (off += NT; off >= pseg; off -= pseg) ++c;  // position of i + NT
         }
         __syncthreads();
         // sliding J-tap sums: each work unit is one (angle, sub-interval,
         // coefficient k < D1) and one of `pieces` runs of consecutive bins
         {
-            const int triples = cnt * smax * D1;
-            const int pieces = max(1, NT / triples);
-            const int len = (rmax + pieces - 1) / pieces;
-            for (int q = tid; q < triples * pieces; q += NT) {
-                const int piece = q % pieces, r0 = q / pieces;
-                const int k = r0 % D1, r = r0 / D1;
-                const int sidx = r % smax, c = r / smax;
-                if (sidx >= s_w[4 * c + 2]) continue;
+            for (int q = tid; q < units; q += NT) {
+                int piece = (int)(pk_u & 0xfffu), k = (int)(pk_u >> 12 & 0xfu), sidx = (int)(pk_u >> 16 & 0xffu),
+                    c = (int)(pk_u >> 24);
+                if (q != tid) {  // (only when a full chunk has more units than threads)
+                    const int r0 = q / pieces, r = r0 / D1;
+                    piece = q - r0 * pieces;
+                    k = r0 - r * D1;
+                    c = r / smax;
+                    sidx = r - c * smax;
+                }
+                if (c >= cnt || sidx >= s_w[4 * c + 2]) continue;
                 const int mlo = piece * len, mhi = min(s_w[4 * c + 1], mlo + len);
                 T cj[JM];
                 const T *cf = s_C + c * per_coef + sidx * J * D1 + k;
@@ -308,17 +350,22 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
             const T *Ec = s_E + (size_t)c * eang;
             const T zrow = zf + (T)d1 * dz1 + (T)d2 * dz2;
             const T rstep = (T)RSTEP * dz2;
-            // value of the angle's interpolant at pixel i, given its
-            // sub-interval and offset in it
-            auto eval = [&](int i, int mi, int sub, T u) {
-                const T *e = Ec + (mi * smax + sub) * D1P;
-                T ev[HN];
-#pragma unroll
-                for (int k = 0; k < HN; ++k) ev[k] = e[k];
+            // value of the angle's interpolant at pixel i, given its row
+            // (bin, sub-interval) and offset t in the bin (u = t - start)
+            auto row = [&](int mi, int sub) { return Ec + (__umul24(mi, smax) + sub) * D1P; };
+            auto horner = [&](int i, const T *ev, T u) {
                 T v = ev[HN - 1];
 #pragma unroll
                 for (int k = HN - 2; k >= 0; --k) v = v * u + ev[k];
                 csum[i] += v;
+            };
+            // bin of pixel i in the window; the unsigned minimum keeps it in
+            // [0, R) (it is there already up to a rounding of the in-tile
+            // position, which the window's one-bin margins absorb)
+            auto bin_of = [&](T zl, T &t) {
+                int fl;
+                split_floor(zl, fl, t);
+                return (int)min((unsigned)(base + fl), (unsigned)(R - 1));
             };
             if (nsub <= 4) {  // (uniform) branch-free search over at most 3 breakpoints
                 const T b0 = bk[0];
@@ -326,28 +373,30 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
                         b3 = nsub > 3 ? bk[3] : T(2);  // 2: absent (t < 1)
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
-                    const T zl = zrow + (T)i * rstep;
-                    const T fl = floor(zl);
-                    const T t = zl - fl;
-                    int mi = base + (int)fl;
-                    mi = min(max(mi, 0), R - 1);
+                    T t;
+                    const int mi = bin_of(zrow + (T)i * rstep, t);
                     const bool g1 = t >= b1, g2 = t >= b2, g3 = t >= b3;
+                    const T *e = row(mi, (int)g1 + (int)g2 + (int)g3);
                     T bs = g1 ? b1 : b0;  // breakpoints ascend: the last one passed
                     bs = g2 ? b2 : bs;
                     bs = g3 ? b3 : bs;
-                    eval(i, mi, (int)g1 + (int)g2 + (int)g3, t - bs);
+                    T ev[HN];
+#pragma unroll
+                    for (int k = 0; k < HN; ++k) ev[k] = e[k];
+                    horner(i, ev, t - bs);
                 }
             } else {
 #pragma unroll
                 for (int i = 0; i < PPT; ++i) {
-                    const T zl = zrow + (T)i * rstep;
-                    const T fl = floor(zl);
-                    const T t = zl - fl;
-                    int mi = base + (int)fl;
-                    mi = min(max(mi, 0), R - 1);
+                    T t;
+                    const int mi = bin_of(zrow + (T)i * rstep, t);
                     int sub = 0;
                     for (int s2 = 1; s2 < nsub; ++s2) sub += (t >= bk[s2]) ? 1 : 0;
-                    eval(i, mi, sub, t - bk[sub]);
+                    const T *e = row(mi, sub);
+                    T ev[HN];
+#pragma unroll
+                    for (int k = 0; k < HN; ++k) ev[k] = e[k];
+                    horner(i, ev, t - bk[sub]);
                 }
             }
         }
@@ -418,14 +467,16 @@ static void bp_configure_t(gct_plan *p, int t)
 {
     p->bp_ch[t] = 0;
     p->bp_groups[t] = 1;
-    if (p->bp.D1 > 8 || p->bp.J > 16) return;  // beyond the kernel's limits
+    // beyond the kernel's limits (coefficients, taps, the packed per-thread
+    // work decompositions)
+    if (p->bp.D1 > 8 || p->bp.J > 16 || p->bp.smax > 255 || bp_rmax(p) + 16 > 4095) return;
     const void *fn = bp_tile_fn<T>(p);
     int best_ch = 0, best_nb = 0;
     for (int ch : {8, 4, 2, 1}) {
         const size_t lds = bp_tile_lds(p, sizeof(T), ch);
         if (lds > 65536) continue;
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, lds) != hipSuccess) nb = 1;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, BP_NT, lds) != hipSuccess) nb = 1;
         if (nb > best_nb) {
             best_nb = nb;
             best_ch = ch;
@@ -505,7 +556,7 @@ hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, hip
             const double *geo_ = reinterpret_cast<const double *>(p->dev.bp_geo);
             const int32_t *ints_ = reinterpret_cast<const int32_t *>(p->dev.bp_int);
 #define GCT_BP_TILE(JM_, HN_)                                                                              \
-    hipLaunchKernelGGL((k_bp_tile<T, JM_, HN_>), grid, dim3(256), lds, s, pf, dst, N, p->n, p->M + 2 * p->K, \
+    hipLaunchKernelGGL((k_bp_tile<T, JM_, HN_>), grid, dim3(BP_NT), lds, s, pf, dst, N, p->n, p->M + 2 * p->K, \
                        p->K, groups, geo_, ints_, brk_, coef_, p->bp.smax, p->bp.J, p->bp.D1, rmax, ch)
             // Horner length: the kernel degree + 1 rounded up to 4, 6 or 8
             const int hn = p->bp.D1 <= 4 ? 4 : (p->bp.D1 <= 6 ? 6 : 8);

@@ -71,8 +71,9 @@ struct BPDims {
     double tile_win;        // max over angles of (BP_TX-1)|dz1| + (BP_TY-1)|dz2|: bins a tile spans
 };
 
-// Pixel tile of the back-projection kernel (columns x rows).
-constexpr int BP_TX = 64, BP_TY = 32;
+// Pixel tile of the back-projection kernel (columns x rows), its threads
+// per block and the minimum resident waves per SIMD it is compiled for.
+constexpr int BP_TX = 64, BP_TY = 32, BP_NT = 256, BP_WAVES = 5;
 // Gram build: taps per tile side (one block of 4 waves per tile): batched
 // builds 16, the single-slice build 8 with the block's waves splitting the
 // angles

@@ -188,8 +188,11 @@ int gct_prefilter(const gct_plan *plan, gct_dtype dtype, const void *g_s, void *
  * ghat_theta(y) = sum_m p[m] beta_d((y - y_m)/lambda_y).  Each (pixel, angle,
  * bin) weight is a univariate box spline with directions {l1|c|, l2|s|,
  * zeta, lambda_y x (d+1)}, evaluated exactly from per-angle piecewise
- * polynomials.  g_s: sino_elems; b: image_elems.  Workspace holds the
- * prefiltered sinogram. */
+ * polynomials.  g_s: sino_elems; b: image_elems.  Workspace
+ * (gct_workspace_size(plan, GCT_OP_BACKPROJECT, dtype) bytes) holds the
+ * prefiltered sinogram, the per-angle polynomial tables of the weighted
+ * sinogram sums (one row per angle, detector bin reached by the image and
+ * sub-interval) and the partial images of the angle groups. */
 int gct_backproject_boxspline(const gct_plan *plan, gct_dtype dtype, const void *g_s, void *b,
                               void *ws, void *stream);
 

@@ -173,6 +173,71 @@ k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp,
     if (k1 < N && k2 < N) b[(size_t)k2 * N + k1] = acc;
 }
 
+// Per-angle interpolant tables for the tiled kernel.  For angle a, bin row
+// m in [0, MT) (bin mA_a + m of the angle's window over the whole tile grid)
+// and sub-interval s:
+//   E[a][m][s][k] = sum_{j < J} p[a][mA_a + m + jlo_a + j] C[a][s][j][k],
+// the polynomial (in the offset u from the sub-interval's start) of the
+// weighted sum of the J sinogram samples that reach a pixel whose projection
+// falls in that bin and sub-interval; k < D1, padded to 8 with zeros (rows of
+// absent sub-intervals are zero).  p is the prefiltered row, zero outside
+// [0, M + 2K).  Built once per angle and bin instead of once per (tile,
+// angle): a bin row is shared by every tile whose window contains it.  One
+// thread per (m, s) row (neighbouring threads write neighbouring rows); the
+// sums run over j in increasing order.
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_bp_etab(const T *__restrict__ pf, T *__restrict__ etab, int Mp, int K, int MT,
+          const int32_t *__restrict__ ints, const T *__restrict__ coef, int smax, int J, int D1)
+{
+    constexpr int D1P = 8;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *sC = reinterpret_cast<T *>(smem_raw);  // [smax][J][8] of this angle, zero past D1
+    const int a = blockIdx.y, per = smax * J * D1;
+    for (int i = threadIdx.x; i < smax * J * D1P; i += blockDim.x) {
+        const int k = i % D1P, sj = i / D1P;
+        sC[i] = k < D1 ? coef[(size_t)a * per + sj * D1 + k] : T(0);
+    }
+    __syncthreads();
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= MT * smax) return;
+    const int m = i / smax, sidx = i - m * smax;
+    T e[D1P];
+#pragma unroll
+    for (int k = 0; k < D1P; ++k) e[k] = T(0);
+    if (sidx < ints[4 * a]) {
+        const int base = ints[4 * a + 3] + m + ints[4 * a + 1] + K;  // p index of tap 0
+        const T *prow = pf + (size_t)a * Mp;
+        for (int j = 0; j < J; ++j) {
+            const int mi = base + j;
+            const T pv = (mi >= 0 && mi < Mp) ? prow[mi] : T(0);
+            const T *c = sC + (sidx * J + j) * D1P;
+#pragma unroll
+            for (int k = 0; k < D1P; ++k) e[k] += pv * c[k];  // (+0 stays +0 past D1)
+        }
+    }
+    // the row as 16-byte stores (rows are 16-byte aligned)
+    uint4 *dst = reinterpret_cast<uint4 *>(etab + (size_t)(a * MT + m) * smax * D1P + sidx * D1P);
+    const uint4 *src = reinterpret_cast<const uint4 *>(e);
+#pragma unroll
+    for (int q = 0; q < (int)(D1P * sizeof(T) / 16); ++q) dst[q] = src[q];
+}
+
+// Tiled back projection (the default).  A block owns a BP_TX x BP_TY pixel
+// tile and one of `groups` contiguous ranges of angles (partial images are
+// summed by k_bp_reduce in group order).  Per chunk of CH angles:
+//   - thread c: the tile's bin window [mlo, mlo + R) and the split of
+//     the tile origin's projection z_t into an integer zi and a fraction;
+//     a pixel at offset (d1, d2) in the tile then has z = zi + zl with
+//     zl = frac(z_t) + d1 dz1 + d2 dz2 computed in T (|zl| < R);
+//   - the window's rows of the angle's table (k_bp_etab) are copied to LDS
+//     (16 bytes per thread and step; rows outside the table are zero);
+//   - each thread evaluates 8 pixels (rows 4 apart) per angle: one floor,
+//     a sub-interval search, one or two 16-byte LDS reads, an HN-term Horner
+//     scheme (HN >= D1: the coefficients past D1 are the zero padding).
+// The windows of a run of BP_WB angles are computed at once (their geometry
+// loads wait once per run, not per chunk).  The chunk's angles are summed
+// plainly per pixel, then added to a compensated total once per chunk.
 // z = i + t with i = floor(z) and t in [0, 1): in FP32 one fract and one
 // floor-convert instead of floor, convert and subtract.  The values are the
 // same (z - floor(z) is exact) except where z is a tiny negative number and
@@ -190,82 +255,51 @@ __device__ __forceinline__ void split_floor(T z, int &i, T &t)
     }
 }
 
-// Tiled variant (the default).  A block owns a BP_TX x BP_TY pixel tile and
-// one of `groups` contiguous ranges of angles (partial images are summed by
-// k_bp_reduce in group order), so the per-angle table work is shared by
-// 2048 pixels while a 512^2 image still gives 1024 blocks.  Per chunk of CH
-// angles:
-//   - thread c < CH: the tile's bin window [mlo, mlo + R) and the split of
-//     the tile origin's projection z_t into an integer zi and a fraction;
-//     a pixel at offset (d1, d2) in the tile then has z = zi + zl with
-//     zl = frac(z_t) + d1 dz1 + d2 dz2 computed in T (|zl| < R);
-//   - E[c][m][s][k] = sum_j p[c][m + j] C[c][s][j][k] as J-tap sliding sums
-//     per (angle, sub-interval, coefficient), split in runs of bins over all
-//     threads; k padded to 8 with zeros (written once per block);
-//   - each thread evaluates 8 pixels (rows 4 apart) per angle: one floor,
-//     a sub-interval search, one or two 16-byte LDS reads, an HN-term Horner
-//     scheme (HN >= D1: the coefficients past D1 are the zero padding).
-// At least 5 waves per SIMD (96 VGPRs, a few spilled): with 4 the register
-// count alone held a CU to 4 blocks; the kernel is VALU-bound and the extra
-// wave hides more of its LDS latency (0.44 -> 0.43 ms at 512^2 / 720 angles).
-template <typename T, int JM, int HN>
+template <typename T, int HN>
 __global__ void __launch_bounds__(BP_NT, BP_WAVES)
-k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, int K, int groups,
+k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT, int groups,
           const double *__restrict__ geo, const int32_t *__restrict__ ints, const T *__restrict__ brk,
-          const T *__restrict__ coef, int smax, int J, int D1, int rmax, int CH)
+          int smax, int rmax, int CH)
 {
-    constexpr int NT = BP_NT, D1P = 8, PPT = BP_TX * BP_TY / NT, RSTEP = NT / BP_TX;
+    constexpr int NT = BP_NT, D1P = 8, PPT = BP_TX * BP_TY / NT, RSTEP = NT / BP_TX, WB = BP_WB;
+    constexpr int V = 16 / sizeof(T);  // elements per 16-byte piece
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int per_coef = smax * J * D1;
-    const int pseg = rmax + JM;  // J-tap windows never leave the segment
     const int eang = rmax * smax * D1P;
-    T *s_E = reinterpret_cast<T *>(smem_raw);  // [CH][rmax][smax][D1P]
-    T *s_C = s_E + (size_t)CH * eang;          // [CH][smax][J][D1]
-    T *s_p = s_C + CH * per_coef;              // [CH][rmax + J]
-    T *s_b = s_p + CH * pseg;                  // [CH][smax]
-    T *s_f = s_b + CH * smax;                  // [CH][3]: frac(z_t), dz1, dz2
-    int *s_w = reinterpret_cast<int *>(s_f + CH * 3);  // [CH][4]: mlo, R, nsub, zi - mlo
-    const int tid = threadIdx.x;
+    // table rows E [CH][rmax][smax][D1P]; for a run of WB angles:
+    // breakpoints [WB][smax], (frac(z_t), dz1, dz2) [WB][3] and (g0, R, nsub,
+    // zi - mlo) [WB][4], g0 = mlo - mA_a the window's first row in the
+    // angle's table
+    T *s_E = reinterpret_cast<T *>(smem_raw);
+    T *s_b = s_E + (size_t)CH * eang;
+    T *s_f = s_b + WB * smax;
+    int *s_w = reinterpret_cast<int *>(s_f + WB * 3);
+    const int tid = threadIdx.x, lane = tid & 63;
     const int k1a = blockIdx.x * BP_TX, k2a = blockIdx.y * BP_TY;
     const int d1 = tid % BP_TX, d2 = tid / BP_TX;  // rows d2 + RSTEP i
     const int gsz = (n + groups - 1) / groups;
     const int abeg = blockIdx.z * gsz, aend = min(n, abeg + gsz);
+    const int rowp = smax * D1P / V;  // 16-byte pieces per bin row of a table
+    // the table rows of window entries [c0, c0 + cnt) (angles A + c) to
+    // LDS, 16 bytes per thread and step (rows outside [0, MT) are zero)
+    auto stage = [&](int A, int c0, int cnt) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(etab);
+        for (int c = 0; c < cnt; ++c) {
+            const int *w = s_w + 4 * (c0 + c);
+            const int a = A + c0 + c, tot = w[1] * rowp, g0 = w[0];
+            const int lo = max(0, -g0) * rowp, hi = min(w[1], MT - g0) * rowp;
+            const int64_t off = ((int64_t)a * MT + g0) * rowp;  // piece i of the window: src[off + i]
+            uint4 *dst = reinterpret_cast<uint4 *>(s_E + (size_t)c * eang);
+            for (int i = tid; i < tot; i += NT) dst[i] = (i >= lo && i < hi) ? src[off + i] : make_uint4(0, 0, 0, 0);
+        }
+    };
     T acc[PPT], comp[PPT];
 #pragma unroll
     for (int i = 0; i < PPT; ++i) acc[i] = comp[i] = T(0);
-    // the padding coefficients k in [D1, 8) of every E row stay zero: the
-    // table build writes only k < D1
-    for (int i = tid; i < CH * rmax * smax * (D1P - D1); i += NT) {
-        const int kk = i % (D1P - D1), row = i / (D1P - D1);
-        s_E[(size_t)row * D1P + D1 + kk] = T(0);
-    }
-    // Work decompositions that stay the same for every chunk, computed once
-    // (integer divisions by launch parameters are long instruction
-    // sequences): the table build's units (angle c, sub-interval, coefficient
-    // k, run of bins) for a full chunk of CH angles, the first of them this
-    // thread's, and the segment-staging position of element tid.
-    const int triplesF = CH * smax * D1;
-    const int pieces = max(1, NT / triplesF);
-    const int len = (rmax + pieces - 1) / pieces;
-    const int units = triplesF * pieces;
-    // The two decompositions are kept packed in one register each (the host
-    // guarantees the field widths: smax < 256, pieces < 4096, segments <
-    // 65536 entries) and unpacked per chunk: held unpacked through the
-    // per-pixel evaluation they cost spills to scratch.
-    unsigned pk_u, pk_p;
-    {
-        const int r0 = tid / pieces, r = r0 / D1, c = r / smax;
-        pk_u = (unsigned)(tid - r0 * pieces) | (unsigned)(r0 - r * D1) << 12 | (unsigned)(r - c * smax) << 16 |
-               (unsigned)c << 24;
-        const int pc = tid / pseg;
-        pk_p = (unsigned)(tid - pc * pseg) | (unsigned)pc << 16;
-    }
-    for (int a0 = abeg; a0 < aend; a0 += CH) {
-        const int cnt = min(CH, aend - a0);
-        asm volatile("" : "+v"(pk_u), "+v"(pk_p));  // unpacked here, not hoisted
-        __syncthreads();  // the previous chunk's evaluations are done with LDS
-        if (tid < cnt) {
-            const int a = a0 + tid;
+    for (int A = abeg; A < aend; A += WB) {
+        const int cntW = min(WB, aend - A);
+        // windows of the run's angles (the previous run's are no longer read)
+        if (tid < cntW) {
+            const int a = A + tid;
             const double z0 = geo[4 * a], dz1 = geo[4 * a + 1], dz2 = geo[4 * a + 2];
             const double zt = z0 + (double)k1a * dz1 + (double)k2a * dz2;
             const double e1 = (BP_TX - 1) * dz1, e2 = (BP_TY - 1) * dz2;
@@ -273,140 +307,95 @@ k_bp_tile(const T *__restrict__ pf, T *__restrict__ out, int N, int n, int Mp, i
             const double zmax = zt + fmax(e1, 0.0) + fmax(e2, 0.0);
             const int mlo = (int)floor(zmin) - 1;
             const double zi = floor(zt);
-            s_w[4 * tid] = mlo;
-            s_w[4 * tid + 1] = min((int)floor(zmax) + 2 - mlo, rmax);
-            s_w[4 * tid + 2] = ints[4 * a];
-            s_w[4 * tid + 3] = (int)zi - mlo;
-            s_f[3 * tid] = (T)(zt - zi);
-            s_f[3 * tid + 1] = (T)dz1;
-            s_f[3 * tid + 2] = (T)dz2;
+            int *w = s_w + 4 * tid;
+            T *f = s_f + 3 * tid;
+            w[0] = mlo - ints[4 * a + 3];
+            w[1] = min((int)floor(zmax) + 2 - mlo, rmax);
+            w[2] = ints[4 * a];
+            w[3] = (int)zi - mlo;
+            f[0] = (T)(zt - zi);
+            f[1] = (T)dz1;
+            f[2] = (T)dz2;
         }
-        for (int i = tid; i < cnt * per_coef; i += NT) s_C[i] = coef[(size_t)a0 * per_coef + i];
-        for (int i = tid; i < cnt * smax; i += NT) s_b[i] = brk[(size_t)a0 * smax + i];
-        __syncthreads();
-        for (int i = tid, c = (int)(pk_p >> 16), off = (int)(pk_p & 0xffffu); i < cnt * pseg; i += NT) {
-            const int a = a0 + c;
-            const int mlo = s_w[4 * c], R = s_w[4 * c + 1];
-            const int mi = mlo + ints[4 * a + 1] + off + K;
-            s_p[i] = (off < R + J - 1 && mi >= 0 && mi < Mp) ? pf[(size_t)a * Mp + mi] : T(0);
-            for (off += NT; off >= pseg; off -= pseg) ++c;  // position of i + NT
-        }
-        __syncthreads();
-        // sliding J-tap sums: each work unit is one (angle, sub-interval,
-        // coefficient k < D1) and one of `pieces` runs of consecutive bins
-        {
-            for (int q = tid; q < units; q += NT) {
-                int piece = (int)(pk_u & 0xfffu), k = (int)(pk_u >> 12 & 0xfu), sidx = (int)(pk_u >> 16 & 0xffu),
-                    c = (int)(pk_u >> 24);
-                if (q != tid) {  // (only when a full chunk has more units than threads)
-                    const int r0 = q / pieces, r = r0 / D1;
-                    piece = q - r0 * pieces;
-                    k = r0 - r * D1;
-                    c = r / smax;
-                    sidx = r - c * smax;
-                }
-                if (c >= cnt || sidx >= s_w[4 * c + 2]) continue;
-                const int mlo = piece * len, mhi = min(s_w[4 * c + 1], mlo + len);
-                T cj[JM];
-                const T *cf = s_C + c * per_coef + sidx * J * D1 + k;
+        for (int i = tid; i < cntW * smax; i += NT) s_b[i] = brk[(size_t)A * smax + i];
+        for (int c0 = 0; c0 < cntW; c0 += CH) {
+            const int cnt = min(CH, cntW - c0);
+            __syncthreads();  // windows written; the previous chunk's evaluations are done
+            stage(A, c0, cnt);
+            __syncthreads();
+            // the chunk's angles summed plainly per pixel, then added to the
+            // compensated total once per chunk
+            T csum[PPT];
 #pragma unroll
-                for (int j = 0; j < JM; ++j) cj[j] = j < J ? cf[j * D1] : T(0);
-                const T *pp = s_p + c * pseg;
-                T *E = s_E + (size_t)c * eang + sidx * D1P + k;
-                int mi = mlo;
-                // 8 bins at a time from one register window of JM + 7 samples
-                // (one LDS read per bin instead of JM); the window ends
-                // before mhi + JM - 1 <= pseg
-                for (; mi + 8 <= mhi; mi += 8) {
-                    T w[JM + 7];
+            for (int i = 0; i < PPT; ++i) csum[i] = T(0);
+            for (int c = 0; c < cnt; ++c) {
+                const int *w = s_w + 4 * (c0 + c);
+                const T *f = s_f + 3 * (c0 + c);
+                const int R = w[1], nsub = w[2], base = w[3];
+                const T zf = f[0], dz1 = f[1], dz2 = f[2];
+                const T *bk = s_b + (c0 + c) * smax;
+                const T *Ec = s_E + (size_t)c * eang;
+                const T zrow = zf + (T)d1 * dz1 + (T)d2 * dz2;
+                const T rstep = (T)RSTEP * dz2;
+                // value of the angle's interpolant at pixel i, given its row
+                // (bin, sub-interval) and offset t in the bin (u = t - start)
+                auto row = [&](int mi, int sub) { return Ec + (__umul24(mi, smax) + sub) * D1P; };
+                auto horner = [&](int i, const T *ev, T u) {
+                    T v = ev[HN - 1];
 #pragma unroll
-                    for (int q2 = 0; q2 < JM + 7; ++q2) w[q2] = pp[mi + q2];
+                    for (int k = HN - 2; k >= 0; --k) v = v * u + ev[k];
+                    csum[i] += v;
+                };
+                // bin of pixel i in the window; the unsigned minimum keeps it
+                // in [0, R) (it is there already up to a rounding of the
+                // in-tile position, which the window's one-bin margins absorb)
+                auto bin_of = [&](T zl, T &t) {
+                    int fl;
+                    split_floor(zl, fl, t);
+                    return (int)min((unsigned)(base + fl), (unsigned)(R - 1));
+                };
+                if (nsub <= 4) {  // (uniform) branch-free search over at most 3 breakpoints
+                    const T b0 = bk[0];
+                    const T b1 = nsub > 1 ? bk[1] : T(2), b2 = nsub > 2 ? bk[2] : T(2),
+                            b3 = nsub > 3 ? bk[3] : T(2);  // 2: absent (t < 1)
 #pragma unroll
-                    for (int o = 0; o < 8; ++o) {
-                        T e = 0;
+                    for (int i = 0; i < PPT; ++i) {
+                        T t;
+                        const int mi = bin_of(zrow + (T)i * rstep, t);
+                        const bool g1 = t >= b1, g2 = t >= b2, g3 = t >= b3;
+                        const T *e = row(mi, (int)g1 + (int)g2 + (int)g3);
+                        T bs = g1 ? b1 : b0;  // breakpoints ascend: the last one passed
+                        bs = g2 ? b2 : bs;
+                        bs = g3 ? b3 : bs;
+                        T ev[HN];
 #pragma unroll
-                        for (int j = 0; j < JM; ++j) e += w[o + j] * cj[j];
-                        E[(mi + o) * smax * D1P] = e;
+                        for (int k = 0; k < HN; ++k) ev[k] = e[k];
+                        horner(i, ev, t - bs);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < PPT; ++i) {
+                        T t;
+                        const int mi = bin_of(zrow + (T)i * rstep, t);
+                        int sub = 0;
+                        for (int s2 = 1; s2 < nsub; ++s2) sub += (t >= bk[s2]) ? 1 : 0;
+                        const T *e = row(mi, sub);
+                        T ev[HN];
+#pragma unroll
+                        for (int k = 0; k < HN; ++k) ev[k] = e[k];
+                        horner(i, ev, t - bk[sub]);
                     }
                 }
-                for (; mi < mhi; ++mi) {
-                    T e = 0;
+            }
 #pragma unroll
-                    for (int j = 0; j < JM; ++j) e += pp[mi + j] * cj[j];
-                    E[mi * smax * D1P] = e;
-                }
+            for (int i = 0; i < PPT; ++i) {
+                const T yk = csum[i] - comp[i];
+                const T tk = acc[i] + yk;
+                comp[i] = (tk - acc[i]) - yk;
+                acc[i] = tk;
             }
         }
-        __syncthreads();
-        // the chunk's angles summed plainly per pixel, then added to the
-        // compensated total once per chunk
-        T csum[PPT];
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) csum[i] = T(0);
-        for (int c = 0; c < cnt; ++c) {
-            const int R = s_w[4 * c + 1], nsub = s_w[4 * c + 2], base = s_w[4 * c + 3];
-            const T zf = s_f[3 * c], dz1 = s_f[3 * c + 1], dz2 = s_f[3 * c + 2];
-            const T *bk = s_b + c * smax;
-            const T *Ec = s_E + (size_t)c * eang;
-            const T zrow = zf + (T)d1 * dz1 + (T)d2 * dz2;
-            const T rstep = (T)RSTEP * dz2;
-            // value of the angle's interpolant at pixel i, given its row
-            // (bin, sub-interval) and offset t in the bin (u = t - start)
-            auto row = [&](int mi, int sub) { return Ec + (__umul24(mi, smax) + sub) * D1P; };
-            auto horner = [&](int i, const T *ev, T u) {
-                T v = ev[HN - 1];
-#pragma unroll
-                for (int k = HN - 2; k >= 0; --k) v = v * u + ev[k];
-                csum[i] += v;
-            };
-            // bin of pixel i in the window; the unsigned minimum keeps it in
-            // [0, R) (it is there already up to a rounding of the in-tile
-            // position, which the window's one-bin margins absorb)
-            auto bin_of = [&](T zl, T &t) {
-                int fl;
-                split_floor(zl, fl, t);
-                return (int)min((unsigned)(base + fl), (unsigned)(R - 1));
-            };
-            if (nsub <= 4) {  // (uniform) branch-free search over at most 3 breakpoints
-                const T b0 = bk[0];
-                const T b1 = nsub > 1 ? bk[1] : T(2), b2 = nsub > 2 ? bk[2] : T(2),
-                        b3 = nsub > 3 ? bk[3] : T(2);  // 2: absent (t < 1)
-#pragma unroll
-                for (int i = 0; i < PPT; ++i) {
-                    T t;
-                    const int mi = bin_of(zrow + (T)i * rstep, t);
-                    const bool g1 = t >= b1, g2 = t >= b2, g3 = t >= b3;
-                    const T *e = row(mi, (int)g1 + (int)g2 + (int)g3);
-                    T bs = g1 ? b1 : b0;  // breakpoints ascend: the last one passed
-                    bs = g2 ? b2 : bs;
-                    bs = g3 ? b3 : bs;
-                    T ev[HN];
-#pragma unroll
-                    for (int k = 0; k < HN; ++k) ev[k] = e[k];
-                    horner(i, ev, t - bs);
-                }
-            } else {
-#pragma unroll
-                for (int i = 0; i < PPT; ++i) {
-                    T t;
-                    const int mi = bin_of(zrow + (T)i * rstep, t);
-                    int sub = 0;
-                    for (int s2 = 1; s2 < nsub; ++s2) sub += (t >= bk[s2]) ? 1 : 0;
-                    const T *e = row(mi, sub);
-                    T ev[HN];
-#pragma unroll
-                    for (int k = 0; k < HN; ++k) ev[k] = e[k];
-                    horner(i, ev, t - bk[sub]);
-                }
-            }
-        }
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-            const T yk = csum[i] - comp[i];
-            const T tk = acc[i] + yk;
-            comp[i] = (tk - acc[i]) - yk;
-            acc[i] = tk;
-        }
+        __syncthreads();  // the run's windows are read before the next run writes them
     }
     T *dst = groups > 1 ? out + (size_t)blockIdx.z * N * N : out;
     const int k1 = k1a + d1;
@@ -429,29 +418,31 @@ __global__ void __launch_bounds__(256) k_bp_reduce(const T *__restrict__ part, i
     }
 }
 
-// Tiled kernel for the plan's kernel shape (taps JM, Horner length HN).
+// Tiled kernel for the plan's Horner length HN (the kernel degree + 1
+// rounded up to 4, 6 or 8).
+static int bp_hn(const gct_plan *p) { return p->bp.D1 <= 4 ? 4 : (p->bp.D1 <= 6 ? 6 : 8); }
 template <typename T>
 static const void *bp_tile_fn(const gct_plan *p)
 {
-    const int hn = p->bp.D1 <= 4 ? 4 : (p->bp.D1 <= 6 ? 6 : 8);
-    if (p->bp.J <= 8)
-        return hn == 4 ? reinterpret_cast<const void *>(&k_bp_tile<T, 8, 4>)
-                       : (hn == 6 ? reinterpret_cast<const void *>(&k_bp_tile<T, 8, 6>)
-                                  : reinterpret_cast<const void *>(&k_bp_tile<T, 8, 8>));
-    return hn == 4 ? reinterpret_cast<const void *>(&k_bp_tile<T, 16, 4>)
-                   : (hn == 6 ? reinterpret_cast<const void *>(&k_bp_tile<T, 16, 6>)
-                              : reinterpret_cast<const void *>(&k_bp_tile<T, 16, 8>));
+    const int hn = bp_hn(p);
+    return hn == 4 ? reinterpret_cast<const void *>(&k_bp_tile<T, 4>)
+                   : (hn == 6 ? reinterpret_cast<const void *>(&k_bp_tile<T, 6>)
+                              : reinterpret_cast<const void *>(&k_bp_tile<T, 8>));
 }
 
 // Bins of a tile's window and the LDS bytes of the tiled kernel for `ch`
-// angles per chunk.
+// angles per chunk (table rows; breakpoints and windows of a run of BP_WB
+// angles).
 static int bp_rmax(const gct_plan *p) { return (int)std::ceil(p->bp.tile_win) + 4; }
 static size_t bp_tile_lds(const gct_plan *p, size_t elem, int ch)
 {
-    const int rmax = bp_rmax(p), jm = p->bp.J <= 8 ? 8 : 16;  // the kernel's tap count JM
-    const size_t per = (size_t)rmax * p->bp.smax * 8 + (size_t)p->bp.smax * p->bp.J * p->bp.D1 +
-                       (rmax + jm) + p->bp.smax + 3;
-    return ch * per * elem + ch * 4 * sizeof(int);
+    return ((size_t)ch * bp_rmax(p) * p->bp.smax * 8 + (size_t)BP_WB * (p->bp.smax + 3)) * elem +
+           (size_t)BP_WB * 4 * sizeof(int);
+}
+// LDS bytes of the table kernel (one angle's coefficients, padded to 8)
+static size_t bp_etab_lds(const gct_plan *p, size_t elem)
+{
+    return (size_t)p->bp.smax * p->bp.J * 8 * elem;
 }
 
 // Launch shape of the tiled kernel for one element size, chosen for
@@ -467,9 +458,9 @@ static void bp_configure_t(gct_plan *p, int t)
 {
     p->bp_ch[t] = 0;
     p->bp_groups[t] = 1;
-    // beyond the kernel's limits (coefficients, taps, the packed per-thread
-    // work decompositions)
-    if (p->bp.D1 > 8 || p->bp.J > 16 || p->bp.smax > 255 || bp_rmax(p) + 16 > 4095) return;
+    // beyond the kernels' limits (8 coefficients per table row, 16 taps,
+    // one angle's coefficients in LDS)
+    if (p->bp.D1 > 8 || p->bp.J > 16 || bp_etab_lds(p, sizeof(T)) > 65536) return;
     const void *fn = bp_tile_fn<T>(p);
     int best_ch = 0, best_nb = 0;
     for (int ch : {8, 4, 2, 1}) {
@@ -511,6 +502,20 @@ void bp_configure(gct_plan *p)
 
 int bp_angle_groups(const gct_plan *p, size_t elem) { return p->bp_groups[elem == 4 ? 0 : 1]; }
 
+BPWorkspace bp_workspace(const gct_plan *p, size_t elem)
+{
+    const int t = elem == 4 ? 0 : 1;
+    const bool tiled = p->bp_ch[t] > 0;
+    BPWorkspace w;
+    size_t o = align256((size_t)p->n * (p->M + 2 * p->K) * elem);
+    w.etab = o;
+    if (tiled) o += align256((size_t)p->n * p->bp.MT * p->bp.smax * 8 * elem);
+    w.part = o;
+    if (tiled && p->bp_groups[t] > 1) o += align256((size_t)p->bp_groups[t] * p->N * p->N * elem);
+    w.total = o;
+    return w;
+}
+
 // Tile side, bins per tile window and angles per chunk such that the LDS
 // stays within 64 KB: 32 x 32 tiles when they fit, else 16 x 16, else 8 x 8
 // (kernels with many sub-intervals: several detector boxes in FP64).
@@ -540,7 +545,7 @@ int bp_fallback_tile(const gct_plan *p, size_t elem)
 }
 
 template <typename T>
-hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, hipStream_t s)
+hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, T *etab, hipStream_t s)
 {
     const int N = p->N;
     const T *brk_ = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.bp_brk_f32 : p->dev.bp_brk_f64);
@@ -548,27 +553,23 @@ hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, hip
     {
         const int t = sizeof(T) == 4 ? 0 : 1;
         const int ch = p->bp_ch[t], rmax = bp_rmax(p);
-        const size_t lds = bp_tile_lds(p, sizeof(T), ch);
         if (ch > 0) {
-            const int groups = p->bp_groups[t];
-            const dim3 grid((N + BP_TX - 1) / BP_TX, (N + BP_TY - 1) / BP_TY, groups);
-            T *dst = groups > 1 ? part : b;
+            const int groups = p->bp_groups[t], MT = p->bp.MT, smax = p->bp.smax;
             const double *geo_ = reinterpret_cast<const double *>(p->dev.bp_geo);
             const int32_t *ints_ = reinterpret_cast<const int32_t *>(p->dev.bp_int);
-#define GCT_BP_TILE(JM_, HN_)                                                                              \
-    hipLaunchKernelGGL((k_bp_tile<T, JM_, HN_>), grid, dim3(BP_NT), lds, s, pf, dst, N, p->n, p->M + 2 * p->K, \
-                       p->K, groups, geo_, ints_, brk_, coef_, p->bp.smax, p->bp.J, p->bp.D1, rmax, ch)
-            // Horner length: the kernel degree + 1 rounded up to 4, 6 or 8
-            const int hn = p->bp.D1 <= 4 ? 4 : (p->bp.D1 <= 6 ? 6 : 8);
-            if (p->bp.J <= 8) {
-                if (hn == 4) GCT_BP_TILE(8, 4);
-                else if (hn == 6) GCT_BP_TILE(8, 6);
-                else GCT_BP_TILE(8, 8);
-            } else {
-                if (hn == 4) GCT_BP_TILE(16, 4);
-                else if (hn == 6) GCT_BP_TILE(16, 6);
-                else GCT_BP_TILE(16, 8);
-            }
+            hipLaunchKernelGGL(k_bp_etab<T>, dim3((unsigned)((MT * smax + 255) / 256), (unsigned)p->n), dim3(256),
+                               bp_etab_lds(p, sizeof(T)), s, pf, etab, p->M + 2 * p->K, p->K, MT, ints_, coef_,
+                               smax, p->bp.J, p->bp.D1);
+            const dim3 grid((N + BP_TX - 1) / BP_TX, (N + BP_TY - 1) / BP_TY, groups);
+            T *dst = groups > 1 ? part : b;
+            const size_t lds = bp_tile_lds(p, sizeof(T), ch);
+#define GCT_BP_TILE(HN_)                                                                                      \
+    hipLaunchKernelGGL((k_bp_tile<T, HN_>), grid, dim3(BP_NT), lds, s, (const T *)etab, dst, N, p->n, MT, groups, \
+                       geo_, ints_, brk_, smax, rmax, ch)
+            const int hn = bp_hn(p);
+            if (hn == 4) GCT_BP_TILE(4);
+            else if (hn == 6) GCT_BP_TILE(6);
+            else GCT_BP_TILE(8);
 #undef GCT_BP_TILE
             if (groups > 1) {
                 const size_t len = (size_t)N * N;
@@ -685,8 +686,9 @@ hipError_t launch_forward(const gct_plan *p, const T *c, T *g, hipStream_t s)
 
 template hipError_t launch_prefilter<float>(const gct_plan *, const float *, float *, hipStream_t);
 template hipError_t launch_prefilter<double>(const gct_plan *, const double *, double *, hipStream_t);
-template hipError_t launch_backproject<float>(const gct_plan *, const float *, float *, float *, hipStream_t);
-template hipError_t launch_backproject<double>(const gct_plan *, const double *, double *, double *,
+template hipError_t launch_backproject<float>(const gct_plan *, const float *, float *, float *, float *,
+                                              hipStream_t);
+template hipError_t launch_backproject<double>(const gct_plan *, const double *, double *, double *, double *,
                                                hipStream_t);
 template hipError_t launch_forward<float>(const gct_plan *, const float *, float *, hipStream_t);
 template hipError_t launch_forward<double>(const gct_plan *, const double *, double *, hipStream_t);

@@ -69,11 +69,13 @@ struct BPDims {
     int32_t D1;     // polynomial coefficients per weight (degree + 1)
     double span_per_pixel;  // max over angles of (l1|c| + l2|s|) / lambda_y: bins per pixel step
     double tile_win;        // max over angles of (BP_TX-1)|dz1| + (BP_TY-1)|dz2|: bins a tile spans
+    int32_t MT;             // bin rows of the per-angle interpolant tables (every tile window)
 };
 
 // Pixel tile of the back-projection kernel (columns x rows), its threads
-// per block and the minimum resident waves per SIMD it is compiled for.
-constexpr int BP_TX = 64, BP_TY = 32, BP_NT = 256, BP_WAVES = 5;
+// per block, the minimum resident waves per SIMD it is compiled for, and the
+// angles whose bin windows it computes at once.
+constexpr int BP_TX = 64, BP_TY = 32, BP_NT = 256, BP_WAVES = 5, BP_WB = 64;
 // Gram build: taps per tile side (one block of 4 waves per tile): batched
 // builds 16, the single-slice build 8 with the block's waves splitting the
 // angles
@@ -208,8 +210,15 @@ template <typename T>
 hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s);
 
 template <typename T>
-hipError_t launch_backproject(const gct_plan *p, const T *prefiltered, T *b, T *partial, hipStream_t s);
+hipError_t launch_backproject(const gct_plan *p, const T *prefiltered, T *b, T *partial, T *etab, hipStream_t s);
 int bp_angle_groups(const gct_plan *p, size_t elem);
+// Back-projection workspace: the prefiltered sinogram at offset 0, then (the
+// tiled kernel) the per-angle interpolant tables at `etab`, then (several
+// angle groups) one partial image per group at `part`; byte offsets.
+struct BPWorkspace {
+    size_t etab, part, total;
+};
+BPWorkspace bp_workspace(const gct_plan *p, size_t elem);
 // Tile side of the per-angle back-projection kernel (taken when the tiled
 // kernel's tables do not fit, bp_ch == 0), or 0 when its LDS does not fit.
 int bp_fallback_tile(const gct_plan *p, size_t elem);

@@ -457,6 +457,24 @@ static int build_plan(const gct_geometry *g, const Detector &det, gct_plan *p)
                         t.coef[((size_t)s * t.J + j) * t.D1 + q];
         }
     }
+    // rows of the back projection's per-angle interpolant tables: every bin
+    // window of the tile grid (ragged tiles included: the grid's extent),
+    // from two bins below the lowest projection to three above the highest;
+    // the first row's bin per angle in ints[4 a + 3]
+    {
+        const double X1 = (double)(BP_TX * ((g->N + BP_TX - 1) / BP_TX) - 1);
+        const double X2 = (double)(BP_TY * ((g->N + BP_TY - 1) / BP_TY) - 1);
+        int MT = 1;
+        for (int a = 0; a < n; ++a) {
+            const double z0 = geo[4 * a], e1 = X1 * geo[4 * a + 1], e2 = X2 * geo[4 * a + 2];
+            const double zmin = z0 + std::min(e1, 0.0) + std::min(e2, 0.0);
+            const double zmax = z0 + std::max(e1, 0.0) + std::max(e2, 0.0);
+            const int mA = (int)std::floor(zmin) - 2;
+            ints[4 * a + 3] = mA;
+            MT = std::max(MT, (int)std::floor(zmax) + 3 - mA);
+        }
+        p->bp.MT = MT;
+    }
     // FFT twiddles e^{-2 pi i k / P}
     std::vector<double> tw((size_t)p->P);  // interleaved (re, im), P/2 entries
     for (int k = 0; k < p->P / 2; ++k) {
@@ -674,12 +692,7 @@ size_t gct_workspace_size(const gct_plan *p, int op, gct_dtype dt)
     switch (op) {
     case GCT_OP_GRAM_SPECTRUM: return spectrum_ws_bytes(p, e);
     case GCT_OP_GRAM_APPLY: return apply_ws_bytes(p, e);
-    case GCT_OP_BACKPROJECT: {
-        // prefiltered sinogram, then one partial image per angle group
-        const int g = bp_angle_groups(p, e);
-        return align256((size_t)p->n * (p->M + 2 * p->K) * e) +
-               (g > 1 ? align256((size_t)g * p->N * p->N * e) : 0);
-    }
+    case GCT_OP_BACKPROJECT: return bp_workspace(p, e).total;
     case GCT_OP_CG: return cg_ws_bytes(p, e);
     default: return 0;
     }
@@ -750,15 +763,16 @@ int gct_backproject_boxspline(const gct_plan *p, gct_dtype dt, const void *g_s, 
     if (misaligned(ws)) return fail(GCT_EINVAL, "workspace must be 256-byte aligned");
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     hipError_t e;
-    const size_t esz = dt == GCT_F32 ? 4 : 8;
-    void *part = reinterpret_cast<char *>(ws) + align256((size_t)p->n * (p->M + 2 * p->K) * esz);
+    const BPWorkspace W = bp_workspace(p, dt == GCT_F32 ? 4 : 8);
+    void *part = reinterpret_cast<char *>(ws) + W.part, *etab = reinterpret_cast<char *>(ws) + W.etab;
     if (dt == GCT_F32) {
         e = launch_prefilter<float>(p, (const float *)g_s, (float *)ws, s);
-        if (e == hipSuccess) e = launch_backproject<float>(p, (const float *)ws, (float *)b, (float *)part, s);
+        if (e == hipSuccess)
+            e = launch_backproject<float>(p, (const float *)ws, (float *)b, (float *)part, (float *)etab, s);
     } else {
         e = launch_prefilter<double>(p, (const double *)g_s, (double *)ws, s);
         if (e == hipSuccess)
-            e = launch_backproject<double>(p, (const double *)ws, (double *)b, (double *)part, s);
+            e = launch_backproject<double>(p, (const double *)ws, (double *)b, (double *)part, (double *)etab, s);
     }
     return check_hip(e, "backproject launch");
 }

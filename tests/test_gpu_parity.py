@@ -333,7 +333,7 @@ def _bins(N, zeta, ly):
 
 
 # Fine detector sampling (lambda_y < lambda_x, Sec. 6 sampling-rate sweep):
-# the tiled kernel's per-(tile, angle) tables outgrow its 64 KB of LDS (FP64
+# a tile window's table rows outgrow the tiled kernel's 64 KB of LDS (FP64
 # at lambda_y = 0.25; FP32 at 0.125 without blur) or its 16-tap limit (FP32
 # at 0.125 with blur), so the per-angle kernel runs (tile side 16 or 32).
 PER_ANGLE = [(Case(48, 30, M=_bins(48, 1.0, 0.25), zeta=1.0, ly=0.25), torch.float64),

@@ -569,6 +569,13 @@ struct gct_batch {
     std::vector<CGGraph> graphs;
     hipStream_t capture_stream = nullptr;
     int64_t dev_bytes = 0;  // bytes of the block maps and slice descriptors
+    // Concurrent transform groups: the apply passes of the costliest group
+    // run on the caller's stream, those of the others on `side`, forked and
+    // joined through events (each group's three passes touch only its own
+    // slices, so the chains are independent).
+    int main_group = 0;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -588,6 +595,9 @@ void free_batch(gct_batch *b)
     for (auto &g : b->graphs) (void)hipGraphExecDestroy(g.exec);
     b->graphs.clear();
     if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+    if (b->ev_join) (void)hipEventDestroy(b->ev_join);
     for (auto &g : b->groups) {
         for (int2 *m : {g.rows, g.cols, g.srows, g.scols, g.rows2})
             if (m) (void)hipFree(m);
@@ -628,6 +638,50 @@ BLayout blayout(const gct_batch *b, size_t elem)
 template <typename T>
 int dti() { return sizeof(T) == 4 ? 0 : 1; }
 
+// The side stream and its events (default priority; made with the batch).
+hipError_t batch_side(const gct_batch *b)
+{
+    gct_batch *mb = const_cast<gct_batch *>(b);
+    hipError_t e = hipSuccess;
+    if (!mb->side) e = hipStreamCreateWithFlags(&mb->side, hipStreamNonBlocking);
+    if (e == hipSuccess && !mb->ev_fork) e = hipEventCreateWithFlags(&mb->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess && !mb->ev_join) e = hipEventCreateWithFlags(&mb->ev_join, hipEventDisableTiming);
+    return e;
+}
+
+// The three passes of one transform group on stream s.
+template <typename T>
+void group_passes(const gct_batch *b, const BatchGroup &g, const T *Ghat, const T *src, T *y, C2<T> *W1, C2<T> *W2,
+                  hipStream_t s, const CGState *st, T *pupd, const T *dotv, double *partial)
+{
+    const BatchSlice *sl = b->dev[dti<T>()];
+    const int E = g.E[dti<T>()], Ec = g.Ec[dti<T>()];
+    const size_t lds = fft_lds_bytes<T>(1 << g.logP, E), ldsc = fft_lds_bytes<T>(1 << g.logP, Ec);
+    auto rows_fwd = [&]() {
+        if constexpr (sizeof(T) == 4) {
+            if (g.nrows2) {
+                GCT_LAUNCH_B2(kb_rows_fwd2, T, g.logP, E, dim3(g.nrows2), rows2_lds_bytes<T>(1 << g.logP, false), s,
+                              g.rows2, sl, src, W1, st, pupd);
+                return;
+            }
+        }
+        GCT_LAUNCH_B(kb_rows_fwd, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, src, W1, st, pupd);
+    };
+    auto rows_inv = [&]() {
+        if constexpr (sizeof(T) == 4) {
+            if (g.nrows2) {
+                GCT_LAUNCH_B2(kb_rows_inv2, T, g.logP, E, dim3(g.nrows2), rows2_lds_bytes<T>(1 << g.logP, true), s,
+                              g.rows2, sl, W2, y, st, dotv, partial);
+                return;
+            }
+        }
+        GCT_LAUNCH_B(kb_rows_inv, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, W2, y, st, dotv, partial);
+    };
+    rows_fwd();
+    GCT_LAUNCH_B(kb_cols, T, g.logP, Ec, dim3(g.ncols), ldsc, s, g.cols, sl, W1, W2, Ghat, st);
+    rows_inv();
+}
+
 template <typename T>
 hipError_t batch_apply_passes(const gct_batch *b, const T *Ghat, const T *src, T *y, void *ws,
                               hipStream_t s, const CGState *st, T *pupd, const T *dotv,
@@ -636,38 +690,22 @@ hipError_t batch_apply_passes(const gct_batch *b, const T *Ghat, const T *src, T
     const BLayout L = blayout(b, sizeof(T));
     char *w = reinterpret_cast<char *>(ws);
     C2<T> *W1 = reinterpret_cast<C2<T> *>(w + L.W1), *W2 = reinterpret_cast<C2<T> *>(w + L.W2);
-    const BatchSlice *sl = b->dev[dti<T>()];
-    for (const auto &g : b->groups) {
-        const int E = g.E[dti<T>()];
-        if constexpr (sizeof(T) == 4) {
-            if (g.nrows2) {
-                GCT_LAUNCH_B2(kb_rows_fwd2, T, g.logP, E, dim3(g.nrows2), rows2_lds_bytes<T>(1 << g.logP, false), s,
-                              g.rows2, sl, src, W1, st, pupd);
-                continue;
-            }
-        }
-        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
-        GCT_LAUNCH_B(kb_rows_fwd, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, src, W1, st, pupd);
+    const int ng = (int)b->groups.size();
+    if (ng == 1) {
+        group_passes<T>(b, b->groups[0], Ghat, src, y, W1, W2, s, st, pupd, dotv, partial);
+        return hipGetLastError();
     }
-    for (const auto &g : b->groups) {
-        const int E = g.Ec[dti<T>()];
-        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
-        GCT_LAUNCH_B(kb_cols, T, g.logP, E, dim3(g.ncols), lds, s, g.cols, sl, W1, W2, Ghat, st);
-    }
-    for (const auto &g : b->groups) {
-        const int E = g.E[dti<T>()];
-        if constexpr (sizeof(T) == 4) {
-            if (g.nrows2) {
-                GCT_LAUNCH_B2(kb_rows_inv2, T, g.logP, E, dim3(g.nrows2), rows2_lds_bytes<T>(1 << g.logP, true), s,
-                              g.rows2, sl, W2, y, st, dotv, partial);
-                continue;
-            }
-        }
-        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
-        GCT_LAUNCH_B(kb_rows_inv, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, W2, y, st, dotv,
-                     partial);
-    }
-    return hipGetLastError();
+    if (!b->side || !b->ev_fork || !b->ev_join) return hipErrorInvalidResourceHandle;
+    hipError_t e = hipEventRecord(b->ev_fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->side, b->ev_fork, 0);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < ng; ++i)
+        if (i != b->main_group) group_passes<T>(b, b->groups[i], Ghat, src, y, W1, W2, b->side, st, pupd, dotv, partial);
+    group_passes<T>(b, b->groups[b->main_group], Ghat, src, y, W1, W2, s, st, pupd, dotv, partial);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(b->ev_join, b->side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_join, 0);
+    return e;
 }
 
 template <typename T>
@@ -913,6 +951,25 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         if (rc) {
             free_batch(b);
             return rc;
+        }
+    }
+    // the costliest transform group (slices x P^2 log2 P) runs on the caller's stream
+    {
+        double best = -1.0;
+        for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
+            const double P = (double)(1 << b->groups[gi].logP);
+            const double cost = (double)b->groups[gi].ncols / (P / 2 + 1) * P * P * b->groups[gi].logP;
+            if (cost > best) {
+                best = cost;
+                b->main_group = gi;
+            }
+        }
+    }
+    if (b->groups.size() > 1) {  // side stream and events made here, never during a capture
+        const hipError_t e = batch_side(b);
+        if (e != hipSuccess) {
+            free_batch(b);
+            return check_hip(e, "batch side stream");
         }
     }
     std::vector<int2> gm;

@@ -88,7 +88,8 @@ typedef struct gct_plan gct_plan;
 /* Sizes (in elements) of the arrays a plan works on. */
 typedef struct {
     int32_t N, n_angles, M, prefilter_K;
-    int32_t fft_size;        /* P: power of two >= 2N-1 used for the circulant embedding */
+    int32_t fft_size;        /* P >= 2N-1 of the circulant embedding: the smallest power of two,
+                                or three times a power of two (1536, 3072) where that is smaller */
     int64_t gram_elems;      /* (2N-1)^2 */
     int64_t spectrum_elems;  /* (P/2+1) * P, real */
     int64_t image_elems;     /* N^2 */

@@ -35,7 +35,7 @@ __device__ __forceinline__ bool slice_halted(const CGState *st, int s)
 // ---------------------------------------------------------------------------
 // Batched transform passes
 // ---------------------------------------------------------------------------
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 kb_rows_fwd(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
             const T *__restrict__ src, C2<T> *__restrict__ W1, const CGState *st, T *pupd)
@@ -43,17 +43,17 @@ kb_rows_fwd(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
     if (slice_halted(st, m.x)) return;
     const BatchSlice &d = sl[m.x];
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     // data first, then the twiddles: their latencies overlap
     C2<T> v[E];
-    rows_fwd_load<T, LOGP, E>(2 * m.y, src + d.img, d.N, pupd ? pupd + d.img : nullptr,
+    rows_fwd_load<T, PC, E>(2 * m.y, src + d.img, d.N, pupd ? pupd + d.img : nullptr,
                               pupd ? (T)st[m.x].beta : T(0), v);
     const C2<T> *tws =
         stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
-    rows_fwd_regs<T, LOGP, E>(2 * m.y, v, W1 + d.w, d.N, x, tws);
+    rows_fwd_regs<T, PC, E>(2 * m.y, v, W1 + d.w, d.N, x, tws);
 }
 
 // Two row pairs per block (rows 4j .. 4j+3 of a slice), for the long
@@ -63,12 +63,12 @@ kb_rows_fwd(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
 // run per block instead of two 16-byte ones (the transposed scratch is
 // written a few bytes per cache line; fewer, larger requests move it
 // faster).  FP32 with even N (paired 16-byte accesses).
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(512)
 kb_rows_fwd2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
              const T *__restrict__ src, C2<T> *__restrict__ W1, const CGState *st, T *pupd)
 {
-    constexpr int P = 1 << LOGP, hP = P / 2, G = P / E;
+    constexpr int P = fft_size(PC), hP = P / 2, G = P / E;
     const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
     if (slice_halted(st, m.x)) return;
     const BatchSlice &d = sl[m.x];
@@ -114,7 +114,7 @@ kb_rows_fwd2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
         const int k = i >> 1, g2 = i & 1, r0 = 4 * m.y + 2 * g2;
         if (r0 >= N) continue;
         const C2<T> *xg = xs + g2 * P;
-        const C2<T> Zk = xg[k], Zm = xg[(P - k) & (P - 1)];
+        const C2<T> Zk = xg[k], Zm = xg[(P - k) % P];
         const C2<T> a = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
         const C2<T> b = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
         store_pair(out + (size_t)k * N + r0, a, b);
@@ -125,13 +125,13 @@ kb_rows_fwd2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
 // spectra column by column (32-byte runs, pair fastest) into LDS, then each
 // group transforms its pair as the single-pair inverse row pass; FP64 partial dot of the block
 // in the slot of its first pair (the second pair's slot holds 0).
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(512)
 kb_rows_inv2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
              const C2<T> *__restrict__ W2, T *__restrict__ y, const CGState *st,
              const T *__restrict__ dotv, double *__restrict__ partial)
 {
-    constexpr int P = 1 << LOGP, hP = P / 2, G = P / E, XS = P + 2;  // per-group area (spectra + 2)
+    constexpr int P = fft_size(PC), hP = P / 2, G = P / E, XS = P + 2;  // per-group area (spectra + 2)
     const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
     if (slice_halted(st, m.x)) return;
     const BatchSlice &d = sl[m.x];
@@ -193,7 +193,7 @@ kb_rows_inv2(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     }
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 kb_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
         const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat,
@@ -202,19 +202,19 @@ kb_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     const int2 m = map[blockIdx.x];
     if (slice_halted(st, m.x)) return;
     const BatchSlice &d = sl[m.x];
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     C2<T> v[E];
     T gs[E];
-    cols_load<T, LOGP, E>(m.y, W1 + d.w, Ghat + d.spec, d.N, v, gs);
+    cols_load<T, PC, E>(m.y, W1 + d.w, Ghat + d.spec, d.N, v, gs);
     const C2<T> *tws =
         stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
-    cols_regs<T, LOGP, E>(m.y, v, gs, W2 + d.w, d.N, x, tws);
+    cols_regs<T, PC, E>(m.y, v, gs, W2 + d.w, d.N, x, tws);
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 kb_rows_inv(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
             const C2<T> *__restrict__ W2, T *__restrict__ y, const CGState *st,
@@ -223,53 +223,53 @@ kb_rows_inv(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
     const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
     if (slice_halted(st, m.x)) return;
     const BatchSlice &d = sl[m.x];
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     C2<T> v[E];
-    rows_inv_load<T, LOGP, E>(2 * m.y, W2 + d.w, d.N, v);
+    rows_inv_load<T, PC, E>(2 * m.y, W2 + d.w, d.N, v);
     const C2<T> *tws =
         stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     fft_passes<T, E, P, 1, true, true>(v, x, threadIdx.x, tws);
-    const double acc = rows_inv_store<T, LOGP, E>(2 * m.y, v, y + d.img, d.N, dotv ? dotv + d.img : nullptr);
+    const double acc = rows_inv_store<T, PC, E>(2 * m.y, v, y + d.img, d.N, dotv ? dotv + d.img : nullptr);
     if (partial) {
         const double s = block_sum_lds(acc, reinterpret_cast<double *>(smem_raw));
         if (threadIdx.x == 0) partial[d.rpart + m.y] = s;
     }
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 kb_spec_rows(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
              const T *__restrict__ G, C2<T> *__restrict__ R)
 {
     const int2 m = map[xcd_swizzle(blockIdx.x, gridDim.x)];
     const BatchSlice &d = sl[m.x];
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws =
         stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
     // R of a slice uses (P/2+1) P complex, i.e. 2 d.spec reals' worth of offset
-    body_spec_rows<T, LOGP, E>(m.y, G + d.gram, R + d.spec, d.N, x, tws);
+    body_spec_rows<T, PC, E>(m.y, G + d.gram, R + d.spec, d.N, x, tws);
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 kb_spec_cols(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl,
              const C2<T> *__restrict__ R, T *__restrict__ Ghat)
 {
     const int2 m = map[blockIdx.x];
     const BatchSlice &d = sl[m.x];
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws =
         stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), reinterpret_cast<const C2<T> *>(d.tw));
     __syncthreads();
-    body_spec_cols<T, LOGP, E>(m.y, R + d.spec, Ghat + d.spec, x, tws,
+    body_spec_cols<T, PC, E>(m.y, R + d.spec, Ghat + d.spec, x, tws,
                                T(1.0 / ((double)P * (double)P)));
 }
 
@@ -482,22 +482,24 @@ __global__ void __launch_bounds__(256) kb_resid_fin(CGState *st, const double *p
 }
 
 // ---------------------------------------------------------------------------
-// Dispatch on (log2 P, E).  E candidates: fft_elems(P) and, for P >= 512,
-// fft_elems(P) / 2 (except P = 4096, which needs 16 at 256 threads).
+// Dispatch on (size code, E).  E candidates: fft_elems(P) and, for P = 2^k
+// >= 512, fft_elems(P) / 2 (except P = 4096, which needs 16 at 256
+// threads); for P = 3 * 2^k (1536, 3072), 24 and 12.
 // ---------------------------------------------------------------------------
-static bool e_ok(int logP, int E)
+static bool e_ok(int pc, int E)
 {
-    const int P = 1 << logP, E0 = fft_elems(P);
+    const int P = fft_size(pc), E0 = fft_elems(P);
     if (E == E0) return true;
+    if (P % 3 == 0) return (E == 12 || E == 24) && P / E <= 256;
     return P >= 512 && P <= 2048 && E == E0 / 2;
 }
 
 #define GCT_BCASE(kern, T, LG, E, grid, lds, s, ...) \
-    hipLaunchKernelGGL((kern<T, LG, E>), grid, dim3((1 << LG) / E), lds, s, __VA_ARGS__)
+    hipLaunchKernelGGL((kern<T, LG, E>), grid, dim3(fft_size(LG) / E), lds, s, __VA_ARGS__)
 
-#define GCT_LAUNCH_B(kern, T, logP, E, grid, lds, s, ...)                                         \
+#define GCT_LAUNCH_B(kern, T, pc, E, grid, lds, s, ...)                                         \
     do {                                                                                         \
-        switch (logP) {                                                                          \
+        switch (pc) {                                                                          \
         case 2: GCT_BCASE(kern, T, 2, 4, grid, lds, s, __VA_ARGS__); break;                      \
         case 3: GCT_BCASE(kern, T, 3, 4, grid, lds, s, __VA_ARGS__); break;                      \
         case 4: GCT_BCASE(kern, T, 4, 4, grid, lds, s, __VA_ARGS__); break;                      \
@@ -517,7 +519,8 @@ static bool e_ok(int logP, int E)
             if (E == 16) GCT_BCASE(kern, T, 11, 16, grid, lds, s, __VA_ARGS__);                  \
             else GCT_BCASE(kern, T, 11, 8, grid, lds, s, __VA_ARGS__);                           \
             break;                                                                               \
-        default: GCT_BCASE(kern, T, 12, 16, grid, lds, s, __VA_ARGS__); break;                   \
+        case 12: GCT_BCASE(kern, T, 12, 16, grid, lds, s, __VA_ARGS__); break;                   \
+        GCT_MIXED_CASES(GCT_BCASE, kern, T, E, grid, lds, s, __VA_ARGS__)                        \
         }                                                                                        \
     } while (0)
 
@@ -529,7 +532,7 @@ using namespace gct;
 // Host batch object
 // ---------------------------------------------------------------------------
 struct BatchGroup {
-    int logP;
+    int pc;
     int E[2];   // tuned elements per thread of the row passes, [f32, f64]
     int Ec[2];  // and of the column pass
     int2 *rows = nullptr, *cols = nullptr, *srows = nullptr, *scols = nullptr;
@@ -549,10 +552,10 @@ inline size_t rows2_lds_bytes(int P, bool inv)
     return b > 512 * sizeof(double) ? b : 512 * sizeof(double);
 }
 
-#define GCT_LAUNCH_B2(kern, T, logP, E, grid, lds, s, ...)                                               \
+#define GCT_LAUNCH_B2(kern, T, pc, E, grid, lds, s, ...)                                               \
     do {                                                                                                \
-        if (logP == 10 && E == 16) hipLaunchKernelGGL((kern<T, 10, 16>), grid, dim3(128), lds, s, __VA_ARGS__); \
-        else if (logP == 10) hipLaunchKernelGGL((kern<T, 10, 8>), grid, dim3(256), lds, s, __VA_ARGS__);    \
+        if (pc == 10 && E == 16) hipLaunchKernelGGL((kern<T, 10, 16>), grid, dim3(128), lds, s, __VA_ARGS__); \
+        else if (pc == 10) hipLaunchKernelGGL((kern<T, 10, 8>), grid, dim3(256), lds, s, __VA_ARGS__);    \
         else if (E == 16) hipLaunchKernelGGL((kern<T, 11, 16>), grid, dim3(256), lds, s, __VA_ARGS__);      \
         else hipLaunchKernelGGL((kern<T, 11, 8>), grid, dim3(512), lds, s, __VA_ARGS__);                    \
     } while (0)
@@ -656,29 +659,29 @@ void group_passes(const gct_batch *b, const BatchGroup &g, const T *Ghat, const 
 {
     const BatchSlice *sl = b->dev[dti<T>()];
     const int E = g.E[dti<T>()], Ec = g.Ec[dti<T>()];
-    const size_t lds = fft_lds_bytes<T>(1 << g.logP, E), ldsc = fft_lds_bytes<T>(1 << g.logP, Ec);
+    const size_t lds = fft_lds_bytes<T>(fft_size(g.pc), E), ldsc = fft_lds_bytes<T>(fft_size(g.pc), Ec);
     auto rows_fwd = [&]() {
         if constexpr (sizeof(T) == 4) {
             if (g.nrows2) {
-                GCT_LAUNCH_B2(kb_rows_fwd2, T, g.logP, E, dim3(g.nrows2), rows2_lds_bytes<T>(1 << g.logP, false), s,
+                GCT_LAUNCH_B2(kb_rows_fwd2, T, g.pc, E, dim3(g.nrows2), rows2_lds_bytes<T>(fft_size(g.pc), false), s,
                               g.rows2, sl, src, W1, st, pupd);
                 return;
             }
         }
-        GCT_LAUNCH_B(kb_rows_fwd, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, src, W1, st, pupd);
+        GCT_LAUNCH_B(kb_rows_fwd, T, g.pc, E, dim3(g.nrows), lds, s, g.rows, sl, src, W1, st, pupd);
     };
     auto rows_inv = [&]() {
         if constexpr (sizeof(T) == 4) {
             if (g.nrows2) {
-                GCT_LAUNCH_B2(kb_rows_inv2, T, g.logP, E, dim3(g.nrows2), rows2_lds_bytes<T>(1 << g.logP, true), s,
+                GCT_LAUNCH_B2(kb_rows_inv2, T, g.pc, E, dim3(g.nrows2), rows2_lds_bytes<T>(fft_size(g.pc), true), s,
                               g.rows2, sl, W2, y, st, dotv, partial);
                 return;
             }
         }
-        GCT_LAUNCH_B(kb_rows_inv, T, g.logP, E, dim3(g.nrows), lds, s, g.rows, sl, W2, y, st, dotv, partial);
+        GCT_LAUNCH_B(kb_rows_inv, T, g.pc, E, dim3(g.nrows), lds, s, g.rows, sl, W2, y, st, dotv, partial);
     };
     rows_fwd();
-    GCT_LAUNCH_B(kb_cols, T, g.logP, Ec, dim3(g.ncols), ldsc, s, g.cols, sl, W1, W2, Ghat, st);
+    GCT_LAUNCH_B(kb_cols, T, g.pc, Ec, dim3(g.ncols), ldsc, s, g.cols, sl, W1, W2, Ghat, st);
     rows_inv();
 }
 
@@ -716,13 +719,13 @@ hipError_t batch_spectrum(const gct_batch *b, const T *G, T *Ghat, void *ws, hip
     const BatchSlice *sl = b->dev[dti<T>()];
     for (const auto &g : b->groups) {
         const int E = g.E[dti<T>()];
-        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
-        GCT_LAUNCH_B(kb_spec_rows, T, g.logP, E, dim3(g.nsrows), lds, s, g.srows, sl, G, R);
+        const size_t lds = fft_lds_bytes<T>(fft_size(g.pc), E);
+        GCT_LAUNCH_B(kb_spec_rows, T, g.pc, E, dim3(g.nsrows), lds, s, g.srows, sl, G, R);
     }
     for (const auto &g : b->groups) {
         const int E = g.E[dti<T>()];
-        const size_t lds = fft_lds_bytes<T>(1 << g.logP, E);
-        GCT_LAUNCH_B(kb_spec_cols, T, g.logP, E, dim3(g.nscols), lds, s, g.scols, sl, R, Ghat);
+        const size_t lds = fft_lds_bytes<T>(fft_size(g.pc), E);
+        GCT_LAUNCH_B(kb_spec_cols, T, g.pc, E, dim3(g.nscols), lds, s, g.scols, sl, R, Ghat);
     }
     return hipGetLastError();
 }
@@ -880,7 +883,7 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         const gct_plan *p = plans[i];
         BatchSlice d{};
         d.N = p->N;
-        d.logP = p->logP;
+        d.pc = p->pc;
         d.n = p->gram_n;  // Gram-filter table entries
         d.nrow = (p->N + 1) / 2;
         d.img = b->img_total;
@@ -894,7 +897,7 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
         d.rpart = b->rpart_total;
         b->rpart_total += d.nrow;
         b->host[i] = d;
-        by_p[p->logP].push_back(i);
+        by_p[p->pc].push_back(i);
     }
     // descriptors with the f32 and f64 tables of each plan
     for (int t = 0; t < 2; ++t) {
@@ -920,11 +923,11 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
     // block maps per FFT size
     for (auto &kv : by_p) {
         BatchGroup g;
-        g.logP = kv.first;
-        const int P = 1 << g.logP;
+        g.pc = kv.first;
+        const int P = fft_size(g.pc);
         g.E[0] = g.E[1] = g.Ec[0] = g.Ec[1] = fft_elems(P);
         std::vector<int2> rows, cols, srows, scols, rows2;
-        bool pair2 = g.logP == 10 || g.logP == 11;
+        bool pair2 = g.pc == 10 || g.pc == 11;
         for (int i : kv.second) {
             const int N = plans[i]->N;
             pair2 = pair2 && N % 2 == 0 && b->host[i].w % 2 == 0;
@@ -957,8 +960,8 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
     {
         double best = -1.0;
         for (int gi = 0; gi < (int)b->groups.size(); ++gi) {
-            const double P = (double)(1 << b->groups[gi].logP);
-            const double cost = (double)b->groups[gi].ncols / (P / 2 + 1) * P * P * b->groups[gi].logP;
+            const double P = (double)fft_size(b->groups[gi].pc);
+            const double cost = (double)b->groups[gi].ncols / (P / 2 + 1) * P * P * std::log2(P);
             if (cost > best) {
                 best = cost;
                 b->main_group = gi;
@@ -1145,12 +1148,12 @@ int gct_batch_autotune(gct_batch *b, gct_dtype dt, const void *Ghat, void *ws, i
     for (int q = 0; q < 2 * (int)b->groups.size() && err == hipSuccess; ++q) {
         BatchGroup &g = b->groups[q / 2];
         int &Eq = q % 2 == 0 ? g.E[t] : g.Ec[t];
-        const int P = 1 << g.logP, E0 = fft_elems(P);
+        const int P = fft_size(g.pc), E0 = fft_elems(P);
         const int before = Eq;
         int best = Eq;
         float best_ms = 1e30f;
         for (int E : {E0, E0 / 2}) {
-            if (E < 4 || !e_ok(g.logP, E)) continue;
+            if (E < 4 || !e_ok(g.pc, E)) continue;
             Eq = E;
             for (int rep = 0; rep <= reps && err == hipSuccess; ++rep) {
                 if (rep == 1) err = hipEventRecord(e0, s);

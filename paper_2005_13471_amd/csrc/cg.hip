@@ -522,11 +522,14 @@ int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chose
         if (ge) (void)hipGraphExecDestroy(ge);
         return best;
     };
+    // candidate elements per thread: 16, 8, 4 (powers of two), 24, 12 (three times a power of two)
+    const int c3 = p->P % 3 == 0;
+    auto cand = [c3](int i) { return c3 ? (i == 0 ? 24 : (i == 1 ? 12 : 0)) : 16 >> i; };
     int best = p->fft_e[t], best_c = p->fft_ec[t];
     float best_ms = 1e30f;
     for (int pr = 0; pr < 9 && err == hipSuccess; ++pr) {
-        const int E = 16 >> (pr / 3), Ec = 16 >> (pr % 3);
-        if (!apply_e_ok(p->logP, E) || !apply_e_ok(p->logP, Ec)) continue;
+        const int E = cand(pr / 3), Ec = cand(pr % 3);
+        if (!apply_e_ok(p->pc, E) || !apply_e_ok(p->pc, Ec)) continue;
         p->fft_e[t] = E;
         p->fft_ec[t] = Ec;
         const float ms = time_graph(
@@ -552,8 +555,8 @@ int plan_autotune(gct_plan *p, const T *Ghat, void *ws, int reps, int32_t *chose
     int best_cg = p->cg_e[t], best_cgc = p->cg_ec[t];
     float best_cg_ms = 1e30f;
     for (int pr = 0; pr < 9 && err == hipSuccess; ++pr) {
-        const int E = 16 >> (pr / 3), Ec = 16 >> (pr % 3);
-        if (!apply_e_ok(p->logP, E) || !apply_e_ok(p->logP, Ec)) continue;
+        const int E = cand(pr / 3), Ec = cand(pr % 3);
+        if (!apply_e_ok(p->pc, E) || !apply_e_ok(p->pc, Ec)) continue;
         p->cg_e[t] = E;
         p->cg_ec[t] = Ec;
         const float ms = time_graph(

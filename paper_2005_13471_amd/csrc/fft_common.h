@@ -1,18 +1,21 @@
-// Group-level FFTs for the Gram-filter kernels: register-blocked Stockham.
+// Group-level FFTs for the Gram-filtering kernels: register-blocked Stockham.
 //
-// A length-P transform (P = 2^logP) is owned by G = P/E threads; thread t
-// holds E elements in registers in the strided layout v[q] = x[t + G q],
-// q < E.  The transform runs as Stockham autosort passes of radix R (E, E,
-// ..., then the remaining factor), each thread computing E/R radix-R
-// butterflies per pass in registers.  The first pass reads the registers
-// directly (its butterfly inputs are exactly x[t + G r]); the last pass
-// leaves its outputs in registers in the same strided layout; only the
-// passes in between exchange through LDS.  So input and output need no
-// permutation, a forward and an inverse transform can be chained in
-// registers, and loads/stores of x[t + G q] are coalesced across a wave.
+// Transform lengths P = 2^k or 3 * 2^k.  A length-P transform is owned by
+// G = P/E threads; thread t holds E elements in registers in the strided
+// layout v[q] = x[t + G q], q < E.  The transform runs as Stockham autosort
+// passes: the first of radix E, then each of radix gcd(E, remaining length)
+// (so every radix divides E), each thread computing E/R radix-R butterflies
+// per pass in registers.  The first pass reads the registers directly (its
+// butterfly inputs are exactly x[t + G r]); the last pass leaves its outputs
+// in registers in the same strided layout; only the passes in between
+// exchange through LDS.  So input and output need no permutation, a forward
+// and an inverse transform can be chained in registers, and loads/stores of
+// x[t + G q] are coalesced across a wave.
 //
 // E = 16 for P >= 1024 (one wave per 1024-point transform: passes 16, 16,
-// 4), E = 8 for P = 512, E = 4 for P <= 256.
+// 4), E = 8 for P = 512, E = 4 for P <= 256; for P = 3 * 2^k (1536 and 3072
+// points) E = 24 (1536 points: passes 24, 8, 8) or 12, the radix-3 factor
+// in the first pass.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -23,6 +26,29 @@ template <typename T>
 struct C2 {
     T x, y;
 };
+
+// Transform length of a size code: 2^c for c < 32, 3 * 2^(c - 32) above.
+__host__ __device__ constexpr int fft_size(int code) { return code < 32 ? 1 << code : 3 << (code - 32); }
+
+constexpr int cgcd(int a, int b) { return b == 0 ? a : cgcd(b, a % b); }
+
+// cos and sin of 2 pi n / d at compile time (Taylor series after reduction
+// to [-pi, pi]; the twiddles of the composite small DFTs)
+constexpr double ctrig(double x, bool sine)
+{
+    const double pi = 3.14159265358979323846;
+    while (x > pi) x -= 2 * pi;
+    while (x < -pi) x += 2 * pi;
+    double term = sine ? x : 1.0, sum = term;
+    for (int i = sine ? 1 : 0; i < 40; i += 1) {
+        const int a = sine ? 2 * i : 2 * i + 1, b = sine ? 2 * i + 1 : 2 * i + 2;
+        term *= -x * x / ((double)a * (double)b);
+        sum += term;
+    }
+    return sum;
+}
+constexpr double cos2pi(int n, int d) { return ctrig(2.0 * 3.14159265358979323846 * n / d, false); }
+constexpr double sin2pi(int n, int d) { return ctrig(2.0 * 3.14159265358979323846 * n / d, true); }
 
 template <typename T>
 __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b)
@@ -143,13 +169,76 @@ __device__ __forceinline__ void dft16(C2<T> *v)
     for (int q = 0; q < 16; ++q) v[q] = o[q];
 }
 
+// 3-point DFT: with t = b + c, d = b - c and s = sin(2 pi / 3),
+// X0 = a + t, X1,2 = a - t/2 -+ i s d (forward; signs swapped for the inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ void dft3s(C2<T> &a, C2<T> &b, C2<T> &c)
+{
+    const T s = T(0.86602540378443864676);
+    const C2<T> t = cadd(b, c), d = csub(b, c);
+    const C2<T> m = {a.x - T(0.5) * t.x, a.y - T(0.5) * t.y};
+    const C2<T> sd = mul_mi<T, INV>(C2<T>{s * d.x, s * d.y});  // -+ i s d
+    a = cadd(a, t);
+    b = cadd(m, sd);
+    c = csub(m, sd);
+}
+
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dftR(C2<T> *v);
+
+// y[k1][n2] *= W_R^(n2 k1) for k1 = 1, 2 and n2 = 1 .. R2-1 (R = 3 R2), the
+// factors evaluated at compile time
+template <typename T, int R2, bool INV, int K1, int N2>
+__device__ __forceinline__ void dft3x_twiddle(C2<T> (&y)[3][R2])
+{
+    if constexpr (K1 < 3) {
+        if constexpr (N2 < R2) {
+            constexpr double c = cos2pi(N2 * K1, 3 * R2), s = sin2pi(N2 * K1, 3 * R2);
+            y[K1][N2] = cmul(y[K1][N2], C2<T>{T(c), INV ? T(s) : T(-s)});
+            dft3x_twiddle<T, R2, INV, K1, N2 + 1>(y);
+        } else {
+            dft3x_twiddle<T, R2, INV, K1 + 1, 1>(y);
+        }
+    }
+}
+
+// Length 3 R2 (R2 = 1, 2, 4, 8), natural order in and out: n = R2 n1 + n2,
+// k = k1 + 3 k2; 3-point DFTs over n1, twiddles W_R^(n2 k1), R2-point DFTs
+// over n2.
+template <typename T, int R2, bool INV>
+__device__ __forceinline__ void dft3x(C2<T> *v)
+{
+    constexpr int R = 3 * R2;
+    C2<T> y[3][R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) {
+        C2<T> a = v[n2], b = v[R2 + n2], c = v[2 * R2 + n2];
+        dft3s<T, INV>(a, b, c);
+        y[0][n2] = a;
+        y[1][n2] = b;
+        y[2][n2] = c;
+    }
+    dft3x_twiddle<T, R2, INV, 1, 1>(y);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+        if constexpr (R2 > 1) dftR<T, R2, INV>(y[k1]);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) v[k1 + 3 * k2] = y[k1][k2];
+    }
+}
+
 template <typename T, int R, bool INV>
 __device__ __forceinline__ void dftR(C2<T> *v)
 {
-    if constexpr (R == 2) dft2<T, INV>(v);
+    if constexpr (R == 1) return;
+    else if constexpr (R % 3 == 0) dft3x<T, R / 3, INV>(v);
+    else if constexpr (R == 2) dft2<T, INV>(v);
     else if constexpr (R == 4) dft4<T, INV>(v);
     else if constexpr (R == 8) dft8<T, INV>(v);
-    else dft16<T, INV>(v);
+    else {
+        static_assert(R == 16, "radix");
+        dft16<T, INV>(v);
+    }
 }
 
 // LDS layout of a transform: with ping-pong (two data areas of P entries
@@ -182,13 +271,14 @@ __device__ __forceinline__ void fft_pass(C2<T> (&v)[E], C2<T> *x, int t, const C
     constexpr int stride = P / R;
     constexpr int tstep = P / (NS * R);
     constexpr int hP = P / 2;
+    static_assert(E % R == 0 && P % (NS * R) == 0, "radix schedule");
     const C2<T> *xin = PP ? x + (A ^ 1) * P : x;
     C2<T> *xout = PP ? x + A * P : x;
     C2<T> u[E];
 #pragma unroll
     for (int b = 0; b < B; ++b) {
         const int j = t + G * b;
-        const int k = j & (NS - 1);
+        const int k = j % NS;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             if constexpr (FIRST) {
@@ -213,7 +303,7 @@ __device__ __forceinline__ void fft_pass(C2<T> (&v)[E], C2<T> *x, int t, const C
 #pragma unroll
         for (int b = 0; b < B; ++b) {
             const int j = t + G * b;
-            const int k = j & (NS - 1);
+            const int k = j % NS;
             const int base = (j - k) * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) xout[base + r * NS] = u[b * R + r];
@@ -226,13 +316,16 @@ template <typename T, int E, int P, int NS, bool INV, bool FIRST, bool PP = fft_
 __device__ __forceinline__ void fft_passes(C2<T> (&v)[E], C2<T> *x, int t, const C2<T> *tw)
 {
     constexpr int REM = P / NS;
-    constexpr int R = REM >= E ? E : REM;
+    constexpr int R = cgcd(E, REM);  // E for the first pass (E divides P)
     constexpr bool LAST = REM == R;
     fft_pass<T, E, P, NS, R, INV, FIRST, LAST, PP, A>(v, x, t, tw);
     if constexpr (!LAST) fft_passes<T, E, P, NS * R, INV, false, PP, A ^ 1>(v, x, t, tw);
 }
 
 // Elements per thread for a length-P transform.
-__host__ __device__ constexpr int fft_elems(int P) { return P >= 1024 ? 16 : (P == 512 ? 8 : 4); }
+__host__ __device__ constexpr int fft_elems(int P)
+{
+    return P % 3 == 0 ? 24 : (P >= 1024 ? 16 : (P == 512 ? 8 : 4));
+}
 
 }  // namespace gct

@@ -83,11 +83,11 @@ __device__ __forceinline__ void load_pair(const C2<T> *p, C2<T> &a, C2<T> &b)
 // written transposed as W1[k][row], k in [0, P/2].  From registers: v[q]
 // holds (row ra, row ra+1) at column t + G q (zero past N); one complex
 // FFT, split into the two real-row spectra.
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __device__ __forceinline__ void rows_fwd_regs(int ra, C2<T> (&v)[E], C2<T> *__restrict__ W1, int N, C2<T> *x,
                                               const C2<T> *tws)
 {
-    constexpr int P = 1 << LOGP, hP = P >> 1, G = P / E;
+    constexpr int P = fft_size(PC), hP = P >> 1, G = P / E;
     const int t = threadIdx.x;
     const int rb = ra + 1;
     fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
@@ -99,7 +99,7 @@ __device__ __forceinline__ void rows_fwd_regs(int ra, C2<T> (&v)[E], C2<T> *__re
     // both (FP32) where they are 16-byte aligned (N even, aligned base)
     const bool pair = sizeof(T) == 4 && (N & 1) == 0 && (reinterpret_cast<uintptr_t>(W1) & 15) == 0;
     for (int k = t; k <= hP; k += G) {
-        const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
+        const C2<T> Zk = x[k], Zm = x[(P - k) % P];
         const C2<T> a = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
         const C2<T> b = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
         if (pair) {
@@ -117,11 +117,11 @@ __device__ __forceinline__ void rows_fwd_regs(int ra, C2<T> (&v)[E], C2<T> *__re
 // the two global latencies then overlap.  rows_fwd_load: with pupd, the
 // rows are first updated in place as p = src + bt * p (CG direction
 // update).
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __device__ __forceinline__ void rows_fwd_load(int ra, const T *__restrict__ src, int N, T *pupd, T bt,
                                               C2<T> (&v)[E])
 {
-    constexpr int P = 1 << LOGP, G = P / E;
+    constexpr int P = fft_size(PC), G = P / E;
     const int t = threadIdx.x;
     const bool hb = ra + 1 < N;  // row ra < N always
     const size_t oa = (size_t)ra * N, ob = hb ? oa + N : oa;
@@ -168,23 +168,23 @@ __device__ __forceinline__ void rows_fwd_load(int ra, const T *__restrict__ src,
     }
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __device__ __forceinline__ void body_rows_fwd(int ra, const T *__restrict__ src,
                                               C2<T> *__restrict__ W1, int N, C2<T> *x,
                                               const C2<T> *tws, T *pupd, T bt)
 {
     C2<T> v[E];
-    rows_fwd_load<T, LOGP, E>(ra, src, N, pupd, bt, v);
-    rows_fwd_regs<T, LOGP, E>(ra, v, W1, N, x, tws);
+    rows_fwd_load<T, PC, E>(ra, src, N, pupd, bt, v);
+    rows_fwd_regs<T, PC, E>(ra, v, W1, N, x, tws);
 }
 
 // Columns: FFT along k2 of column col (N nonzero of P), times the real
 // spectrum, inverse FFT (in registers between the two), first N entries.
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __device__ __forceinline__ void cols_load(int col, const C2<T> *__restrict__ W1, const T *__restrict__ Ghat,
                                           int N, C2<T> (&v)[E], T (&gs)[E])
 {
-    constexpr int P = 1 << LOGP, G = P / E;
+    constexpr int P = fft_size(PC), G = P / E;
     const int t = threadIdx.x;
     const C2<T> *in = W1 + (size_t)col * N;
     const T *g = Ghat + (size_t)col * P;
@@ -197,11 +197,11 @@ __device__ __forceinline__ void cols_load(int col, const C2<T> *__restrict__ W1,
     }
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __device__ __forceinline__ void cols_regs(int col, C2<T> (&v)[E], const T (&gs)[E], C2<T> *__restrict__ W2,
                                           int N, C2<T> *x, const C2<T> *tws)
 {
-    constexpr int P = 1 << LOGP, G = P / E;
+    constexpr int P = fft_size(PC), G = P / E;
     const int t = threadIdx.x;
     fft_passes<T, E, P, 1, false, true>(v, x, t, tws);
 #pragma unroll
@@ -218,10 +218,10 @@ __device__ __forceinline__ void cols_regs(int col, C2<T> (&v)[E], const T (&gs)[
 // Rows inverse: Hermitian row spectra of rows ra, ra+1 (loaded as one
 // complex spectrum) -> one complex inverse FFT (fft_passes) -> v[q] =
 // (row ra, row ra+1) at column t + G q -> two real rows of y.
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __device__ __forceinline__ void rows_inv_load(int ra, const C2<T> *__restrict__ W2, int N, C2<T> (&v)[E])
 {
-    constexpr int P = 1 << LOGP, hP = P >> 1, G = P / E;
+    constexpr int P = fft_size(PC), hP = P >> 1, G = P / E;
     const int t = threadIdx.x;
     const int rb = ra + 1;
     const bool pair = sizeof(T) == 4 && (N & 1) == 0 && (reinterpret_cast<uintptr_t>(W2) & 15) == 0;
@@ -255,11 +255,11 @@ __device__ __forceinline__ void rows_inv_load(int ra, const C2<T> *__restrict__ 
 
 // The two real output rows from v (after the inverse transform) into y;
 // returns this thread's FP64 partial of dotv . y (0 if dotv is null).
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __device__ __forceinline__ double rows_inv_store(int ra, const C2<T> (&v)[E], T *__restrict__ y, int N,
                                                  const T *__restrict__ dotv)
 {
-    constexpr int P = 1 << LOGP, G = P / E;
+    constexpr int P = fft_size(PC), G = P / E;
     const int t = threadIdx.x;
     const int rb = ra + 1;
     double acc = 0.0;
@@ -333,12 +333,12 @@ __device__ __forceinline__ int embed_tap(int q, int N, int P)
 }
 
 // embedded rows 2 seq and 2 seq + 1 -> R[k][row], k in [0, P/2]
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __device__ __forceinline__ void body_spec_rows(int seq, const T *__restrict__ G,
                                                C2<T> *__restrict__ R, int N, C2<T> *x,
                                                const C2<T> *tws)
 {
-    constexpr int P = 1 << LOGP, hP = P >> 1, Gt = P / E;
+    constexpr int P = fft_size(PC), hP = P >> 1, Gt = P / E;
     const int t = threadIdx.x, W = 2 * N - 1;
     const int ka = embed_tap(2 * seq, N, P), kb = embed_tap(2 * seq + 1, N, P);
     C2<T> v[E];
@@ -357,7 +357,7 @@ __device__ __forceinline__ void body_spec_rows(int seq, const T *__restrict__ G,
     for (int q = 0; q < E; ++q) x[t + Gt * q] = v[q];
     __syncthreads();
     for (int k = t; k <= hP; k += Gt) {
-        const C2<T> Zk = x[k], Zm = x[(P - k) & (P - 1)];
+        const C2<T> Zk = x[k], Zm = x[(P - k) % P];
         R[(size_t)k * P + 2 * seq] = {(Zk.x + Zm.x) * T(0.5), (Zk.y - Zm.y) * T(0.5)};
         R[(size_t)k * P + 2 * seq + 1] = {(Zk.y + Zm.y) * T(0.5), (Zm.x - Zk.x) * T(0.5)};
     }
@@ -365,12 +365,12 @@ __device__ __forceinline__ void body_spec_rows(int seq, const T *__restrict__ G,
 }
 
 // column k of R -> Ghat[k][.] = Re FFT / P^2
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __device__ __forceinline__ void body_spec_cols(int col, const C2<T> *__restrict__ R,
                                                T *__restrict__ Ghat, C2<T> *x, const C2<T> *tws,
                                                T scale)
 {
-    constexpr int P = 1 << LOGP, Gt = P / E;
+    constexpr int P = fft_size(PC), Gt = P / E;
     const int t = threadIdx.x;
     C2<T> v[E];
 #pragma unroll
@@ -391,10 +391,26 @@ inline size_t fft_lds_bytes(int P, int E)
     return b > red ? b : red;
 }
 
-// Valid (log2 P, E) pairs: E in {4, 8, 16}, E <= P, at most 256 threads.
-__host__ __device__ constexpr bool fft_combo_ok(int logP, int E)
+// Switch cases of the P = 3 * 2^k transforms (size codes 41 and 42: 1536
+// and 3072 points) for a launch macro CASE(kern, T, code, E, grid, lds, s,
+// ...), E = 24 or 12.
+#define GCT_MIXED_CASES(CASE, kern, T, E, grid, lds, s, ...)                       \
+    case 41:                                                                       \
+        if (E == 12) CASE(kern, T, 41, 12, grid, lds, s, __VA_ARGS__);             \
+        else CASE(kern, T, 41, 24, grid, lds, s, __VA_ARGS__);                     \
+        break;                                                                     \
+    default:                                                                       \
+        if (E == 12) CASE(kern, T, 42, 12, grid, lds, s, __VA_ARGS__);             \
+        else CASE(kern, T, 42, 24, grid, lds, s, __VA_ARGS__);                     \
+        break;
+
+// Valid (size code, E) pairs: E in {4, 8, 16} for powers of two, {12, 24}
+// for three times a power of two; E divides P, at most 256 threads.
+__host__ __device__ constexpr bool fft_combo_ok(int pc, int E)
 {
-    return E <= (1 << logP) && ((1 << logP) / E) <= 256 && logP >= 2 && logP <= 12;
+    return ((pc >= 2 && pc <= 12 && (E == 4 || E == 8 || E == 16)) ||
+            (pc >= 41 && pc <= 42 && (E == 12 || E == 24))) &&
+           fft_size(pc) % E == 0 && (fft_size(pc) / E) <= 256;
 }
 
 }  // namespace gct

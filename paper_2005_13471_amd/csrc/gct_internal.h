@@ -117,7 +117,7 @@ struct CGState {
 // packed arrays: image arrays (N^2 per slice), Gram filters ((2N-1)^2),
 // spectra ((P/2+1) P reals) and Gram-filtering scratch ((P/2+1) N complex).
 struct BatchSlice {
-    int32_t N, logP, n, nrow;   // nrow = ceil(N/2) row pairs
+    int32_t N, pc, n, nrow;   // pc: transform size code (fft_size); nrow = ceil(N/2) row pairs
     int64_t img, gram, spec, w;
     int64_t rpart;              // first row-pair partial of this slice
     const void *ga;             // GramAngle<T> table of the slice's plan
@@ -152,7 +152,7 @@ struct CGGraph {
 struct gct_plan {
     int32_t N, n, M, K;
     double lx1, lx2, ly, zeta;
-    int32_t P, logP;
+    int32_t P, pc;  // transform size and its code (fft_size(pc) == P)
     // Gram-filter table entries (angle, term of the detector's
     // autocorrelation; one term per angle for zero or one box) and
     // footprint boxes per angle
@@ -184,7 +184,7 @@ int fail(int code, const std::string &msg);
 int check_hip(hipError_t e, const char *what);
 
 // ---------------------------------------------------------------------------
-bool apply_e_ok(int logP, int E);
+bool apply_e_ok(int pc, int E);
 
 // One fused CG iteration of the single-slice solver (gram_apply.hip): the
 // update from the previous dots + forward rows of r, columns, inverse rows
@@ -229,10 +229,36 @@ int bp_fallback_tile(const gct_plan *p, size_t elem);
 // 128; elsewhere the largest tile, 256 threads at most per transform).
 inline void default_pass_elems(int P, int &rows, int &cols)
 {
-    rows = cols = P >= 1024 ? 16 : (P == 512 ? 8 : 4);
+    rows = cols = P % 3 == 0 ? 24 : (P >= 1024 ? 16 : (P == 512 ? 8 : 4));
     if (P == 1024) {
         rows = 4;
         cols = 8;
+    }
+}
+
+// Transform size of a plan: the smallest P >= 2N - 1 among powers of two and
+// (from 1536 up) three times a power of two; its size code (log2 P, or 32 +
+// log2(P / 3)).  Below 1536 points the passes are latency-bound and the
+// power-of-two kernels, though longer, run as fast or faster (measured at
+// N = 384: 768 points 14.8 us per apply, 1024 points 14.3 us); at N = 600
+// and 768, 1536 points take 26.7 and 28.5 us against 31.6 and 33.5 us at
+// 2048.
+inline void choose_fft_size(int N, int &P, int &code)
+{
+    P = 4;
+    code = 2;
+    while (P < 2 * N - 1) {
+        P <<= 1;
+        ++code;
+    }
+    int P3 = 1536, c3 = 41;
+    while (P3 < 2 * N - 1) {
+        P3 <<= 1;
+        ++c3;
+    }
+    if (P3 < P) {
+        P = P3;
+        code = c3;
     }
 }
 void bp_configure(gct_plan *p);

@@ -2,8 +2,8 @@
 // so y = H^T H c is the zero-padded linear convolution of the N x N
 // coefficients with the (2N-1)^2 Gram filter.  It is evaluated exactly (up
 // to rounding) through the P x P circulant embedding, P >= 2N-1 a power of
-// two: y = IFFT2(Ghat . FFT2(c_padded))[0:N, 0:N], with Ghat real and even
-// because G[k] = G[-k].
+// two or (1536, 3072) three times one: y = IFFT2(Ghat . FFT2(c_padded))[0:N,
+// 0:N], with Ghat real and even because G[k] = G[-k].
 //
 // Three passes, each a block-local FFT (fft_common.h):
 //   rows:    pairs of image rows -> one complex FFT -> two real-row spectra,
@@ -23,77 +23,77 @@ namespace gct {
 
 // One transform per block, P/E threads; E is the plan's choice for the
 // apply passes (gct_plan_autotune), fft_elems(P) for the spectrum.
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 k_rows_fwd(const T *__restrict__ src, C2<T> *__restrict__ W1, int N, const C2<T> *__restrict__ tw)
 {
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
     // data first, then the twiddles: their latencies overlap
     C2<T> v[E];
-    rows_fwd_load<T, LOGP, E>(2 * rp, src, N, nullptr, T(0), v);
+    rows_fwd_load<T, PC, E>(2 * rp, src, N, nullptr, T(0), v);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
-    rows_fwd_regs<T, LOGP, E>(2 * rp, v, W1, N, x, tws);
+    rows_fwd_regs<T, PC, E>(2 * rp, v, W1, N, x, tws);
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 k_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat, int N,
        const C2<T> *__restrict__ tw)
 {
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     C2<T> v[E];
     T gs[E];
-    cols_load<T, LOGP, E>(blockIdx.x, W1, Ghat, N, v, gs);
+    cols_load<T, PC, E>(blockIdx.x, W1, Ghat, N, v, gs);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
-    cols_regs<T, LOGP, E>(blockIdx.x, v, gs, W2, N, x, tws);
+    cols_regs<T, PC, E>(blockIdx.x, v, gs, W2, N, x, tws);
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 k_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ y, int N, const C2<T> *__restrict__ tw)
 {
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
     C2<T> v[E];
-    rows_inv_load<T, LOGP, E>(2 * rp, W2, N, v);
+    rows_inv_load<T, PC, E>(2 * rp, W2, N, v);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
     fft_passes<T, E, P, 1, true, true>(v, x, threadIdx.x, tws);
-    (void)rows_inv_store<T, LOGP, E>(2 * rp, v, y, N, nullptr);
+    (void)rows_inv_store<T, PC, E>(2 * rp, v, y, N, nullptr);
 }
 
-template <typename T, int LOGP>
+template <typename T, int PC>
 __global__ void __launch_bounds__(256)
 k_spec_rows(const T *__restrict__ G, C2<T> *__restrict__ R, int N, const C2<T> *__restrict__ tw)
 {
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / fft_elems(P)>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
-    body_spec_rows<T, LOGP, fft_elems(P)>(xcd_swizzle(blockIdx.x, gridDim.x), G, R, N, x, tws);
+    body_spec_rows<T, PC, fft_elems(P)>(xcd_swizzle(blockIdx.x, gridDim.x), G, R, N, x, tws);
 }
 
-template <typename T, int LOGP>
+template <typename T, int PC>
 __global__ void __launch_bounds__(256)
 k_spec_cols(const C2<T> *__restrict__ R, T *__restrict__ Ghat, const C2<T> *__restrict__ tw,
             T scale)
 {
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / fft_elems(P)>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
-    body_spec_cols<T, LOGP, fft_elems(P)>(blockIdx.x, R, Ghat, x, tws, scale);
+    body_spec_cols<T, PC, fft_elems(P)>(blockIdx.x, R, Ghat, x, tws, scale);
 }
 
 // ---------------------------------------------------------------------------
@@ -149,13 +149,13 @@ __device__ __forceinline__ void dot_pair(const double *part, int np, const doubl
     block_sum2<NT>(g, d, red);
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__restrict__ sv,
                const T *__restrict__ w, C2<T> *__restrict__ W1, int N, const C2<T> *__restrict__ tw,
                CGState *st, const double *__restrict__ part, int np, int par)
 {
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *xs = reinterpret_cast<C2<T> *>(smem_raw);
     double *red = reinterpret_cast<double *>(smem_raw);
@@ -257,7 +257,7 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
             v[q] = {rv[0], rv[1]};
         }
         __syncthreads();  // the reduction's LDS reads are done before the transform writes
-        rows_fwd_regs<T, LOGP, E>(ra, v, W1, N, xs, tws);
+        rows_fwd_regs<T, PC, E>(ra, v, W1, N, xs, tws);
         return;
     } else if (lead) {
         st->pend[par ^ 1] = 1;  // first launch: transform r_0 only
@@ -265,34 +265,34 @@ k_cgf_rows_fwd(T *__restrict__ x, T *__restrict__ r, T *__restrict__ p, T *__res
     }
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(xs + fft_data_elems<T>(P), tw);
     __syncthreads();
-    body_rows_fwd<T, LOGP, E>(ra, r, W1, N, xs, tws, nullptr, T(0));
+    body_rows_fwd<T, PC, E>(ra, r, W1, N, xs, tws, nullptr, T(0));
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 k_cgf_cols(const C2<T> *__restrict__ W1, C2<T> *__restrict__ W2, const T *__restrict__ Ghat, int N,
            const C2<T> *__restrict__ tw, const CGState *st, int par)
 {
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     // the column's loads go out with the state word's (in range either way)
     const int64_t stat = st->stat[par ^ 1];
     C2<T> v[E];
     T gs[E];
-    cols_load<T, LOGP, E>(blockIdx.x, W1, Ghat, N, v, gs);
+    cols_load<T, PC, E>(blockIdx.x, W1, Ghat, N, v, gs);
     if (stat != CG_RUNNING) return;
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
-    cols_regs<T, LOGP, E>(blockIdx.x, v, gs, W2, N, x, tws);
+    cols_regs<T, PC, E>(blockIdx.x, v, gs, W2, N, x, tws);
 }
 
-template <typename T, int LOGP, int E>
+template <typename T, int PC, int E>
 __global__ void __launch_bounds__(256)
 k_cgf_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ w, const T *__restrict__ r, int N,
                const C2<T> *__restrict__ tw, const CGState *st, double *__restrict__ part, int np, int par)
 {
-    constexpr int P = 1 << LOGP;
+    constexpr int P = fft_size(PC);
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2<T> *x = reinterpret_cast<C2<T> *>(smem_raw);
     const int rp = xcd_swizzle(blockIdx.x, gridDim.x);
@@ -312,7 +312,7 @@ k_cgf_rows_inv(const C2<T> *__restrict__ W2, T *__restrict__ w, const T *__restr
         lr[q][1] = r[ob + nc];
     }
     C2<T> v[E];
-    rows_inv_load<T, LOGP, E>(ra, W2, N, v);
+    rows_inv_load<T, PC, E>(ra, W2, N, v);
     if (stat != CG_RUNNING) return;
     const C2<T> *tws = stage_twiddles<T, twiddles_in_lds<T>(P), P / 2, P / E>(x + fft_data_elems<T>(P), tw);
     __syncthreads();
@@ -352,9 +352,9 @@ struct FftCfg {
 };
 
 template <typename T>
-static FftCfg fft_cfg(int logP)
+static FftCfg fft_cfg(int pc)
 {
-    const int P = 1 << logP;
+    const int P = fft_size(pc);
     return FftCfg{P / fft_elems(P), fft_lds_bytes<T>(P, fft_elems(P))};
 }
 
@@ -377,10 +377,10 @@ size_t spectrum_ws_bytes(const gct_plan *p, size_t elem)
 int apply_row_blocks(const gct_plan *p, size_t /*elem*/) { return (p->N + 1) / 2; }
 
 // Dispatch on log2 P (4 .. 4096).
-#define GCT_LAUNCH_FFT(kern, T, logP, cfg, grid, s, ...)                                        \
+#define GCT_LAUNCH_FFT(kern, T, pc, cfg, grid, s, ...)                                        \
     do {                                                                                       \
         const dim3 blk_(cfg.threads);                                                          \
-        switch (logP) {                                                                        \
+        switch (pc) {                                                                        \
         case 2: hipLaunchKernelGGL((kern<T, 2>), grid, blk_, cfg.lds, s, __VA_ARGS__); break;  \
         case 3: hipLaunchKernelGGL((kern<T, 3>), grid, blk_, cfg.lds, s, __VA_ARGS__); break;  \
         case 4: hipLaunchKernelGGL((kern<T, 4>), grid, blk_, cfg.lds, s, __VA_ARGS__); break;  \
@@ -391,29 +391,33 @@ int apply_row_blocks(const gct_plan *p, size_t /*elem*/) { return (p->N + 1) / 2
         case 9: hipLaunchKernelGGL((kern<T, 9>), grid, blk_, cfg.lds, s, __VA_ARGS__); break;  \
         case 10: hipLaunchKernelGGL((kern<T, 10>), grid, blk_, cfg.lds, s, __VA_ARGS__); break; \
         case 11: hipLaunchKernelGGL((kern<T, 11>), grid, blk_, cfg.lds, s, __VA_ARGS__); break; \
-        default: hipLaunchKernelGGL((kern<T, 12>), grid, blk_, cfg.lds, s, __VA_ARGS__); break; \
+        case 12: hipLaunchKernelGGL((kern<T, 12>), grid, blk_, cfg.lds, s, __VA_ARGS__); break; \
+        case 41: hipLaunchKernelGGL((kern<T, 41>), grid, blk_, cfg.lds, s, __VA_ARGS__); break; \
+        default: hipLaunchKernelGGL((kern<T, 42>), grid, blk_, cfg.lds, s, __VA_ARGS__); break; \
         }                                                                                      \
     } while (0)
 
 // Elements per thread the apply passes can take for a length-P transform:
 // fft_elems(P) always; for P = 512 also 4, for P = 1024 also 8 and 4, for
-// P = 2048 also 8 (at most 256 threads per transform).
-bool apply_e_ok(int logP, int E)
+// P = 2048 also 8; for P = 3 * 2^k (1536, 3072) 24 and 12 (at most 256
+// threads per transform).
+bool apply_e_ok(int pc, int E)
 {
-    const int P = 1 << logP;
+    const int P = fft_size(pc);
     if (E == fft_elems(P)) return true;
     if (P == 512) return E == 4;
     if (P == 1024) return E == 8 || E == 4;
     if (P == 2048) return E == 8;
+    if (P % 3 == 0) return (E == 12 || E == 24) && P / E <= 256;
     return false;
 }
 
 #define GCT_ACASE(kern, T, LG, E, grid, lds, s, ...) \
-    hipLaunchKernelGGL((kern<T, LG, E>), grid, dim3((1 << LG) / E), lds, s, __VA_ARGS__)
+    hipLaunchKernelGGL((kern<T, LG, E>), grid, dim3(fft_size(LG) / E), lds, s, __VA_ARGS__)
 
-#define GCT_LAUNCH_FFTE(kern, T, logP, E, grid, lds, s, ...)                              \
+#define GCT_LAUNCH_FFTE(kern, T, pc, E, grid, lds, s, ...)                              \
     do {                                                                                  \
-        switch (logP) {                                                                   \
+        switch (pc) {                                                                   \
         case 2: GCT_ACASE(kern, T, 2, 4, grid, lds, s, __VA_ARGS__); break;               \
         case 3: GCT_ACASE(kern, T, 3, 4, grid, lds, s, __VA_ARGS__); break;               \
         case 4: GCT_ACASE(kern, T, 4, 4, grid, lds, s, __VA_ARGS__); break;               \
@@ -434,7 +438,8 @@ bool apply_e_ok(int logP, int E)
             if (E == 8) GCT_ACASE(kern, T, 11, 8, grid, lds, s, __VA_ARGS__);             \
             else GCT_ACASE(kern, T, 11, 16, grid, lds, s, __VA_ARGS__);                   \
             break;                                                                        \
-        default: GCT_ACASE(kern, T, 12, 16, grid, lds, s, __VA_ARGS__); break;            \
+        case 12: GCT_ACASE(kern, T, 12, 16, grid, lds, s, __VA_ARGS__); break;            \
+        GCT_MIXED_CASES(GCT_ACASE, kern, T, E, grid, lds, s, __VA_ARGS__)                 \
         }                                                                                 \
     } while (0)
 
@@ -442,7 +447,7 @@ bool apply_e_ok(int logP, int E)
 template <typename T>
 hipError_t launch_gram_apply(const gct_plan *p, const T *Ghat, const T *c, T *y, void *ws, hipStream_t s)
 {
-    const int N = p->N, P = p->P, logP = p->logP;
+    const int N = p->N, P = p->P, pc = p->pc;
     const int t = sizeof(T) == 4 ? 0 : 1, E = p->fft_e[t], Ec = p->fft_ec[t];
     const size_t lds = fft_lds_bytes<T>(P, E), ldsc = fft_lds_bytes<T>(P, Ec);
     const size_t w1 = align256((size_t)(P / 2 + 1) * N * 2 * sizeof(T));
@@ -450,9 +455,9 @@ hipError_t launch_gram_apply(const gct_plan *p, const T *Ghat, const T *c, T *y,
     C2<T> *W2 = reinterpret_cast<C2<T> *>(reinterpret_cast<char *>(ws) + w1);
     const C2<T> *tw = twiddles<T>(p);
     const dim3 rgrid((N + 1) / 2), cgrid(P / 2 + 1);
-    GCT_LAUNCH_FFTE(k_rows_fwd, T, logP, E, rgrid, lds, s, c, W1, N, tw);
-    GCT_LAUNCH_FFTE(k_cols, T, logP, Ec, cgrid, ldsc, s, W1, W2, Ghat, N, tw);
-    GCT_LAUNCH_FFTE(k_rows_inv, T, logP, E, rgrid, lds, s, W2, y, N, tw);
+    GCT_LAUNCH_FFTE(k_rows_fwd, T, pc, E, rgrid, lds, s, c, W1, N, tw);
+    GCT_LAUNCH_FFTE(k_cols, T, pc, Ec, cgrid, ldsc, s, W1, W2, Ghat, N, tw);
+    GCT_LAUNCH_FFTE(k_rows_inv, T, pc, E, rgrid, lds, s, W2, y, N, tw);
     return hipGetLastError();
 }
 
@@ -460,7 +465,7 @@ template <typename T>
 hipError_t launch_cgf_iteration(const gct_plan *p, const T *Ghat, T *x, T *r, T *pv, T *sv, T *w, void *ws,
                                 double *part, CGState *st, int par, hipStream_t s)
 {
-    const int N = p->N, P = p->P, logP = p->logP;
+    const int N = p->N, P = p->P, pc = p->pc;
     const int t = sizeof(T) == 4 ? 0 : 1, E = p->cg_e[t], Ec = p->cg_ec[t];
     const size_t lds = fft_lds_bytes<T>(P, E), ldsc = fft_lds_bytes<T>(P, Ec);
     const size_t w1 = align256((size_t)(P / 2 + 1) * N * 2 * sizeof(T));
@@ -469,11 +474,11 @@ hipError_t launch_cgf_iteration(const gct_plan *p, const T *Ghat, T *x, T *r, T 
     const C2<T> *tw = twiddles<T>(p);
     const int np = (N + 1) / 2;
     const dim3 rgrid(np), cgrid(P / 2 + 1);
-    GCT_LAUNCH_FFTE(k_cgf_rows_fwd, T, logP, E, rgrid, lds, s, x, r, pv, sv, (const T *)w, W1, N, tw, st,
+    GCT_LAUNCH_FFTE(k_cgf_rows_fwd, T, pc, E, rgrid, lds, s, x, r, pv, sv, (const T *)w, W1, N, tw, st,
                     (const double *)part, np, par);
-    GCT_LAUNCH_FFTE(k_cgf_cols, T, logP, Ec, cgrid, ldsc, s, (const C2<T> *)W1, W2, Ghat, N, tw,
+    GCT_LAUNCH_FFTE(k_cgf_cols, T, pc, Ec, cgrid, ldsc, s, (const C2<T> *)W1, W2, Ghat, N, tw,
                     (const CGState *)st, par);
-    GCT_LAUNCH_FFTE(k_cgf_rows_inv, T, logP, E, rgrid, lds, s, (const C2<T> *)W2, w, (const T *)r, N, tw,
+    GCT_LAUNCH_FFTE(k_cgf_rows_inv, T, pc, E, rgrid, lds, s, (const C2<T> *)W2, w, (const T *)r, N, tw,
                     (const CGState *)st, part, np, par);
     return hipGetLastError();
 }
@@ -487,13 +492,13 @@ template hipError_t launch_cgf_iteration<double>(const gct_plan *, const double 
 template <typename T>
 hipError_t launch_gram_spectrum(const gct_plan *p, const T *G, T *Ghat, void *ws, hipStream_t s)
 {
-    const int N = p->N, P = p->P, logP = p->logP;
-    const FftCfg c = fft_cfg<T>(logP);
+    const int N = p->N, P = p->P, pc = p->pc;
+    const FftCfg c = fft_cfg<T>(pc);
     C2<T> *R = reinterpret_cast<C2<T> *>(ws);
     const C2<T> *tw = twiddles<T>(p);
-    GCT_LAUNCH_FFT(k_spec_rows, T, logP, c, dim3(P / 2), s, G, R, N, tw);
+    GCT_LAUNCH_FFT(k_spec_rows, T, pc, c, dim3(P / 2), s, G, R, N, tw);
     const T scale = T(1.0 / ((double)P * (double)P));
-    GCT_LAUNCH_FFT(k_spec_cols, T, logP, c, dim3(P / 2 + 1), s, R, Ghat, tw, scale);
+    GCT_LAUNCH_FFT(k_spec_cols, T, pc, c, dim3(P / 2 + 1), s, R, Ghat, tw, scale);
     return hipGetLastError();
 }
 

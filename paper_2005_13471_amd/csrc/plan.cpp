@@ -597,13 +597,10 @@ static int create_plan(const gct_geometry *geom, const Detector &det, gct_plan *
         p->lx2 = geom->lambda_x[1];
         p->ly = geom->lambda_y;
         p->zeta = geom->zeta_blur;
-        int P = 4, logP = 2;
-        while (P < 2 * p->N - 1) {
-            P <<= 1;
-            ++logP;
-        }
+        int P, pc;
+        choose_fft_size(p->N, P, pc);
         p->P = P;
-        p->logP = logP;
+        p->pc = pc;
         // elements per thread of the transform passes until gct_plan_autotune
         int er, ec;
         default_pass_elems(P, er, ec);
@@ -838,7 +835,7 @@ int gct_plan_set_pass_elems(gct_plan *p, gct_dtype dt, int32_t Er, int32_t Ec)
     default_pass_elems(p->P, dr, dc);
     if (Er == 0) Er = dr;
     if (Ec == 0) Ec = dc;
-    if (!apply_e_ok(p->logP, Er) || !apply_e_ok(p->logP, Ec))
+    if (!apply_e_ok(p->pc, Er) || !apply_e_ok(p->pc, Ec))
         return fail(GCT_EINVAL, "elements per thread not available for this transform size");
     const int t = dt == GCT_F32 ? 0 : 1;
     if (p->fft_e[t] != Er || p->fft_ec[t] != Ec || p->cg_e[t] != Er || p->cg_ec[t] != Ec) {

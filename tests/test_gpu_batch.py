@@ -62,10 +62,13 @@ def test_batch_gram_build_and_apply_match_oracle(batch_setup, dt):
 def test_batch_apply_bitwise_equals_single_slice(batch_setup):
     """Same device bodies and tile shapes: from the same Gram filter the
     batched spectrum and apply reproduce the single-slice ones bit for bit
-    (before autotuning).  The Gram builds themselves use different tile
-    shapes (the single-slice build splits each tile's angles over the block's
-    waves), so their sums are ordered differently and agree to FP32
-    rounding."""
+    (before autotuning) at the power-of-two transform sizes; at three times
+    a power of two the apply agrees to a few units in the last place (the
+    same arithmetic in separately compiled kernels, where the compiler
+    contracts the radix-3 butterflies' products and sums differently).  The
+    Gram builds themselves use different tile shapes (the single-slice build
+    splits each tile's angles over the block's waves), so their sums are
+    ordered differently and agree to FP32 rounding."""
     gct, B, plans, ogs = batch_setup
     dt = torch.float32
     G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
@@ -88,7 +91,12 @@ def test_batch_apply_bitwise_equals_single_slice(batch_setup):
         yi = torch.empty(P.N * P.N, dtype=dt, device="cuda")
         gct.gram_apply(P, Gh, torch.as_tensor(cs[i].reshape(-1), dtype=dt, device="cuda"), yi,
                        P.workspace(gct.OP_GRAM_APPLY, dt))
-        assert torch.equal(yi.view(P.N, P.N), B.image(y, i))
+        size = P.info.fft_size
+        if size & (size - 1) == 0:
+            assert torch.equal(yi.view(P.N, P.N), B.image(y, i)), size
+        else:
+            d = float((yi.view(P.N, P.N) - B.image(y, i)).abs().max())
+            assert d <= 1e-6 * float(yi.abs().max()), (size, d)
 
 
 @pytest.mark.parametrize("dt", [torch.float32, torch.float64])
@@ -157,8 +165,9 @@ def test_batch_autotune_keeps_results(batch_setup):
     chosen = gct.batch_autotune(B, Ghat, B.workspace(gct.OP_CG, dt), reps=2)
     both = gct.batch_get_pass_elems(B, dt)
     say("autotune choice per FFT size (rows, cols)", both)
-    assert len(chosen) == B.groups and all(e in (4, 8, 16) for e in chosen)
-    assert [r for r, _ in both] == chosen and all(c in (4, 8, 16) for _, c in both)
+    assert B.groups == 4
+    assert len(chosen) == B.groups and all(e in (4, 8, 16, 12, 24) for e in chosen)
+    assert [r for r, _ in both] == chosen and all(c in (4, 8, 16, 12, 24) for _, c in both)
     cs = [inputs.uniform_coeffs(N, 4000 + i) for i, (N, _, _) in enumerate(SLICES)]
     y = torch.empty(B.image_elems, dtype=dt, device="cuda")
     gct.batch_gram_apply(B, Ghat, _packed(B, cs, dt), y, B.workspace(gct.OP_GRAM_APPLY, dt))
@@ -179,11 +188,11 @@ def test_batch_rejects_bad_arguments(batch_setup):
 # long transforms: 1024- and 2048-point groups, where FP32 row passes take
 # two row pairs per block when every slice of the group has even N (the
 # second batch has an odd N in the 1024-point group, which keeps the
-# one-pair kernels there)
-LONG = [[(300, 60, 1.0), (260, 40, 0.0), (520, 30, 1.0), (302, 20, 0.5)],
-        [(300, 60, 1.0), (301, 24, 0.5), (520, 30, 1.0)]]
+# one-pair kernels there), and 1536-point groups (three times a power of two)
+LONG = [[(400, 60, 1.0), (390, 40, 0.0), (800, 30, 1.0), (402, 20, 0.5), (600, 20, 1.0)],
+        [(400, 60, 1.0), (401, 24, 0.5), (800, 30, 1.0), (700, 16, 0.5)]]
 # slices whose group takes the two-pair row kernels
-LONG_PAIRED = [{300, 260, 520, 302}, {520}]
+LONG_PAIRED = [{400, 390, 800, 402}, {800}]
 
 
 @pytest.mark.parametrize("which", [0, 1])

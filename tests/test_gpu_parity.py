@@ -164,14 +164,18 @@ def test_gram_apply_config2_sampled(gct):
     assert err <= 1e-4
 
 
-CASE_P1024 = Case(300, 60, zeta=1.0)   # FFT size 1024: 16, 8 or 4 elements per thread
+CASE_P1024 = Case(400, 60, zeta=1.0)   # FFT size 1024: 16, 8 or 4 elements per thread
 CASE_P512 = Case(200, 40, zeta=0.5)    # FFT size 512: 8 or 4
+CASE_P1536 = Case(700, 24, zeta=0.5)   # FFT size 1536 = 3 x 512: 24 or 12
+CASE_P3072 = Case(1100, 8, zeta=0.5)   # FFT size 3072 = 3 x 1024: 24 or 12
 
 
 @pytest.mark.parametrize("dt", DTYPES)
 @pytest.mark.parametrize("case,elems", [(CASE_P1024, 16), (CASE_P1024, 8), (CASE_P1024, 4),
                                         (CASE_P512, 8), (CASE_P512, 4), (CASE_P1024, (4, 8)),
-                                        (CASE_P1024, (16, 4)), (CASE_P512, (4, 8))], ids=repr)
+                                        (CASE_P1024, (16, 4)), (CASE_P512, (4, 8)),
+                                        (CASE_P1536, 24), (CASE_P1536, 12), (CASE_P1536, (12, 24)),
+                                        (CASE_P3072, 24), (CASE_P3072, (12, 24))], ids=repr)
 def test_gram_apply_every_transform_tiling(gct, case, elems, dt):
     """Each elements-per-thread variant of the apply passes (one value for
     every pass, or separate ones for the row passes and the column pass)
@@ -197,19 +201,24 @@ def test_default_transform_tilings(gct):
     the row passes take 4 and the column pass 8, elsewhere the largest tile;
     0 restores the default after an explicit choice."""
     P1024, P512 = CASE_P1024.plan(gct), CASE_P512.plan(gct)
+    assert P1024.info.fft_size == 1024 and P512.info.fft_size == 512
     assert gct.plan_get_pass_elems(P1024) == (4, 8, 4, 8)
     assert gct.plan_get_pass_elems(P512) == (8, 8, 8, 8)
+    P1536 = CASE_P1536.plan(gct)
+    assert P1536.info.fft_size == 1536 and Case(300, 8).plan(gct).info.fft_size == 1024
+    assert gct.plan_get_pass_elems(P1536) == (24, 24, 24, 24)
     gct.plan_set_fft_elems(P1024, 16)
     assert gct.plan_get_pass_elems(P1024) == (16, 16, 16, 16)
     gct.plan_set_pass_elems(P1024, 0, 0)
     assert gct.plan_get_pass_elems(P1024) == (4, 8, 4, 8)
 
 
-def test_plan_autotune_then_cg(gct):
+@pytest.mark.parametrize("N", [400, 600])  # FFT sizes 1024 and 1536
+def test_plan_autotune_then_cg(gct, N):
     """The autotuner picks a candidate; CG with the tuned plan converges to
     the same stopping rule as with the default tiling, in about as many
     iterations."""
-    case, dt = Case(260, 360, zeta=1.0), torch.float32   # FFT size 1024, fully sampled
+    case, dt = Case(N, 360, zeta=1.0), torch.float32
     P = case.plan(gct)
     G = torch.empty(P.info.gram_elems, dtype=dt, device="cuda")
     gct.gram_build(P, G)
@@ -222,12 +231,13 @@ def test_plan_autotune_then_cg(gct):
     r0 = gct.cg_solve(P, Ghat, b, x, ws, rtol=1e-4, max_iter=500)
     E = gct.plan_autotune(P, Ghat, ws, reps=3)
     say("  autotune chose", gct.plan_get_pass_elems(P, dt), "default iters", r0.iters)
-    assert len(E) == 2 and all(e in (16, 8, 4) for e in gct.plan_get_pass_elems(P, dt))
+    allowed = (16, 8, 4) if P.info.fft_size == 1024 else (24, 12)
+    assert len(E) == 2 and all(e in allowed for e in gct.plan_get_pass_elems(P, dt))
     r1 = gct.cg_solve(P, Ghat, b, x, ws, rtol=1e-4, max_iter=500)
     assert r0.status == gct.GCT_OK and r1.status == gct.GCT_OK
     assert r1.rel_res_true <= 1.1e-4 and abs(r1.iters - r0.iters) <= max(3, r0.iters // 10)
     # the fused CG passes with different row and column tilings
-    for rows, cols in ((4, 8), (16, 4)):
+    for rows, cols in (((4, 8), (16, 4)) if P.info.fft_size == 1024 else ((12, 24), (24, 12))):
         gct.plan_set_pass_elems(P, rows, cols, dt)
         r2 = gct.cg_solve(P, Ghat, b, x, ws, rtol=1e-4, max_iter=500)
         say("  rows/cols", rows, cols, "iters", r2.iters)

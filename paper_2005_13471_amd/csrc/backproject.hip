@@ -273,7 +273,7 @@ k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT,
     T *s_b = s_E + (size_t)CH * eang;
     T *s_f = s_b + WB * smax;
     int *s_w = reinterpret_cast<int *>(s_f + WB * 3);
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int k1a = blockIdx.x * BP_TX, k2a = blockIdx.y * BP_TY;
     const int d1 = tid % BP_TX, d2 = tid / BP_TX;  // rows d2 + RSTEP i
     const int gsz = (n + groups - 1) / groups;

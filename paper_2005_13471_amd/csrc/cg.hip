@@ -7,12 +7,11 @@
 // and every kernel queued after it returns at once.
 //
 // An iteration is three kernels, the Gram-filtering passes with the vector
-// work folded in (gram_apply.hip, k_cgf_*): the inverse row pass also forms
-// the FP64 partial dots p.Ap, r.Ap and Ap.Ap, and the next forward row pass
-// derives alpha = ||r||^2 / p.Ap, the updated norm
-// ||r - alpha Ap||^2 = ||r||^2 - 2 alpha r.Ap + alpha^2 Ap.Ap and beta from
-// them, updates x, r and p on its rows and transforms p.  In exact
-// arithmetic these are the textbook CG iterates.
+// work folded in (gram_apply.hip, k_cgf_*), in the Chronopoulos-Gear
+// arrangement: the inverse row pass forms w = A r and the FP64 partial dots
+// r.r and r.w; the next forward row pass reduces them, derives beta and
+// alpha, updates p, s = A p, x and r on its rows and transforms the new r.
+// In exact arithmetic these are the textbook CG iterates.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -220,7 +219,7 @@ static CGLayout cg_layout(const gct_plan *p, size_t elem)
     L.Ap = o; o += img;
     L.sv = o; o += img;  // s = A p of the fused iteration
     L.xt = o; o += img;  // iterate of the autotuner's trial solves
-    L.part = o; o += align256((size_t)3 * np * sizeof(double));  // three partial dots per row pair
+    L.part = o; o += align256((size_t)2 * np * sizeof(double));  // r.r and r.w per row pair
     L.part2 = o; o += align256((size_t)np * sizeof(double));
     L.st = o; o += align256(sizeof(CGState));
     L.total = o;

@@ -236,13 +236,17 @@ int gct_plan_get_pass_elems(const gct_plan *plan, gct_dtype dtype, int32_t *out)
 
 /* Launch shape the plan chose for gct_backproject_boxspline in `dtype`
  * (Sec. 5 back projection; the arithmetic is the same on every path): out
- * (HOST, 3 ints) = {angles per chunk of the pixel-tiled kernel, whose
+ * (HOST, 4 ints) = {angles per chunk of the pixel-tiled kernel, whose
  * per-(tile, angle) tables must fit in 64 KB of LDS (0: they do not, and the
  * per-angle kernel runs instead), angle groups of the tiled kernel (1 when
  * it does not run), tile side of the per-angle kernel (32, 16 or 8; 0
  * when the tiled kernel runs; also 0 when neither fits, and back projection
- * then returns GCT_EHIP)}.  Fine detector sampling (small lambda_y relative to the
- * pixel) and FP64 widen the tables. */
+ * then returns GCT_EHIP), sub-interval breakpoints the tiled kernel holds in
+ * registers per angle (5, 9 or, FP32 only, 16: at least the most
+ * sub-intervals of any angle; 0 when they are searched in LDS or the tiled
+ * kernel does not run)}.  Fine detector sampling (small lambda_y relative to
+ * the pixel) and FP64 widen the tables; detectors of several boxes add
+ * sub-intervals. */
 int gct_plan_get_bp_shape(const gct_plan *plan, gct_dtype dtype, int32_t *out);
 
 /* Result of gct_cg_solve (host struct). */

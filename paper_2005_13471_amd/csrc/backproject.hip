@@ -233,8 +233,10 @@ k_bp_etab(const T *__restrict__ pf, T *__restrict__ etab, int Mp, int K, int MT,
 //   - the window's rows of the angle's table (k_bp_etab) are copied to LDS
 //     (16 bytes per thread and step; rows outside the table are zero);
 //   - each thread evaluates 8 pixels (rows 4 apart) per angle: one floor,
-//     a sub-interval search, one or two 16-byte LDS reads, an HN-term Horner
-//     scheme (HN >= D1: the coefficients past D1 are the zero padding).
+//     a sub-interval search (branch-free over the SB breakpoints the angle
+//     keeps in registers; SB = 0: a loop over them in LDS), one or two
+//     16-byte LDS reads, an HN-term Horner scheme (HN >= D1: the
+//     coefficients past D1 are the zero padding).
 // The windows of a run of BP_WB angles are computed at once (their geometry
 // loads wait once per run, not per chunk).  The chunk's angles are summed
 // plainly per pixel, then added to a compensated total once per chunk.
@@ -255,7 +257,7 @@ __device__ __forceinline__ void split_floor(T z, int &i, T &t)
     }
 }
 
-template <typename T, int HN>
+template <typename T, int HN, int SB>
 __global__ void __launch_bounds__(BP_NT, BP_WAVES)
 k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT, int groups,
           const double *__restrict__ geo, const int32_t *__restrict__ ints, const T *__restrict__ brk,
@@ -354,19 +356,26 @@ k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT,
                     split_floor(zl, fl, t);
                     return (int)min((unsigned)(base + fl), (unsigned)(R - 1));
                 };
-                if (nsub <= 4) {  // (uniform) branch-free search over at most 3 breakpoints
-                    const T b0 = bk[0];
-                    const T b1 = nsub > 1 ? bk[1] : T(2), b2 = nsub > 2 ? bk[2] : T(2),
-                            b3 = nsub > 3 ? bk[3] : T(2);  // 2: absent (t < 1)
+                if constexpr (SB > 0) {
+                    // branch-free search over the angle's breakpoints held in
+                    // registers (SB >= smax; entries at or past nsub are 2,
+                    // never passed since t < 1)
+                    T bb[SB];
+#pragma unroll
+                    for (int q = 0; q < SB; ++q) bb[q] = q < smax ? bk[q] : T(2);
 #pragma unroll
                     for (int i = 0; i < PPT; ++i) {
                         T t;
                         const int mi = bin_of(zrow + (T)i * rstep, t);
-                        const bool g1 = t >= b1, g2 = t >= b2, g3 = t >= b3;
-                        const T *e = row(mi, (int)g1 + (int)g2 + (int)g3);
-                        T bs = g1 ? b1 : b0;  // breakpoints ascend: the last one passed
-                        bs = g2 ? b2 : bs;
-                        bs = g3 ? b3 : bs;
+                        int sub = 0;
+                        T bs = bb[0];  // breakpoints ascend: the last one passed
+#pragma unroll
+                        for (int q = 1; q < SB; ++q) {
+                            const bool g = t >= bb[q];
+                            sub += (int)g;
+                            bs = g ? bb[q] : bs;
+                        }
+                        const T *e = row(mi, sub);
                         T ev[HN];
 #pragma unroll
                         for (int k = 0; k < HN; ++k) ev[k] = e[k];
@@ -419,15 +428,41 @@ __global__ void __launch_bounds__(256) k_bp_reduce(const T *__restrict__ part, i
 }
 
 // Tiled kernel for the plan's Horner length HN (the kernel degree + 1
-// rounded up to 4, 6 or 8).
+// rounded up to 4, 6 or 8) and breakpoint registers SB (the most
+// sub-intervals of an angle rounded up to 5, 9 or, in FP32, 16; 0: more,
+// searched in LDS).  With one detector box generic angles have 5
+// sub-intervals at bin width 1 (the fractional parts of the footprint's four
+// kinks, and 0) and 9 at bin width 1/2.
 static int bp_hn(const gct_plan *p) { return p->bp.D1 <= 4 ? 4 : (p->bp.D1 <= 6 ? 6 : 8); }
+static int bp_sb(const gct_plan *p, size_t elem)
+{
+    const int s = p->bp.smax;
+    return s <= 5 ? 5 : (s <= 9 ? 9 : (s <= 16 && elem == 4 ? 16 : 0));
+}
+int bp_breakpoint_regs(const gct_plan *p, size_t elem) { return bp_sb(p, elem); }
+#define GCT_BP_TILE_CASES(CASE)                                                                        \
+    switch (bp_hn(p) * 32 + bp_sb(p, sizeof(T))) {                                                    \
+    case 4 * 32 + 5: CASE(4, 5); break;                                                               \
+    case 4 * 32 + 9: CASE(4, 9); break;                                                               \
+    case 4 * 32 + 16: CASE(4, 16); break;                                                             \
+    case 4 * 32 + 0: CASE(4, 0); break;                                                               \
+    case 6 * 32 + 5: CASE(6, 5); break;                                                               \
+    case 6 * 32 + 9: CASE(6, 9); break;                                                               \
+    case 6 * 32 + 16: CASE(6, 16); break;                                                             \
+    case 6 * 32 + 0: CASE(6, 0); break;                                                               \
+    case 8 * 32 + 5: CASE(8, 5); break;                                                               \
+    case 8 * 32 + 9: CASE(8, 9); break;                                                               \
+    case 8 * 32 + 16: CASE(8, 16); break;                                                             \
+    default: CASE(8, 0); break;                                                                       \
+    }
 template <typename T>
 static const void *bp_tile_fn(const gct_plan *p)
 {
-    const int hn = bp_hn(p);
-    return hn == 4 ? reinterpret_cast<const void *>(&k_bp_tile<T, 4>)
-                   : (hn == 6 ? reinterpret_cast<const void *>(&k_bp_tile<T, 6>)
-                              : reinterpret_cast<const void *>(&k_bp_tile<T, 8>));
+    const void *fn = nullptr;
+#define GCT_BP_FN(HN_, SB_) fn = reinterpret_cast<const void *>(&k_bp_tile<T, HN_, SB_>)
+    GCT_BP_TILE_CASES(GCT_BP_FN)
+#undef GCT_BP_FN
+    return fn;
 }
 
 // Bins of a tile's window and the LDS bytes of the tiled kernel for `ch`
@@ -563,13 +598,10 @@ hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, T *
             const dim3 grid((N + BP_TX - 1) / BP_TX, (N + BP_TY - 1) / BP_TY, groups);
             T *dst = groups > 1 ? part : b;
             const size_t lds = bp_tile_lds(p, sizeof(T), ch);
-#define GCT_BP_TILE(HN_)                                                                                      \
-    hipLaunchKernelGGL((k_bp_tile<T, HN_>), grid, dim3(BP_NT), lds, s, (const T *)etab, dst, N, p->n, MT, groups, \
-                       geo_, ints_, brk_, smax, rmax, ch)
-            const int hn = bp_hn(p);
-            if (hn == 4) GCT_BP_TILE(4);
-            else if (hn == 6) GCT_BP_TILE(6);
-            else GCT_BP_TILE(8);
+#define GCT_BP_TILE(HN_, SB_)                                                                             \
+    hipLaunchKernelGGL((k_bp_tile<T, HN_, SB_>), grid, dim3(BP_NT), lds, s, (const T *)etab, dst, N, p->n, MT, \
+                       groups, geo_, ints_, brk_, smax, rmax, ch)
+            GCT_BP_TILE_CASES(GCT_BP_TILE)
 #undef GCT_BP_TILE
             if (groups > 1) {
                 const size_t len = (size_t)N * N;

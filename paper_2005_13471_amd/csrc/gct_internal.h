@@ -222,6 +222,9 @@ BPWorkspace bp_workspace(const gct_plan *p, size_t elem);
 // Tile side of the per-angle back-projection kernel (taken when the tiled
 // kernel's tables do not fit, bp_ch == 0), or 0 when its LDS does not fit.
 int bp_fallback_tile(const gct_plan *p, size_t elem);
+// Breakpoints the tiled back-projection kernel holds in registers per angle
+// (5, 9 or 16; 0: searched in LDS).
+int bp_breakpoint_regs(const gct_plan *p, size_t elem);
 
 // Default elements per thread of the row passes and of the column pass for a
 // transform of size P (what the autotuner picks on MI355X at P = 1024: the

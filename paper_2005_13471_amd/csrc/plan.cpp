@@ -880,6 +880,7 @@ int gct_plan_get_bp_shape(const gct_plan *p, gct_dtype dt, int32_t *out)
     out[0] = p->bp_ch[t];
     out[1] = p->bp_ch[t] > 0 ? p->bp_groups[t] : 1;
     out[2] = p->bp_ch[t] > 0 ? 0 : bp_fallback_tile(p, e);
+    out[3] = p->bp_ch[t] > 0 ? bp_breakpoint_regs(p, e) : 0;
     return GCT_OK;
 }
 

@@ -368,8 +368,9 @@ def plan_get_pass_elems(plan: Plan, dtype=torch.float32):
 def plan_get_bp_shape(plan: Plan, dtype=torch.float32):
     """Back-projection launch shape: (angles per chunk of the tiled kernel,
     0 when the per-angle kernel runs; angle groups; per-angle tile side, 0
-    when the tiled kernel runs)."""
-    out = (ctypes.c_int32 * 3)()
+    when the tiled kernel runs; breakpoints held in registers by the tiled
+    kernel, 0 when searched in memory or when it does not run)."""
+    out = (ctypes.c_int32 * 4)()
     _check(lib.gct_plan_get_bp_shape(plan.handle, F32 if dtype == torch.float32 else F64, out))
     return tuple(int(v) for v in out)
 

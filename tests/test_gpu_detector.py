@@ -23,8 +23,11 @@ def _bins(N, wmax, ly):
 
 
 class DCase:
-    def __init__(self, N, n, boxes, ly=1.0, lx=(1.0, 1.0), shift=0.0):
-        self.N, self.boxes, self.ly, self.lx = N, boxes, ly, lx
+    # regs: breakpoints the tiled back projection holds in registers per
+    # angle in (FP32, FP64), 0 for a search in memory (13 sub-intervals with
+    # boxes of widths 1 and 1/2, 17 and 25 for the others)
+    def __init__(self, N, n, boxes, ly=1.0, lx=(1.0, 1.0), shift=0.0, regs=(0, 0)):
+        self.N, self.boxes, self.ly, self.lx, self.regs = N, boxes, ly, lx, regs
         self.theta = inputs.angles(n) + shift
         self.n = n
         self.M = _bins(N, max(w for w, _ in boxes), ly)
@@ -39,7 +42,7 @@ class DCase:
         return f"N={self.N} n={self.n} boxes={self.boxes} ly={self.ly} lx={self.lx}"
 
 
-CASES = [DCase(32, 24, [(1.0, 0.6), (0.5, 0.8)]),
+CASES = [DCase(32, 24, [(1.0, 0.6), (0.5, 0.8)], regs=(16, 0)),
          DCase(27, 17, [(1.2, 0.3), (0.7, 0.5), (0.3, 0.8)], ly=0.8, lx=(0.9, 1.1), shift=0.013),
          DCase(20, 12, [(0.8, 1.0), (0.4, -0.5)])]
 
@@ -85,8 +88,11 @@ def test_multibox_gram_forward_backproject(gct, case, dt):
     gct.backproject_boxspline(P, torch.as_tensor(sino.reshape(-1), dtype=dt, device="cuda"), b,
                               P.workspace(gct.OP_BACKPROJECT, dt))
     eb = normwise(_host(b).reshape(case.N, case.N), oracle.backproject(og, sino))
-    say("  backproject", eb, "shape", gct.plan_get_bp_shape(P, dt))
+    shape = gct.plan_get_bp_shape(P, dt)
+    say("  backproject", eb, "shape", shape)
     assert eb <= tol("bp", dt)
+    if shape[0] > 0:
+        assert shape[3] == case.regs[0 if dt == torch.float32 else 1], shape
 
 
 def test_multibox_cg_converges_with_oracle_recheck(gct):

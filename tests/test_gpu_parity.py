@@ -217,8 +217,11 @@ def test_default_transform_tilings(gct):
 def test_plan_autotune_then_cg(gct, N):
     """The autotuner picks a candidate; CG with the tuned plan converges to
     the same stopping rule as with the default tiling, in about as many
-    iterations."""
-    case, dt = Case(N, 360, zeta=1.0), torch.float32
+    iterations.  The angles sample the image fully (n > pi N / 2): with
+    fewer the system is ill-conditioned, CG takes about 200 iterations with
+    a residual that oscillates around the threshold, and where it first
+    dips below depends on the rounding of each tiling."""
+    case, dt = Case(N, (8 * N) // 5, zeta=1.0), torch.float32
     P = case.plan(gct)
     G = torch.empty(P.info.gram_elems, dtype=dt, device="cuda")
     gct.gram_build(P, G)
@@ -360,6 +363,29 @@ def test_backproject_per_angle_kernel(gct, case, dt):
     say("backproject per-angle", case, dt, "shape", shape)
     assert shape[0] == 0 and shape[2] in (8, 16, 32), shape
     g = _sino(case, 1004)
+    got = _bp_gpu(gct, case, dt, g)
+    ref = oracle.backproject(case.og(), g)
+    err = normwise(got, ref)
+    say("  normwise", err)
+    assert err <= tol("bp", dt)
+
+
+# Sub-interval breakpoints per angle (Sec. 5: the fractional parts of the
+# footprint's kinks within a bin, and 0): 5 without blur or with blur 1 at
+# bin width 1, 9 with blur 1/2 or at bin width 3/4.  The tiled kernel holds
+# them in registers (5 or 9); each tier against the oracle.
+BP_TIERS = [(Case(40, 30, zeta=1.0), 5), (Case(40, 30, zeta=0.0), 5), (Case(40, 30, zeta=0.5), 9),
+            (Case(40, 30, M=_bins(40, 1.0, 0.75), zeta=1.0, ly=0.75), 9)]
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("case,regs", BP_TIERS, ids=lambda v: repr(v))
+def test_backproject_breakpoint_registers(gct, case, regs, dt):
+    P = case.plan(gct)
+    shape = gct.plan_get_bp_shape(P, dt)
+    say("backproject breakpoints", case, dt, "shape", shape)
+    assert shape[0] > 0 and shape[3] == regs, shape
+    g = _sino(case, 1006)
     got = _bp_gpu(gct, case, dt, g)
     ref = oracle.backproject(case.og(), g)
     err = normwise(got, ref)

@@ -71,9 +71,11 @@ hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s
 // B-spline basis of the interpolated sinogram.
 //
 // On each sub-interval s of t = z - floor(z), kappa(j - t) is a polynomial
-// in u = t - brk[s] with coefficients C[s][j][.] (built exactly on the host),
-// so the whole angle's contribution is the piecewise polynomial
-//   S(z) = sum_k u^k E[m0][s][k],  E[m][s][k] = sum_j p[m + jlo + j] C[s][j][k],
+// in t with coefficients C[s][j][.] (built on the host in FP64: exact in the
+// offset from the sub-interval's start brk[s], then re-expanded in powers of
+// t, so that no breakpoint is subtracted per pixel), so the whole angle's
+// contribution is the piecewise polynomial
+//   S(z) = sum_k t^k E[m0][s][k],  E[m][s][k] = sum_j p[m + jlo + j] C[s][j][k],
 // m0 = floor(z).  A block owns a TILE x TILE pixel tile; per angle it forms E
 // for the few bins the tile projects onto (in LDS), then every pixel finds
 // its (m0, s) and evaluates one polynomial.  FP64 is used only for z.
@@ -159,10 +161,9 @@ k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp,
             const T *bk = s_b + c * smax;
             int sub = 0;
             for (int i = 1; i < nsub; ++i) sub += (t >= bk[i]) ? 1 : 0;
-            const T u = t - bk[sub];
             const T *e = E + (mi * nsub + sub) * D1;
             T v = e[D1 - 1];
-            for (int k = D1 - 2; k >= 0; --k) v = v * u + e[k];
+            for (int k = D1 - 2; k >= 0; --k) v = v * t + e[k];
             const T yk = v - comp;
             const T tk = acc + yk;
             comp = (tk - acc) - yk;
@@ -177,7 +178,7 @@ k_backproject(const T *__restrict__ pf, T *__restrict__ b, int N, int n, int Mp,
 // m in [0, MT) (bin mA_a + m of the angle's window over the whole tile grid)
 // and sub-interval s:
 //   E[a][m][s][k] = sum_{j < J} p[a][mA_a + m + jlo_a + j] C[a][s][j][k],
-// the polynomial (in the offset u from the sub-interval's start) of the
+// the polynomial (in the offset t within the bin) of the
 // weighted sum of the J sinogram samples that reach a pixel whose projection
 // falls in that bin and sub-interval; k < D1, padded to 8 with zeros (rows of
 // absent sub-intervals are zero).  p is the prefiltered row, zero outside
@@ -340,7 +341,7 @@ k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT,
                 const T zrow = zf + (T)d1 * dz1 + (T)d2 * dz2;
                 const T rstep = (T)RSTEP * dz2;
                 // value of the angle's interpolant at pixel i, given its row
-                // (bin, sub-interval) and offset t in the bin (u = t - start)
+                // (bin, sub-interval) and offset t in the bin
                 auto row = [&](int mi, int sub) { return Ec + (__umul24(mi, smax) + sub) * D1P; };
                 auto horner = [&](int i, const T *ev, T u) {
                     T v = ev[HN - 1];
@@ -368,18 +369,13 @@ k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT,
                         T t;
                         const int mi = bin_of(zrow + (T)i * rstep, t);
                         int sub = 0;
-                        T bs = bb[0];  // breakpoints ascend: the last one passed
 #pragma unroll
-                        for (int q = 1; q < SB; ++q) {
-                            const bool g = t >= bb[q];
-                            sub += (int)g;
-                            bs = g ? bb[q] : bs;
-                        }
+                        for (int q = 1; q < SB; ++q) sub += (int)(t >= bb[q]);
                         const T *e = row(mi, sub);
                         T ev[HN];
 #pragma unroll
                         for (int k = 0; k < HN; ++k) ev[k] = e[k];
-                        horner(i, ev, t - bs);
+                        horner(i, ev, t);
                     }
                 } else {
 #pragma unroll
@@ -392,7 +388,7 @@ k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT,
                         T ev[HN];
 #pragma unroll
                         for (int k = 0; k < HN; ++k) ev[k] = e[k];
-                        horner(i, ev, t - bk[sub]);
+                        horner(i, ev, t);
                     }
                 }
             }

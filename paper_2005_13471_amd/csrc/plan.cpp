@@ -449,12 +449,24 @@ static int build_plan(const gct_geometry *g, const Detector &det, gct_plan *p)
         ints[4 * a] = t.h.nsub;
         ints[4 * a + 1] = t.h.jlo;
         ints[4 * a + 2] = t.h.degree;
+        // the device kernels evaluate each sub-interval's polynomial in the
+        // offset t within the bin: sum_q c_q (t - b)^q re-expanded in powers
+        // of t, d_k = sum_{q >= k} c_q C(q, k) (-b)^(q - k), in FP64
         for (int s = 0; s < t.h.nsub; ++s) {
-            brk[(size_t)a * smax + s] = t.brk[s];
-            for (int j = 0; j < t.J; ++j)
-                for (int q = 0; q < t.D1; ++q)
-                    coef[(((size_t)a * smax + s) * J + j) * D1 + q] =
-                        t.coef[((size_t)s * t.J + j) * t.D1 + q];
+            const double b = t.brk[s];
+            brk[(size_t)a * smax + s] = b;
+            for (int j = 0; j < t.J; ++j) {
+                const double *c = &t.coef[((size_t)s * t.J + j) * t.D1];
+                for (int k = 0; k < t.D1; ++k) {
+                    double d = 0.0, binom = 1.0, pw = 1.0;  // C(q, k), (-b)^(q - k) at q = k
+                    for (int q = k; q < t.D1; ++q) {
+                        d += c[q] * binom * pw;
+                        binom = binom * (q + 1) / (q + 1 - k);
+                        pw *= -b;
+                    }
+                    coef[(((size_t)a * smax + s) * J + j) * D1 + k] = d;
+                }
+            }
         }
     }
     // rows of the back projection's per-angle interpolant tables: every bin

@@ -95,6 +95,11 @@ typedef struct {
     int64_t image_elems;     /* N^2 */
     int64_t sino_elems;      /* n_angles * M */
     int64_t prefiltered_elems; /* n_angles * (M + 2K) */
+    int32_t gram_symmetry;   /* 8: G has the square's eight symmetries (square pixels, an angle
+                                set closed under theta -> theta + pi/2 and theta -> -theta mod pi,
+                                e.g. theta_i = i pi / n with n even), so gct_gram_build
+                                evaluates one octant of taps; 2: G[k] = G[-k] only, half the
+                                taps evaluated */
 } gct_plan_info;
 
 /* Validate the geometry and build the per-angle tables: box-spline

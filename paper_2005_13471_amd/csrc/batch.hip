@@ -909,6 +909,7 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
             v[i].ghmax = plans[i]->gram_hmax;
             v[i].l1 = plans[i]->lx1;
             v[i].l2 = plans[i]->lx2;
+            v[i].gd4 = plans[i]->gram_d4;
             v[i].tw = t == 0 ? plans[i]->dev.tw_f32 : plans[i]->dev.tw_f64;
         }
         b->dev_bytes += (int64_t)(count * sizeof(BatchSlice));
@@ -977,8 +978,10 @@ int gct_batch_create(const gct_plan *const *plans, int32_t count, gct_batch **ou
     }
     std::vector<int2> gm;
     for (int i = 0; i < count; ++i) {
-        const int N = plans[i]->N;
-        const int tiles = ((2 * N - 1 + GRAM_TILE - 1) / GRAM_TILE) * ((N + GRAM_TILE - 1) / GRAM_TILE);
+        const int N = plans[i]->N, T = (N + GRAM_TILE - 1) / GRAM_TILE;
+        // the tiles of the half plane k2 >= 0, or (eight symmetries) of the
+        // octant 0 <= k2 <= k1
+        const int tiles = plans[i]->gram_d4 ? T * (T + 1) / 2 : ((2 * N - 1 + GRAM_TILE - 1) / GRAM_TILE) * T;
         for (int k = 0; k < tiles; ++k) gm.push_back(make_int2(i, k));
     }
     b->ngram = (int)gm.size();

@@ -208,7 +208,6 @@ __device__ __forceinline__ void dft3x_twiddle(C2<T> (&y)[3][R2])
 template <typename T, int R2, bool INV>
 __device__ __forceinline__ void dft3x(C2<T> *v)
 {
-    constexpr int R = 3 * R2;
     C2<T> y[3][R2];
 #pragma unroll
     for (int n2 = 0; n2 < R2; ++n2) {

@@ -126,6 +126,7 @@ struct BatchSlice {
     const double *gth;
     double ghmax;               // largest support half-width of A_theta
     double l1, l2;              // pixel sides
+    int32_t gd4;                // the plan's gram_d4
 };
 
 // Key of a captured chunk of CG iterations.
@@ -158,6 +159,8 @@ struct gct_plan {
     // footprint boxes per angle
     int32_t gram_n = 0, fwd_nb = 1;
     double gram_hmax;  // largest support half-width of A_theta over the angles
+    int gram_d4;       // G has the square's eight symmetries (square pixels, angle set
+                       // closed under theta -> theta + pi/2 and theta -> -theta, mod pi)
     // elements per thread of the transforms, [F32, F64]: the row passes and
     // the column pass of an apply, and the same for the fused CG passes
     int32_t fft_e[2], fft_ec[2];

@@ -24,7 +24,10 @@
 // Tap offsets are formed in FP64 (k1 cx + k2 sx reaches ~1.5e3 at N = 1024
 // while the spline needs them to ~1e-7) and rounded once.  The sum over
 // angles is compensated (Kahan).  G[k] = G[-k] holds exactly (the footprint
-// is even), so half the taps are evaluated and mirrored.
+// is even), so half the taps are evaluated and mirrored; when the plan's
+// angle set and pixels give G the eight symmetries of the square (gram_d4),
+// only the octant 0 <= k2 <= k1 is evaluated and each tap is written to its
+// eight images.
 #include <cmath>
 
 #include "gct_internal.h"
@@ -66,7 +69,9 @@ __device__ __forceinline__ T gram_A(const GramAngle<T> &g, T x, bool blur)
 
 // One square tile of taps per block (side below), covering only taps with
 // k2 > 0 or (k2 = 0, k1 >= 0); each such tap also writes its mirror -k (G
-// is even).
+// is even).  With d4 the tiles cover the octant instead: tile (bx, by),
+// by <= bx, holds taps (bx TS + tx, by TS + ty), and the taps with
+// k2 <= k1 < N write all eight images.
 //
 // Angular windows.  Tap k projects to k1 l1 cos + k2 l2 sin = rho cos(theta -
 // phi) with (rho, phi) the polar form of (k1 l1, k2 l2), so A_theta(k) can be
@@ -117,11 +122,23 @@ __device__ __forceinline__ int lower_idx_wave(const double *th, int n, double v)
     return min(n, base + __popcll(__ballot(below)));
 }
 
+// Tile (bx, by) of the octant's triangle of T tiles a side, by <= bx, from
+// its index k in [0, T (T + 1) / 2) (rows of the triangle in order).
+__device__ __forceinline__ void octant_tile(int k, int T, int &bx, int &by)
+{
+    by = 0;
+    while (k >= T - by) {
+        k -= T - by;
+        ++by;
+    }
+    bx = by + k;
+}
+
 template <typename T, bool SPLIT>
 __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G, int N, int n,
                                                const GramAngle<T> *__restrict__ ga,
                                                const int32_t *__restrict__ ord, const double *__restrict__ th,
-                                               double hmax, double l1, double l2)
+                                               double hmax, double l1, double l2, bool d4)
 {
     constexpr int TS = SPLIT ? GRAM_TILE_SPLIT : GRAM_TILE;
     __shared__ GramAngle<T> sg[256];
@@ -131,10 +148,10 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tap = SPLIT ? lane : tid;  // SPLIT: every wave holds the tile's 64 taps
     const int tx = tap % TS, ty = tap / TS;
-    const int k1a = bx * TS - (N - 1);  // first tap column of the tile
-    const int k2a = by * TS;            // first tap row (>= 0)
+    const int k1a = d4 ? bx * TS : bx * TS - (N - 1);  // first tap column of the tile
+    const int k2a = by * TS;                          // first tap row (>= 0)
     const int k1 = k1a + tx, k2 = k2a + ty;
-    const bool live = k1 <= N - 1 && k2 <= N - 1 && (k2 > 0 || k1 >= 0);
+    const bool live = d4 ? (k1 <= N - 1 && k2 <= k1) : (k1 <= N - 1 && k2 <= N - 1 && (k2 > 0 || k1 >= 0));
     const double ka = k1a, kb = k1a + TS - 1, la = k2a, lb = k2a + TS - 1;
     // the tile's runs of sorted angles (the same in every thread)
     int run_lo[2] = {0, 0}, run_hi[2] = {n, 0};
@@ -197,11 +214,21 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
                 acc = tk;
             }
         }
-    if (!SPLIT) {
-        if (live) {
-            G[(size_t)(k2 + N - 1) * W + (k1 + N - 1)] = acc;
-            G[(size_t)(N - 1 - k2) * W + (N - 1 - k1)] = acc;
+    // tap (a, b) of value v at row b, column a; with d4 its eight images
+    auto put = [&](T v) {
+        G[(size_t)(k2 + N - 1) * W + (k1 + N - 1)] = v;
+        G[(size_t)(N - 1 - k2) * W + (N - 1 - k1)] = v;
+        if (d4) {
+            G[(size_t)(k2 + N - 1) * W + (N - 1 - k1)] = v;
+            G[(size_t)(N - 1 - k2) * W + (k1 + N - 1)] = v;
+            G[(size_t)(k1 + N - 1) * W + (k2 + N - 1)] = v;
+            G[(size_t)(N - 1 - k1) * W + (N - 1 - k2)] = v;
+            G[(size_t)(k1 + N - 1) * W + (N - 1 - k2)] = v;
+            G[(size_t)(N - 1 - k1) * W + (k2 + N - 1)] = v;
         }
+    };
+    if (!SPLIT) {
+        if (live) put(acc);
         return;
     }
     racc[wave][lane] = acc;
@@ -218,17 +245,18 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
             c = (tk - s) - yk;
             s = tk;
         }
-        G[(size_t)(k2 + N - 1) * W + (k1 + N - 1)] = s;
-        G[(size_t)(N - 1 - k2) * W + (N - 1 - k1)] = s;
+        put(s);
     }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ ga, const int32_t *__restrict__ ord,
-             const double *__restrict__ th, double hmax, double l1, double l2)
+             const double *__restrict__ th, double hmax, double l1, double l2, int d4)
 {
-    body_gram_tile<T, true>(blockIdx.x, blockIdx.y, G, N, n, ga, ord, th, hmax, l1, l2);
+    int bx = blockIdx.x, by = blockIdx.y;  // d4: a one-dimensional grid over the octant's tiles
+    if (d4) octant_tile(blockIdx.x, (N + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT, bx, by);
+    body_gram_tile<T, true>(bx, by, G, N, n, ga, ord, th, hmax, l1, l2, d4 != 0);
 }
 
 // Batched: block b covers tile map[b].y of slice map[b].x.
@@ -238,21 +266,28 @@ kb_gram_build(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl, T
 {
     const int2 m = map[blockIdx.x];
     const BatchSlice &d = sl[m.x];
-    const int tiles_x = (2 * d.N - 1 + GRAM_TILE - 1) / GRAM_TILE;
-    body_gram_tile<T, false>(m.y % tiles_x, m.y / tiles_x, G + d.gram, d.N, d.n, reinterpret_cast<const GramAngle<T> *>(d.ga),
-                      d.gord, d.gth, d.ghmax, d.l1, d.l2);
+    int bx, by;
+    if (d.gd4) {
+        octant_tile(m.y, (d.N + GRAM_TILE - 1) / GRAM_TILE, bx, by);
+    } else {
+        const int tiles_x = (2 * d.N - 1 + GRAM_TILE - 1) / GRAM_TILE;
+        bx = m.y % tiles_x;
+        by = m.y / tiles_x;
+    }
+    body_gram_tile<T, false>(bx, by, G + d.gram, d.N, d.n, reinterpret_cast<const GramAngle<T> *>(d.ga), d.gord,
+                             d.gth, d.ghmax, d.l1, d.l2, d.gd4 != 0);
 }
 
 template <typename T>
 hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s)
 {
-    const int W = 2 * p->N - 1;
-    const dim3 grid((W + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT, (p->N + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT);
+    const int W = 2 * p->N - 1, TN = (p->N + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT;
+    const dim3 grid = p->gram_d4 ? dim3(TN * (TN + 1) / 2) : dim3((W + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT, TN);
     const GramAngle<T> *ga =
         reinterpret_cast<const GramAngle<T> *>(sizeof(T) == 4 ? p->dev.gram_f32 : p->dev.gram_f64);
     hipLaunchKernelGGL(k_gram_build<T>, grid, dim3(256), 0, s, G, p->N, p->gram_n, ga,
                        reinterpret_cast<const int32_t *>(p->dev.gram_ord),
-                       reinterpret_cast<const double *>(p->dev.gram_th), p->gram_hmax, p->lx1, p->lx2);
+                       reinterpret_cast<const double *>(p->dev.gram_th), p->gram_hmax, p->lx1, p->lx2, p->gram_d4);
     return hipGetLastError();
 }
 

@@ -314,6 +314,38 @@ static FwdAngle<T> fwd_angle(const AngleDirs &d, double l1, double l2, double ze
 }
 
 // Back-projection kernel of one angle as sub-interval polynomials (see
+// Whether G has the eight symmetries of the square (Sec. 4: G[k] sums
+// A_theta(k1 l1 c + k2 l2 s), and A_theta depends on |c| and |s| alone, the
+// same way on both): with square pixels, an angle set closed under
+// theta -> theta + pi/2 and under theta -> -theta (mod pi, multiplicities
+// included) makes G[k1][k2] = G[k2][-k1] = G[-k1][k2].  Uniform sets
+// theta_i = i pi / n with n even qualify.  Angles are compared within 1e-14
+// (a few units in the last place of pi): a tap at distance 2^11 then moves by
+// less than 1e-10 of a bin.
+static bool gram_symmetric(const double *theta, int n, double l1, double l2)
+{
+    if (l1 != l2 || n < 1) return false;
+    const double tol = 1e-14;
+    auto norm = [&](double t) {
+        t = std::fmod(t, M_PI);
+        if (t < 0.0) t += M_PI;
+        if (t >= M_PI - tol) t = 0.0;  // pi is 0
+        return t;
+    };
+    std::vector<double> a(n), r(n), m(n);
+    for (int i = 0; i < n; ++i) {
+        a[i] = norm(theta[i]);
+        r[i] = norm(a[i] + 0.5 * M_PI);
+        m[i] = norm(M_PI - a[i]);
+    }
+    std::sort(a.begin(), a.end());
+    std::sort(r.begin(), r.end());
+    std::sort(m.begin(), m.end());
+    for (int i = 0; i < n; ++i)
+        if (std::fabs(r[i] - a[i]) > tol || std::fabs(m[i] - a[i]) > tol) return false;
+    return true;
+}
+
 // BPAngleHost).  coef is [nsub][J][D1] for this angle, J and D1 its own.
 struct BPAngleTable {
     BPAngleHost h;
@@ -527,6 +559,7 @@ static int build_plan(const gct_geometry *g, const Detector &det, gct_plan *p)
         std::vector<double> ths(ne);
         for (int e = 0; e < ne; ++e) ths[e] = th[ord[e]];
         p->gram_hmax = hmax;
+        p->gram_d4 = gram_symmetric(g->theta, n, l1, l2) ? 1 : 0;
         if ((rc = up(&p->dev.gram_ord, ord))) return rc;
         if ((rc = up(&p->dev.gram_th, ths))) return rc;
     }
@@ -691,6 +724,7 @@ int gct_plan_get_info(const gct_plan *p, gct_plan_info *info)
     info->image_elems = (int64_t)p->N * p->N;
     info->sino_elems = (int64_t)p->n * p->M;
     info->prefiltered_elems = (int64_t)p->n * (p->M + 2 * p->K);
+    info->gram_symmetry = p->gram_d4 ? 8 : 2;
     return GCT_OK;
 }
 

@@ -43,7 +43,7 @@ class _PlanInfo(ctypes.Structure):
                 ("prefilter_K", ctypes.c_int32), ("fft_size", ctypes.c_int32),
                 ("gram_elems", ctypes.c_int64), ("spectrum_elems", ctypes.c_int64),
                 ("image_elems", ctypes.c_int64), ("sino_elems", ctypes.c_int64),
-                ("prefiltered_elems", ctypes.c_int64)]
+                ("prefiltered_elems", ctypes.c_int64), ("gram_symmetry", ctypes.c_int32)]
 
 
 class _CGResult(ctypes.Structure):
@@ -195,6 +195,7 @@ class PlanInfo:
     image_elems: int
     sino_elems: int
     prefiltered_elems: int
+    gram_symmetry: int  # 8: one octant of Gram taps evaluated; 2: half of them
 
 
 class Plan:

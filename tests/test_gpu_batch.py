@@ -39,6 +39,8 @@ def _packed(batch, arrays, dt):
 def test_batch_gram_build_and_apply_match_oracle(batch_setup, dt):
     gct, B, plans, ogs = batch_setup
     say("batch gram_build / apply", dt)
+    # the first slice's uniform even angle set: one octant of taps evaluated
+    assert [p.info.gram_symmetry for p in plans] == [8, 2, 2, 2, 2]
     G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
     gct.batch_gram_build(B, G)
     Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")

@@ -90,6 +90,33 @@ def test_gram_build_full(gct, case, dt):
     assert np.max(np.abs(got - got[::-1, ::-1])) <= 4 * tol("gram", dt) * np.max(np.abs(ref))
 
 
+# Which taps the Gram build evaluates (Sec. 4: G sums A_theta(k1 l1 c + k2 l2 s)
+# and A_theta depends on |c| and |s| alike): one octant when the pixels are
+# square and the angle set is closed under theta -> theta + pi/2 and
+# theta -> -theta (mod pi), its images written by symmetry; half the plane
+# otherwise.  Both against the oracle, which evaluates every tap.
+GRAM_SYM = [(CFG1, 8), (Case(40, 30, zeta=1.0), 8), (Case(37, 45, zeta=1.0), 2),
+            (Case(40, 30, zeta=1.0, theta=inputs.angles(30) + 0.013), 2),
+            (Case(40, 30, zeta=1.0, lx=(0.9, 1.2)), 2),
+            (Case(33, 32, zeta=0.5, theta=inputs.angles(32)[::-1].copy()), 8),
+            (Case(33, 4, zeta=0.0, theta=np.array([0.0, np.pi / 2, np.pi / 2, 0.0])), 8),
+            (Case(33, 3, zeta=0.0, theta=np.array([0.0, np.pi / 2, np.pi / 2])), 2)]
+
+
+@pytest.mark.parametrize("dt", DTYPES)
+@pytest.mark.parametrize("case,sym", GRAM_SYM, ids=lambda v: repr(v))
+def test_gram_build_symmetry(gct, case, sym, dt):
+    P = case.plan(gct)
+    say("gram_build symmetry", case, dt, P.info.gram_symmetry)
+    assert P.info.gram_symmetry == sym
+    got = _gram(gct, case, dt)
+    err = normwise(got, oracle.gram(case.og()))
+    say("  normwise", err)
+    assert err <= tol("gram", dt)
+    if sym == 8:  # the images are copies of the octant's values
+        assert np.array_equal(got, got.T) and np.array_equal(got, got[::-1, :])
+
+
 @pytest.mark.parametrize("N", [1, 2, 3])
 def test_gram_build_tiny_sizes(gct, N):
     case = Case(N, 7, zeta=0.7, theta=inputs.angles(7) + 0.2)

@@ -89,10 +89,10 @@ __device__ __forceinline__ T gram_A(const GramAngle<T> &g, T x, bool blur)
 // pass are packed in order into LDS (wave ballots, so the order is fixed;
 // per-angle loads straight from the tables were a chain of two dependent
 // scalar loads per angle).  SPLIT (one slice, 8 x 8 taps per block): the
-// block's 4 waves each hold the tile's 64 taps and take every 4th packed
-// angle, so the tiles at the origin, which every angle reaches and which
-// set the kernel's duration, cost a quarter of the angles per wave; the
-// four compensated partial sums are added in wave order at the end.  Not
+// block's NW waves (4 or 8) each hold the tile's 64 taps and take every
+// NW-th packed angle, so the tiles at the origin, which every angle reaches
+// and which set the kernel's duration, cost 1/NW of the angles per wave;
+// the NW compensated partial sums are added in wave order at the end.  Not
 // SPLIT (batches, 16 x 16 taps per block, many more tiles than CUs): every
 // thread owns one tap and takes every packed angle.
 __device__ __forceinline__ int lower_idx(const double *th, int n, double v)
@@ -134,7 +134,7 @@ __device__ __forceinline__ void octant_tile(int k, int T, int &bx, int &by)
     bx = by + k;
 }
 
-template <typename T, bool SPLIT>
+template <typename T, bool SPLIT, int NW>
 __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G, int N, int n,
                                                const GramAngle<T> *__restrict__ ga,
                                                const int32_t *__restrict__ ord, const double *__restrict__ th,
@@ -142,8 +142,8 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
 {
     constexpr int TS = SPLIT ? GRAM_TILE_SPLIT : GRAM_TILE;
     __shared__ GramAngle<T> sg[256];
-    __shared__ int wcnt[4];
-    __shared__ T racc[4][64], rcomp[4][64];
+    __shared__ int wcnt[NW];
+    __shared__ T racc[NW][64], rcomp[NW][64];
     const int W = 2 * N - 1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tap = SPLIT ? lane : tid;  // SPLIT: every wave holds the tile's 64 taps
@@ -185,7 +185,7 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
             const int cnt = min(256, run_hi[run] - j0);
             GramAngle<T> g;
             bool hit = false;
-            if (tid < cnt) {
+            if (tid < cnt) {  // (the first 256 threads)
                 g = ga[ord[j0 + tid]];
                 // projected interval of the tile (extreme corners)
                 const double p1 = ka * g.cx, p2 = kb * g.cx, q1 = la * g.sx, q2 = lb * g.sx;
@@ -198,13 +198,13 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
             __syncthreads();
             int off = 0, total = 0;
 #pragma unroll
-            for (int w = 0; w < 4; ++w) {
+            for (int w = 0; w < NW; ++w) {
                 off += w < wave ? wcnt[w] : 0;
                 total += wcnt[w];
             }
             if (hit) sg[off + __popcll(mask & ((1ull << lane) - 1ull))] = g;
             __syncthreads();
-            for (int jj = SPLIT ? wave : 0; jj < total; jj += SPLIT ? 4 : 1) {
+            for (int jj = SPLIT ? wave : 0; jj < total; jj += SPLIT ? NW : 1) {
                 const GramAngle<T> &h = sg[jj];
                 const T dd = (T)(dk1 * h.cx + dk2 * h.sx);
                 const T v = h.S > T(0) ? gram_A(h, dd, true) : gram_A(h, dd, false);
@@ -235,10 +235,10 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
     rcomp[wave][lane] = comp;
     __syncthreads();
     if (wave == 0 && live) {
-        // compensated sum of the four partial sums (value acc - comp each), in order
+        // compensated sum of the NW partial sums (value acc - comp each), in order
         T s = 0, c = 0;
 #pragma unroll
-        for (int w = 0; w < 8; ++w) {
+        for (int w = 0; w < 2 * NW; ++w) {
             const T v = (w & 1) ? -rcomp[w >> 1][lane] : racc[w >> 1][lane];
             const T yk = v - c;
             const T tk = s + yk;
@@ -249,14 +249,14 @@ __device__ __forceinline__ void body_gram_tile(int bx, int by, T *__restrict__ G
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256)
+template <typename T, int NW>
+__global__ void __launch_bounds__(64 * NW)
 k_gram_build(T *__restrict__ G, int N, int n, const GramAngle<T> *__restrict__ ga, const int32_t *__restrict__ ord,
              const double *__restrict__ th, double hmax, double l1, double l2, int d4)
 {
     int bx = blockIdx.x, by = blockIdx.y;  // d4: a one-dimensional grid over the octant's tiles
     if (d4) octant_tile(blockIdx.x, (N + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT, bx, by);
-    body_gram_tile<T, true>(bx, by, G, N, n, ga, ord, th, hmax, l1, l2, d4 != 0);
+    body_gram_tile<T, true, NW>(bx, by, G, N, n, ga, ord, th, hmax, l1, l2, d4 != 0);
 }
 
 // Batched: block b covers tile map[b].y of slice map[b].x.
@@ -274,7 +274,7 @@ kb_gram_build(const int2 *__restrict__ map, const BatchSlice *__restrict__ sl, T
         bx = m.y % tiles_x;
         by = m.y / tiles_x;
     }
-    body_gram_tile<T, false>(bx, by, G + d.gram, d.N, d.n, reinterpret_cast<const GramAngle<T> *>(d.ga), d.gord,
+    body_gram_tile<T, false, 4>(bx, by, G + d.gram, d.N, d.n, reinterpret_cast<const GramAngle<T> *>(d.ga), d.gord,
                              d.gth, d.ghmax, d.l1, d.l2, d.gd4 != 0);
 }
 
@@ -283,11 +283,24 @@ hipError_t launch_gram_build(const gct_plan *p, T *G, hipStream_t s)
 {
     const int W = 2 * p->N - 1, TN = (p->N + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT;
     const dim3 grid = p->gram_d4 ? dim3(TN * (TN + 1) / 2) : dim3((W + GRAM_TILE_SPLIT - 1) / GRAM_TILE_SPLIT, TN);
+    // Waves per block: the tiles at the origin, which every angle reaches,
+    // take n / NW angles per wave; the far tiles take few, and larger blocks
+    // leave more of their waves idle and fewer blocks resident.  8 waves when
+    // the tiles are few against the angles (at most 6 n), else 4.  Measured
+    // on MI355X (ms, 4 / 8 / 16 waves): 512^2 / 720 angles, octant 0.069 /
+    // 0.043 / 0.056, half plane 0.073 / 0.084 / 0.144; 1024^2 / 1440 octant
+    // 0.132 / 0.100 / 0.178; 2048^2 / 1800 octant 0.23 / 0.44 / 0.84.
+    const bool wide = (long long)grid.x * grid.y <= 6LL * p->n;
     const GramAngle<T> *ga =
         reinterpret_cast<const GramAngle<T> *>(sizeof(T) == 4 ? p->dev.gram_f32 : p->dev.gram_f64);
-    hipLaunchKernelGGL(k_gram_build<T>, grid, dim3(256), 0, s, G, p->N, p->gram_n, ga,
-                       reinterpret_cast<const int32_t *>(p->dev.gram_ord),
-                       reinterpret_cast<const double *>(p->dev.gram_th), p->gram_hmax, p->lx1, p->lx2, p->gram_d4);
+    const int32_t *ord = reinterpret_cast<const int32_t *>(p->dev.gram_ord);
+    const double *th = reinterpret_cast<const double *>(p->dev.gram_th);
+    if (wide)
+        hipLaunchKernelGGL((k_gram_build<T, 8>), grid, dim3(512), 0, s, G, p->N, p->gram_n, ga, ord, th, p->gram_hmax,
+                           p->lx1, p->lx2, p->gram_d4);
+    else
+        hipLaunchKernelGGL((k_gram_build<T, 4>), grid, dim3(256), 0, s, G, p->N, p->gram_n, ga, ord, th, p->gram_hmax,
+                           p->lx1, p->lx2, p->gram_d4);
     return hipGetLastError();
 }
 

@@ -360,10 +360,10 @@ k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT,
                 if constexpr (SB > 0) {
                     // branch-free search over the angle's breakpoints held in
                     // registers (SB >= smax; entries at or past nsub are 2,
-                    // never passed since t < 1)
+                    // never passed since t < 1; the first, 0, is not needed)
                     T bb[SB];
 #pragma unroll
-                    for (int q = 0; q < SB; ++q) bb[q] = q < smax ? bk[q] : T(2);
+                    for (int q = 1; q < SB; ++q) bb[q] = q < smax ? bk[q] : T(2);
 #pragma unroll
                     for (int i = 0; i < PPT; ++i) {
                         T t;
@@ -440,15 +440,15 @@ int bp_breakpoint_regs(const gct_plan *p, size_t elem) { return bp_sb(p, elem); 
     switch (bp_hn(p) * 32 + bp_sb(p, sizeof(T))) {                                                    \
     case 4 * 32 + 5: CASE(4, 5); break;                                                               \
     case 4 * 32 + 9: CASE(4, 9); break;                                                               \
-    case 4 * 32 + 16: CASE(4, 16); break;                                                             \
+    case 4 * 32 + 16: if constexpr (sizeof(T) == 4) CASE(4, 16); break; /* FP32 only */              \
     case 4 * 32 + 0: CASE(4, 0); break;                                                               \
     case 6 * 32 + 5: CASE(6, 5); break;                                                               \
     case 6 * 32 + 9: CASE(6, 9); break;                                                               \
-    case 6 * 32 + 16: CASE(6, 16); break;                                                             \
+    case 6 * 32 + 16: if constexpr (sizeof(T) == 4) CASE(6, 16); break;                              \
     case 6 * 32 + 0: CASE(6, 0); break;                                                               \
     case 8 * 32 + 5: CASE(8, 5); break;                                                               \
     case 8 * 32 + 9: CASE(8, 9); break;                                                               \
-    case 8 * 32 + 16: CASE(8, 16); break;                                                             \
+    case 8 * 32 + 16: if constexpr (sizeof(T) == 4) CASE(8, 16); break;                              \
     default: CASE(8, 0); break;                                                                       \
     }
 template <typename T>

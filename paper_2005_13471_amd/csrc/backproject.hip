@@ -15,12 +15,16 @@ namespace gct {
 // (zero outside the row), so the taps read LDS instead of 2K+1 global loads
 // per output; the terms are summed in ascending tap order, and the zero
 // samples add exact zeros, so the result equals the plain truncated sum.
+// KC: the truncation K fixed at compile time (the default 40: the tap loop
+// unrolls and the taps are loaded once per wave, not once per term), or 0
+// (K at run time).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int KC>
 __global__ void __launch_bounds__(256)
-k_prefilter(const T *__restrict__ g, T *__restrict__ out, int n, int M, int K,
+k_prefilter(const T *__restrict__ g, T *__restrict__ out, int n, int M, int Kr,
             const T *__restrict__ q, const int32_t *__restrict__ deg)
 {
+    const int K = KC > 0 ? KC : Kr;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *s_row = reinterpret_cast<T *>(smem_raw);  // row[m0 - 2K .. m0 + 255]
     const int Mp = M + 2 * K;
@@ -46,7 +50,12 @@ k_prefilter(const T *__restrict__ g, T *__restrict__ out, int n, int M, int K,
     // term j reads row[mo - K - j] = s_row[threadIdx.x + K - j]
     const T *w = s_row + threadIdx.x + K;
     T acc = 0;
-    for (int j = -K; j <= K; ++j) acc += q[j + K] * w[-j];
+    if constexpr (KC > 0) {
+#pragma unroll
+        for (int j = -KC; j <= KC; ++j) acc += q[j + KC] * w[-j];
+    } else {
+        for (int j = -K; j <= K; ++j) acc += q[j + K] * w[-j];
+    }
     out[(size_t)a * Mp + mo] = acc;
 }
 
@@ -58,8 +67,11 @@ hipError_t launch_prefilter(const gct_plan *p, const T *g, T *out, hipStream_t s
     const size_t lds = (size_t)(256 + 2 * p->K) * sizeof(T);
     if (lds > 64 * 1024) return hipErrorInvalidConfiguration;
     const T *q = reinterpret_cast<const T *>(sizeof(T) == 4 ? p->dev.q_f32 : p->dev.q_f64);
-    hipLaunchKernelGGL(k_prefilter<T>, grid, dim3(256), lds, s, g, out, p->n, p->M, p->K, q,
-                       reinterpret_cast<const int32_t *>(p->dev.deg));
+    const int32_t *deg = reinterpret_cast<const int32_t *>(p->dev.deg);
+    if (p->K == 40)
+        hipLaunchKernelGGL((k_prefilter<T, 40>), grid, dim3(256), lds, s, g, out, p->n, p->M, p->K, q, deg);
+    else
+        hipLaunchKernelGGL((k_prefilter<T, 0>), grid, dim3(256), lds, s, g, out, p->n, p->M, p->K, q, deg);
     return hipGetLastError();
 }
 

@@ -274,12 +274,19 @@ template <typename T, int HN, int SB>
 __global__ void __launch_bounds__(BP_NT, BP_WAVES)
 k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT, int groups,
           const double *__restrict__ geo, const int32_t *__restrict__ ints, const T *__restrict__ brk,
-          int smax, int rmax, int CH)
+          int smax, int rmax, int CH, int LP)
 {
     constexpr int NT = BP_NT, D1P = 8, PPT = BP_TX * BP_TY / NT, RSTEP = NT / BP_TX, WB = BP_WB;
     constexpr int V = 16 / sizeof(T);  // elements per 16-byte piece
+    // a table row is PR pieces in global memory, of which its HN coefficients
+    // fill NPR; in LDS the rows are LP pieces apart (bp_lp: odd where the
+    // tables still fit, so that rows at random bins fall on 8 distinct
+    // 16-byte positions per 128 bytes; with 32-byte rows, 4 of them, the
+    // gathers met twice the bank conflicts)
+    constexpr int PR = D1P / V, NPR = (HN + V - 1) / V;
+    const int LRS = LP * V;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int eang = rmax * smax * D1P;
+    const int eang = rmax * smax * LRS;
     // table rows E [CH][rmax][smax][D1P]; for a run of WB angles:
     // breakpoints [WB][smax], (frac(z_t), dz1, dz2) [WB][3] and (g0, R, nsub,
     // zi - mlo) [WB][4], g0 = mlo - mA_a the window's first row in the
@@ -293,18 +300,22 @@ k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT,
     const int d1 = tid % BP_TX, d2 = tid / BP_TX;  // rows d2 + RSTEP i
     const int gsz = (n + groups - 1) / groups;
     const int abeg = blockIdx.z * gsz, aend = min(n, abeg + gsz);
-    const int rowp = smax * D1P / V;  // 16-byte pieces per bin row of a table
+    const int rowp = smax * NPR;  // 16-byte pieces copied per bin of a table window
     // the table rows of window entries [c0, c0 + cnt) (angles A + c) to
-    // LDS, 16 bytes per thread and step (rows outside [0, MT) are zero)
+    // LDS, 16 bytes per thread and step (rows outside [0, MT) are zero):
+    // piece i is piece i % NPR of the window's row i / NPR
     auto stage = [&](int A, int c0, int cnt) {
         const uint4 *src = reinterpret_cast<const uint4 *>(etab);
         for (int c = 0; c < cnt; ++c) {
             const int *w = s_w + 4 * (c0 + c);
             const int a = A + c0 + c, tot = w[1] * rowp, g0 = w[0];
             const int lo = max(0, -g0) * rowp, hi = min(w[1], MT - g0) * rowp;
-            const int64_t off = ((int64_t)a * MT + g0) * rowp;  // piece i of the window: src[off + i]
+            const int64_t r0 = ((int64_t)a * MT + g0) * smax;  // the window's first row
             uint4 *dst = reinterpret_cast<uint4 *>(s_E + (size_t)c * eang);
-            for (int i = tid; i < tot; i += NT) dst[i] = (i >= lo && i < hi) ? src[off + i] : make_uint4(0, 0, 0, 0);
+            for (int i = tid; i < tot; i += NT) {
+                const int r = i / NPR, k = i - r * NPR;
+                dst[r * LP + k] = (i >= lo && i < hi) ? src[(r0 + r) * PR + k] : make_uint4(0, 0, 0, 0);
+            }
         }
     };
     T acc[PPT], comp[PPT];
@@ -354,7 +365,7 @@ k_bp_tile(const T *__restrict__ etab, T *__restrict__ out, int N, int n, int MT,
                 const T rstep = (T)RSTEP * dz2;
                 // value of the angle's interpolant at pixel i, given its row
                 // (bin, sub-interval) and offset t in the bin
-                auto row = [&](int mi, int sub) { return Ec + (__umul24(mi, smax) + sub) * D1P; };
+                auto row = [&](int mi, int sub) { return Ec + (__umul24(mi, smax) + sub) * LRS; };
                 auto horner = [&](int i, const T *ev, T u) {
                     T v = ev[HN - 1];
 #pragma unroll
@@ -477,9 +488,15 @@ static const void *bp_tile_fn(const gct_plan *p)
 // angles per chunk (table rows; breakpoints and windows of a run of BP_WB
 // angles).
 static int bp_rmax(const gct_plan *p) { return (int)std::ceil(p->bp.tile_win) + 4; }
-static size_t bp_tile_lds(const gct_plan *p, size_t elem, int ch)
+// pieces of 16 bytes that a table row's coefficients fill (NPR of k_bp_tile)
+static int bp_npr(const gct_plan *p, size_t elem)
 {
-    return ((size_t)ch * bp_rmax(p) * p->bp.smax * 8 + (size_t)BP_WB * (p->bp.smax + 3)) * elem +
+    const int v = (int)(16 / elem);
+    return (bp_hn(p) + v - 1) / v;
+}
+static size_t bp_tile_lds(const gct_plan *p, size_t elem, int ch, int lp)
+{
+    return ((size_t)ch * bp_rmax(p) * p->bp.smax * lp * (16 / elem) + (size_t)BP_WB * (p->bp.smax + 3)) * elem +
            (size_t)BP_WB * 4 * sizeof(int);
 }
 // LDS bytes of the table kernel (one angle's coefficients, padded to 8)
@@ -501,22 +518,30 @@ static void bp_configure_t(gct_plan *p, int t)
 {
     p->bp_ch[t] = 0;
     p->bp_groups[t] = 1;
+    p->bp_lp[t] = 0;
     // beyond the kernels' limits (8 coefficients per table row, 16 taps,
     // one angle's coefficients in LDS)
     if (p->bp.D1 > 8 || p->bp.J > 16 || bp_etab_lds(p, sizeof(T)) > 65536) return;
     const void *fn = bp_tile_fn<T>(p);
-    int best_ch = 0, best_nb = 0;
-    for (int ch : {8, 4, 2, 1}) {
-        const size_t lds = bp_tile_lds(p, sizeof(T), ch);
-        if (lds > 65536) continue;
-        int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, BP_NT, lds) != hipSuccess) nb = 1;
-        if (nb > best_nb) {
-            best_nb = nb;
-            best_ch = ch;
+    int best_ch = 0, best_nb = 0, best_lp = 0;
+    // the odd row stride first; the dense one when only that fits
+    const int npr = bp_npr(p, sizeof(T));
+    for (int lp : {npr | 1, npr}) {
+        for (int ch : {8, 4, 2, 1}) {
+            const size_t lds = bp_tile_lds(p, sizeof(T), ch, lp);
+            if (lds > 65536) continue;
+            int nb = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, BP_NT, lds) != hipSuccess) nb = 1;
+            if (nb > best_nb) {
+                best_nb = nb;
+                best_ch = ch;
+                best_lp = lp;
+            }
         }
+        if (best_ch > 0) break;
     }
     if (best_ch == 0) return;
+    p->bp_lp[t] = best_lp;
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || cus < 1)
         cus = 256;
@@ -605,10 +630,11 @@ hipError_t launch_backproject(const gct_plan *p, const T *pf, T *b, T *part, T *
                                smax, p->bp.J, p->bp.D1);
             const dim3 grid((N + BP_TX - 1) / BP_TX, (N + BP_TY - 1) / BP_TY, groups);
             T *dst = groups > 1 ? part : b;
-            const size_t lds = bp_tile_lds(p, sizeof(T), ch);
+            const int lp = p->bp_lp[t];
+            const size_t lds = bp_tile_lds(p, sizeof(T), ch, lp);
 #define GCT_BP_TILE(HN_, SB_)                                                                             \
     hipLaunchKernelGGL((k_bp_tile<T, HN_, SB_>), grid, dim3(BP_NT), lds, s, (const T *)etab, dst, N, p->n, MT, \
-                       groups, geo_, ints_, brk_, smax, rmax, ch)
+                       groups, geo_, ints_, brk_, smax, rmax, ch, lp)
             GCT_BP_TILE_CASES(GCT_BP_TILE)
 #undef GCT_BP_TILE
             if (groups > 1) {

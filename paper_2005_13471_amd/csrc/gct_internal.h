@@ -167,8 +167,9 @@ struct gct_plan {
     int32_t cg_e[2], cg_ec[2];
     gct::BPDims bp;
     // launch shape of the tiled back projection, [F32, F64] (bp_configure):
-    // angles per chunk (0: the tiled kernel does not apply) and angle groups
-    int32_t bp_ch[2], bp_groups[2];
+    // angles per chunk (0: the tiled kernel does not apply), angle groups and
+    // the LDS row stride of its tables in 16-byte pieces
+    int32_t bp_ch[2], bp_groups[2], bp_lp[2];
     gct::DeviceTables dev;
     int64_t dev_bytes = 0;  // bytes of the device tables
     int device;

@@ -374,11 +374,11 @@ def _bins(N, zeta, ly):
 
 # Fine detector sampling (lambda_y < lambda_x, Sec. 6 sampling-rate sweep):
 # a tile window's table rows outgrow the tiled kernel's 64 KB of LDS (FP64
-# at lambda_y = 0.25; FP32 at 0.125 without blur) or its 16-tap limit (FP32
-# at 0.125 with blur), so the per-angle kernel runs (tile side 16 or 32).
+# at lambda_y = 0.25; FP32 at 0.0625 without blur) or its 16-tap limit (FP32
+# at 0.125 with blur), so the per-angle kernel runs (tile side 8, 16 or 32).
 PER_ANGLE = [(Case(48, 30, M=_bins(48, 1.0, 0.25), zeta=1.0, ly=0.25), torch.float64),
              (Case(48, 30, M=_bins(48, 1.0, 0.125), zeta=1.0, ly=0.125), torch.float32),
-             (Case(40, 26, M=_bins(40, 0.0, 0.125), zeta=0.0, ly=0.125), torch.float32)]
+             (Case(40, 26, M=_bins(40, 0.0, 0.0625), zeta=0.0, ly=0.0625), torch.float32)]
 
 
 @pytest.mark.parametrize("case,dt", PER_ANGLE, ids=lambda v: repr(v))

@@ -56,7 +56,8 @@ struct FwdAngle {
 // where kappa = l1 l2 M_{Xi / lambda_y}, Xi = {l1|c|, l2|s|, zeta,
 // lambda_y x (d+1)}.  On each sub-interval [brk[s], brk[s+1]) of t the
 // weights kappa(j - t) are polynomials in u = t - brk[s] with coefficients
-// coef[s][j][0..D].
+// coef[s][j][0..D] (the host tables; the device tables hold them re-expanded
+// in powers of t).
 struct BPAngleHost {
     double z0, dz1, dz2;
     int32_t nsub, jlo, degree;

@@ -399,6 +399,50 @@ def test_cg_solves_tiny_system_exactly(oracle_lib):
     assert hist[-1] <= 1e-13
 
 
+def test_cg_history_rounding_sensitivity(oracle_lib):
+    """CG residual histories on the n64 / a90 system are not unique under
+    rounding: the same textbook iteration in FP64 with the normal operator
+    applied by an FFT of the circulant embedding (numpy, here) instead of
+    the oracle's direct sum agrees with the oracle's history to ~1e-14 for
+    9 iterations, departs by O(1) around iterations 13-16 (a perturbation
+    grows ~100x per iteration there) and meets it again near iteration 20.
+    This is why CG parity compares early iterations, the final residual and
+    the oracle's re-check of the returned iterate, not whole histories."""
+    N, n, M = 64, 90, 92
+    og = oracle_lib.Geometry(N, inputs.angles(n), M)
+    G = oracle_lib.gram(og)
+    c, _ = inputs.phantom(N, 10, 1000)
+    b = oracle_lib.backproject(og, oracle_lib.forward(og, c))
+    _, _, h_ref = oracle_lib.cg(G, b, maxit=20, rtol=0.0)
+    P, W = 2 * N, 2 * N - 1
+    Gp = np.zeros((P, P))
+    idx = (np.arange(W) - (N - 1)) % P
+    Gp[np.ix_(idx, idx)] = G
+    Gh = np.fft.fft2(Gp)
+
+    def apply(x):
+        xp = np.zeros((P, P))
+        xp[:N, :N] = x
+        return np.real(np.fft.ifft2(np.fft.fft2(xp) * Gh))[:N, :N]
+
+    x, r = np.zeros_like(b), b.copy()
+    p, rr, bn = r.copy(), float(np.sum(r * r)), float(np.linalg.norm(b))
+    h = [np.sqrt(rr) / bn]
+    for _ in range(20):
+        Ap = apply(p)
+        al = rr / float(np.sum(p * Ap))
+        x += al * p
+        r -= al * Ap
+        rn = float(np.sum(r * r))
+        p = r + (rn / rr) * p
+        rr = rn
+        h.append(np.sqrt(rr) / bn)
+    rel = np.abs(np.array(h) - h_ref) / h_ref
+    assert np.max(rel[:9]) <= 1e-12
+    assert np.max(rel[13:17]) >= 0.1
+    assert np.max(rel[18:21]) <= 1e-4
+
+
 def test_cg_energy_error_monotone_and_true_residual(oracle_lib):
     N = 8
     g = oracle_lib.Geometry(N, inputs.angles(10), 16, zeta=1.0)

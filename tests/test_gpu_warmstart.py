@@ -21,6 +21,10 @@ def setup():
     assert W.have_trained(), "trained warm-start weights are missing from the package"
     cfg = W.WarmConfig()
     prob = W.Problem(cfg, batch_slices=SLICES)
+    # the default transform tilings rather than the autotuner's choice, which
+    # depends on timings: the iteration counts compared below move with the
+    # rounding of the passes, so the comparison should not depend on the box
+    gct.plan_set_pass_elems(prob.plan, 0, 0)
     seeds = range(W.TEST_SEEDS[0], W.TEST_SEEDS[0] + SLICES)
     b, xs, iters = W.generate(prob, seeds, None, log=lambda *a: None, normalize=False)
     return gct, W, prob, b, xs, iters
@@ -39,6 +43,7 @@ def test_trained_net_cuts_cg_iterations(setup):
     # moves the iteration at which the residual crosses the threshold; the
     # FFT blocking chosen by the plan's tuning moves it too)
     d = np.abs(cmp["plain_iters"] - iters)
+    say("single-slice vs batched iterations: mean |d|", np.mean(d), "max", np.max(d))
     assert np.mean(d) <= 1.5 and np.max(d) <= max(5, int(0.15 * np.max(iters)))
     # both forms meet the same stopping rule (true residual, FP32 slack)
     assert np.all(cmp["plain_res"] <= 1.05e-4) and np.all(cmp["warm_res"] <= 1.05e-4)

@@ -270,10 +270,10 @@ def test_batch_long_transforms_match_single_slice_and_oracle(which):
 # slices at the sizes of the 256-slice benchmark batch: the largest N and
 # angle count (the batched Gram build takes its angular windows in several
 # runs of 256 angles), a 2048-point transform of N = 768, and a small slice
-CONFIG3 = [(1024, 1440, 0.5), (768, 720, 1.0), (128, 180, 0.0)]
+LARGE_SLICES = [(1024, 1440, 0.5), (768, 720, 1.0), (128, 180, 0.0)]
 
 
-def test_batch_config3_sizes_match_oracle():
+def test_batch_large_slices_match_oracle():
     """Batch of benchmark-sized slices against the oracle: sampled Gram taps
     (oracle.gram_at), sampled outputs of the batched apply (the oracle's
     direct sum with its exact filter), and batched CG to 1e-4 on back
@@ -282,24 +282,24 @@ def test_batch_config3_sizes_match_oracle():
     from paper_2005_13471_amd import gramct as gct
     dt = torch.float32
     plans, ogs = [], []
-    for i, (N, n, z) in enumerate(CONFIG3):
+    for i, (N, n, z) in enumerate(LARGE_SLICES):
         th = inputs.angles(n)
         M = inputs.detector_bins(N, z)
         plans.append(gct.Plan(N, th, M, zeta=z))
         ogs.append(oracle.Geometry(N, th, M, zeta=z))
-    say("batch config-3 sizes", [(p.N, p.info.n_angles) for p in plans])
+    say("batch large slices", [(p.N, p.info.n_angles) for p in plans])
     B = gct.Batch(plans)
     G = torch.empty(B.gram_elems, dtype=dt, device="cuda")
     gct.batch_gram_build(B, G)
     Ghat = torch.empty(B.spectrum_elems, dtype=dt, device="cuda")
     gct.batch_gram_spectrum(B, G, Ghat, B.workspace(gct.OP_GRAM_SPECTRUM, dt))
-    cs = [inputs.uniform_coeffs(N, 6000 + i) for i, (N, _, _) in enumerate(CONFIG3)]
+    cs = [inputs.uniform_coeffs(N, 6000 + i) for i, (N, _, _) in enumerate(LARGE_SLICES)]
     y = torch.empty(B.image_elems, dtype=dt, device="cuda")
     gct.batch_gram_apply(B, Ghat, _packed(B, cs, dt), y, B.workspace(gct.OP_GRAM_APPLY, dt))
     # right-hand sides as in the benchmark: back projections of noisy
     # sinograms of 40-ellipse phantoms (line integrals of the ellipses)
     rhs = []
-    for i, (N, n, z) in enumerate(CONFIG3):
+    for i, (N, n, z) in enumerate(LARGE_SLICES):
         ells = inputs.random_ellipses(N, 40, 7000 + i)
         sino = inputs.add_noise(inputs.analytic_sinogram(ells, plans[i].theta, plans[i].M, zeta=z),
                                 0.01, inputs.NOISE_SEED_BASE + 7000 + i)

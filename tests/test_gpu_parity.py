@@ -61,10 +61,10 @@ class Case:
         return f"N={self.N} n={self.n} M={self.M} zeta={self.zeta} ly={self.ly} lx={self.lx}"
 
 
-CFG1 = Case(64, 90, M=92)
+N64_A90 = Case(64, 90, M=92)
 SMALL = [Case(37, 45, zeta=1.0), Case(23, 17, zeta=0.5, ly=0.75, lx=(0.9, 1.2), theta=inputs.angles(17) + 0.013),
          Case(16, 8, zeta=0.0, theta=np.array([0.0, np.pi / 2, np.pi / 4, 0.1, 3.0, 1.0, 2.0, 1.5]))]
-CFG2 = Case(512, 720, M=730, zeta=1.0)
+N512_A720 = Case(512, 720, M=730, zeta=1.0)
 
 
 # --------------------------------------------------------------------------
@@ -79,7 +79,7 @@ def _gram(gct, case, dt):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("case", [CFG1] + SMALL, ids=repr)
+@pytest.mark.parametrize("case", [N64_A90] + SMALL, ids=repr)
 def test_gram_build_full(gct, case, dt):
     say("gram_build", case, dt)
     got = _gram(gct, case, dt)
@@ -95,7 +95,7 @@ def test_gram_build_full(gct, case, dt):
 # square and the angle set is closed under theta -> theta + pi/2 and
 # theta -> -theta (mod pi), its images written by symmetry; half the plane
 # otherwise.  Both against the oracle, which evaluates every tap.
-GRAM_SYM = [(CFG1, 8), (Case(40, 30, zeta=1.0), 8), (Case(37, 45, zeta=1.0), 2),
+GRAM_SYM = [(N64_A90, 8), (Case(40, 30, zeta=1.0), 8), (Case(37, 45, zeta=1.0), 2),
             (Case(40, 30, zeta=1.0, theta=inputs.angles(30) + 0.013), 2),
             (Case(40, 30, zeta=1.0, lx=(0.9, 1.2)), 2),
             (Case(33, 32, zeta=0.5, theta=inputs.angles(32)[::-1].copy()), 8),
@@ -125,10 +125,10 @@ def test_gram_build_tiny_sizes(gct, N):
         assert normwise(_gram(gct, case, dt), oracle.gram(case.og())) <= tol("gram", dt)
 
 
-def test_gram_build_config2(gct):
-    say("gram_build", CFG2)
-    got = _gram(gct, CFG2, torch.float32)
-    ref = oracle.gram(CFG2.og())
+def test_gram_build_n512_a720(gct):
+    say("gram_build", N512_A720)
+    got = _gram(gct, N512_A720, torch.float32)
+    ref = oracle.gram(N512_A720.og())
     err = normwise(got, ref)
     say("  normwise", err)
     assert err <= 1e-5
@@ -148,7 +148,7 @@ def _apply_gpu(gct, case, dt, G_host, c):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("case", [CFG1] + SMALL + [Case(1, 3), Case(2, 5, zeta=1.0), Case(3, 4)], ids=repr)
+@pytest.mark.parametrize("case", [N64_A90] + SMALL + [Case(1, 3), Case(2, 5, zeta=1.0), Case(3, 4)], ids=repr)
 def test_gram_apply_oracle_filter(gct, case, dt):
     """Oracle G in, GPU spectrum + FFT convolution vs the oracle's direct sum."""
     say("gram_apply", case, dt)
@@ -162,9 +162,9 @@ def test_gram_apply_oracle_filter(gct, case, dt):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-def test_gram_apply_end_to_end_config1(gct, dt):
+def test_gram_apply_end_to_end_n64_a90(gct, dt):
     """GPU-built G -> spectrum -> apply vs the oracle's G and direct sum."""
-    case = CFG1
+    case = N64_A90
     say("gram_apply end-to-end", case, dt)
     P = case.plan(gct)
     G = torch.empty(P.info.gram_elems, dtype=dt, device="cuda")
@@ -178,8 +178,8 @@ def test_gram_apply_end_to_end_config1(gct, dt):
     assert normwise(host(y).reshape(case.N, case.N), ref) <= tol("apply", dt)
 
 
-def test_gram_apply_config2_sampled(gct):
-    case = CFG2
+def test_gram_apply_n512_a720_sampled(gct):
+    case = N512_A720
     say("gram_apply sampled", case)
     G = oracle.gram(case.og())
     c = inputs.uniform_coeffs(case.N, 2000)
@@ -320,7 +320,7 @@ def _sino(case, seed):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("case", [CFG1] + SMALL, ids=repr)
+@pytest.mark.parametrize("case", [N64_A90] + SMALL, ids=repr)
 def test_prefilter(gct, case, dt):
     say("prefilter", case, dt)
     P = case.plan(gct)
@@ -343,7 +343,7 @@ TINY = [Case(1, 3), Case(2, 5, zeta=1.0), Case(3, 4, zeta=0.5)]
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("case", [CFG1] + SMALL + TINY, ids=repr)
+@pytest.mark.parametrize("case", [N64_A90] + SMALL + TINY, ids=repr)
 def test_backproject_full(gct, case, dt):
     say("backproject", case, dt)
     g = _sino(case, 1002)
@@ -440,8 +440,8 @@ def test_backproject_rate_quarter(gct, dt):
     assert err <= tol("bp", dt)
 
 
-def test_backproject_config2_sampled(gct):
-    case = CFG2
+def test_backproject_n512_a720_sampled(gct):
+    case = N512_A720
     say("backproject sampled", case)
     ells = inputs.random_ellipses(case.N, 40, 1000)
     g = inputs.add_noise(inputs.analytic_sinogram(ells, case.theta, case.M, zeta=case.zeta), 0.01,
@@ -479,7 +479,7 @@ TINY_FP = [Case(1, 3, zeta=1.0), Case(2, 5), Case(3, 4, zeta=0.5)]
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-@pytest.mark.parametrize("case", [CFG1] + SMALL + TINY_FP, ids=repr)
+@pytest.mark.parametrize("case", [N64_A90] + SMALL + TINY_FP, ids=repr)
 def test_forward_full(gct, case, dt):
     say("forward", case, dt)
     c, _ = inputs.phantom(case.N, 10, 1000)
@@ -490,8 +490,8 @@ def test_forward_full(gct, case, dt):
     assert err <= tol("fp", dt)
 
 
-def test_forward_config2_sampled(gct):
-    case = CFG2
+def test_forward_n512_a720_sampled(gct):
+    case = N512_A720
     say("forward sampled", case)
     c, _ = inputs.phantom(case.N, 40, 1000)
     got = _fp_gpu(gct, case, torch.float32, c).reshape(-1)
@@ -531,8 +531,8 @@ def _cg_setup(gct, case, dt, G_host=None):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-def test_cg_config1_histories(gct, dt):
-    """20 CG iterations on config 1 against the FP64 oracle.
+def test_cg_n64_a90_histories(gct, dt):
+    """20 CG iterations at 64^2 / 90 angles against the FP64 oracle.
 
     CG residual histories are not unique under rounding on this system: an
     independent FP64 FFT implementation of the same iteration departs from
@@ -542,7 +542,7 @@ def test_cg_config1_histories(gct, dt):
     iterations (before FP32 / FP64 rounding can have grown past the bound),
     the iteration-20 residual, and the oracle's own re-check of the returned
     iterate."""
-    case = CFG1
+    case = N64_A90
     say("cg", case, dt)
     og = case.og()
     G = oracle.gram(og)
@@ -572,10 +572,10 @@ def test_cg_config1_histories(gct, dt):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-def test_cg_config1_converges_like_oracle(gct, dt):
+def test_cg_n64_a90_converges_like_oracle(gct, dt):
     """CG to 1e-4: iteration count close to the oracle's and the oracle's
     recomputed residual of the returned iterate within the tolerance."""
-    case = CFG1
+    case = N64_A90
     og = case.og()
     G = oracle.gram(og)
     c, _ = inputs.phantom(case.N, 10, 1000)
@@ -595,12 +595,12 @@ def test_cg_config1_converges_like_oracle(gct, dt):
     assert true_rel <= (1.01e-4 if dt == torch.float32 else 1.0001e-4)
 
 
-def test_cg_config2_converges(gct):
-    """Config 2 scale: CG to 1e-4; the oracle recomputes the whole residual
+def test_cg_n512_a720_converges(gct):
+    """At 512^2 / 720 angles: CG to 1e-4; the oracle recomputes the whole residual
     of the returned iterate (direct sum, 2.7e11 multiply-adds)."""
-    case = CFG2
+    case = N512_A720
     dt = torch.float32
-    say("cg config2", case)
+    say("cg n512_a720", case)
     og = case.og()
     G = oracle.gram(og)
     P, Ghat = _cg_setup(gct, case, dt, G)
@@ -625,12 +625,12 @@ def test_cg_config2_converges(gct):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-def test_sd_config1_histories(gct, dt):
+def test_sd_n64_a90_histories(gct, dt):
     """60 steepest-descent iterations (the paper's solver, Sec. 6.2) on
-    config 1 against the FP64 oracle's.  Unlike CG, steepest descent carries
+    64^2 / 90 angles against the FP64 oracle's.  Unlike CG, steepest descent carries
     no conjugacy that rounding can destroy, so the whole history is
     compared; the oracle re-checks the returned iterate."""
-    case = CFG1
+    case = N64_A90
     say("sd", case, dt)
     og = case.og()
     G = oracle.gram(og)
@@ -653,11 +653,11 @@ def test_sd_config1_histories(gct, dt):
 
 
 @pytest.mark.parametrize("dt", DTYPES)
-def test_sd_config1_converges_like_oracle(gct, dt):
-    """Steepest descent to 1e-4 on noisy config-1 data: the oracle's
+def test_sd_n64_a90_converges_like_oracle(gct, dt):
+    """Steepest descent to 1e-4 on noisy 64^2 / 90-angle data: the oracle's
     iteration count (about 110, against about 17 for CG) and the oracle's
     recomputed residual of the returned iterate."""
-    case = CFG1
+    case = N64_A90
     og = case.og()
     G = oracle.gram(og)
     c, _ = inputs.phantom(case.N, 10, 1000)
@@ -681,12 +681,12 @@ def test_sd_config1_converges_like_oracle(gct, dt):
     assert true_rel <= (1.01e-4 if dt == torch.float32 else 1.0001e-4)
 
 
-def test_sd_config2_converges(gct):
-    """Config 2 scale: steepest descent to 1e-4 (FP32); the oracle recomputes
+def test_sd_n512_a720_converges(gct):
+    """At 512^2 / 720 angles: steepest descent to 1e-4 (FP32); the oracle recomputes
     the whole residual of the returned iterate."""
-    case = CFG2
+    case = N512_A720
     dt = torch.float32
-    say("sd config2", case)
+    say("sd n512_a720", case)
     og = case.og()
     G = oracle.gram(og)
     P, Ghat = _cg_setup(gct, case, dt, G)
@@ -715,7 +715,7 @@ def test_cg_success_means_true_residual(gct, dt, rtol):
     while the true one stalls, so the solver restarts from its iterate and
     finally reports GCT_ENOTCONV rather than success; in FP64 the same
     tolerance is reached and reported as success."""
-    case = CFG1
+    case = N64_A90
     og = case.og()
     G = oracle.gram(og)
     c, _ = inputs.phantom(case.N, 10, 1000)
